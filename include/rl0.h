@@ -1,0 +1,159 @@
+/*
+ * librl0 -- Robust-l0 decoding of expander sketches on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Mendoza-Smith, Tanner, Wechsung, "A robust parallel algorithm for
+ * combinatorial compressed sensing" (arXiv 1704.09012).  The decoder is Alg. 1
+ * (Robust-l0) with the continuous scores of Table "scores"; with sigma = 0 it reduces
+ * to Alg. 2 (Parallel-l0).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers without an _h suffix are DEVICE pointers owned by the caller; the
+ *     library never frees them.  Pointers with an _h suffix are host pointers.
+ *   - The expander A in {0,1}^{m x n} (Definition "Expander matrices": exactly d ones
+ *     per column) is passed as A_cols: int32 [n][d], row-major, where A_cols[j*d + p]
+ *     is the p-th row index of column j.  The d indices of a column must be distinct,
+ *     ascending and in [0, m).
+ *   - Vectors are float32: x has n entries, y has m entries.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     stream-ordered; a call that fills a host-side stats struct synchronises its
+ *     stream before returning.
+ *   - Return codes: RL0_OK, or a negative RL0_E* code; rl0_last_error() then returns
+ *     a message (kept per calling thread).  Non-convergence of the decoder is not an
+ *     error (stats.converged = 0).
+ *   - Working memory is allocated by the library on first use and cached per
+ *     (device, stream); it is released by rl0_release().
+ */
+#ifndef RL0_H
+#define RL0_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RL0_OK 0
+#define RL0_EINVAL (-1)     /* bad sizes or parameters, non-finite or out-of-range values */
+#define RL0_EINDEX (-2)     /* A_cols: an index out of [0, m), repeated or not ascending */
+#define RL0_ENOMEM (-3)     /* device allocation failed */
+#define RL0_EHIP (-4)       /* a HIP runtime call failed */
+#define RL0_ENOWEIGHTS (-5) /* learned posterior requested without weights */
+#define RL0_ERANGE (-6)     /* a value left the 64-bit fixed-point range (|v| >= 2^22) */
+
+#define RL0_TABLE_N 4096    /* intervals of each score table */
+#define RL0_MAX_D 16        /* largest supported column weight d */
+
+/* Decoder parameters (Alg. 1 "KwData": alpha, mu, nu, c; variant flags of Table
+ * "variants").  Fill with rl0_params_default() and override fields as needed. */
+typedef struct rl0_params {
+    int32_t k;              /* sparsity k used by H_k and by rho = k/m in the posteriors */
+    float sigma;            /* noise std sigma_n of nu = N(0, sigma_n^2); 0 = noiseless
+                               (Parallel-l0 indicator scores) */
+    float sigma_signal;     /* signal std sigma_s of mu = N(0, sigma_s^2) (default 1) */
+    float alpha;            /* consensus threshold, alpha in (1, d] (default 2) */
+    float c;                /* decrement of t per iteration, in (0, 1); 0 selects the
+                               paper's rule eq:finetune_c_cont */
+    int32_t series_terms;   /* ell, explicit terms of eq:pz_approx/eq:pe_approx (default 4) */
+    int32_t max_iters;      /* 0 = ceil(1/c) (t runs 1, 1-c, ... > 0) */
+    int32_t l1_test;        /* 0 = column reading sum_{N(j)}|r-omega| <= sum_{N(j)}|r|,
+                               1 = literal |r_i - omega| <= |r_i| */
+    int32_t posterior;      /* 0 = analytic scores, 1 = learned network (mlp != NULL) */
+    const void* mlp;        /* device pointer to packed network weights (posterior = 1) */
+    int32_t validate;       /* 1 = check A_cols on the device before decoding */
+} rl0_params;
+
+/* What a decode did.  l1 values are ||r_hat||_1; the fixed-point one is exact. */
+typedef struct rl0_stats {
+    int32_t iterations;     /* loop iterations executed (sweeps run) */
+    int32_t accepted;       /* iterations whose ||r||_1 decreased */
+    int32_t converged;      /* ||r_hat||_1 <= m sigma sqrt(2/pi) at exit */
+    int32_t updates_total;  /* column updates proposed by the sweeps, summed */
+    int64_t l1_final_fx;    /* sum_i rint(2^30 |r_hat_i|) */
+    double l1_final;        /* l1_final_fx * 2^-30 */
+    double l1_tol;          /* m sigma sqrt(2/pi) (Sec. 4 "Stopping conditions") */
+    float t_final;          /* t of the last executed iteration */
+    int32_t error_flags;    /* device-side flags; nonzero only with an error return */
+} rl0_stats;
+
+/* Host copy of the decoder's constants, for inspection and tests. */
+typedef struct rl0_constants {
+    int32_t n_iters;                 /* iterations the t-sweep allows */
+    int32_t exact;                   /* 1 when sigma = 0 (indicator scores) */
+    double c;                        /* decrement of t actually used */
+    double tol;                      /* m sigma sqrt(2/pi) */
+    double range_z, range_e;         /* table ranges R_z, R_e */
+    float inv_h_z, inv_h_e;          /* fl32(N / R) */
+    float table_z[RL0_TABLE_N + 1];  /* fl32(p_breve_z(i R_z / N)) */
+    float table_e[RL0_TABLE_N + 1];  /* fl32(p_breve_e(i R_e / N)) */
+} rl0_constants;
+
+/* Fill *p with the paper's defaults for an instance of GM(n, m, k, d, N(0,1),
+ * N(0, sigma^2)): alpha = 2, c = 0 (= the rule eq:finetune_c_cont: 0.01 if m/n <= 0.05,
+ * else 0.025, taken as exact decimals), ell = 4, analytic posterior, validation on.
+ * Returns RL0_EINVAL on bad sizes. */
+int rl0_params_default(rl0_params* p_h, int32_t n, int32_t m, int32_t d, int32_t k, float sigma);
+
+/* Host only, no device work.  Computes the posteriors p_breve_z, p_breve_e
+ * (eq:pz_approx, eq:pe_approx normalised as in eq:breve) and their tables exactly as
+ * rl0_decode uses them.  t_h, if not NULL, receives n_iters values t_it = fl32(1 - it c)
+ * and tau_h the matching thresholds: row p of a column is a candidate of the outer test
+ * 1 - p_breve_z(r_p) >= t (Alg. 1) iff |r_p| >= tau (both float32); each array must hold
+ * at least max(ceil(1/c), max_iters) entries. */
+int rl0_compute_constants(const rl0_params* p_h, int32_t n, int32_t m, int32_t d,
+                          rl0_constants* out_h, float* t_h, float* tau_h);
+
+/* y = A x (Sec. 1; the measurement map of Definition "Generating model").
+ * y_i = fl32(2^-40 * sum_{j : i in N(j)} rint(2^40 x_j)), an order-independent integer
+ * sum that equals the exactly rounded A x whenever every x_j is a multiple of 2^-40.
+ * A_cols [n][d], x [n], y [m] on the device.  A_cols is validated first (RL0_EINDEX, and y
+ * is left unwritten); RL0_ERANGE if some |x_j| >= 2^22.  Synchronises the stream. */
+int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* x,
+               float* y, void* stream);
+
+/* Device-side check of A_cols: RL0_EINDEX if any index is outside [0, m) or a column
+ * is not strictly ascending.  Synchronises the stream. */
+int rl0_validate(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, void* stream);
+
+/* Robust-l0 (Alg. 1): recover x_hat ~ x from y_hat = A x + eta.
+ * A_cols [n][d] and y [m] on the device; x_out [n] (device) receives x_hat, the best
+ * accepted iterate.  If st_h != NULL the stream is synchronised and *st_h filled.
+ * RL0_EINVAL for d < 1 or d > min(m, RL0_MAX_D), k < 1 or k >= m, alpha outside (1, d],
+ * c outside [0, 1), sigma < 0, sigma_signal <= 0; RL0_EINDEX when validate = 1 and
+ * A_cols is malformed; RL0_ERANGE if y or an iterate leaves the fixed-point range. */
+int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* y,
+               const rl0_params* p_h, float* x_out, rl0_stats* st_h, void* stream);
+
+/* One iteration of Alg. 1's loop body from a caller-held state, for per-iteration
+ * checks and resumption.  In: x_hat [n], r_hat [m] (device; r_hat must be the
+ * residual of x_hat), *L_hat_h = sum_i rint(2^30 |r_hat_i|), it (t = fl32(1 - it c)).
+ * Out: x_hat, r_hat, *L_hat_h updated in place if the iteration is accepted; *accepted_h
+ * = 1/0.  Optional device outputs (NULL to skip), per column: updated [n] (int32 0/1),
+ * omega [n] (float32, 0 where not updated), x_trial [n] (H_k(x') before acceptance),
+ * and r_trial [m].  Synchronises the stream. */
+int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* y,
+             const rl0_params* p_h, int32_t it, float* x_hat, float* r_hat, int64_t* L_hat_h,
+             int32_t* accepted_h, int32_t* updated, float* omega, float* x_trial,
+             float* r_trial, void* stream);
+
+/* Timing of the column sweep (the loop's dominant kernel).  While enabled, rl0_decode
+ * records a pair of HIP events on its stream around every sweep launch and, once the
+ * decode has synchronised, adds the elapsed times of the sweeps that ran to a running
+ * total.  Enabling (or disabling) resets the total. */
+int rl0_profile_enable(int32_t enable);
+
+/* Total sweep time in milliseconds and number of timed sweep launches since the last
+ * rl0_profile_enable. */
+int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* rl0_last_error(void);
+
+/* Frees every cached device buffer of the calling process (all devices, streams). */
+void rl0_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RL0_H */

@@ -1,0 +1,37 @@
+// Host-side constants of the Robust-l0 decoder (see constants.cpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace rl0 {
+
+constexpr int kTableN = 4096;
+
+struct Problem {
+    int n = 0, m = 0, d = 0, k = 0;
+    double sigma = 0.0, sigma_s = 1.0;
+    double c = 0.0;
+    int ell = 4;
+    int max_iters = 0;
+};
+
+struct HostConstants {
+    bool exact = false;
+    double c = 0.0, tol = 0.0;
+    int n_iters = 0;
+    double range_z = 0.0, range_e = 0.0;
+    float inv_h_z = 0.0f, inv_h_e = 0.0f;
+    float table_z[kTableN + 1];
+    float table_e[kTableN + 1];
+    std::vector<float> t;            // t_it = fl32(1 - it c)
+    std::vector<uint32_t> tau_bits;  // outer test threshold per iteration (float bits)
+    uint32_t e_zero_bits = 0;        // |v_p - v_l| >= this  =>  e-score 0
+};
+
+double c_rule(double delta);
+int iterations_for(double c);
+bool compute_constants(const Problem& pr, HostConstants* hc);
+float table_score(const float* T, float inv_h, float a);
+
+}  // namespace rl0

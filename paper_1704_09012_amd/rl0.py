@@ -1,0 +1,262 @@
+"""Python binding of librl0 (include/rl0.h): argument marshalling only.
+
+Every step of the decoder runs in the HIP library.  Tensors are torch CUDA (HIP)
+tensors; torch supplies device memory and the current stream and nothing else.  If the
+library is not built the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librl0.so")
+
+RL0_TABLE_N = 4096
+RL0_MAX_D = 16
+
+ERRORS = {
+    -1: "RL0_EINVAL",
+    -2: "RL0_EINDEX",
+    -3: "RL0_ENOMEM",
+    -4: "RL0_EHIP",
+    -5: "RL0_ENOWEIGHTS",
+    -6: "RL0_ERANGE",
+}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("sigma", ctypes.c_float),
+        ("sigma_signal", ctypes.c_float),
+        ("alpha", ctypes.c_float),
+        ("c", ctypes.c_float),
+        ("series_terms", ctypes.c_int32),
+        ("max_iters", ctypes.c_int32),
+        ("l1_test", ctypes.c_int32),
+        ("posterior", ctypes.c_int32),
+        ("mlp", ctypes.c_void_p),
+        ("validate", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("accepted", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("updates_total", ctypes.c_int32),
+        ("l1_final_fx", ctypes.c_int64),
+        ("l1_final", ctypes.c_double),
+        ("l1_tol", ctypes.c_double),
+        ("t_final", ctypes.c_float),
+        ("error_flags", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Constants(ctypes.Structure):
+    _fields_ = [
+        ("n_iters", ctypes.c_int32),
+        ("exact", ctypes.c_int32),
+        ("c", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("range_z", ctypes.c_double),
+        ("range_e", ctypes.c_double),
+        ("inv_h_z", ctypes.c_float),
+        ("inv_h_e", ctypes.c_float),
+        ("table_z", ctypes.c_float * (RL0_TABLE_N + 1)),
+        ("table_e", ctypes.c_float * (RL0_TABLE_N + 1)),
+    ]
+
+
+class Rl0Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librl0.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1704_09012_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, V = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+        L.rl0_params_default.argtypes = [ctypes.POINTER(Params), I32, I32, I32, I32, ctypes.c_float]
+        L.rl0_compute_constants.argtypes = [ctypes.POINTER(Params), I32, I32, I32, ctypes.POINTER(Constants), P, P]
+        L.rl0_sketch.argtypes = [P, I32, I32, I32, P, P, V]
+        L.rl0_validate.argtypes = [P, I32, I32, I32, V]
+        L.rl0_decode.argtypes = [P, I32, I32, I32, P, ctypes.POINTER(Params), P, ctypes.POINTER(Stats), V]
+        L.rl0_step.argtypes = [P, I32, I32, I32, P, ctypes.POINTER(Params), I32, P, P,
+                               ctypes.POINTER(I64), ctypes.POINTER(I32), P, P, P, P, V]
+        L.rl0_profile_enable.argtypes = [I32]
+        L.rl0_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+        L.rl0_last_error.restype = ctypes.c_char_p
+        L.rl0_release.argtypes = []
+        for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
+                     "rl0_decode", "rl0_step"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise Rl0Error(rc, lib().rl0_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def params_default(n: int, m: int, d: int, k: int, sigma: float, **overrides) -> Params:
+    p = Params()
+    _check(lib().rl0_params_default(ctypes.byref(p), n, m, d, k, ctypes.c_float(sigma)))
+    for key, val in overrides.items():
+        if not hasattr(p, key):
+            raise KeyError(key)
+        setattr(p, key, val)
+    return p
+
+
+@dataclass
+class HostConstants:
+    n_iters: int
+    exact: bool
+    c: float
+    tol: float
+    range_z: float
+    range_e: float
+    inv_h_z: np.float32
+    inv_h_e: np.float32
+    table_z: np.ndarray
+    table_e: np.ndarray
+    t: np.ndarray
+    tau: np.ndarray
+
+
+def compute_constants(p: Params, n: int, m: int, d: int) -> HostConstants:
+    out = Constants()
+    cap = max(200, p.max_iters + 1)
+    t = np.zeros(cap, np.float32)
+    tau = np.zeros(cap, np.float32)
+    _check(lib().rl0_compute_constants(ctypes.byref(p), n, m, d, ctypes.byref(out),
+                                       t.ctypes.data_as(ctypes.c_void_p), tau.ctypes.data_as(ctypes.c_void_p)))
+    k = out.n_iters
+    return HostConstants(n_iters=k, exact=bool(out.exact), c=out.c, tol=out.tol, range_z=out.range_z,
+                         range_e=out.range_e, inv_h_z=np.float32(out.inv_h_z), inv_h_e=np.float32(out.inv_h_e),
+                         table_z=np.ctypeslib.as_array(out.table_z).copy(),
+                         table_e=np.ctypeslib.as_array(out.table_e).copy(), t=t[:k].copy(), tau=tau[:k].copy())
+
+
+def validate(A_cols, m: int) -> None:
+    torch = _torch()
+    n, d = A_cols.shape
+    _check(lib().rl0_validate(_dev_ptr(A_cols, torch.int32, name="A_cols"), n, m, d, _stream()))
+
+
+def sketch(A_cols, x, m: int, out=None):
+    """y = A x on the device (rl0_sketch)."""
+    torch = _torch()
+    n, d = A_cols.shape
+    y = out if out is not None else torch.empty(m, dtype=torch.float32, device=x.device)
+    _check(lib().rl0_sketch(_dev_ptr(A_cols, torch.int32, (n, d), "A_cols"), n, m, d,
+                            _dev_ptr(x, torch.float32, (n,), "x"), _dev_ptr(y, torch.float32, (m,), "y"),
+                            _stream()))
+    return y
+
+
+def decode(A_cols, y, sigma: float | None = None, d: int | None = None, params: Params | None = None,
+           k: int | None = None, out=None, **overrides):
+    """Robust-l0 (rl0_decode).  Returns (x_hat tensor, stats dict)."""
+    torch = _torch()
+    n, dd = A_cols.shape
+    if d is not None and d != dd:
+        raise ValueError("d does not match A_cols")
+    m = y.shape[0]
+    if params is None:
+        if sigma is None or k is None:
+            raise ValueError("give params, or sigma and k")
+        params = params_default(n, m, dd, k, sigma, **overrides)
+    else:
+        for key, val in overrides.items():
+            setattr(params, key, val)
+    x = out if out is not None else torch.empty(n, dtype=torch.float32, device=y.device)
+    st = Stats()
+    _check(lib().rl0_decode(_dev_ptr(A_cols, torch.int32, (n, dd), "A_cols"), n, m, dd,
+                            _dev_ptr(y, torch.float32, (m,), "y"), ctypes.byref(params),
+                            _dev_ptr(x, torch.float32, (n,), "x_out"), ctypes.byref(st), _stream()))
+    return x, st.as_dict()
+
+
+def step(A_cols, y, params: Params, it: int, x_hat, r_hat, L_hat: int, debug: bool = True):
+    """One loop iteration (rl0_step) in place on x_hat, r_hat.  Returns a dict."""
+    torch = _torch()
+    n, d = A_cols.shape
+    m = y.shape[0]
+    L = ctypes.c_int64(L_hat)
+    acc = ctypes.c_int32(0)
+    dbg = {}
+    if debug:
+        dbg = {
+            "updated": torch.zeros(n, dtype=torch.int32, device=y.device),
+            "omega": torch.zeros(n, dtype=torch.float32, device=y.device),
+            "x_trial": torch.zeros(n, dtype=torch.float32, device=y.device),
+            "r_trial": torch.zeros(m, dtype=torch.float32, device=y.device),
+        }
+    ptr = lambda key: ctypes.c_void_p(dbg[key].data_ptr()) if debug else None  # noqa: E731
+    _check(lib().rl0_step(_dev_ptr(A_cols, torch.int32, (n, d), "A_cols"), n, m, d,
+                          _dev_ptr(y, torch.float32, (m,), "y"), ctypes.byref(params), it,
+                          _dev_ptr(x_hat, torch.float32, (n,), "x_hat"),
+                          _dev_ptr(r_hat, torch.float32, (m,), "r_hat"), ctypes.byref(L), ctypes.byref(acc),
+                          ptr("updated"), ptr("omega"), ptr("x_trial"), ptr("r_trial"), _stream()))
+    out = {"L_hat": int(L.value), "accepted": bool(acc.value)}
+    out.update(dbg)
+    return out
+
+
+def profile_enable(enable: bool = True) -> None:
+    """Time every sweep launch of rl0_decode with HIP events (resets the total)."""
+    _check(lib().rl0_profile_enable(1 if enable else 0))
+
+
+def profile_read() -> tuple[float, int]:
+    """(total sweep milliseconds, sweep launches) since the last profile_enable."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().rl0_profile_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def release() -> None:
+    lib().rl0_release()

@@ -1,0 +1,119 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, rejects bad
+arguments before touching a device, and computes its host constants (score tables,
+t-sweep, outer-test thresholds) exactly as the oracle does.  No device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import decoder as D
+from oracle import scores as S
+from paper_1704_09012_amd import instances as I
+from paper_1704_09012_amd import rl0 as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    syms = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            syms += re.findall(r"^\s*(?:int|void|const char\*|size_t)\s+(rl0_\w+)\s*\(", text, re.M)
+    return sorted(set(syms))
+
+
+def test_library_exports_every_declared_symbol():
+    L = R.lib()
+    syms = _declared_symbols()
+    assert "rl0_decode" in syms and "rl0_sketch" in syms and "rl0_step" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_params_default_follow_the_paper():
+    p = R.params_default(1024, 256, 7, 25, 0.01)
+    assert p.k == 25 and p.alpha == 2.0 and p.series_terms == 4 and p.validate == 1 and p.c == 0.0
+    assert R.compute_constants(p, 1024, 256, 7).c == 0.025      # delta = 0.25 > 0.05 (eq:finetune_c_cont)
+    p = R.params_default(100000, 1000, 7, 25, 0.01)
+    assert R.compute_constants(p, 100000, 1000, 7).c == 0.01    # delta = 0.01 <= 0.05
+
+
+@pytest.mark.parametrize("field,value", [
+    ("k", 0), ("k", 256), ("alpha", 1.0), ("alpha", 7.5), ("c", 1.0), ("c", -0.1),
+    ("sigma", -1.0), ("sigma", float("nan")), ("sigma_signal", 0.0), ("series_terms", 0),
+    ("max_iters", -1), ("l1_test", 2), ("posterior", 3),
+])
+def test_bad_params_are_rejected_on_the_host(field, value):
+    p = R.params_default(1024, 256, 7, 25, 0.01)
+    setattr(p, field, value)
+    with pytest.raises(R.Rl0Error) as e:
+        R.compute_constants(p, 1024, 256, 7)
+    assert e.value.code == -1
+
+
+def test_learned_posterior_without_weights():
+    p = R.params_default(1024, 256, 7, 25, 0.01)
+    p.posterior = 1
+    with pytest.raises(R.Rl0Error) as e:
+        R.compute_constants(p, 1024, 256, 7)
+    assert e.value.code == -5
+
+
+@pytest.mark.parametrize("n,m,d", [(0, 10, 2), (10, 0, 2), (10, 10, 0), (10, 10, 17), (10, 5, 6)])
+def test_bad_dims_are_rejected(n, m, d):
+    with pytest.raises(R.Rl0Error) as e:
+        R.params_default(n, m, d, 1, 0.01)
+    assert e.value.code == -1
+
+
+CONFIGS = [
+    (1024, 256, 7, 25, 40),
+    (2 ** 20, 104857, 7, 10485, 20),
+    (2 ** 20, 104857, 7, 10485, 40),
+    (2 ** 20, 104857, 7, 10485, 60),
+    (2 ** 24, 2 ** 21, 8, 2 ** 18, None),   # sigma = 0.01
+    (4096, 150, 7, 20, 30),                 # delta <= 0.05: c = 0.01
+]
+
+
+@pytest.mark.parametrize("n,m,d,k,snr", CONFIGS)
+def test_host_constants_equal_the_oracle(n, m, d, k, snr):
+    sig = 0.01 if snr is None else I.sigma_for_snr(snr, n, m, k, d)
+    sig = float(np.float32(sig))
+    p = R.params_default(n, m, d, k, sig)
+    hc = R.compute_constants(p, n, m, d)
+    C = D.make_constants(n, m, d, k, sig)
+    assert hc.n_iters == C.n_iters
+    assert np.array_equal(hc.table_z, C.Tz.T) and np.array_equal(hc.table_e, C.Te.T)
+    assert hc.inv_h_z == C.Tz.inv_h and hc.inv_h_e == C.Te.inv_h
+    assert hc.tol == pytest.approx(C.tol, rel=1e-15)
+    ts = np.array([S.t_of(i, C.c) for i in range(C.n_iters)], np.float32)
+    assert np.array_equal(hc.t, ts)
+
+
+@pytest.mark.parametrize("n,m,d,k,snr", CONFIGS[:4])
+def test_outer_threshold_equals_the_outer_test(n, m, d, k, snr):
+    """|r| >= tau_t  <=>  fl32(1 - p_breve_z(r)) >= t, on every float near tau and at random."""
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    p = R.params_default(n, m, d, k, sig)
+    hc = R.compute_constants(p, n, m, d)
+    C = D.make_constants(n, m, d, k, sig)
+    rng = np.random.Generator(np.random.PCG64(0))
+    for it in range(C.n_iters):
+        t = hc.t[it]
+        tau = hc.tau[it]
+        tb = np.float32(tau).view(np.uint32)
+        near = (np.arange(-300, 300, dtype=np.int64) + int(tb)).clip(0, 0x7F800000).astype(np.uint32).view(np.float32)
+        rnd = (rng.random(20000) * 10 * sig).astype(np.float32)
+        a = np.concatenate([near, rnd])
+        formula = (np.float32(1.0) - S.lookup(C.Tz, a)).astype(np.float32) >= t
+        assert np.array_equal(a >= tau, formula), it
+
+
+def test_exact_mode_constants():
+    p = R.params_default(1024, 256, 7, 25, 0.0)
+    hc = R.compute_constants(p, 1024, 256, 7)
+    assert hc.exact and hc.tol == 0.0
+    assert np.all(hc.tau == np.float32(1e-45))
