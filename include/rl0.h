@@ -146,6 +146,11 @@ int rl0_profile_enable(int32_t enable);
  * rl0_profile_enable. */
 int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h);
 
+/* Total milliseconds, since the last rl0_profile_enable, of the three kernels of every
+ * timed loop iteration: ms_total_h[0] the column sweep, [1] H_k with the residual
+ * change, [2] the residual rounding and ||r||_1 (ms_total_h holds 3 doubles). */
+int rl0_profile_read_kernels(double* ms_total_h);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* rl0_last_error(void);
 

@@ -9,6 +9,9 @@ namespace rl0 {
 constexpr int kMaxD = 16;
 constexpr int kFxShift = 40;   // residual / sketch fixed point: 40 fractional bits
 constexpr int kL1Shift = 30;   // ||r||_1 fixed point: 30 fractional bits
+constexpr int kHistBins = 2048;
+constexpr int kSweepGridMax = 256;   // workgroups of the sweep (each owns a candidate segment)
+constexpr int kRowGrid = 256;        // workgroups of the row kernels (each owns a partial sum)
 
 enum ErrFlag : int {
     kErrRange = 1,      // a value left the fixed-point range
@@ -16,22 +19,29 @@ enum ErrFlag : int {
     kErrNonFinite = 4,  // y holds NaN or Inf
 };
 
-// Device-resident state of one decode.  Two-slot fields are indexed by iteration
-// parity so that iteration it can clear the slot of it+1 while its own is read.
+// Loop state after the decision of one iteration.  Iteration it decides iteration it-1
+// at its start and writes slot[it & 1]; it reads slot[(it - 1) & 1], which nothing
+// writes during iteration it, so no two kernels race on a slot.
+struct Slot {
+    long long L_hat;   // ||r_hat||_1 in units of 2^-30
+    int cur;           // buffer index holding (x_hat, r_hat, S_hat)
+    int done;          // no further iteration runs
+    int pending;       // this iteration ran and awaits its decision
+    int accepted;      // accepted iterations so far
+    int iterations;    // executed iterations so far
+    int accepted_last; // the last decision accepted
+};
+
+// Nothing here is updated by contended atomics: every workgroup writes its own entry
+// (candidate segment length, proposed updates, partial ||r||_1) and readers add them up.
 struct DevState {
-    long long L_hat;             // ||r_hat||_1 in units of 2^-30
-    long long L_trial[2];        // ||r||_1 of the trial iterate
-    int cand_count[2];           // entries in the candidate list
-    int done;                    // converged, out of iterations, or failed
-    int cur;                     // which residual buffer holds r_hat
-    int executed_it;             // last iteration that ran (-1 before any)
-    int accepted_flag;           // that iteration was accepted
-    int iterations;
-    int accepted;
-    int updates_total;
-    int err;                     // ErrFlag bits
-    int n_kept;                  // |supp H_k(x')| of the last iteration
-    unsigned long long kth_key;  // smallest key kept by H_k
+    Slot slot[2];
+    unsigned long long kth_key[2];        // smallest key H_k keeps
+    int updates_total;                    // column updates proposed, summed over iterations
+    int err;                              // ErrFlag bits
+    int seg_count[2][kSweepGridMax];      // candidates written by each sweep workgroup
+    int seg_updates[2][kSweepGridMax];    // updates proposed by each sweep workgroup
+    long long L_part[2][kRowGrid];        // partial ||r||_1 of the trial residual
 };
 
 struct DecodeDims {
@@ -46,43 +56,60 @@ struct ScoreTables {
 };
 
 struct IterParams {
-    float t;           // threshold of this iteration
-    uint32_t tau_bits; // |v| >= tau  <=>  fl32(1 - p_breve_z(v)) >= t
+    float t;              // threshold of this iteration
+    uint32_t tau_bits;    // |v| >= tau  <=>  fl32(1 - p_breve_z(v)) >= t
+    uint32_t tau_next;    // the same for iteration it + 1 (bitmask for the next sweep)
     float alpha;
     int l1_test;
     int it;
     int n_iters;
-    double tol_fx;     // tolerance in units of 2^-30
+    double tol_fx;        // tolerance in units of 2^-30 (negative: never converged)
 };
 
+// Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.
 struct Workspace {
-    long long* Sy;       // rint(2^40 y) [m]
-    long long* S;        // trial residual accumulator [m]
-    float* r_buf[2];     // r_hat and trial residual [m]
-    int* cand_j;         // candidate list (column) [n]
-    float* cand_x;       // candidate list (x'_j) [n]
+    long long* Sy;        // rint(2^40 y) [m]
+    long long* S[2];      // fixed-point residual [m]
+    float* r[2];          // float32 residual [m]
+    uint32_t* bm[2];      // bit i: |r[b]_i| >= tau of the next sweep [ceil(m/32)]
+    float* xs[2];         // x (dense, zero off the support) [n]
+    uint32_t* sb[2];      // support bitmap of xs[b] [ceil(n/32)]
+    int* cand_j[2];       // candidate list per iteration parity, one segment per sweep
+    float* cand_x[2];     //   workgroup of seg_cap entries: column j, x'_j and
+    float* cand_h[2];     //   x_hat_j (0 if j was not in the support)
+    int seg_cap;          // entries per segment
+    int sweep_grid;       // sweep workgroups (= segments)
     DevState* st;
 };
 
 struct DebugOut {
-    int* updated;        // [n] or nullptr
-    float* omega;        // [n] or nullptr
-    float* x_trial;      // [n] or nullptr
+    int* updated;        // [n] or nullptr (zeroed by the caller)
+    float* omega;        // [n] or nullptr (zeroed by the caller)
 };
+
+size_t workspace_bytes(int n, int m);
+void carve_workspace(void* base, int n, int m, Workspace* w);
 
 hipError_t launch_validate(const int32_t* A, int n, int m, int d, int* err, hipStream_t s);
 hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, float* y,
                          long long* S, int* err, hipStream_t s);
-// reset the state, optionally validate A_cols, x_hat = 0, r_hat = y, L_hat = L(y)
-hipError_t launch_init(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
-                       float* x_hat, const Workspace& w, const IterParams& ip, hipStream_t s);
-// One loop iteration.  ev_sweep[0], ev_sweep[1] (optional) are recorded on s right
-// before and after the sweep kernel.
-hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const float* y,
-                            float* x_hat, const Workspace& w, const ScoreTables& tb,
-                            const IterParams& ip, const DebugOut& dbg, hipStream_t s,
-                            hipEvent_t* ev_sweep = nullptr);
-hipError_t launch_fix(const float* y, long long* Sy, int m, DevState* st, hipStream_t s);
-hipError_t launch_reset_state(DevState* st, long long L_hat, hipStream_t s);
+hipError_t launch_clear_state(DevState* st, hipStream_t s);
+hipError_t launch_zero_i32(int* p, long long count, hipStream_t s);
+hipError_t launch_zero_f32(float* p, long long count, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStream_t s);
+
+// Prepare a run that starts at iteration it0 from x_hat0 (nullptr: x = 0).
+// validate: check A_cols first (a malformed A stops the run before any sweep).
+hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
+                          const float* x_hat0, const Workspace& w, const IterParams& ip0,
+                          hipStream_t s);
+// One loop iteration (sweep, H_k and residual, finish).  ev_sweep (optional, 4 events)
+// gets events recorded before the sweep and after each of the three kernels.
+hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
+                            const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
+                            hipStream_t s, hipEvent_t* ev_sweep = nullptr);
+// Decide the last iteration (it = n_iters) and write x_out = x_hat.
+hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
+                         float* x_out, hipStream_t s);
 
 }  // namespace rl0

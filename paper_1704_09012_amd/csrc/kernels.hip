@@ -1,16 +1,22 @@
 // HIP kernels of the Robust-l0 decoder for gfx950 (MI355X).
 //
-// One decode iteration (the while-loop body of Alg. 1) is
-//   sweep    every column j reads its d residual entries, runs the noisy consensus test
-//            and proposes x'_j; columns in supp(x_hat) or updated join a candidate list
-//   select   H_k: the k-th largest key (|x'_j| bits, then smaller j) over the list
-//   residual r = y - A H_k(x') in 64-bit fixed point (exact integer atomics, so the
-//            result does not depend on the order of the atomics), rounded to float32
-//   accept   keep (x', r) if ||r||_1 (exact integer) decreased; advance t; stop test
+// One iteration of Alg. 1's loop is three kernels:
+//   sweep         decides the previous iteration (accept/reject, stop test) from device
+//                 state, makes the trial buffers equal to the current ones again, then runs
+//                 the column loop: each column tests its rows against a 1-bit-per-row
+//                 bitmask of the outer test held in LDS; only columns with a candidate row
+//                 gather their exact residuals and run the noisy consensus test.  Columns in
+//                 supp(x_hat) or updated join the candidate list of H_k.
+//   select_apply  H_k: the k-th largest key (|x'_j| bits, then smaller j) by an 11-bit
+//                 radix select started from the sweep's histogram; then the trial support
+//                 and the exact integer change of the residual of every changed column.
+//   finish_rows   r = fl32(2^-40 S) and ||r||_1 (an exact integer), and the outer-test
+//                 bitmasks for the next iteration of both the trial and the current residual.
+// Every launch is stream-ordered and the host never waits between iterations.
 //
 // Floating point follows a fixed contract so that results are bitwise reproducible:
 // float32 operations in the written order, no contraction (-ffp-contract=off and the
-// pragma below), IEEE division.
+// pragma below), IEEE division; residuals and ||r||_1 are integer sums.
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -26,6 +32,14 @@ constexpr double kTwo40 = 1099511627776.0;          // 2^40
 constexpr double kTwoM40 = 1.0 / 1099511627776.0;   // 2^-40
 constexpr double kTwo30 = 1073741824.0;             // 2^30
 constexpr double kFxLimit = 4611686018427387904.0;  // 2^62
+constexpr int kSweepBlock = 1024;
+constexpr int kSweepCols = 4;                     // columns per sweep thread per chunk
+constexpr int kSweepChunk = kSweepBlock * kSweepCols;
+constexpr int kQueueRowInts = 7168;                 // 28 KiB of row indices of queued columns
+constexpr int kBmLdsWords = 12288;                  // 48 KiB: bitmasks of m <= 393216 rows
+constexpr int kSelectBlock = 1024;
+constexpr int kSelectGrid = 64;
+constexpr int kRowBlock = 1024;
 
 __device__ __forceinline__ long long to_fx(float v, int* err) {
     const double s = static_cast<double>(v) * kTwo40;
@@ -44,6 +58,8 @@ __device__ __forceinline__ long long l1_term(float r) {
     return __double2ll_rn(static_cast<double>(fabsf(r)) * kTwo30);
 }
 
+__device__ __forceinline__ uint32_t abs_bits(float v) { return __float_as_uint(v) & 0x7FFFFFFFu; }
+
 __device__ __forceinline__ float table_score(const float* __restrict__ T, float inv_h, float a) {
     const float u = a * inv_h;
     if (!(u < static_cast<float>(kTableN))) return 0.0f;
@@ -60,27 +76,12 @@ __device__ __forceinline__ float score(const float* __restrict__ T, float inv_h,
 }
 
 __device__ __forceinline__ unsigned long long hk_key(int j, float x) {
-    const unsigned int mag = __float_as_uint(x) & 0x7FFFFFFFu;
-    return (static_cast<unsigned long long>(mag) << 32) |
+    return (static_cast<unsigned long long>(abs_bits(x)) << 32) |
            static_cast<unsigned long long>(0xFFFFFFFFu - static_cast<unsigned int>(j));
-}
-
-// Wave-aggregated slot reservation in an append list.  Every lane of the wave must call.
-__device__ __forceinline__ int wave_append(bool pred, int* counter) {
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0ull) return -1;
-    const int lane = __lane_id();
-    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-    base = __shfl(base, leader);
-    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-    return pred ? base + rank : -1;
 }
 
 template <int BLOCK>
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
-    // wave reduction then LDS across waves
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -93,7 +94,55 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
     return tot;  // valid in thread 0
 }
 
-// ------------------------------------------------------------------ validation, sketch
+// Decision on iteration it-1 (Alg. 1: keep (x', r) iff ||r||_1 < ||r_hat||_1) and the
+// stop test for iteration it ("while not converged and t > 0").  p = slot of iteration
+// it-1, Lt = ||r||_1 of its trial iterate, err = the error flags.
+__device__ __forceinline__ Slot decide_from(const Slot p, int err, int it, int n_iters, double tol_fx,
+                                            long long Lt) {
+    Slot s = p;
+    s.accepted_last = 0;
+    if (p.pending) {
+        const int acc = (Lt < p.L_hat) && (err == 0);
+        if (acc) {
+            s.L_hat = Lt;
+            s.cur = p.cur ^ 1;
+            s.accepted = p.accepted + 1;
+        }
+        s.accepted_last = acc;
+        s.iterations = p.iterations + 1;
+    }
+    s.pending = 0;
+    if (!s.done) s.done = (err != 0) || (static_cast<double>(s.L_hat) <= tol_fx) || (it >= n_iters);
+    if (!s.done) s.pending = 1;
+    return s;
+}
+
+__device__ __forceinline__ Slot decide(const DevState* st, int it, int n_iters, double tol_fx, long long Lt) {
+    return decide_from(st->slot[(it & 1) ^ 1], st->err, it, n_iters, tol_fx, Lt);
+}
+
+// trial_l1 computed by a whole workgroup (blockDim.x >= 64, a multiple of 64); the
+// result is returned to every thread.  The partial sums were written by other CUs, so
+// their loads are issued in parallel rather than one after another.
+__device__ __forceinline__ long long trial_l1_block(const DevState* st, int par, long long* sh) {
+    long long v = 0;
+    for (int b = threadIdx.x; b < kRowGrid; b += blockDim.x) v += st->L_part[par][b];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    const int waves = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int w = 0; w < waves; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// Sum of kRowBlock-thread block values; result valid in thread 0.
+__device__ __forceinline__ long long block_sum_rows(long long v, long long* sh) {
+    return block_sum_ll<kRowBlock>(v, sh);
+}
+
+// ------------------------------------------------------------------ small utilities
 
 __global__ void k_validate(const int32_t* __restrict__ A, int n, int m, int d, int* err) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,9 +163,19 @@ __global__ void k_zero_ll(long long* __restrict__ S, int m) {
     if (i < m) S[i] = 0;
 }
 
-__global__ void k_zero_f32(float* __restrict__ x, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = 0.0f;
+__global__ void k_zero_i32(int* __restrict__ p, long long count) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, long long count) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0f;
+}
+
+__global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, long long count) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = src[i];
 }
 
 __global__ void k_sketch_scatter(const int32_t* __restrict__ A, int n, int d,
@@ -136,77 +195,127 @@ __global__ void k_sketch_finish(const long long* __restrict__ S, float* __restri
     if (i < m) y[i] = from_fx(S[i]);
 }
 
-// ------------------------------------------------------------------ decode: init
+// ------------------------------------------------------------------ prepare
 
-__global__ void k_reset_state(DevState* st, long long L_hat) {
-    st->L_hat = L_hat;
-    st->L_trial[0] = st->L_trial[1] = 0;
-    st->cand_count[0] = st->cand_count[1] = 0;
-    st->done = 0;
-    st->cur = 0;
-    st->executed_it = -1;
-    st->accepted_flag = 0;
-    st->iterations = 0;
-    st->accepted = 0;
-    st->updates_total = 0;
-    st->err = 0;
-    st->n_kept = 0;
-    st->kth_key = 0ull;
+__global__ void k_prep_state(DevState* st) {
+    int* p = reinterpret_cast<int*>(st);
+    const int words = static_cast<int>(sizeof(DevState) / sizeof(int));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
 }
 
-// Sy = rint(2^40 y); r0 = fl32(2^-40 Sy) (the residual of x = 0); L_hat = L(r0)
-__global__ __launch_bounds__(256) void k_init(const float* __restrict__ y, long long* __restrict__ Sy,
-                                              float* __restrict__ r0, int m, DevState* st, int add_l1) {
-    __shared__ long long sh[4];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    long long l = 0;
-    if (i < m) {
-        const float yi = y[i];
-        if (!isfinite(yi)) atomicOr(&st->err, kErrNonFinite);
-        const long long s = to_fx(yi, &st->err);
-        Sy[i] = s;
-        const float r = from_fx(s);
-        if (r0) r0[i] = r;
-        l = l1_term(r);
+// xs[0] = xs[1] = x0 (or 0), support bitmaps of it
+__global__ __launch_bounds__(256) void k_prep_cols(const float* __restrict__ x0, float* xs0, float* xs1,
+                                                   uint32_t* sb0, uint32_t* sb1, int n) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    float v = 0.0f;
+    if (j < n) {
+        v = x0 ? x0[j] : 0.0f;
+        xs0[j] = v;
+        xs1[j] = v;
     }
-    const long long tot = block_sum_ll<256>(l, sh);
-    if (add_l1 && threadIdx.x == 0 && tot != 0)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&st->L_hat), static_cast<unsigned long long>(tot));
+    const unsigned long long b = __ballot(j < n && v != 0.0f);
+    const int base = blockIdx.x * 256 + (threadIdx.x & ~63);
+    const int words = (n + 31) >> 5;
+    if ((threadIdx.x & 63) == 0) {
+        const int w0 = base >> 5;
+        if (w0 < words) { sb0[w0] = static_cast<uint32_t>(b); sb1[w0] = static_cast<uint32_t>(b); }
+        if (w0 + 1 < words) { sb0[w0 + 1] = static_cast<uint32_t>(b >> 32); sb1[w0 + 1] = static_cast<uint32_t>(b >> 32); }
+    }
 }
 
-__global__ void k_init_done(DevState* st, int n_iters, double tol_fx) {
-    if (st->err || n_iters <= 0 || static_cast<double>(st->L_hat) <= tol_fx) st->done = 1;
+// Sy = rint(2^40 y), S0 = Sy
+__global__ void k_prep_rows(const float* __restrict__ y, long long* __restrict__ Sy, long long* __restrict__ S0,
+                            int m, DevState* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const float yi = y[i];
+    if (!isfinite(yi)) atomicOr(&st->err, kErrNonFinite);
+    const long long s = to_fx(yi, &st->err);
+    Sy[i] = s;
+    S0[i] = s;
 }
 
-// ------------------------------------------------------------------ decode: sweep
+// S0 -= A x0 (columns with x0_j != 0)
+__global__ void k_prep_scatter(const int32_t* __restrict__ A, int n, int d, const float* __restrict__ x0,
+                               long long* __restrict__ S0, DevState* st) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n || st->err) return;
+    const float v = x0[j];
+    if (v == 0.0f) return;
+    const long long fx = to_fx(v, &st->err);
+    const int32_t* col = A + static_cast<size_t>(j) * d;
+    for (int p = 0; p < d; ++p)
+        atomicAdd(reinterpret_cast<unsigned long long*>(S0 + col[p]), static_cast<unsigned long long>(-fx));
+}
+
+// Bits of rows [base, base + 64) (base a multiple of 64) from a wave ballot.
+__device__ __forceinline__ void store_bits(uint32_t* bm, int words, int base, unsigned long long b) {
+    const int w0 = base >> 5;
+    if (w0 < words) bm[w0] = static_cast<uint32_t>(b);
+    if (w0 + 1 < words) bm[w0 + 1] = static_cast<uint32_t>(b >> 32);
+}
+
+// r0 = fl32(2^-40 S0), partial L(r0) into L_part[slot], outer-test bitmask of r0
+__global__ __launch_bounds__(kRowBlock) void k_prep_rows2(const long long* __restrict__ S0, float* __restrict__ r0,
+                                                          uint32_t* __restrict__ bm0, int m, uint32_t tau,
+                                                          DevState* st, int slot) {
+    __shared__ long long sh[kRowBlock / 64];
+    const int words = (m + 31) >> 5;
+    long long l = 0;
+    for (int base = blockIdx.x * kRowBlock; base < m; base += gridDim.x * kRowBlock) {
+        const int i = base + threadIdx.x;
+        bool bit = false;
+        if (i < m) {
+            const float v = from_fx(S0[i]);
+            r0[i] = v;
+            l += l1_term(v);
+            bit = abs_bits(v) >= tau;
+        }
+        const unsigned long long b = __ballot(bit);
+        if ((threadIdx.x & 63) == 0) store_bits(bm0, words, base + (threadIdx.x & ~63), b);
+    }
+    const long long tot = block_sum_rows(l, sh);
+    if (threadIdx.x == 0) st->L_part[slot][blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_prep_slot(DevState* st, int slot) {
+    __shared__ long long red[4];
+    const long long L0 = trial_l1_block(st, slot, red);
+    if (threadIdx.x != 0) return;
+    Slot& s = st->slot[slot];
+    s.L_hat = L0;
+    s.cur = 0;
+    s.done = 0;
+    s.pending = 0;
+    s.accepted = 0;
+    s.iterations = 0;
+    s.accepted_last = 0;
+}
+
+// ------------------------------------------------------------------ sweep
 
 struct SweepArgs {
     const int32_t* A;
-    int n;
-    const float* r_buf0;
-    const float* r_buf1;
-    const float* x_hat;
+    int n, m;
+    int chunks;      // ceil(n / kSweepChunk)
+    int bm_lds;      // the outer-test bitmask fits in LDS
+    Workspace w;
     ScoreTables tb;
     IterParams ip;
-    int* cand_j;
-    float* cand_x;
-    DevState* st;
     DebugOut dbg;
 };
 
-// Column body of Alg. 1 on the snapshot r_hat, float32 contract.  Returns whether the
-// column proposes an update and the chosen omega.
+// Column body of Alg. 1 on the snapshot r_hat, float32 contract.  cmask marks the rows
+// that pass the outer test.  Returns whether the column proposes an update and omega.
 template <int D>
 __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int cmask,
                                               const ScoreTables& tb, float alpha, int l1_test,
                                               float* omega_out) {
-    float z[D];
     float n_z = 0.0f;
     float S1 = 0.0f;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
-        z[p] = score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v[p]));
-        n_z = n_z + z[p];
+        n_z = n_z + score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v[p]));
         S1 = S1 + fabsf(v[p]);
     }
     bool has = false;
@@ -242,208 +351,538 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
     return has;
 }
 
+// The sweep: one workgroup per CU, each owning chunks of kSweepChunk columns and one
+// segment of the candidate list.  The kernel is a short chain of memory rounds, each
+// issuing all its loads at once:
+//   1. decision-independent: this workgroup's column indices, the score tables, the
+//      partial sums of ||r||_1 and the slot of the previous iteration;
+//   2. after the accept decision (buffer index c): the outer-test bitmask, the support
+//      words of my columns, the previous iteration's candidates (to make the trial
+//      buffers equal to the current ones again) and the copy S_trial = S_hat;
+//   3. the exact residual entries of the columns that have a candidate row.
 template <int D>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
-    DevState* st = a.st;
-    if (st->done | st->err) return;
-    const float* __restrict__ r = st->cur ? a.r_buf1 : a.r_buf0;
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    bool emit = false, upd = false;
-    float xp = 0.0f, om = 0.0f;
-    if (j < a.n) {
-        float v[D];
-        const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * D;
-        unsigned int cmask = 0u;
-#pragma unroll
-        for (int p = 0; p < D; ++p) {
-            v[p] = r[col[p]];
-            if ((__float_as_uint(v[p]) & 0x7FFFFFFFu) >= a.ip.tau_bits) cmask |= 1u << p;
-        }
-        const float xh = a.x_hat[j];
-        if (cmask) upd = column_update<D>(v, cmask, a.tb, a.ip.alpha, a.ip.l1_test, &om);
-        xp = upd ? xh + om : xh;
-        emit = upd || (xh != 0.0f);
-        if (a.dbg.updated) a.dbg.updated[j] = upd ? 1 : 0;
-        if (a.dbg.omega) a.dbg.omega[j] = upd ? om : 0.0f;
-    }
-    const int slot = wave_append(emit, &st->cand_count[a.ip.it & 1]);
-    if (slot >= 0) {
-        a.cand_j[slot] = j;
-        a.cand_x[slot] = xp;
-    }
-    const unsigned long long um = __ballot(upd);
-    if (__lane_id() == 0 && um) atomicAdd(&st->updates_total, __popcll(um));
-}
-
-// ------------------------------------------------------------------ decode: H_k select
-
-// One workgroup: the k-th largest key among nonzero candidates by 11-bit radix passes.
-__global__ __launch_bounds__(1024) void k_select(const int* __restrict__ cand_j,
-                                                 const float* __restrict__ cand_x, DevState* st,
-                                                 int it, int k) {
-    if (st->done | st->err) return;
-    __shared__ unsigned int hist[2048];
-    __shared__ unsigned int scan[1024];
-    __shared__ unsigned long long prefix, pmask;
-    __shared__ unsigned int remaining;
-    __shared__ unsigned int nz_total;
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
+    constexpr int kQueueRows = kQueueRowInts / D;
+    __shared__ uint32_t bml[kBmLdsWords];
+    __shared__ float Tz[kTableN + 1];
+    __shared__ float Te[kTableN + 1];
+    __shared__ int queue[kSweepChunk];
+    __shared__ int qrows[kQueueRows * D];
+    __shared__ int qn, seg_n, seg_upd;
+    __shared__ Slot s_sh;
+    __shared__ int pc_sh;
+    __shared__ unsigned long long kth_sh;
+    __shared__ long long red[kSweepBlock / 64];
+    const int it = a.ip.it, me = it & 1, pv = me ^ 1;
     const int tid = threadIdx.x;
-    const int count = st->cand_count[it & 1];
-    if (tid == 0) nz_total = 0;
-    __syncthreads();
-    unsigned int nz = 0;
-    for (int e = tid; e < count; e += 1024) nz += (cand_x[e] != 0.0f);
-    atomicAdd(&nz_total, nz);
-    __syncthreads();
-    if (nz_total <= static_cast<unsigned int>(k)) {
+    const int seg = blockIdx.x;
+    const size_t seg_base = static_cast<size_t>(seg) * a.w.seg_cap;
+    DevState* st = a.w.st;
+
+    // ---- round 1
+    int rows[kSweepCols][D];
+    {
+        const int chunk = blockIdx.x;
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q) {
+            const int j = chunk * kSweepChunk + q * kSweepBlock + tid;
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = j < a.n ? a.A[static_cast<size_t>(j) * D + p] : 0;
+        }
+    }
+    float tz0 = 0.0f, tz1 = 0.0f, tz2 = 0.0f, tz3 = 0.0f, tz4 = 0.0f;
+    float te0 = 0.0f, te1 = 0.0f, te2 = 0.0f, te3 = 0.0f, te4 = 0.0f;
+    if (!a.tb.exact) {
+        // kTableN + 1 = 4097 entries = 4 per thread + one
+        tz0 = a.tb.Tz[tid];
+        tz1 = a.tb.Tz[tid + kSweepBlock];
+        tz2 = a.tb.Tz[tid + 2 * kSweepBlock];
+        tz3 = a.tb.Tz[tid + 3 * kSweepBlock];
+        te0 = a.tb.Te[tid];
+        te1 = a.tb.Te[tid + kSweepBlock];
+        te2 = a.tb.Te[tid + 2 * kSweepBlock];
+        te3 = a.tb.Te[tid + 3 * kSweepBlock];
         if (tid == 0) {
-            st->kth_key = 1ull << 32;
-            st->n_kept = static_cast<int>(nz_total);
+            tz4 = a.tb.Tz[kTableN];
+            te4 = a.tb.Te[kTableN];
         }
-        return;
+    }
+    Slot prev{};
+    int pc = 0;
+    unsigned long long kth_prev = 0;
+    int err = 0;
+    if (tid == 0) {
+        prev = st->slot[pv];
+        pc = st->seg_count[pv][seg];
+        kth_prev = st->kth_key[pv];
+        err = st->err;
+    }
+    long long lp = tid < kRowGrid ? st->L_part[pv][tid] : 0;
+    if (!a.tb.exact) {
+        Tz[tid] = tz0;
+        Tz[tid + kSweepBlock] = tz1;
+        Tz[tid + 2 * kSweepBlock] = tz2;
+        Tz[tid + 3 * kSweepBlock] = tz3;
+        Te[tid] = te0;
+        Te[tid + kSweepBlock] = te1;
+        Te[tid + 2 * kSweepBlock] = te2;
+        Te[tid + 3 * kSweepBlock] = te3;
+        if (tid == 0) {
+            Tz[kTableN] = tz4;
+            Te[kTableN] = te4;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) lp += __shfl_down(lp, off);
+    if ((tid & 63) == 0) red[tid >> 6] = lp;
+    __syncthreads();
+    if (tid == 0) {
+        long long Lt = 0;
+        for (int w = 0; w < kSweepBlock / 64; ++w) Lt += red[w];
+        s_sh = decide_from(prev, err, it, a.ip.n_iters, a.ip.tol_fx, Lt);
+        pc_sh = pc;
+        kth_sh = kth_prev;
+        seg_n = 0;
+        seg_upd = 0;
+    }
+    __syncthreads();
+    const Slot s = s_sh;
+    if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
+    if (s.done) return;
+    const int c = s.cur, tr = c ^ 1;
+    const uint32_t* __restrict__ bmg = a.w.bm[c];
+    const float* __restrict__ r = a.w.r[c];
+    const float* __restrict__ xs = a.w.xs[c];
+    const uint32_t* __restrict__ sb = a.w.sb[c];
+    int* __restrict__ out_j = a.w.cand_j[me] + seg_base;
+    float* __restrict__ out_x = a.w.cand_x[me] + seg_base;
+    float* __restrict__ out_h = a.w.cand_h[me] + seg_base;
+    ScoreTables lt = a.tb;
+    lt.Tz = Tz;
+    lt.Te = Te;
+
+    // ---- round 2
+    uint32_t bw[kBmLdsWords / kSweepBlock];
+    const int words = (a.m + 31) >> 5;
+    if (a.bm_lds) {
+#pragma unroll
+        for (int q = 0; q < kBmLdsWords / kSweepBlock; ++q) {
+            const int wi = q * kSweepBlock + tid;
+            bw[q] = wi < words ? bmg[wi] : 0u;
+        }
+    }
+    uint32_t sbw[kSweepCols];
+#pragma unroll
+    for (int q = 0; q < kSweepCols; ++q) {
+        const int j = blockIdx.x * kSweepChunk + q * kSweepBlock + tid;
+        sbw[q] = j < a.n ? sb[j >> 5] : 0u;
+    }
+    // previous candidates of this segment: the trial buffer differs from the current one
+    // exactly at those whose H_k value changed; give it the current value again
+    const int pcn = pc_sh;
+    const unsigned long long kthp = kth_sh;
+    const int acc_prev = s.accepted_last;
+    for (int e = tid; e < pcn; e += kSweepBlock) {
+        const int j = a.w.cand_j[pv][seg_base + e];
+        const float xp = a.w.cand_x[pv][seg_base + e];
+        const float xh = a.w.cand_h[pv][seg_base + e];
+        const float nv = (xp != 0.0f && hk_key(j, xp) >= kthp) ? xp : 0.0f;
+        if (nv == xh) continue;
+        const float cur_v = acc_prev ? nv : xh;
+        a.w.xs[tr][j] = cur_v;
+        const uint32_t bit = 1u << (j & 31);
+        if (cur_v != 0.0f) atomicOr(&a.w.sb[tr][j >> 5], bit);
+        else atomicAnd(&a.w.sb[tr][j >> 5], ~bit);
+    }
+    for (int i = blockIdx.x * kSweepBlock + tid; i < a.m; i += gridDim.x * kSweepBlock) a.w.S[tr][i] = a.w.S[c][i];
+    if (a.bm_lds) {
+#pragma unroll
+        for (int q = 0; q < kBmLdsWords / kSweepBlock; ++q) {
+            const int wi = q * kSweepBlock + tid;
+            if (wi < words) bml[wi] = bw[q];
+        }
+    }
+
+    for (int chunk = blockIdx.x; chunk < a.chunks; chunk += gridDim.x) {
+        if (chunk != static_cast<int>(blockIdx.x)) {
+#pragma unroll
+            for (int q = 0; q < kSweepCols; ++q) {
+                const int j = chunk * kSweepChunk + q * kSweepBlock + tid;
+#pragma unroll
+                for (int p = 0; p < D; ++p) rows[q][p] = j < a.n ? a.A[static_cast<size_t>(j) * D + p] : 0;
+                sbw[q] = j < a.n ? sb[j >> 5] : 0u;
+            }
+        }
+        if (tid == 0) qn = 0;
+        __syncthreads();
+        // outer test of every row of my columns: one bit each from the bitmask
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q) {
+            const int j = chunk * kSweepChunk + q * kSweepBlock + tid;
+            if (j >= a.n) continue;
+            unsigned int cm = 0u;
+#pragma unroll
+            for (int p = 0; p < D; ++p) {
+                const int row = rows[q][p];
+                const uint32_t word = a.bm_lds ? bml[row >> 5] : bmg[row >> 5];
+                cm |= ((word >> (row & 31)) & 1u) << p;
+            }
+            const bool sup = (sbw[q] >> (j & 31)) & 1u;
+            if (cm) {
+                const int qi = atomicAdd(&qn, 1);
+                queue[qi] = j;
+                if (qi < kQueueRows) {
+#pragma unroll
+                    for (int p = 0; p < D; ++p) qrows[qi * D + p] = rows[q][p];
+                }
+            } else if (sup) {
+                // a support column with no candidate row keeps x'_j = x_hat_j
+                const int o = atomicAdd(&seg_n, 1);
+                const float xh = xs[j];
+                out_j[o] = j;
+                out_x[o] = xh;
+                out_h[o] = xh;
+            }
+        }
+        __syncthreads();
+        // ---- round 3: the noisy consensus test, one queued column per thread
+        const int nq = qn;
+        for (int e = tid; e < nq; e += kSweepBlock) {
+            const int jq = queue[e];
+            int rr[D];
+            if (e < kQueueRows) {
+#pragma unroll
+                for (int p = 0; p < D; ++p) rr[p] = qrows[e * D + p];
+            } else {
+                const int32_t* __restrict__ col = a.A + static_cast<size_t>(jq) * D;
+#pragma unroll
+                for (int p = 0; p < D; ++p) rr[p] = col[p];
+            }
+            const uint32_t sword = sb[jq >> 5];
+            float v[D];
+#pragma unroll
+            for (int p = 0; p < D; ++p) v[p] = r[rr[p]];
+            const bool sup = (sword >> (jq & 31)) & 1u;
+            const float xhq = sup ? xs[jq] : 0.0f;
+            unsigned int cm = 0u;
+#pragma unroll
+            for (int p = 0; p < D; ++p)
+                if (abs_bits(v[p]) >= a.ip.tau_bits) cm |= 1u << p;
+            float om = 0.0f;
+            const bool upd = column_update<D>(v, cm, lt, a.ip.alpha, a.ip.l1_test, &om);
+            if (a.dbg.updated) a.dbg.updated[jq] = upd ? 1 : 0;
+            if (a.dbg.omega) a.dbg.omega[jq] = upd ? om : 0.0f;
+            if (upd) atomicAdd(&seg_upd, 1);
+            if (upd || sup) {
+                const int o = atomicAdd(&seg_n, 1);
+                out_j[o] = jq;
+                out_x[o] = upd ? xhq + om : xhq;
+                out_h[o] = xhq;
+            }
+        }
+        __syncthreads();
     }
     if (tid == 0) {
-        prefix = 0ull;
-        pmask = 0ull;
-        remaining = static_cast<unsigned int>(k);
+        st->seg_count[me][seg] = seg_n;
+        st->seg_updates[me][seg] = seg_upd;
     }
-    const int shifts[6] = {53, 42, 31, 20, 9, 0};
-    const int widths[6] = {11, 11, 11, 11, 11, 9};
-    for (int pass = 0; pass < 6; ++pass) {
-        const int sh = shifts[pass];
-        const unsigned int dmask = (1u << widths[pass]) - 1u;
-        hist[tid] = 0u;
-        hist[tid + 1024] = 0u;
+}
+
+// ------------------------------------------------------------------ H_k and residual change
+
+struct SelectArgs {
+    const int32_t* A;
+    int d, k;
+    Workspace w;
+    int it;
+};
+
+// Within one workgroup: the digit of the bucket (among 2048, highest first) that holds
+// the `rem`-th largest of the counted keys, the count above it and the bucket's count.
+__device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, int* digit_out,
+                           unsigned* above_out, unsigned* bucket_out) {
+    const int tid = threadIdx.x;
+    const unsigned hi = hist[2047 - 2 * tid], lo = hist[2046 - 2 * tid];
+    scan[tid] = hi + lo;
+    __syncthreads();
+    for (int off = 1; off < kSelectBlock; off <<= 1) {
+        const unsigned add = tid >= off ? scan[tid - off] : 0u;
         __syncthreads();
-        const unsigned long long pf = prefix, pm = pmask;
-        for (int e = tid; e < count; e += 1024) {
-            const float x = cand_x[e];
-            if (x == 0.0f) continue;
-            const unsigned long long key = hk_key(cand_j[e], x);
-            if ((key & pm) == pf) atomicAdd(&hist[(key >> sh) & dmask], 1u);
-        }
+        scan[tid] += add;
         __syncthreads();
-        // thread t owns bins 2047-2t and 2046-2t; inclusive scan over t (top bins first)
-        const unsigned int hi = hist[2047 - 2 * tid], lo = hist[2046 - 2 * tid];
-        scan[tid] = hi + lo;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const unsigned int add = tid >= off ? scan[tid - off] : 0u;
-            __syncthreads();
-            scan[tid] += add;
-            __syncthreads();
-        }
-        const unsigned int incl = scan[tid];
-        const unsigned int before = incl - hi - lo;
-        const unsigned int rem = remaining;
-        __syncthreads();
-        int digit = -1;
-        unsigned int above = 0;
-        if (before < rem && rem <= before + hi) {
-            digit = 2047 - 2 * tid;
-            above = before;
-        } else if (before + hi < rem && rem <= incl) {
-            digit = 2046 - 2 * tid;
-            above = before + hi;
-        }
-        if (digit >= 0) {
-            prefix = pf | (static_cast<unsigned long long>(digit) << sh);
-            pmask = pm | (static_cast<unsigned long long>(dmask) << sh);
-            remaining = rem - above;
-        }
-        __syncthreads();
+    }
+    const unsigned incl = scan[tid];
+    const unsigned before = incl - hi - lo;
+    if (before < rem && rem <= before + hi) {
+        *digit_out = 2047 - 2 * tid;
+        *above_out = before;
+        *bucket_out = hi;
+    } else if (before + hi < rem && rem <= incl) {
+        *digit_out = 2046 - 2 * tid;
+        *above_out = before + hi;
+        *bucket_out = lo;
+    }
+    __syncthreads();
+}
+
+constexpr int kLdsKeys = 12288;   // candidate keys a select workgroup caches in LDS
+constexpr int kSelPer = 12;       // candidate loads in flight per select thread (kLdsKeys / block)
+
+// Entry e of the concatenated segments (seg_start: exclusive prefix sums of the segment
+// lengths, in LDS, ascending) -> its index in the candidate arrays.
+__device__ __forceinline__ size_t entry_index(const int* seg_start, int nseg, int cap, int e) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return static_cast<size_t>(lo) * cap + (e - seg_start[lo]);
+}
+
+// H_k's effect on one candidate: the trial support value and the exact change of the
+// residual of column j.
+__device__ __forceinline__ void apply_candidate(const SelectArgs& a, int tr, unsigned long long kth, int j,
+                                                float xp, float xh, int* err) {
+    const bool kept = (xp != 0.0f) && (hk_key(j, xp) >= kth);
+    const float nv = kept ? xp : 0.0f;
+    if (nv == xh) return;
+    const long long delta = (xh != 0.0f ? to_fx(xh, err) : 0) - (nv != 0.0f ? to_fx(nv, err) : 0);
+    if (delta != 0) {
+        const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
+        for (int p = 0; p < a.d; ++p)
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.w.S[tr] + col[p]), static_cast<unsigned long long>(delta));
+    }
+    a.w.xs[tr][j] = nv;
+    if ((nv != 0.0f) != (xh != 0.0f)) {
+        const uint32_t bit = 1u << (j & 31);
+        if (nv != 0.0f) atomicOr(&a.w.sb[tr][j >> 5], bit);
+        else atomicAnd(&a.w.sb[tr][j >> 5], ~bit);
+    }
+}
+
+// Every workgroup computes the k-th largest key of H_k (the same value everywhere);
+// workgroup b then applies the candidates of waves w with w % gridDim.x == b.
+__global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
+    __shared__ unsigned long long keys[kLdsKeys];
+    __shared__ unsigned hist[kHistBins];
+    __shared__ unsigned scan[kSelectBlock];
+    __shared__ int seg_start[kSweepGridMax];
+    __shared__ int digit;
+    __shared__ unsigned above, bucket, nz_sh;
+    __shared__ int upd_sh;
+    __shared__ Slot s_sh;
+    const int me = a.it & 1;
+    DevState* st = a.w.st;
+    const int tid = threadIdx.x;
+    const int nseg = a.w.sweep_grid;
+    const int cap = a.w.seg_cap;
+    const int G = gridDim.x;
+    const int* __restrict__ cj = a.w.cand_j[me];
+    const float* __restrict__ cx = a.w.cand_x[me];
+    const float* __restrict__ ch = a.w.cand_h[me];
+
+    // ---- round 1: slot and segment lengths
+    int myc = 0, myu = 0;
+    if (tid < nseg) {
+        myc = st->seg_count[me][tid];
+        if (blockIdx.x == 0) myu = st->seg_updates[me][tid];
     }
     if (tid == 0) {
-        st->kth_key = prefix;
-        st->n_kept = k;
+        s_sh = st->slot[me];
+        nz_sh = 0u;
+        upd_sh = 0;
+    }
+    if (tid < kSweepGridMax) seg_start[tid] = myc;
+    hist[tid] = 0u;
+    hist[tid + kSelectBlock] = 0u;
+    __syncthreads();
+    if (s_sh.done) return;
+    const int tr = s_sh.cur ^ 1;
+    if (myu) atomicAdd(&upd_sh, myu);
+    for (int off = 1; off < kSweepGridMax; off <<= 1) {
+        const int add = (tid < kSweepGridMax && tid >= off) ? seg_start[tid - off] : 0;
+        __syncthreads();
+        if (tid < kSweepGridMax) seg_start[tid] += add;
+        __syncthreads();
+    }
+    const int count = seg_start[nseg - 1];
+    __syncthreads();
+    if (tid < kSweepGridMax) seg_start[tid] -= myc;   // exclusive
+    if (blockIdx.x == 0 && tid == 0) st->updates_total += upd_sh;
+    __syncthreads();
+    const bool fast = count <= kLdsKeys;
+
+    // ---- round 2: candidates (all of them in registers and LDS on the fast path)
+    float xr[kSelPer], hr[kSelPer];
+    int jr[kSelPer];
+    unsigned nz = 0;
+    for (int base = 0; base < count; base += kSelectBlock * kSelPer) {
+#pragma unroll
+        for (int q = 0; q < kSelPer; ++q) {
+            const int e = base + q * kSelectBlock + tid;
+            xr[q] = 0.0f;
+            hr[q] = 0.0f;
+            jr[q] = 0;
+            if (e < count) {
+                const size_t ix = entry_index(seg_start, nseg, cap, e);
+                xr[q] = cx[ix];
+                jr[q] = cj[ix];
+                if (fast && ((e >> 6) % G) == static_cast<int>(blockIdx.x)) hr[q] = ch[ix];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kSelPer; ++q) {
+            const int e = base + q * kSelectBlock + tid;
+            if (e >= count) continue;
+            const unsigned long long key = xr[q] != 0.0f ? hk_key(jr[q], xr[q]) : 0ull;
+            if (fast) keys[e] = key;
+            if (key) {
+                ++nz;
+                atomicAdd(&hist[static_cast<unsigned>(key >> 52)], 1u);
+            }
+        }
+    }
+    if (nz) atomicAdd(&nz_sh, nz);
+    __syncthreads();
+
+    // ---- the k-th largest key
+    unsigned long long kth;
+    if (nz_sh <= static_cast<unsigned>(a.k)) {
+        kth = 1ull << 32;   // every nonzero entry is kept
+    } else {
+        unsigned rem = static_cast<unsigned>(a.k);
+        find_digit(hist, rem, scan, &digit, &above, &bucket);
+        unsigned long long prefix = static_cast<unsigned long long>(digit) << 52;
+        unsigned long long pmask = 0x7FFull << 52;
+        rem -= above;
+        bool exact = (rem == bucket);
+        const int shifts[5] = {41, 30, 19, 8, 0};
+        const int widths[5] = {11, 11, 11, 11, 8};
+        for (int pass = 0; pass < 5 && !exact; ++pass) {
+            const int sh = shifts[pass];
+            const unsigned dmask = (1u << widths[pass]) - 1u;
+            hist[tid] = 0u;
+            hist[tid + kSelectBlock] = 0u;
+            __syncthreads();
+            if (fast) {
+                for (int e = tid; e < count; e += kSelectBlock) {
+                    const unsigned long long key = keys[e];
+                    if (key && (key & pmask) == prefix) atomicAdd(&hist[(key >> sh) & dmask], 1u);
+                }
+            } else {
+                for (int e = tid; e < count; e += kSelectBlock) {
+                    const size_t ix = entry_index(seg_start, nseg, cap, e);
+                    const float x = cx[ix];
+                    if (x == 0.0f) continue;
+                    const unsigned long long key = hk_key(cj[ix], x);
+                    if ((key & pmask) == prefix) atomicAdd(&hist[(key >> sh) & dmask], 1u);
+                }
+            }
+            __syncthreads();
+            find_digit(hist, rem, scan, &digit, &above, &bucket);
+            prefix |= static_cast<unsigned long long>(digit) << sh;
+            pmask |= static_cast<unsigned long long>(dmask) << sh;
+            rem -= above;
+            exact = (rem == bucket);
+        }
+        kth = prefix;
+    }
+    if (blockIdx.x == 0 && tid == 0) st->kth_key[me] = kth;
+
+    // ---- trial support and exact residual change of every changed column
+    if (fast) {
+#pragma unroll
+        for (int q = 0; q < kSelPer; ++q) {
+            const int e = q * kSelectBlock + tid;
+            if (e < count && ((e >> 6) % G) == static_cast<int>(blockIdx.x))
+                apply_candidate(a, tr, kth, jr[q], xr[q], hr[q], &st->err);
+        }
+    } else {
+        for (int e = tid; e < count; e += kSelectBlock) {
+            if (((e >> 6) % G) != static_cast<int>(blockIdx.x)) continue;
+            const size_t ix = entry_index(seg_start, nseg, cap, e);
+            apply_candidate(a, tr, kth, cj[ix], cx[ix], ch[ix], &st->err);
+        }
     }
 }
 
-// ------------------------------------------------------------------ decode: residual
+// ------------------------------------------------------------------ finish rows
 
-__global__ void k_copy_ll(const long long* __restrict__ src, long long* __restrict__ dst, int m,
-                          const DevState* st) {
-    if (st->done | st->err) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) dst[i] = src[i];
-}
+struct FinishArgs {
+    int m;
+    Workspace w;
+    int it;
+    uint32_t tau_next;
+};
 
-__global__ void k_res_scatter(const int32_t* __restrict__ A, int d, const int* __restrict__ cand_j,
-                              const float* __restrict__ cand_x, long long* __restrict__ S,
-                              DevState* st, int it) {
-    if (st->done | st->err) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= st->cand_count[it & 1]) return;
-    const float x = cand_x[e];
-    if (x == 0.0f) return;
-    const int j = cand_j[e];
-    if (hk_key(j, x) < st->kth_key) return;
-    const long long fx = to_fx(x, &st->err);
-    const int32_t* col = A + static_cast<size_t>(j) * d;
-    for (int p = 0; p < d; ++p)
-        atomicAdd(reinterpret_cast<unsigned long long*>(S + col[p]), static_cast<unsigned long long>(-fx));
-}
-
-__global__ __launch_bounds__(256) void k_res_finish(const long long* __restrict__ S, float* r_buf0,
-                                                    float* r_buf1, int m, DevState* st, int it) {
-    if (st->done | st->err) return;
-    __shared__ long long sh[4];
-    float* __restrict__ r = st->cur ? r_buf0 : r_buf1;   // the trial buffer
-    const int i = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
+    __shared__ long long sh[kRowBlock / 64];
+    const int me = a.it & 1;
+    DevState* st = a.w.st;
+    const Slot s = st->slot[me];
+    const int words = (a.m + 31) >> 5;
     long long l = 0;
-    if (i < m) {
-        const float v = from_fx(S[i]);
-        r[i] = v;
-        l = l1_term(v);
+    for (int base = blockIdx.x * kRowBlock; base < a.m; base += gridDim.x * kRowBlock) {
+        const int i = base + threadIdx.x;
+        // both buffers are loaded in the same round as the slot that says which is which
+        long long s0 = 0, s1 = 0;
+        if (i < a.m) {
+            s0 = a.w.S[0][i];
+            s1 = a.w.S[1][i];
+        }
+        if (s.done) return;
+        const int c = s.cur, tr = c ^ 1;
+        bool bt = false, bc = false;
+        if (i < a.m) {
+            const float v = from_fx(tr ? s1 : s0);
+            const float vc = from_fx(tr ? s0 : s1);
+            a.w.r[tr][i] = v;
+            l += l1_term(v);
+            bt = abs_bits(v) >= a.tau_next;
+            bc = abs_bits(vc) >= a.tau_next;
+        }
+        const unsigned long long bmt = __ballot(bt);
+        const unsigned long long bmc = __ballot(bc);
+        if ((threadIdx.x & 63) == 0) {
+            const int wb = base + (threadIdx.x & ~63);
+            store_bits(a.w.bm[tr], words, wb, bmt);
+            store_bits(a.w.bm[c], words, wb, bmc);
+        }
     }
-    const long long tot = block_sum_ll<256>(l, sh);
-    if (threadIdx.x == 0 && tot != 0)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&st->L_trial[it & 1]), static_cast<unsigned long long>(tot));
+    if (s.done) return;
+    const long long tot = block_sum_rows(l, sh);
+    if (threadIdx.x == 0) st->L_part[me][blockIdx.x] = tot;
 }
 
-// ------------------------------------------------------------------ decode: accept
+// ------------------------------------------------------------------ final decision
 
-__global__ void k_decide(DevState* st, int it, int n_iters, double tol_fx) {
-    if (st->done) return;
-    if (st->err) {
-        st->done = 1;
-        return;
-    }
-    const long long Lt = st->L_trial[it & 1];
-    const int acc = (Lt < st->L_hat) && (st->err == 0);
-    st->accepted_flag = acc;
-    st->executed_it = it;
-    st->iterations = it + 1;
-    if (acc) {
-        st->L_hat = Lt;
-        st->accepted += 1;
-        st->cur ^= 1;
-    }
-    // clear the other parity's slots for iteration it + 1
-    st->L_trial[(it + 1) & 1] = 0;
-    st->cand_count[(it + 1) & 1] = 0;
-    if (st->err || it + 1 >= n_iters || static_cast<double>(st->L_hat) <= tol_fx) st->done = 1;
+__global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n_iters, double tol_fx) {
+    __shared__ long long red[4];
+    const long long Lt = trial_l1_block(st, (it & 1) ^ 1, red);
+    if (threadIdx.x == 0) st->slot[it & 1] = decide(st, it, n_iters, tol_fx, Lt);
 }
 
-__global__ void k_commit(const int* __restrict__ cand_j, const float* __restrict__ cand_x,
-                         float* __restrict__ x_hat, float* __restrict__ x_trial,
-                         const DevState* st, int it) {
-    if (st->executed_it != it) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= st->cand_count[it & 1]) return;
-    const int j = cand_j[e];
-    const float x = cand_x[e];
-    const bool kept = (x != 0.0f) && (hk_key(j, x) >= st->kth_key);
-    const float val = kept ? x : 0.0f;
-    if (x_trial) x_trial[j] = val;
-    if (st->accepted_flag) x_hat[j] = val;
+__global__ void k_copy_out(const Workspace w, float* __restrict__ x_out, int n, int it) {
+    const int c = w.st->slot[it & 1].cur;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) x_out[j] = w.xs[c][j];
 }
 
 inline int blocks(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
+int sweep_grid(int n) {
+    // one workgroup per CU, persistent over chunks of kSweepChunk columns
+    const int chunks = blocks(n, kSweepChunk);
+    return chunks < kSweepGridMax ? chunks : kSweepGridMax;
+}
+
+int seg_capacity(int n) {
+    const int chunks = blocks(n, kSweepChunk);
+    return blocks(chunks, sweep_grid(n)) * kSweepChunk;
+}
+
 template <int D>
 hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s) {
-    k_sweep<D><<<blocks(a.n, 256), 256, 0, s>>>(a);
+    k_sweep<D><<<a.w.sweep_grid, kSweepBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -469,7 +908,39 @@ hipError_t launch_sweep(int d, const SweepArgs& a, hipStream_t s) {
     }
 }
 
+size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
 }  // namespace
+
+// ------------------------------------------------------------------ workspace
+
+size_t workspace_bytes(int n, int m) {
+    const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
+    const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
+    return 3 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm) + 2 * al(4ull * n) + 2 * al(4 * wn) +
+           6 * al(4 * cand) + al(sizeof(DevState));
+}
+
+void carve_workspace(void* base, int n, int m, Workspace* w) {
+    const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
+    const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
+    w->Sy = reinterpret_cast<long long*>(take(8ull * m));
+    for (int b = 0; b < 2; ++b) w->S[b] = reinterpret_cast<long long*>(take(8ull * m));
+    for (int b = 0; b < 2; ++b) w->r[b] = reinterpret_cast<float*>(take(4ull * m));
+    for (int b = 0; b < 2; ++b) w->bm[b] = reinterpret_cast<uint32_t*>(take(4 * wm));
+    for (int b = 0; b < 2; ++b) w->xs[b] = reinterpret_cast<float*>(take(4ull * n));
+    for (int b = 0; b < 2; ++b) w->sb[b] = reinterpret_cast<uint32_t*>(take(4 * wn));
+    for (int b = 0; b < 2; ++b) {
+        w->cand_j[b] = reinterpret_cast<int*>(take(4 * cand));
+        w->cand_x[b] = reinterpret_cast<float*>(take(4 * cand));
+        w->cand_h[b] = reinterpret_cast<float*>(take(4 * cand));
+    }
+    w->seg_cap = seg_capacity(n);
+    w->sweep_grid = sweep_grid(n);
+    w->st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
+}
 
 // ------------------------------------------------------------------ launchers
 
@@ -487,54 +958,69 @@ hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, 
     return hipGetLastError();
 }
 
-hipError_t launch_reset_state(DevState* st, long long L_hat, hipStream_t s) {
-    k_reset_state<<<1, 1, 0, s>>>(st, L_hat);
+hipError_t launch_clear_state(DevState* st, hipStream_t s) {
+    k_prep_state<<<1, 256, 0, s>>>(st);
     return hipGetLastError();
 }
 
-hipError_t launch_fix(const float* y, long long* Sy, int m, DevState* st, hipStream_t s) {
-    // Sy only; L_hat is left as set by the caller (the state is reset to L_hat first)
-    k_init<<<blocks(m, 256), 256, 0, s>>>(y, Sy, nullptr, m, st, 0);
+hipError_t launch_zero_i32(int* p, long long count, hipStream_t s) {
+    if (count > 0) k_zero_i32<<<blocks(count, 256), 256, 0, s>>>(p, count);
     return hipGetLastError();
 }
 
-hipError_t launch_init(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
-                       float* x_hat, const Workspace& w, const IterParams& ip, hipStream_t s) {
-    k_reset_state<<<1, 1, 0, s>>>(w.st, 0);
+hipError_t launch_zero_f32(float* p, long long count, hipStream_t s) {
+    if (count > 0) k_zero_f32<<<blocks(count, 256), 256, 0, s>>>(p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStream_t s) {
+    if (count > 0) k_copy_f32<<<blocks(count, 256), 256, 0, s>>>(src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
+                          const float* x_hat0, const Workspace& w, const IterParams& ip0, hipStream_t s) {
+    const int slot = (ip0.it & 1) ^ 1;   // the slot iteration it0 reads as "previous"
+    k_prep_state<<<1, 256, 0, s>>>(w.st);
     if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
-    k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat, dm.n);
-    k_init<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.r_buf[0], dm.m, w.st, 1);
-    k_init_done<<<1, 1, 0, s>>>(w.st, ip.n_iters, ip.tol_fx);
+    k_prep_cols<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, w.xs[0], w.xs[1], w.sb[0], w.sb[1], dm.n);
+    k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], dm.m, w.st);
+    if (x_hat0) k_prep_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.d, x_hat0, w.S[0], w.st);
+    k_prep_rows2<<<kRowGrid, kRowBlock, 0, s>>>(w.S[0], w.r[0], w.bm[0], dm.m, ip0.tau_bits, w.st, slot);
+    k_prep_slot<<<1, 256, 0, s>>>(w.st, slot);
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const float* y,
-                            float* x_hat, const Workspace& w, const ScoreTables& tb,
-                            const IterParams& ip, const DebugOut& dbg, hipStream_t s,
-                            hipEvent_t* ev_sweep) {
-    (void)y;
+hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
+                            const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
+                            hipStream_t s, hipEvent_t* ev_sweep) {
     SweepArgs a;
     a.A = A;
     a.n = dm.n;
-    a.r_buf0 = w.r_buf[0];
-    a.r_buf1 = w.r_buf[1];
-    a.x_hat = x_hat;
+    a.m = dm.m;
+    a.chunks = blocks(dm.n, kSweepChunk);
+    a.bm_lds = ((dm.m + 31) / 32) <= kBmLdsWords ? 1 : 0;
+    a.w = w;
     a.tb = tb;
     a.ip = ip;
-    a.cand_j = w.cand_j;
-    a.cand_x = w.cand_x;
-    a.st = w.st;
     a.dbg = dbg;
     if (ev_sweep) hipEventRecord(ev_sweep[0], s);
     hipError_t e = launch_sweep(dm.d, a, s);
     if (e != hipSuccess) return e;
     if (ev_sweep) hipEventRecord(ev_sweep[1], s);
-    k_select<<<1, 1024, 0, s>>>(w.cand_j, w.cand_x, w.st, ip.it, dm.k);
-    k_copy_ll<<<blocks(dm.m, 256), 256, 0, s>>>(w.Sy, w.S, dm.m, w.st);
-    k_res_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.d, w.cand_j, w.cand_x, w.S, w.st, ip.it);
-    k_res_finish<<<blocks(dm.m, 256), 256, 0, s>>>(w.S, w.r_buf[0], w.r_buf[1], dm.m, w.st, ip.it);
-    k_decide<<<1, 1, 0, s>>>(w.st, ip.it, ip.n_iters, ip.tol_fx);
-    k_commit<<<blocks(dm.n, 256), 256, 0, s>>>(w.cand_j, w.cand_x, x_hat, dbg.x_trial, w.st, ip.it);
+    SelectArgs sa{A, dm.d, dm.k, w, ip.it};
+    k_select_apply<<<kSelectGrid, kSelectBlock, 0, s>>>(sa);
+    if (ev_sweep) hipEventRecord(ev_sweep[2], s);
+    FinishArgs fa{dm.m, w, ip.it, ip.tau_next};
+    k_finish_rows<<<kRowGrid, kRowBlock, 0, s>>>(fa);
+    if (ev_sweep) hipEventRecord(ev_sweep[3], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
+                         float* x_out, hipStream_t s) {
+    k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx);
+    if (x_out) k_copy_out<<<blocks(dm.n, 256), 256, 0, s>>>(w, x_out, dm.n, ip_last.it);
     return hipGetLastError();
 }
 

@@ -39,32 +39,34 @@ std::mutex g_mu;
 
 struct SweepProfile {
     bool enabled = false;
-    std::vector<hipEvent_t> pool;   // pairs (before, after)
-    double total_ms = 0.0;
+    std::vector<hipEvent_t> pool;   // per iteration: before sweep, after sweep, select, finish
+    double total_ms[3] = {0.0, 0.0, 0.0};
     long long launches = 0;
 };
 SweepProfile g_prof;
 
 hipEvent_t* profile_events(int it) {
     if (!g_prof.enabled) return nullptr;
-    const size_t need = 2 * static_cast<size_t>(it + 1);
+    const size_t need = 4 * static_cast<size_t>(it + 1);
     while (g_prof.pool.size() < need) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         g_prof.pool.push_back(e);
     }
-    return &g_prof.pool[2 * it];
+    return &g_prof.pool[4 * it];
 }
 
-// after a synchronised decode: add the sweeps of the executed iterations
+// after a synchronised decode: add the kernels of the executed iterations
 void profile_collect(int executed) {
     if (!g_prof.enabled) return;
-    for (int it = 0; it < executed && 2 * static_cast<size_t>(it) + 1 < g_prof.pool.size(); ++it) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, g_prof.pool[2 * it], g_prof.pool[2 * it + 1]) == hipSuccess) {
-            g_prof.total_ms += ms;
-            g_prof.launches += 1;
-        }
+    for (int it = 0; it < executed && 4 * static_cast<size_t>(it) + 3 < g_prof.pool.size(); ++it) {
+        float ms[3] = {0.0f, 0.0f, 0.0f};
+        bool ok = true;
+        for (int k = 0; k < 3; ++k)
+            ok = ok && hipEventElapsedTime(&ms[k], g_prof.pool[4 * it + k], g_prof.pool[4 * it + k + 1]) == hipSuccess;
+        if (!ok) continue;
+        for (int k = 0; k < 3; ++k) g_prof.total_ms[k] += ms[k];
+        g_prof.launches += 1;
     }
 }
 
@@ -113,8 +115,6 @@ struct Buffers {
 
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Buffers>> g_ws;
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
-
 int get_workspace(int device, hipStream_t s, int n, int m, Buffers** out) {
     auto& slot = g_ws[{device, s}];
     if (!slot) slot = std::make_unique<Buffers>();
@@ -126,18 +126,9 @@ int get_workspace(int device, hipStream_t s, int n, int m, Buffers** out) {
             b->block = nullptr;
         }
         const int cn = std::max(n, b->cap_n), cm = std::max(m, b->cap_m);
-        const size_t bytes = 2 * align256(sizeof(long long) * cm) + 2 * align256(sizeof(float) * cm) +
-                             align256(sizeof(int) * cn) + align256(sizeof(float) * cn) +
-                             align256(sizeof(rl0::DevState));
-        if (hipMalloc(&b->block, bytes) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(workspace)");
-        char* p = static_cast<char*>(b->block);
-        b->w.Sy = reinterpret_cast<long long*>(p); p += align256(sizeof(long long) * cm);
-        b->w.S = reinterpret_cast<long long*>(p); p += align256(sizeof(long long) * cm);
-        b->w.r_buf[0] = reinterpret_cast<float*>(p); p += align256(sizeof(float) * cm);
-        b->w.r_buf[1] = reinterpret_cast<float*>(p); p += align256(sizeof(float) * cm);
-        b->w.cand_j = reinterpret_cast<int*>(p); p += align256(sizeof(int) * cn);
-        b->w.cand_x = reinterpret_cast<float*>(p); p += align256(sizeof(float) * cn);
-        b->w.st = reinterpret_cast<rl0::DevState*>(p);
+        if (hipMalloc(&b->block, rl0::workspace_bytes(cn, cm)) != hipSuccess)
+            return fail(RL0_ENOMEM, "hipMalloc(workspace)");
+        rl0::carve_workspace(b->block, cn, cm, &b->w);
         b->cap_n = cn;
         b->cap_m = cm;
     }
@@ -207,15 +198,18 @@ rl0::ScoreTables tables_of(const DeviceConstants* dc) {
 
 rl0::IterParams iter_params(const DeviceConstants* dc, const rl0_params* p, int it) {
     rl0::IterParams ip;
+    const int N = dc->hc.n_iters;
     ip.it = it;
-    ip.t = it < dc->hc.n_iters ? dc->hc.t[it] : static_cast<float>(1.0 - it * dc->hc.c);
-    ip.tau_bits = it < dc->hc.n_iters ? dc->hc.tau_bits[it] : 0x7F800000u;
+    ip.t = it < N ? dc->hc.t[it] : static_cast<float>(1.0 - it * dc->hc.c);
+    ip.tau_bits = it < N ? dc->hc.tau_bits[it] : 0x7F800000u;
+    ip.tau_next = it + 1 < N ? dc->hc.tau_bits[it + 1] : 0x7F800000u;
     ip.alpha = p->alpha;
     ip.l1_test = p->l1_test;
-    ip.n_iters = dc->hc.n_iters;
+    ip.n_iters = N;
     ip.tol_fx = dc->hc.tol * 1073741824.0;
     return ip;
 }
+
 
 }  // namespace
 
@@ -274,7 +268,7 @@ int rl0_validate(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, void* s
     HIP_TRY(hipGetDevice(&dev));
     Buffers* b = nullptr;
     if (int rc = get_workspace(dev, s, 1, 1, &b)) return rc;
-    HIP_TRY(rl0::launch_reset_state(b->w.st, 0, s));
+    HIP_TRY(rl0::launch_clear_state(b->w.st, s));
     HIP_TRY(rl0::launch_validate(A_cols, n, m, d, &b->w.st->err, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -291,8 +285,8 @@ int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     HIP_TRY(hipGetDevice(&dev));
     Buffers* b = nullptr;
     if (int rc = get_workspace(dev, s, 1, m, &b)) return rc;
-    HIP_TRY(rl0::launch_reset_state(b->w.st, 0, s));
-    HIP_TRY(rl0::launch_sketch(A_cols, n, m, d, x, y, b->w.S, &b->w.st->err, s));
+    HIP_TRY(rl0::launch_clear_state(b->w.st, s));
+    HIP_TRY(rl0::launch_sketch(A_cols, n, m, d, x, y, b->w.S[0], &b->w.st->err, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return err_code_of(b->st_host->err);
@@ -312,24 +306,26 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     if (int rc = get_workspace(dev, s, n, m, &b)) return rc;
     const rl0::DecodeDims dm{n, m, d, p->k};
     const rl0::ScoreTables tb = tables_of(dc);
-    HIP_TRY(rl0::launch_init(dm, A_cols, p->validate != 0, y, x_out, b->w, iter_params(dc, p, 0), s));
-    const rl0::DebugOut dbg{nullptr, nullptr, nullptr};
-    for (int it = 0; it < dc->hc.n_iters; ++it)
-        HIP_TRY(rl0::launch_iteration(dm, A_cols, y, x_out, b->w, tb, iter_params(dc, p, it), dbg, s,
-                                      profile_events(it)));
+    const int N = dc->hc.n_iters;
+    HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, nullptr, b->w, iter_params(dc, p, 0), s));
+    const rl0::DebugOut dbg{nullptr, nullptr};
+    for (int it = 0; it < N; ++it)
+        HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, s, profile_events(it)));
+    HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), x_out, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
-    profile_collect(ds.iterations);
+    const rl0::Slot& fin = ds.slot[N & 1];
+    profile_collect(fin.iterations);
     if (st_h) {
-        st_h->iterations = ds.iterations;
-        st_h->accepted = ds.accepted;
-        st_h->l1_final_fx = ds.L_hat;
-        st_h->l1_final = static_cast<double>(ds.L_hat) / 1073741824.0;
+        st_h->iterations = fin.iterations;
+        st_h->accepted = fin.accepted;
+        st_h->l1_final_fx = fin.L_hat;
+        st_h->l1_final = static_cast<double>(fin.L_hat) / 1073741824.0;
         st_h->l1_tol = dc->hc.tol;
-        st_h->converged = (static_cast<double>(ds.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
+        st_h->converged = (static_cast<double>(fin.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
         st_h->updates_total = ds.updates_total;
-        st_h->t_final = ds.iterations > 0 ? dc->hc.t[ds.iterations - 1] : 1.0f;
+        st_h->t_final = fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f;
         st_h->error_flags = ds.err;
     }
     return err_code_of(ds.err);
@@ -351,44 +347,53 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
     Buffers* b = nullptr;
     if (int rc = get_workspace(dev, s, n, m, &b)) return rc;
     const rl0::DecodeDims dm{n, m, d, p->k};
-    rl0::Workspace w = b->w;
-    w.r_buf[0] = r_hat;
-    if (r_trial) w.r_buf[1] = r_trial;
+    const rl0::Workspace& w = b->w;
     rl0::IterParams ip = iter_params(dc, p, it);
     ip.n_iters = it + 1;
     ip.tol_fx = -1.0;  // a single step never stops early
-    HIP_TRY(rl0::launch_reset_state(w.st, *L_hat_h, s));
-    HIP_TRY(rl0::launch_fix(y, w.Sy, m, w.st, s));
-    if (p->validate) HIP_TRY(rl0::launch_validate(A_cols, n, m, d, &w.st->err, s));
-    if (x_trial) HIP_TRY(hipMemsetAsync(x_trial, 0, sizeof(float) * n, s));
-    const rl0::DebugOut dbg{updated, omega, x_trial};
-    HIP_TRY(rl0::launch_iteration(dm, A_cols, y, x_hat, w, tables_of(dc), ip, dbg, s));
+    rl0::IterParams ip_end = iter_params(dc, p, it + 1);
+    ip_end.n_iters = it + 1;
+    ip_end.tol_fx = -1.0;
+    if (updated) HIP_TRY(rl0::launch_zero_i32(updated, n, s));
+    if (omega) HIP_TRY(rl0::launch_zero_f32(omega, n, s));
+    HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, x_hat, w, ip, s));
+    const rl0::DebugOut dbg{updated, omega};
+    HIP_TRY(rl0::launch_iteration(dm, A_cols, w, tables_of(dc), ip, dbg, s));
+    HIP_TRY(rl0::launch_finish(dm, w, ip_end, x_hat, s));
+    // the iteration ran from buffer 0; its trial iterate sits in buffer 1
+    if (x_trial) HIP_TRY(rl0::launch_copy_f32(w.xs[1], x_trial, n, s));
+    if (r_trial) HIP_TRY(rl0::launch_copy_f32(w.r[1], r_trial, m, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     if (int rc = err_code_of(ds.err)) return rc;
-    const int acc = ds.accepted_flag;
-    if (accepted_h) *accepted_h = acc;
-    if (acc) {
-        *L_hat_h = ds.L_hat;
-        HIP_TRY(hipMemcpyAsync(r_hat, w.r_buf[1], sizeof(float) * m, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
+    const rl0::Slot& fin = ds.slot[(it + 1) & 1];
+    if (accepted_h) *accepted_h = fin.accepted_last;
+    *L_hat_h = fin.L_hat;
+    HIP_TRY(rl0::launch_copy_f32(w.r[fin.cur], r_hat, m, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return RL0_OK;
 }
 
 int rl0_profile_enable(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof.enabled = enable != 0;
-    g_prof.total_ms = 0.0;
+    for (double& t : g_prof.total_ms) t = 0.0;
     g_prof.launches = 0;
     return RL0_OK;
 }
 
 int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (sweep_ms_total_h) *sweep_ms_total_h = g_prof.total_ms;
+    if (sweep_ms_total_h) *sweep_ms_total_h = g_prof.total_ms[0];
     if (sweep_launches_h) *sweep_launches_h = g_prof.launches;
+    return RL0_OK;
+}
+
+int rl0_profile_read_kernels(double* ms_total_h) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!ms_total_h) return fail(RL0_EINVAL, "NULL pointer");
+    for (int k = 0; k < 3; ++k) ms_total_h[k] = g_prof.total_ms[k];
     return RL0_OK;
 }
 

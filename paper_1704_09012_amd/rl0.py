@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
                                ctypes.POINTER(I64), ctypes.POINTER(I32), P, P, P, P, V]
         L.rl0_profile_enable.argtypes = [I32]
         L.rl0_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+        L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double)]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
@@ -256,6 +257,13 @@ def profile_read() -> tuple[float, int]:
     n = ctypes.c_int64(0)
     _check(lib().rl0_profile_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def profile_read_kernels() -> dict:
+    """Total milliseconds per kernel of the timed iterations since profile_enable."""
+    arr = (ctypes.c_double * 3)()
+    _check(lib().rl0_profile_read_kernels(arr))
+    return {"sweep": arr[0], "select_apply": arr[1], "finish_rows": arr[2]}
 
 
 def release() -> None:
