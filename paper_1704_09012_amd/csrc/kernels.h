@@ -10,6 +10,7 @@ constexpr int kMaxD = 16;
 constexpr int kFxShift = 40;   // residual / sketch fixed point: 40 fractional bits
 constexpr int kL1Shift = 30;   // ||r||_1 fixed point: 30 fractional bits
 constexpr int kHistBins = 2048;
+constexpr int kTableStrideFloats = 4100;  // floats between the starts of the two score tables
 constexpr int kSweepGridMax = 256;   // workgroups of the sweep (each owns a candidate segment)
 constexpr int kRowGrid = 256;        // workgroups of the row kernels (each owns a partial sum)
 
@@ -40,6 +41,8 @@ struct DevState {
     int updates_total;                    // column updates proposed, summed over iterations
     int err;                              // ErrFlag bits
     int seg_count[2][kSweepGridMax];      // candidates written by each sweep workgroup
+    int seg_front[2][kSweepGridMax];      //   of which at the segment's front (tested columns)
+    int seg_nz[2][kSweepGridMax];         //   of which with x' != 0
     int seg_updates[2][kSweepGridMax];    // updates proposed by each sweep workgroup
     long long L_part[2][kRowGrid];        // partial ||r||_1 of the trial residual
 };
@@ -49,8 +52,8 @@ struct DecodeDims {
 };
 
 struct ScoreTables {
-    const float* Tz;   // kTableN + 1 entries
-    const float* Te;
+    const float* Tz;   // kTableN + 1 entries, 16-byte aligned
+    const float* Te;   // Tz + kTableStrideFloats
     float inv_h_z, inv_h_e;
     int exact;         // indicator scores (sigma = 0)
 };
@@ -66,14 +69,13 @@ struct IterParams {
     double tol_fx;        // tolerance in units of 2^-30 (negative: never converged)
 };
 
-// Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.
+// Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.  x_hat
+// itself lives in the candidate segments (see the sweep kernel).
 struct Workspace {
     long long* Sy;        // rint(2^40 y) [m]
     long long* S[2];      // fixed-point residual [m]
     float* r[2];          // float32 residual [m]
     uint32_t* bm[2];      // bit i: |r[b]_i| >= tau of the next sweep [ceil(m/32)]
-    float* xs[2];         // x (dense, zero off the support) [n]
-    uint32_t* sb[2];      // support bitmap of xs[b] [ceil(n/32)]
     int* cand_j[2];       // candidate list per iteration parity, one segment per sweep
     float* cand_x[2];     //   workgroup of seg_cap entries: column j, x'_j and
     float* cand_h[2];     //   x_hat_j (0 if j was not in the support)
@@ -108,8 +110,12 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
                             hipStream_t s, hipEvent_t* ev_sweep = nullptr);
-// Decide the last iteration (it = n_iters) and write x_out = x_hat.
-hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
+// Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat (the run
+// started at iteration it0).
+hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,
                          float* x_out, hipStream_t s);
+// After launch_finish: H_k(x') of the last executed iteration, zero elsewhere.
+hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, int it0, float* x_trial,
+                            hipStream_t s);
 
 }  // namespace rl0

@@ -28,6 +28,7 @@ namespace rl0 {
 namespace {
 
 constexpr int kTableN = 4096;
+constexpr int kTableStride = kTableStrideFloats;       // table_e starts 16-byte aligned
 constexpr double kTwo40 = 1099511627776.0;          // 2^40
 constexpr double kTwoM40 = 1.0 / 1099511627776.0;   // 2^-40
 constexpr double kTwo30 = 1073741824.0;             // 2^30
@@ -37,6 +38,7 @@ constexpr int kSweepCols = 4;                     // columns per sweep thread pe
 constexpr int kSweepChunk = kSweepBlock * kSweepCols;
 constexpr int kQueueRowInts = 7168;                 // 28 KiB of row indices of queued columns
 constexpr int kBmLdsWords = 12288;                  // 48 KiB: bitmasks of m <= 393216 rows
+constexpr int kBmPer = 4;                           // bitmask words per sweep thread held in registers
 constexpr int kSelectBlock = 1024;
 constexpr int kSelectGrid = 64;
 constexpr int kRowBlock = 1024;
@@ -100,7 +102,6 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
 __device__ __forceinline__ Slot decide_from(const Slot p, int err, int it, int n_iters, double tol_fx,
                                             long long Lt) {
     Slot s = p;
-    s.accepted_last = 0;
     if (p.pending) {
         const int acc = (Lt < p.L_hat) && (err == 0);
         if (acc) {
@@ -203,24 +204,19 @@ __global__ void k_prep_state(DevState* st) {
     for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
 }
 
-// xs[0] = xs[1] = x0 (or 0), support bitmaps of it
-__global__ __launch_bounds__(256) void k_prep_cols(const float* __restrict__ x0, float* xs0, float* xs1,
-                                                   uint32_t* sb0, uint32_t* sb1, int n) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    float v = 0.0f;
-    if (j < n) {
-        v = x0 ? x0[j] : 0.0f;
-        xs0[j] = v;
-        xs1[j] = v;
-    }
-    const unsigned long long b = __ballot(j < n && v != 0.0f);
-    const int base = blockIdx.x * 256 + (threadIdx.x & ~63);
-    const int words = (n + 31) >> 5;
-    if ((threadIdx.x & 63) == 0) {
-        const int w0 = base >> 5;
-        if (w0 < words) { sb0[w0] = static_cast<uint32_t>(b); sb1[w0] = static_cast<uint32_t>(b); }
-        if (w0 + 1 < words) { sb0[w0 + 1] = static_cast<uint32_t>(b >> 32); sb1[w0 + 1] = static_cast<uint32_t>(b >> 32); }
-    }
+// The starting support x0 as the candidate segments of the iteration before it0, in
+// the workgroup that owns each column (kth_key of that parity stays 0: all kept).
+__global__ void k_prep_support(const float* __restrict__ x0, int n, Workspace w, int slot) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float v = x0[j];
+    if (v == 0.0f) return;
+    const int seg = (j / kSweepChunk) % w.sweep_grid;
+    const int o = atomicAdd(&w.st->seg_count[slot][seg], 1);
+    const size_t ix = static_cast<size_t>(seg) * w.seg_cap + (w.seg_cap - 1 - o);   // back of the segment
+    w.cand_j[slot][ix] = j;
+    w.cand_x[slot][ix] = v;
+    w.cand_h[slot][ix] = v;
 }
 
 // Sy = rint(2^40 y), S0 = Sy
@@ -306,7 +302,9 @@ struct SweepArgs {
 };
 
 // Column body of Alg. 1 on the snapshot r_hat, float32 contract.  cmask marks the rows
-// that pass the outer test.  Returns whether the column proposes an update and omega.
+// that pass the outer test; they are visited in ascending row order, so the first row
+// with the strictly largest n_e wins.  Returns whether the column proposes an update
+// and its omega.
 template <int D>
 __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int cmask,
                                               const ScoreTables& tb, float alpha, int l1_test,
@@ -320,13 +318,18 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
     }
     bool has = false;
     float best_ne = 0.0f, best_om = 0.0f;
+    unsigned int rem = cmask;
+    while (rem) {
+        const int p = __builtin_ctz(rem);
+        rem &= rem - 1u;
+        float vp = v[0];
 #pragma unroll
-    for (int p = 0; p < D; ++p) {
-        if (!((cmask >> p) & 1u)) continue;
+        for (int q = 1; q < D; ++q)
+            if (p == q) vp = v[q];
         float n_e = 0.0f, s = 0.0f;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-            const float w = (l == p) ? 1.0f : score(tb.Te, tb.inv_h_e, tb.exact, fabsf(v[p] - v[l]));
+            const float w = (l == p) ? 1.0f : score(tb.Te, tb.inv_h_e, tb.exact, fabsf(vp - v[l]));
             n_e = n_e + w;
             s = s + v[l] * w;
         }
@@ -338,7 +341,7 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
             for (int l = 0; l < D; ++l) Lp = Lp + fabsf(v[l] - om);
             l1_ok = Lp <= S1;
         } else {
-            l1_ok = fabsf(v[p] - om) <= fabsf(v[p]);
+            l1_ok = fabsf(vp - om) <= fabsf(vp);
         }
         const bool pass = ((n_e - n_z) >= alpha) && l1_ok;
         if (pass && (!has || n_e > best_ne)) {
@@ -351,85 +354,126 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
     return has;
 }
 
-// The sweep: one workgroup per CU, each owning chunks of kSweepChunk columns and one
-// segment of the candidate list.  The kernel is a short chain of memory rounds, each
-// issuing all its loads at once:
-//   1. decision-independent: this workgroup's column indices, the score tables, the
-//      partial sums of ||r||_1 and the slot of the previous iteration;
-//   2. after the accept decision (buffer index c): the outer-test bitmask, the support
-//      words of my columns, the previous iteration's candidates (to make the trial
-//      buffers equal to the current ones again) and the copy S_trial = S_hat;
-//   3. the exact residual entries of the columns that have a candidate row.
+// H_k's value of candidate j in an iteration whose k-th key was kth (zero if dropped).
+__device__ __forceinline__ float hk_value(int j, float xp, unsigned long long kth) {
+    return (xp != 0.0f && hk_key(j, xp) >= kth) ? xp : 0.0f;
+}
+
+// The support of x_hat is carried by the candidate segments rather than by a dense
+// array: every column of supp(x_hat) is a candidate of every iteration, and sweep
+// workgroup b writes only the columns it owns into segment b.  From its own previous
+// segment and the accept decision a workgroup therefore knows x_hat on all its columns
+// (the value H_k gave if the iteration was accepted, the value before it otherwise).
+__device__ __forceinline__ float current_value(int accepted, int j, float xp, float xh, unsigned long long kth) {
+    return accepted ? hk_value(j, xp, kth) : xh;
+}
+
+// Row indices of the kSweepCols consecutive columns jb, jb+1, ... (16-byte loads when
+// all of them exist; A_cols is 16-byte aligned and a chunk starts on a multiple of 4).
+template <int D>
+__device__ __forceinline__ void load_rows(const int32_t* __restrict__ A, int n, int jb, int (&rows)[kSweepCols][D]) {
+    if (jb + kSweepCols <= n) {
+        const int4* __restrict__ p4 = reinterpret_cast<const int4*>(A + static_cast<size_t>(jb) * D);
+        int flat[kSweepCols * D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int4 t = p4[k];
+            flat[4 * k] = t.x;
+            flat[4 * k + 1] = t.y;
+            flat[4 * k + 2] = t.z;
+            flat[4 * k + 3] = t.w;
+        }
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q)
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = flat[q * D + p];
+    } else {
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q)
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = (jb + q < n) ? A[static_cast<size_t>(jb + q) * D + p] : 0;
+    }
+}
+
+// The sweep: one workgroup per CU, each owning chunks of kSweepChunk columns (thread t
+// takes the kSweepCols consecutive columns from kSweepCols * t) and one segment of the
+// candidate list.  All loads that do not depend on the accept decision of the previous
+// iteration are issued in one round before it: this workgroup's column indices, the
+// score tables, the partial sums of ||r||_1, the previous segment, and both candidates
+// for the outer-test bitmask and for the S copy (the decision picks one).  A second
+// round gathers the exact residuals of the columns with a candidate row.
 template <int D>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     constexpr int kQueueRows = kQueueRowInts / D;
     __shared__ uint32_t bml[kBmLdsWords];
-    __shared__ float Tz[kTableN + 1];
-    __shared__ float Te[kTableN + 1];
+    __shared__ float Tz[kTableStride];
+    __shared__ float Te[kTableStride];
+    __shared__ float supv[kSweepChunk];
     __shared__ int queue[kSweepChunk];
-    __shared__ int qrows[kQueueRows * D];
-    __shared__ int qn, seg_n, seg_upd;
+    __shared__ int qrows[kQueueRowInts];
+    __shared__ int qn, seg_f, seg_b, seg_z, seg_upd;
     __shared__ Slot s_sh;
-    __shared__ int pc_sh;
-    __shared__ unsigned long long kth_sh;
     __shared__ long long red[kSweepBlock / 64];
     const int it = a.ip.it, me = it & 1, pv = me ^ 1;
     const int tid = threadIdx.x;
     const int seg = blockIdx.x;
     const size_t seg_base = static_cast<size_t>(seg) * a.w.seg_cap;
     DevState* st = a.w.st;
+    const int words = (a.m + 31) >> 5;
+    const bool bm_regs = words <= kBmPer * kSweepBlock;
 
     // ---- round 1
     int rows[kSweepCols][D];
-    {
-        const int chunk = blockIdx.x;
-#pragma unroll
-        for (int q = 0; q < kSweepCols; ++q) {
-            const int j = chunk * kSweepChunk + q * kSweepBlock + tid;
-#pragma unroll
-            for (int p = 0; p < D; ++p) rows[q][p] = j < a.n ? a.A[static_cast<size_t>(j) * D + p] : 0;
-        }
-    }
-    float tz0 = 0.0f, tz1 = 0.0f, tz2 = 0.0f, tz3 = 0.0f, tz4 = 0.0f;
-    float te0 = 0.0f, te1 = 0.0f, te2 = 0.0f, te3 = 0.0f, te4 = 0.0f;
+    load_rows<D>(a.A, a.n, blockIdx.x * kSweepChunk + kSweepCols * tid, rows);
+    float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
+    float tzl = 0.0f, tel = 0.0f;
     if (!a.tb.exact) {
-        // kTableN + 1 = 4097 entries = 4 per thread + one
-        tz0 = a.tb.Tz[tid];
-        tz1 = a.tb.Tz[tid + kSweepBlock];
-        tz2 = a.tb.Tz[tid + 2 * kSweepBlock];
-        tz3 = a.tb.Tz[tid + 3 * kSweepBlock];
-        te0 = a.tb.Te[tid];
-        te1 = a.tb.Te[tid + kSweepBlock];
-        te2 = a.tb.Te[tid + 2 * kSweepBlock];
-        te3 = a.tb.Te[tid + 3 * kSweepBlock];
+        tz4 = reinterpret_cast<const float4*>(a.tb.Tz)[tid];
+        te4 = reinterpret_cast<const float4*>(a.tb.Te)[tid];
         if (tid == 0) {
-            tz4 = a.tb.Tz[kTableN];
-            te4 = a.tb.Te[kTableN];
+            tzl = a.tb.Tz[kTableN];
+            tel = a.tb.Te[kTableN];
         }
     }
     Slot prev{};
-    int pc = 0;
-    unsigned long long kth_prev = 0;
     int err = 0;
     if (tid == 0) {
         prev = st->slot[pv];
-        pc = st->seg_count[pv][seg];
-        kth_prev = st->kth_key[pv];
         err = st->err;
     }
+    const int pc = st->seg_count[pv][seg];
+    const int pf = st->seg_front[pv][seg];
+    const unsigned long long kthp = st->kth_key[pv];
     long long lp = tid < kRowGrid ? st->L_part[pv][tid] : 0;
+    // the previous segment's first front and first back entry of this thread
+    int pj = 0, qj = 0;
+    float pxp = 0.0f, pxh = 0.0f, qxp = 0.0f, qxh = 0.0f;
+    if (tid < a.w.seg_cap) {
+        const size_t fb = seg_base + tid, bb = seg_base + (a.w.seg_cap - 1 - tid);
+        pj = a.w.cand_j[pv][fb];
+        pxp = a.w.cand_x[pv][fb];
+        pxh = a.w.cand_h[pv][fb];
+        qj = a.w.cand_j[pv][bb];
+        qxp = a.w.cand_x[pv][bb];
+        qxh = a.w.cand_h[pv][bb];
+    }
+    uint4 bw0 = make_uint4(0u, 0u, 0u, 0u), bw1 = bw0;
+    if (bm_regs && kBmPer * tid < words) {
+        bw0 = reinterpret_cast<const uint4*>(a.w.bm[0])[tid];
+        bw1 = reinterpret_cast<const uint4*>(a.w.bm[1])[tid];
+    }
+    const int i0 = blockIdx.x * kSweepBlock + tid;
+    long long s0v = 0, s1v = 0;
+    if (i0 < a.m) {
+        s0v = a.w.S[0][i0];
+        s1v = a.w.S[1][i0];
+    }
     if (!a.tb.exact) {
-        Tz[tid] = tz0;
-        Tz[tid + kSweepBlock] = tz1;
-        Tz[tid + 2 * kSweepBlock] = tz2;
-        Tz[tid + 3 * kSweepBlock] = tz3;
-        Te[tid] = te0;
-        Te[tid + kSweepBlock] = te1;
-        Te[tid + 2 * kSweepBlock] = te2;
-        Te[tid + 3 * kSweepBlock] = te3;
+        reinterpret_cast<float4*>(Tz)[tid] = tz4;
+        reinterpret_cast<float4*>(Te)[tid] = te4;
         if (tid == 0) {
-            Tz[kTableN] = tz4;
-            Te[kTableN] = te4;
+            Tz[kTableN] = tzl;
+            Te[kTableN] = tel;
         }
     }
     for (int off = 32; off > 0; off >>= 1) lp += __shfl_down(lp, off);
@@ -439,9 +483,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         long long Lt = 0;
         for (int w = 0; w < kSweepBlock / 64; ++w) Lt += red[w];
         s_sh = decide_from(prev, err, it, a.ip.n_iters, a.ip.tol_fx, Lt);
-        pc_sh = pc;
-        kth_sh = kth_prev;
-        seg_n = 0;
+        seg_f = 0;
+        seg_b = 0;
+        seg_z = 0;
         seg_upd = 0;
     }
     __syncthreads();
@@ -449,10 +493,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
     if (s.done) return;
     const int c = s.cur, tr = c ^ 1;
-    const uint32_t* __restrict__ bmg = a.w.bm[c];
+    const int acc = s.accepted_last;
     const float* __restrict__ r = a.w.r[c];
-    const float* __restrict__ xs = a.w.xs[c];
-    const uint32_t* __restrict__ sb = a.w.sb[c];
+    const uint32_t* __restrict__ bmg = a.w.bm[c];
     int* __restrict__ out_j = a.w.cand_j[me] + seg_base;
     float* __restrict__ out_x = a.w.cand_x[me] + seg_base;
     float* __restrict__ out_h = a.w.cand_h[me] + seg_base;
@@ -460,64 +503,57 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     lt.Tz = Tz;
     lt.Te = Te;
 
-    // ---- round 2
-    uint32_t bw[kBmLdsWords / kSweepBlock];
-    const int words = (a.m + 31) >> 5;
+    // ---- the decision picks: outer-test bitmask into LDS, S_trial = S_hat
     if (a.bm_lds) {
-#pragma unroll
-        for (int q = 0; q < kBmLdsWords / kSweepBlock; ++q) {
-            const int wi = q * kSweepBlock + tid;
-            bw[q] = wi < words ? bmg[wi] : 0u;
+        if (bm_regs) {
+            if (kBmPer * tid < words) {
+                uint4 b;   // selected lane by lane, so the loads above need not complete first
+                b.x = c ? bw1.x : bw0.x;
+                b.y = c ? bw1.y : bw0.y;
+                b.z = c ? bw1.z : bw0.z;
+                b.w = c ? bw1.w : bw0.w;
+                reinterpret_cast<uint4*>(bml)[tid] = b;
+            }
+        } else {
+            for (int wi = tid; wi < words; wi += kSweepBlock) bml[wi] = bmg[wi];
         }
     }
-    uint32_t sbw[kSweepCols];
-#pragma unroll
-    for (int q = 0; q < kSweepCols; ++q) {
-        const int j = blockIdx.x * kSweepChunk + q * kSweepBlock + tid;
-        sbw[q] = j < a.n ? sb[j >> 5] : 0u;
-    }
-    // previous candidates of this segment: the trial buffer differs from the current one
-    // exactly at those whose H_k value changed; give it the current value again
-    const int pcn = pc_sh;
-    const unsigned long long kthp = kth_sh;
-    const int acc_prev = s.accepted_last;
-    for (int e = tid; e < pcn; e += kSweepBlock) {
-        const int j = a.w.cand_j[pv][seg_base + e];
-        const float xp = a.w.cand_x[pv][seg_base + e];
-        const float xh = a.w.cand_h[pv][seg_base + e];
-        const float nv = (xp != 0.0f && hk_key(j, xp) >= kthp) ? xp : 0.0f;
-        if (nv == xh) continue;
-        const float cur_v = acc_prev ? nv : xh;
-        a.w.xs[tr][j] = cur_v;
-        const uint32_t bit = 1u << (j & 31);
-        if (cur_v != 0.0f) atomicOr(&a.w.sb[tr][j >> 5], bit);
-        else atomicAnd(&a.w.sb[tr][j >> 5], ~bit);
-    }
-    for (int i = blockIdx.x * kSweepBlock + tid; i < a.m; i += gridDim.x * kSweepBlock) a.w.S[tr][i] = a.w.S[c][i];
-    if (a.bm_lds) {
-#pragma unroll
-        for (int q = 0; q < kBmLdsWords / kSweepBlock; ++q) {
-            const int wi = q * kSweepBlock + tid;
-            if (wi < words) bml[wi] = bw[q];
-        }
-    }
+    if (i0 < a.m) a.w.S[tr][i0] = c ? s1v : s0v;
+    for (int i = i0 + gridDim.x * kSweepBlock; i < a.m; i += gridDim.x * kSweepBlock) a.w.S[tr][i] = a.w.S[c][i];
 
     for (int chunk = blockIdx.x; chunk < a.chunks; chunk += gridDim.x) {
-        if (chunk != static_cast<int>(blockIdx.x)) {
-#pragma unroll
-            for (int q = 0; q < kSweepCols; ++q) {
-                const int j = chunk * kSweepChunk + q * kSweepBlock + tid;
-#pragma unroll
-                for (int p = 0; p < D; ++p) rows[q][p] = j < a.n ? a.A[static_cast<size_t>(j) * D + p] : 0;
-                sbw[q] = j < a.n ? sb[j >> 5] : 0u;
-            }
-        }
+        const int cbase = chunk * kSweepChunk;
+        const int jb = cbase + kSweepCols * tid;
+        if (chunk != static_cast<int>(blockIdx.x)) load_rows<D>(a.A, a.n, jb, rows);
+        reinterpret_cast<float4*>(supv)[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (tid == 0) qn = 0;
         __syncthreads();
+        // x_hat on this chunk's columns, from the previous segment (front, then back)
+        for (int e = tid; e < pc; e += kSweepBlock) {
+            const bool front = e < pf;
+            const int o = front ? e : e - pf;
+            int j;
+            float xp, xh;
+            if (o == tid) {
+                j = front ? pj : qj;
+                xp = front ? pxp : qxp;
+                xh = front ? pxh : qxh;
+            } else {
+                const size_t ix = seg_base + (front ? o : a.w.seg_cap - 1 - o);
+                j = a.w.cand_j[pv][ix];
+                xp = a.w.cand_x[pv][ix];
+                xh = a.w.cand_h[pv][ix];
+            }
+            const float v = current_value(acc, j, xp, xh, kthp);
+            if (v != 0.0f && j >= cbase && j < cbase + kSweepChunk) supv[j - cbase] = v;
+        }
+        __syncthreads();
         // outer test of every row of my columns: one bit each from the bitmask
+        const float4 sv4 = reinterpret_cast<const float4*>(supv)[tid];
+        const float svq[kSweepCols] = {sv4.x, sv4.y, sv4.z, sv4.w};
 #pragma unroll
         for (int q = 0; q < kSweepCols; ++q) {
-            const int j = chunk * kSweepChunk + q * kSweepBlock + tid;
+            const int j = jb + q;
             if (j >= a.n) continue;
             unsigned int cm = 0u;
 #pragma unroll
@@ -526,7 +562,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 const uint32_t word = a.bm_lds ? bml[row >> 5] : bmg[row >> 5];
                 cm |= ((word >> (row & 31)) & 1u) << p;
             }
-            const bool sup = (sbw[q] >> (j & 31)) & 1u;
             if (cm) {
                 const int qi = atomicAdd(&qn, 1);
                 queue[qi] = j;
@@ -534,19 +569,22 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 #pragma unroll
                     for (int p = 0; p < D; ++p) qrows[qi * D + p] = rows[q][p];
                 }
-            } else if (sup) {
-                // a support column with no candidate row keeps x'_j = x_hat_j
-                const int o = atomicAdd(&seg_n, 1);
-                const float xh = xs[j];
+            } else if (svq[q] != 0.0f) {
+                // a support column with no candidate row keeps x'_j = x_hat_j: the back
+                // of the segment holds the entries with x' = x_hat, the front the others
+                const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
                 out_j[o] = j;
-                out_x[o] = xh;
-                out_h[o] = xh;
+                out_x[o] = svq[q];
+                out_h[o] = svq[q];
             }
         }
         __syncthreads();
-        // ---- round 3: the noisy consensus test, one queued column per thread
+        // ---- round 2: the noisy consensus test of the queued columns, spread over all
+        // waves (entry e of a pass goes to wave e % 16, lane e / 16)
         const int nq = qn;
-        for (int e = tid; e < nq; e += kSweepBlock) {
+        for (int e0 = 0; e0 < nq; e0 += kSweepBlock) {
+            const int e = e0 + (tid & 63) * (kSweepBlock / 64) + (tid >> 6);
+            if (e >= nq) continue;
             const int jq = queue[e];
             int rr[D];
             if (e < kQueueRows) {
@@ -557,12 +595,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 #pragma unroll
                 for (int p = 0; p < D; ++p) rr[p] = col[p];
             }
-            const uint32_t sword = sb[jq >> 5];
             float v[D];
 #pragma unroll
             for (int p = 0; p < D; ++p) v[p] = r[rr[p]];
-            const bool sup = (sword >> (jq & 31)) & 1u;
-            const float xhq = sup ? xs[jq] : 0.0f;
+            const float xhq = supv[jq - cbase];
             unsigned int cm = 0u;
 #pragma unroll
             for (int p = 0; p < D; ++p)
@@ -572,17 +608,27 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             if (a.dbg.updated) a.dbg.updated[jq] = upd ? 1 : 0;
             if (a.dbg.omega) a.dbg.omega[jq] = upd ? om : 0.0f;
             if (upd) atomicAdd(&seg_upd, 1);
-            if (upd || sup) {
-                const int o = atomicAdd(&seg_n, 1);
+            if (upd) {
+                // an updated column goes to the front
+                const float xp = xhq + om;
+                const int o = atomicAdd(&seg_f, 1);
                 out_j[o] = jq;
-                out_x[o] = upd ? xhq + om : xhq;
+                out_x[o] = xp;
+                out_h[o] = xhq;
+                if (xp != 0.0f) atomicAdd(&seg_z, 1);
+            } else if (xhq != 0.0f) {
+                const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                out_j[o] = jq;
+                out_x[o] = xhq;
                 out_h[o] = xhq;
             }
         }
         __syncthreads();
     }
     if (tid == 0) {
-        st->seg_count[me][seg] = seg_n;
+        st->seg_count[me][seg] = seg_f + seg_b;
+        st->seg_front[me][seg] = seg_f;
+        st->seg_nz[me][seg] = seg_z + seg_b;
         st->seg_updates[me][seg] = seg_upd;
     }
 }
@@ -627,23 +673,10 @@ __device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, i
 constexpr int kLdsKeys = 12288;   // candidate keys a select workgroup caches in LDS
 constexpr int kSelPer = 12;       // candidate loads in flight per select thread (kLdsKeys / block)
 
-// Entry e of the concatenated segments (seg_start: exclusive prefix sums of the segment
-// lengths, in LDS, ascending) -> its index in the candidate arrays.
-__device__ __forceinline__ size_t entry_index(const int* seg_start, int nseg, int cap, int e) {
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return static_cast<size_t>(lo) * cap + (e - seg_start[lo]);
-}
-
-// H_k's effect on one candidate: the trial support value and the exact change of the
-// residual of column j.
+// H_k's effect on one candidate: the exact change of the residual of column j.
 __device__ __forceinline__ void apply_candidate(const SelectArgs& a, int tr, unsigned long long kth, int j,
                                                 float xp, float xh, int* err) {
-    const bool kept = (xp != 0.0f) && (hk_key(j, xp) >= kth);
-    const float nv = kept ? xp : 0.0f;
+    const float nv = hk_value(j, xp, kth);
     if (nv == xh) return;
     const long long delta = (xh != 0.0f ? to_fx(xh, err) : 0) - (nv != 0.0f ? to_fx(nv, err) : 0);
     if (delta != 0) {
@@ -651,28 +684,77 @@ __device__ __forceinline__ void apply_candidate(const SelectArgs& a, int tr, uns
         for (int p = 0; p < a.d; ++p)
             atomicAdd(reinterpret_cast<unsigned long long*>(a.w.S[tr] + col[p]), static_cast<unsigned long long>(delta));
     }
-    a.w.xs[tr][j] = nv;
-    if ((nv != 0.0f) != (xh != 0.0f)) {
-        const uint32_t bit = 1u << (j & 31);
-        if (nv != 0.0f) atomicOr(&a.w.sb[tr][j >> 5], bit);
-        else atomicAnd(&a.w.sb[tr][j >> 5], ~bit);
+}
+
+// hist[bin] += 1 for every lane with valid set; lanes of a wave that hit the same bin
+// add together (the magnitudes of a support cluster in a few bins).  Every lane of the
+// wave must call.
+__device__ __forceinline__ void hist_add(unsigned* hist, unsigned bin, bool valid) {
+    unsigned long long active = __ballot(valid);
+    const int lane = __lane_id();
+    while (active) {
+        const int leader = __ffsll(static_cast<long long>(active)) - 1;
+        const unsigned b = __shfl(bin, leader);
+        const unsigned long long same = __ballot(valid && bin == b);
+        if (lane == leader) atomicAdd(&hist[b], static_cast<unsigned>(__popcll(same)));
+        active &= ~same;
     }
+}
+
+// Within one workgroup: exclusive prefix sums of one int per segment (threads < nseg
+// hold their value in v) by wave scans; returns the total.  start[] gets the sums.
+__device__ __forceinline__ int segment_scan(int v, int nseg, int* start, int* wtot) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < kSweepGridMax) {
+        int incl = tid < nseg ? v : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        start[tid] = incl - (tid < nseg ? v : 0);
+        if (lane == 63) wtot[tid >> 6] = incl;
+    }
+    __syncthreads();
+    int total = 0;
+    for (int w = 0; w < kSweepGridMax / 64; ++w) total += wtot[w];
+    if (tid < kSweepGridMax) {
+        int add = 0;
+        for (int w = 0; w < (tid >> 6); ++w) add += wtot[w];
+        start[tid] += add;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Physical index of entry e (0 <= e < count) of a segment whose first `front` entries
+// sit at its start and the rest at its end, backwards.
+__device__ __forceinline__ size_t seg_phys(int seg, int cap, int front, int e) {
+    return static_cast<size_t>(seg) * cap + (e < front ? e : cap - 1 - (e - front));
 }
 
 // Every workgroup computes the k-th largest key of H_k (the same value everywhere);
 // workgroup b then applies the candidates of waves w with w % gridDim.x == b.
+// When the nonzero candidates number at most k (the common case once the support has
+// formed), every one is kept, and only the front of each segment -- the columns the
+// sweep updated, x' != x_hat -- can change the residual: then a workgroup reads just
+// the front entries it applies.
 __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
     __shared__ unsigned long long keys[kLdsKeys];
+    __shared__ unsigned short segmap[kLdsKeys];
     __shared__ unsigned hist[kHistBins];
     __shared__ unsigned scan[kSelectBlock];
+    __shared__ int seg_cnt[kSweepGridMax];
+    __shared__ int seg_frt[kSweepGridMax];
     __shared__ int seg_start[kSweepGridMax];
+    __shared__ int wtot[kSweepGridMax / 64];
     __shared__ int digit;
-    __shared__ unsigned above, bucket, nz_sh;
-    __shared__ int upd_sh;
+    __shared__ unsigned above, bucket;
+    __shared__ int nz_sh, upd_sh;
     __shared__ Slot s_sh;
     const int me = a.it & 1;
     DevState* st = a.w.st;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int nseg = a.w.sweep_grid;
     const int cap = a.w.seg_cap;
     const int G = gridDim.x;
@@ -680,102 +762,107 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
     const float* __restrict__ cx = a.w.cand_x[me];
     const float* __restrict__ ch = a.w.cand_h[me];
 
-    // ---- round 1: slot and segment lengths
-    int myc = 0, myu = 0;
+    // ---- round 1: slot and segment sizes
+    int myc = 0, myf = 0, myz = 0, myu = 0;
     if (tid < nseg) {
         myc = st->seg_count[me][tid];
+        myf = st->seg_front[me][tid];
+        myz = st->seg_nz[me][tid];
         if (blockIdx.x == 0) myu = st->seg_updates[me][tid];
     }
     if (tid == 0) {
         s_sh = st->slot[me];
-        nz_sh = 0u;
+        nz_sh = 0;
         upd_sh = 0;
     }
-    if (tid < kSweepGridMax) seg_start[tid] = myc;
-    hist[tid] = 0u;
-    hist[tid + kSelectBlock] = 0u;
+    if (tid < kSweepGridMax) {
+        seg_cnt[tid] = myc;
+        seg_frt[tid] = myf;
+    }
     __syncthreads();
     if (s_sh.done) return;
     const int tr = s_sh.cur ^ 1;
+    if (myz) atomicAdd(&nz_sh, myz);
     if (myu) atomicAdd(&upd_sh, myu);
-    for (int off = 1; off < kSweepGridMax; off <<= 1) {
-        const int add = (tid < kSweepGridMax && tid >= off) ? seg_start[tid - off] : 0;
-        __syncthreads();
-        if (tid < kSweepGridMax) seg_start[tid] += add;
+    __syncthreads();
+    if (blockIdx.x == 0 && tid == 0) st->updates_total += upd_sh;
+    const bool all_kept = nz_sh <= a.k;
+    // entries visited: the fronts if everything is kept, else everything
+    const int count = segment_scan(all_kept ? myf : myc, nseg, seg_start, wtot);
+    const bool fast = count <= kLdsKeys;
+    if (fast) {
+        for (int sg = tid >> 6; sg < nseg; sg += kSelectBlock / 64) {
+            const int cnt = all_kept ? seg_frt[sg] : seg_cnt[sg];
+            for (int o = lane; o < cnt; o += 64) segmap[seg_start[sg] + o] = static_cast<unsigned short>(sg);
+        }
         __syncthreads();
     }
-    const int count = seg_start[nseg - 1];
-    __syncthreads();
-    if (tid < kSweepGridMax) seg_start[tid] -= myc;   // exclusive
-    if (blockIdx.x == 0 && tid == 0) st->updates_total += upd_sh;
-    __syncthreads();
-    const bool fast = count <= kLdsKeys;
 
-    // ---- round 2: candidates (all of them in registers and LDS on the fast path)
+    // ---- round 2: candidates (in registers and LDS on the fast path)
     float xr[kSelPer], hr[kSelPer];
     int jr[kSelPer];
-    unsigned nz = 0;
-    for (int base = 0; base < count; base += kSelectBlock * kSelPer) {
+    if (fast) {
 #pragma unroll
         for (int q = 0; q < kSelPer; ++q) {
-            const int e = base + q * kSelectBlock + tid;
+            const int e = q * kSelectBlock + tid;
             xr[q] = 0.0f;
             hr[q] = 0.0f;
             jr[q] = 0;
-            if (e < count) {
-                const size_t ix = entry_index(seg_start, nseg, cap, e);
+            // with every entry kept, a workgroup needs only the entries it applies
+            const bool own = ((e >> 6) % G) == static_cast<int>(blockIdx.x);
+            if (e < count && (own || !all_kept)) {
+                const int sg = segmap[e];
+                const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
                 xr[q] = cx[ix];
                 jr[q] = cj[ix];
-                if (fast && ((e >> 6) % G) == static_cast<int>(blockIdx.x)) hr[q] = ch[ix];
+                if (own) hr[q] = ch[ix];
             }
         }
+        if (!all_kept) {
 #pragma unroll
-        for (int q = 0; q < kSelPer; ++q) {
-            const int e = base + q * kSelectBlock + tid;
-            if (e >= count) continue;
-            const unsigned long long key = xr[q] != 0.0f ? hk_key(jr[q], xr[q]) : 0ull;
-            if (fast) keys[e] = key;
-            if (key) {
-                ++nz;
-                atomicAdd(&hist[static_cast<unsigned>(key >> 52)], 1u);
+            for (int q = 0; q < kSelPer; ++q) {
+                const int e = q * kSelectBlock + tid;
+                if (e < count) keys[e] = xr[q] != 0.0f ? hk_key(jr[q], xr[q]) : 0ull;
             }
         }
     }
-    if (nz) atomicAdd(&nz_sh, nz);
     __syncthreads();
 
     // ---- the k-th largest key
     unsigned long long kth;
-    if (nz_sh <= static_cast<unsigned>(a.k)) {
+    if (all_kept) {
         kth = 1ull << 32;   // every nonzero entry is kept
     } else {
+        unsigned long long prefix = 0ull, pmask = 0ull;
         unsigned rem = static_cast<unsigned>(a.k);
-        find_digit(hist, rem, scan, &digit, &above, &bucket);
-        unsigned long long prefix = static_cast<unsigned long long>(digit) << 52;
-        unsigned long long pmask = 0x7FFull << 52;
-        rem -= above;
-        bool exact = (rem == bucket);
-        const int shifts[5] = {41, 30, 19, 8, 0};
-        const int widths[5] = {11, 11, 11, 11, 8};
-        for (int pass = 0; pass < 5 && !exact; ++pass) {
+        bool exact = false;
+        const int shifts[6] = {52, 41, 30, 19, 8, 0};
+        const int widths[6] = {11, 11, 11, 11, 11, 8};
+        for (int pass = 0; pass < 6 && !exact; ++pass) {
             const int sh = shifts[pass];
             const unsigned dmask = (1u << widths[pass]) - 1u;
             hist[tid] = 0u;
             hist[tid + kSelectBlock] = 0u;
             __syncthreads();
-            if (fast) {
-                for (int e = tid; e < count; e += kSelectBlock) {
-                    const unsigned long long key = keys[e];
-                    if (key && (key & pmask) == prefix) atomicAdd(&hist[(key >> sh) & dmask], 1u);
+            for (int e0 = 0; e0 < count; e0 += kSelectBlock) {
+                const int e = e0 + tid;
+                unsigned long long key = 0ull;
+                if (e < count) {
+                    if (fast) {
+                        key = keys[e];
+                    } else {
+                        int lo = 0, hi = nseg - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
+                        }
+                        const size_t ix = seg_phys(lo, cap, seg_frt[lo], e - seg_start[lo]);
+                        const float x = cx[ix];
+                        key = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
+                    }
                 }
-            } else {
-                for (int e = tid; e < count; e += kSelectBlock) {
-                    const size_t ix = entry_index(seg_start, nseg, cap, e);
-                    const float x = cx[ix];
-                    if (x == 0.0f) continue;
-                    const unsigned long long key = hk_key(cj[ix], x);
-                    if ((key & pmask) == prefix) atomicAdd(&hist[(key >> sh) & dmask], 1u);
-                }
+                const bool in = key != 0ull && (key & pmask) == prefix;
+                hist_add(hist, static_cast<unsigned>((key >> sh) & dmask), in);
             }
             __syncthreads();
             find_digit(hist, rem, scan, &digit, &above, &bucket);
@@ -788,7 +875,7 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
     }
     if (blockIdx.x == 0 && tid == 0) st->kth_key[me] = kth;
 
-    // ---- trial support and exact residual change of every changed column
+    // ---- exact residual change of every changed column
     if (fast) {
 #pragma unroll
         for (int q = 0; q < kSelPer; ++q) {
@@ -799,7 +886,12 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
     } else {
         for (int e = tid; e < count; e += kSelectBlock) {
             if (((e >> 6) % G) != static_cast<int>(blockIdx.x)) continue;
-            const size_t ix = entry_index(seg_start, nseg, cap, e);
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const size_t ix = seg_phys(lo, cap, seg_frt[lo], e - seg_start[lo]);
             apply_candidate(a, tr, kth, cj[ix], cx[ix], ch[ix], &st->err);
         }
     }
@@ -861,10 +953,23 @@ __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n
     if (threadIdx.x == 0) st->slot[it & 1] = decide(st, it, n_iters, tol_fx, Lt);
 }
 
-__global__ void k_copy_out(const Workspace w, float* __restrict__ x_out, int n, int it) {
-    const int c = w.st->slot[it & 1].cur;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) x_out[j] = w.xs[c][j];
+// x_out = x_hat (or, with trial = 1, H_k(x') of the last executed iteration) from the
+// candidate segments of the last executed iteration.  x_out is zeroed first.
+__global__ void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end, int it0, int trial) {
+    const Slot fin = w.st->slot[it_end & 1];
+    const int it_last = it0 + fin.iterations - 1;      // it0 - 1 if nothing ran
+    const int par = it_last & 1;
+    const int acc = trial ? 1 : fin.accepted_last;
+    const unsigned long long kth = w.st->kth_key[par];
+    const int seg = blockIdx.x;
+    const int cnt = w.st->seg_count[par][seg];
+    const int front = w.st->seg_front[par][seg];
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const size_t ix = static_cast<size_t>(seg) * w.seg_cap + (e < front ? e : w.seg_cap - 1 - (e - front));
+        const int j = w.cand_j[par][ix];
+        const float v = current_value(acc, j, w.cand_x[par][ix], w.cand_h[par][ix], kth);
+        if (v != 0.0f) x_out[j] = v;
+    }
 }
 
 inline int blocks(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
@@ -917,8 +1022,8 @@ size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 size_t workspace_bytes(int n, int m) {
     const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
-    return 3 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm) + 2 * al(4ull * n) + 2 * al(4 * wn) +
-           6 * al(4 * cand) + al(sizeof(DevState));
+    (void)wn;
+    return 3 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(sizeof(DevState));
 }
 
 void carve_workspace(void* base, int n, int m, Workspace* w) {
@@ -929,9 +1034,8 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     w->Sy = reinterpret_cast<long long*>(take(8ull * m));
     for (int b = 0; b < 2; ++b) w->S[b] = reinterpret_cast<long long*>(take(8ull * m));
     for (int b = 0; b < 2; ++b) w->r[b] = reinterpret_cast<float*>(take(4ull * m));
-    for (int b = 0; b < 2; ++b) w->bm[b] = reinterpret_cast<uint32_t*>(take(4 * wm));
-    for (int b = 0; b < 2; ++b) w->xs[b] = reinterpret_cast<float*>(take(4ull * n));
-    for (int b = 0; b < 2; ++b) w->sb[b] = reinterpret_cast<uint32_t*>(take(4 * wn));
+    for (int b = 0; b < 2; ++b) w->bm[b] = reinterpret_cast<uint32_t*>(take(4 * wm + 16));
+    (void)wn;
     for (int b = 0; b < 2; ++b) {
         w->cand_j[b] = reinterpret_cast<int*>(take(4 * cand));
         w->cand_x[b] = reinterpret_cast<float*>(take(4 * cand));
@@ -983,7 +1087,7 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
     const int slot = (ip0.it & 1) ^ 1;   // the slot iteration it0 reads as "previous"
     k_prep_state<<<1, 256, 0, s>>>(w.st);
     if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
-    k_prep_cols<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, w.xs[0], w.xs[1], w.sb[0], w.sb[1], dm.n);
+    if (x_hat0) k_prep_support<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, dm.n, w, slot);
     k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], dm.m, w.st);
     if (x_hat0) k_prep_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.d, x_hat0, w.S[0], w.st);
     k_prep_rows2<<<kRowGrid, kRowBlock, 0, s>>>(w.S[0], w.r[0], w.bm[0], dm.m, ip0.tau_bits, w.st, slot);
@@ -1017,10 +1121,20 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
+hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,
                          float* x_out, hipStream_t s) {
     k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx);
-    if (x_out) k_copy_out<<<blocks(dm.n, 256), 256, 0, s>>>(w, x_out, dm.n, ip_last.it);
+    if (x_out) {
+        k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_out, dm.n);
+        k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, it0, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, int it0, float* x_trial,
+                            hipStream_t s) {
+    k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_trial, dm.n);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, it0, 1);
     return hipGetLastError();
 }
 

@@ -94,10 +94,10 @@ int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
     }
     auto dc = std::make_unique<DeviceConstants>();
     rl0::compute_constants(pr, &dc->hc);
-    const size_t bytes = 2 * (rl0::kTableN + 1) * sizeof(float);
+    const size_t bytes = 2 * rl0::kTableStrideFloats * sizeof(float);
     if (hipMalloc(&dc->d_tables, bytes) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(tables)");
     HIP_TRY(hipMemcpy(dc->d_tables, dc->hc.table_z, (rl0::kTableN + 1) * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dc->d_tables + rl0::kTableN + 1, dc->hc.table_e, (rl0::kTableN + 1) * sizeof(float),
+    HIP_TRY(hipMemcpy(dc->d_tables + rl0::kTableStrideFloats, dc->hc.table_e, (rl0::kTableN + 1) * sizeof(float),
                       hipMemcpyHostToDevice));
     *out = dc.get();
     g_consts.emplace(key, std::move(dc));
@@ -189,7 +189,7 @@ int err_code_of(int flags) {
 rl0::ScoreTables tables_of(const DeviceConstants* dc) {
     rl0::ScoreTables tb;
     tb.Tz = dc->d_tables;
-    tb.Te = dc->d_tables + rl0::kTableN + 1;
+    tb.Te = dc->d_tables + rl0::kTableStrideFloats;
     tb.inv_h_z = dc->hc.inv_h_z;
     tb.inv_h_e = dc->hc.inv_h_e;
     tb.exact = dc->hc.exact ? 1 : 0;
@@ -296,6 +296,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
                const rl0_params* p, float* x_out, rl0_stats* st_h, void* stream) {
     if (int rc = check_params(p, n, m, d)) return rc;
     if (!A_cols || !y || !x_out) return fail(RL0_EINVAL, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(A_cols) % 16) return fail(RL0_EINVAL, "A_cols must be 16-byte aligned");
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
@@ -311,7 +312,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     const rl0::DebugOut dbg{nullptr, nullptr};
     for (int it = 0; it < N; ++it)
         HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, s, profile_events(it)));
-    HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), x_out, s));
+    HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), 0, x_out, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
@@ -337,6 +338,7 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
              void* stream) {
     if (int rc = check_params(p, n, m, d)) return rc;
     if (!A_cols || !y || !x_hat || !r_hat || !L_hat_h) return fail(RL0_EINVAL, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(A_cols) % 16) return fail(RL0_EINVAL, "A_cols must be 16-byte aligned");
     if (it < 0) return fail(RL0_EINVAL, "it must be >= 0");
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -359,9 +361,9 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
     HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, x_hat, w, ip, s));
     const rl0::DebugOut dbg{updated, omega};
     HIP_TRY(rl0::launch_iteration(dm, A_cols, w, tables_of(dc), ip, dbg, s));
-    HIP_TRY(rl0::launch_finish(dm, w, ip_end, x_hat, s));
+    HIP_TRY(rl0::launch_finish(dm, w, ip_end, it, x_hat, s));
     // the iteration ran from buffer 0; its trial iterate sits in buffer 1
-    if (x_trial) HIP_TRY(rl0::launch_copy_f32(w.xs[1], x_trial, n, s));
+    if (x_trial) HIP_TRY(rl0::launch_trial_out(dm, w, it + 1, it, x_trial, s));
     if (r_trial) HIP_TRY(rl0::launch_copy_f32(w.r[1], r_trial, m, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
