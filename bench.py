@@ -11,8 +11,10 @@ Steps cycle over S pre-generated seeds.
 
 Printed: one JSON line with the throughput in nnz(A)-updates/s (d * n * iterations
 executed / wall time), the time to solution, the recovery error, the roofline of the
-sweep kernel (HIP events on the decode stream around every sweep launch) and the CPU
-oracle's rate on a bounded sample of the same workload.
+sweep kernel and the CPU oracle's rate on a bounded sample of the same workload.  The
+timed steps replay each decode's captured launch graph; the sweep's average launch time
+comes from HIP events on the decode stream around every sweep launch, in a second pass
+over the same steps that launches eagerly (events cannot sit inside the graph).
 """
 from __future__ import annotations
 
@@ -34,6 +36,26 @@ METRIC = "Robust-l0 nnz(A)-updates/s and time-to-solution, n=2^20 d=7, rel err<1
 N, M, K, DD, SNR = 2 ** 20, 104857, 10485, 7, 40
 HBM_PEAK_GBS = 8000.0
 
+# HBM byte counters of the sweep (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, mean KiB
+# per dispatch at this workload) and the factors a 256 MiB plain copy gives each counter;
+# valid only for the kernel source they were taken on.
+SWEEP_COUNTERS = {
+    "kernels_sha256": "910e241d4e5925e1c41894c3d13875622235b74d8f8fa8f29416d9fc16fa4aba",
+    "fetch_kib": 20145.8, "write_kib": 672.3, "fetch_factor": 2.000, "write_factor": 1.000,
+}
+
+
+def sweep_traffic():
+    """Bytes per sweep dispatch from the byte counters, or None once the kernels changed."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1704_09012_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != SWEEP_COUNTERS["kernels_sha256"]:
+            return None
+    c = SWEEP_COUNTERS
+    return 1024.0 * (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"])
+
 
 def sweep_bytes(n: int, m: int, d: int) -> float:
     """Algorithmic bytes of one sweep launch: the index stream (4 d bytes per column) and
@@ -41,16 +63,16 @@ def sweep_bytes(n: int, m: int, d: int) -> float:
     return 4.0 * d * n + 4.0 * m
 
 
-def cpu_baseline(inst, y_hat, sigma: float, iters: int = 4) -> dict:
-    """The oracle (test infrastructure) timed on the host for the first `iters` loop
-    iterations of the same decode; single-threaded numpy."""
+def cpu_baseline(inst, y_hat, sigma: float, budget_s: float = 12.0) -> dict:
+    """The oracle (test infrastructure) timed on the host for the first loop iterations of
+    the same decode, as many as fit in about `budget_s` seconds; single-threaded numpy."""
     from oracle import decoder as D
 
     C = D.make_constants(inst.n, inst.m, inst.d, inst.k, sigma)
     st = D.init_state(y_hat, inst.n)
     t0 = time.perf_counter()
     done = 0
-    for _ in range(iters):
+    while time.perf_counter() - t0 < budget_s:
         if st.it >= C.n_iters or D.converged(st, C):
             break
         st = D.step(inst.A_cols, y_hat, st, C).state
@@ -61,6 +83,24 @@ def cpu_baseline(inst, y_hat, sigma: float, iters: int = 4) -> dict:
                       f"({dt:.1f} s, numpy float32 contract, 1 thread)"}
 
 
+def copy_calibration() -> int:
+    """Plain copies of known size: each reads and writes 256 MiB per launch, so the
+    FETCH_SIZE and WRITE_SIZE counters a profiler reports for them give their scale."""
+    import torch
+
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)                 # the runtime's copy kernel
+    for _ in range(3):
+        torch.neg(src, out=dst)        # an elementwise kernel: 16-byte loads and stores per lane
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
+                      "launches": {"copyBuffer": 3, "neg (elementwise)": 3}}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,14 +108,18 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (3 times), the "
+                         "reference kernel that scales HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the decoder has no multi-GPU path",
                           "n_gpus": args.gpus}))
         return 2
 
     import torch
-    from oracle import decoder as OD          # only for the CPU baseline leg and y_hat check below
     from paper_1704_09012_amd import rl0 as R
 
     dev = torch.device("cuda:0")
@@ -103,7 +147,6 @@ def main() -> int:
     for i in range(args.warmup):
         one_step(i)
     torch.cuda.synchronize()
-    R.profile_enable(True)
     iters = 0
     per_step = []
     t_start = time.perf_counter()
@@ -114,8 +157,21 @@ def main() -> int:
         iters += st["iterations"]
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    sweep_ms, sweep_launches = R.profile_read()
+
+    # Kernel durations: the same K steps again, with HIP events on the decode stream
+    # around every sweep, select and row launch (a decode with events launches eagerly
+    # instead of replaying its captured graph, so this pass is not the timed one).
+    R.profile_enable(True)
+    t_prof = time.perf_counter()
+    for i in range(args.steps):
+        one_step(i)
+    torch.cuda.synchronize()
+    t_prof = time.perf_counter() - t_prof
+    kern = R.profile_read_kernels()
     R.profile_enable(False)
+    # the roofline's launches: the iterations that ran (those after the stopping
+    # condition exit early and are reported apart)
+    sweep_ms, sweep_launches = kern["executed"]["sweep"], kern["executed_launches"]
 
     # recovery error of the last step's instance
     last = insts[(args.steps - 1) % len(insts)]
@@ -144,13 +200,18 @@ def main() -> int:
                                "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode",
                    "n": N, "m": M, "d": DD, "k": K, "snr_db": SNR, "seeds": args.seeds},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(),
                      "kernel": "k_sweep<7>", "avg_launch_us": sweep_avg_s * 1e6,
                      "launches": sweep_launches, "bytes_per_launch": sweep_bytes(N, M, DD)},
+        "kernels_us_per_iteration": {k: 1e3 * v / max(sweep_launches, 1) for k, v in kern["executed"].items()},
+        "kernels_us_per_launch_all": {k: 1e3 * v / max(kern["all_launches"], 1) for k, v in kern["all"].items()},
+        "launches_all": kern["all_launches"],
+        "ms_per_step_eager_profiled": 1e3 * t_prof / args.steps,
     }
     if not args.no_cpu_baseline:
         b = insts[0]
         inst = b["inst"]
+        from oracle import decoder as OD     # the CPU baseline leg only
         y_hat = OD.measure(inst.A_cols, inst.x_dense(), inst.eta, M)
         out["cpu_baseline"] = cpu_baseline(inst, y_hat, sigma)
     print(json.dumps(out), flush=True)

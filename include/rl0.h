@@ -136,20 +136,23 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
              int32_t* accepted_h, int32_t* updated, float* omega, float* x_trial,
              float* r_trial, void* stream);
 
-/* Timing of the column sweep (the loop's dominant kernel).  While enabled, rl0_decode
- * records a pair of HIP events on its stream around every sweep launch and, once the
- * decode has synchronised, adds the elapsed times of the sweeps that ran to a running
- * total.  Enabling (or disabling) resets the total. */
+/* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of
+ * replaying its captured graph), each loop kernel with a pair of HIP events that take
+ * the dispatch's own start and end times on the decode stream; once the decode has
+ * synchronised the elapsed times are added to running totals.  A decode launches a
+ * fixed number of loop iterations; those after the stopping condition held exit early
+ * and are counted apart.  Enabling (or disabling) resets the totals. */
 int rl0_profile_enable(int32_t enable);
 
-/* Total sweep time in milliseconds and number of timed sweep launches since the last
- * rl0_profile_enable. */
+/* Total sweep time in milliseconds and number of timed sweep launches (every launched
+ * iteration) since the last rl0_profile_enable. */
 int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h);
 
-/* Total milliseconds, since the last rl0_profile_enable, of the three kernels of every
- * timed loop iteration: ms_total_h[0] the column sweep, [1] H_k with the residual
- * change, [2] the residual rounding and ||r||_1 (ms_total_h holds 3 doubles). */
-int rl0_profile_read_kernels(double* ms_total_h);
+/* Totals since the last rl0_profile_enable.  ms_total_h (6 doubles): [0] the column
+ * sweep, [1] H_k with the residual change, [2] the residual rounding and ||r||_1, over
+ * every launched iteration; [3..5] the same over the iterations that ran before the
+ * stopping condition.  counts_h (2 int64, may be NULL): the two iteration counts. */
+int rl0_profile_read_kernels(double* ms_total_h, int64_t* counts_h);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* rl0_last_error(void);

@@ -105,11 +105,11 @@ hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStr
 hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0,
                           hipStream_t s);
-// One loop iteration (sweep, H_k and residual, finish).  ev_sweep (optional, 4 events)
-// gets events recorded before the sweep and after each of the three kernels.
+// One loop iteration (sweep, H_k and residual, finish).  ev (optional, 6 events) gets
+// the start and end of the sweep, select and row dispatches, in that order.
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
-                            hipStream_t s, hipEvent_t* ev_sweep = nullptr);
+                            hipStream_t s, const hipEvent_t* ev = nullptr);
 // Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat (the run
 // started at iteration it0).
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,

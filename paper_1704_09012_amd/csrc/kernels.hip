@@ -19,6 +19,7 @@
 // pragma below), IEEE division; residuals and ||r||_1 are integer sums.
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #pragma clang fp contract(off)
@@ -985,30 +986,40 @@ int seg_capacity(int n) {
     return blocks(chunks, sweep_grid(n)) * kSweepChunk;
 }
 
-template <int D>
-hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s) {
-    k_sweep<D><<<a.w.sweep_grid, kSweepBlock, 0, s>>>(a);
+// A launch with optional HIP events that take the dispatch's own start and end times.
+template <class K, class Args>
+hipError_t launch_timed(K kernel, int grid, int block, hipStream_t s, const hipEvent_t* ev, const Args& a) {
+    if (ev) {
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, ev[0], ev[1], 0, a);
+    } else {
+        kernel<<<grid, block, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int d, const SweepArgs& a, hipStream_t s) {
+template <int D>
+hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s, const hipEvent_t* ev) {
+    return launch_timed(k_sweep<D>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+}
+
+hipError_t launch_sweep(int d, const SweepArgs& a, hipStream_t s, const hipEvent_t* ev = nullptr) {
     switch (d) {
-        case 1: return launch_sweep_d<1>(a, s);
-        case 2: return launch_sweep_d<2>(a, s);
-        case 3: return launch_sweep_d<3>(a, s);
-        case 4: return launch_sweep_d<4>(a, s);
-        case 5: return launch_sweep_d<5>(a, s);
-        case 6: return launch_sweep_d<6>(a, s);
-        case 7: return launch_sweep_d<7>(a, s);
-        case 8: return launch_sweep_d<8>(a, s);
-        case 9: return launch_sweep_d<9>(a, s);
-        case 10: return launch_sweep_d<10>(a, s);
-        case 11: return launch_sweep_d<11>(a, s);
-        case 12: return launch_sweep_d<12>(a, s);
-        case 13: return launch_sweep_d<13>(a, s);
-        case 14: return launch_sweep_d<14>(a, s);
-        case 15: return launch_sweep_d<15>(a, s);
-        case 16: return launch_sweep_d<16>(a, s);
+        case 1: return launch_sweep_d<1>(a, s, ev);
+        case 2: return launch_sweep_d<2>(a, s, ev);
+        case 3: return launch_sweep_d<3>(a, s, ev);
+        case 4: return launch_sweep_d<4>(a, s, ev);
+        case 5: return launch_sweep_d<5>(a, s, ev);
+        case 6: return launch_sweep_d<6>(a, s, ev);
+        case 7: return launch_sweep_d<7>(a, s, ev);
+        case 8: return launch_sweep_d<8>(a, s, ev);
+        case 9: return launch_sweep_d<9>(a, s, ev);
+        case 10: return launch_sweep_d<10>(a, s, ev);
+        case 11: return launch_sweep_d<11>(a, s, ev);
+        case 12: return launch_sweep_d<12>(a, s, ev);
+        case 13: return launch_sweep_d<13>(a, s, ev);
+        case 14: return launch_sweep_d<14>(a, s, ev);
+        case 15: return launch_sweep_d<15>(a, s, ev);
+        case 16: return launch_sweep_d<16>(a, s, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1097,7 +1108,7 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
 
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
-                            hipStream_t s, hipEvent_t* ev_sweep) {
+                            hipStream_t s, const hipEvent_t* ev) {
     SweepArgs a;
     a.A = A;
     a.n = dm.n;
@@ -1108,17 +1119,13 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     a.tb = tb;
     a.ip = ip;
     a.dbg = dbg;
-    if (ev_sweep) hipEventRecord(ev_sweep[0], s);
-    hipError_t e = launch_sweep(dm.d, a, s);
+    hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
-    if (ev_sweep) hipEventRecord(ev_sweep[1], s);
-    SelectArgs sa{A, dm.d, dm.k, w, ip.it};
-    k_select_apply<<<kSelectGrid, kSelectBlock, 0, s>>>(sa);
-    if (ev_sweep) hipEventRecord(ev_sweep[2], s);
-    FinishArgs fa{dm.m, w, ip.it, ip.tau_next};
-    k_finish_rows<<<kRowGrid, kRowBlock, 0, s>>>(fa);
-    if (ev_sweep) hipEventRecord(ev_sweep[3], s);
-    return hipGetLastError();
+    const SelectArgs sa{A, dm.d, dm.k, w, ip.it};
+    e = launch_timed(k_select_apply, kSelectGrid, kSelectBlock, s, ev ? ev + 2 : nullptr, sa);
+    if (e != hipSuccess) return e;
+    const FinishArgs fa{dm.m, w, ip.it, ip.tau_next};
+    return launch_timed(k_finish_rows, kRowGrid, kRowBlock, s, ev ? ev + 4 : nullptr, fa);
 }
 
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,

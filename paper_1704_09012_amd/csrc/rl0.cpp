@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -39,34 +41,39 @@ std::mutex g_mu;
 
 struct SweepProfile {
     bool enabled = false;
-    std::vector<hipEvent_t> pool;   // per iteration: before sweep, after sweep, select, finish
-    double total_ms[3] = {0.0, 0.0, 0.0};
-    long long launches = 0;
+    std::vector<hipEvent_t> pool;   // per iteration: start and end of the sweep, select, finish
+    double total_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // all launched, then executed
+    long long launches = 0, executed = 0;
 };
 SweepProfile g_prof;
 
 hipEvent_t* profile_events(int it) {
     if (!g_prof.enabled) return nullptr;
-    const size_t need = 4 * static_cast<size_t>(it + 1);
+    const size_t need = 6 * static_cast<size_t>(it + 1);
     while (g_prof.pool.size() < need) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         g_prof.pool.push_back(e);
     }
-    return &g_prof.pool[4 * it];
+    return &g_prof.pool[6 * it];
 }
 
-// after a synchronised decode: add the kernels of the executed iterations
-void profile_collect(int executed) {
+// after a synchronised decode: add the kernels of the launched iterations (the first
+// `executed` of which ran before the stopping condition)
+void profile_collect(int launched, int executed) {
     if (!g_prof.enabled) return;
-    for (int it = 0; it < executed && 4 * static_cast<size_t>(it) + 3 < g_prof.pool.size(); ++it) {
+    for (int it = 0; it < launched && 6 * static_cast<size_t>(it) + 5 < g_prof.pool.size(); ++it) {
         float ms[3] = {0.0f, 0.0f, 0.0f};
         bool ok = true;
         for (int k = 0; k < 3; ++k)
-            ok = ok && hipEventElapsedTime(&ms[k], g_prof.pool[4 * it + k], g_prof.pool[4 * it + k + 1]) == hipSuccess;
+            ok = ok && hipEventElapsedTime(&ms[k], g_prof.pool[6 * it + 2 * k], g_prof.pool[6 * it + 2 * k + 1]) == hipSuccess;
         if (!ok) continue;
         for (int k = 0; k < 3; ++k) g_prof.total_ms[k] += ms[k];
         g_prof.launches += 1;
+        if (it < executed) {
+            for (int k = 0; k < 3; ++k) g_prof.total_ms[3 + k] += ms[k];
+            g_prof.executed += 1;
+        }
     }
 }
 
@@ -106,12 +113,47 @@ int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
 
 // ---------------------------------------------------------------- working memory
 
+// A decode's whole launch sequence, captured once and replayed: one host call in place
+// of ~4 + 3 * iterations launches.  Everything a launch bakes in is in the key.
+struct DecodeKey {
+    const void* A;
+    const void* y;
+    void* x;
+    const void* dc;
+    int32_t n, m, d;
+    rl0_params p;
+};
+
+struct GraphEntry {
+    DecodeKey key;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long last_use = 0;
+};
+
+constexpr size_t kMaxGraphs = 16;   // per workspace; least recently used is dropped
+
 struct Buffers {
     int cap_n = 0, cap_m = 0;
     void* block = nullptr;
     rl0::Workspace w{};
     rl0::DevState* st_host = nullptr;  // pinned copy of the device state
+    hipStream_t capture = nullptr;     // private stream the launch sequence is captured on
+    std::vector<GraphEntry> graphs;    // replayable decodes on this workspace
+    unsigned long long uses = 0;
 };
+
+bool graphs_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("RL0_GRAPHS");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+void drop_graphs(Buffers* b) {
+    for (GraphEntry& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
 
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Buffers>> g_ws;
 
@@ -122,6 +164,7 @@ int get_workspace(int device, hipStream_t s, int n, int m, Buffers** out) {
     if (b->cap_n < n || b->cap_m < m || !b->block) {
         if (b->block) {
             HIP_TRY(hipStreamSynchronize(s));
+            drop_graphs(b);   // they point into the old block
             HIP_TRY(hipFree(b->block));
             b->block = nullptr;
         }
@@ -183,6 +226,47 @@ int err_code_of(int flags) {
     if (flags & rl0::kErrIndex) return fail(RL0_EINDEX, "A_cols: index out of range or column not strictly ascending");
     if (flags & rl0::kErrNonFinite) return fail(RL0_EINVAL, "y holds a non-finite value");
     if (flags & rl0::kErrRange) return fail(RL0_ERANGE, "a value left the fixed-point range (|v| >= 2^22)");
+    return RL0_OK;
+}
+
+// Launches the decode whose launches `issue` makes, from the workspace's graph cache;
+// a key seen for the first time is captured on the private stream first.
+template <class Issue>
+int replay_decode(Buffers* b, const DecodeKey& key, hipStream_t s, Issue&& issue) {
+    GraphEntry* hit = nullptr;
+    for (GraphEntry& g : b->graphs)
+        if (std::memcmp(&g.key, &key, sizeof(key)) == 0) hit = &g;
+    if (!hit) {
+        if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
+        const int rc = issue(b->capture);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->capture, &graph);
+        if (rc != RL0_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(RL0_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(RL0_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        if (b->graphs.size() >= kMaxGraphs) {
+            // every decode on this workspace synchronises before returning: none in flight
+            size_t lru = 0;
+            for (size_t i = 1; i < b->graphs.size(); ++i)
+                if (b->graphs[i].last_use < b->graphs[lru].last_use) lru = i;
+            (void)hipGraphExecDestroy(b->graphs[lru].exec);
+            b->graphs.erase(b->graphs.begin() + static_cast<std::ptrdiff_t>(lru));
+        }
+        GraphEntry g;
+        g.key = key;
+        g.exec = exec;
+        b->graphs.push_back(g);
+        hit = &b->graphs.back();
+    }
+    hit->last_use = ++b->uses;
+    HIP_TRY(hipGraphLaunch(hit->exec, s));
     return RL0_OK;
 }
 
@@ -308,16 +392,37 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     const rl0::DecodeDims dm{n, m, d, p->k};
     const rl0::ScoreTables tb = tables_of(dc);
     const int N = dc->hc.n_iters;
-    HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, nullptr, b->w, iter_params(dc, p, 0), s));
-    const rl0::DebugOut dbg{nullptr, nullptr};
-    for (int it = 0; it < N; ++it)
-        HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, s, profile_events(it)));
-    HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), 0, x_out, s));
-    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
+    auto issue = [&](hipStream_t q) -> int {
+        HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, nullptr, b->w, iter_params(dc, p, 0), q));
+        const rl0::DebugOut dbg{nullptr, nullptr};
+        for (int it = 0; it < N; ++it)
+            HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, q, profile_events(it)));
+        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), 0, x_out, q));
+        return RL0_OK;
+    };
+    // per-iteration timing events cannot be recorded into a captured graph: a profiled
+    // decode launches eagerly
+    if (graphs_enabled() && !g_prof.enabled) {
+        DecodeKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.A = A_cols;
+        key.y = y;
+        key.x = x_out;
+        key.dc = dc;
+        key.n = n;
+        key.m = m;
+        key.d = d;
+        std::memcpy(&key.p, p, sizeof(*p));
+        if (int rc = replay_decode(b, key, s, issue)) return rc;
+    } else {
+        if (int rc = issue(s)) return rc;
+    }
+    // the slots, counters and flags lead the device state
+    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[N & 1];
-    profile_collect(fin.iterations);
+    profile_collect(N, fin.iterations);
     if (st_h) {
         st_h->iterations = fin.iterations;
         st_h->accepted = fin.accepted;
@@ -382,6 +487,7 @@ int rl0_profile_enable(int32_t enable) {
     g_prof.enabled = enable != 0;
     for (double& t : g_prof.total_ms) t = 0.0;
     g_prof.launches = 0;
+    g_prof.executed = 0;
     return RL0_OK;
 }
 
@@ -392,10 +498,14 @@ int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h) {
     return RL0_OK;
 }
 
-int rl0_profile_read_kernels(double* ms_total_h) {
+int rl0_profile_read_kernels(double* ms_total_h, int64_t* counts_h) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!ms_total_h) return fail(RL0_EINVAL, "NULL pointer");
-    for (int k = 0; k < 3; ++k) ms_total_h[k] = g_prof.total_ms[k];
+    for (int k = 0; k < 6; ++k) ms_total_h[k] = g_prof.total_ms[k];
+    if (counts_h) {
+        counts_h[0] = g_prof.launches;
+        counts_h[1] = g_prof.executed;
+    }
     return RL0_OK;
 }
 
@@ -403,6 +513,8 @@ void rl0_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     hipDeviceSynchronize();
     for (auto& kv : g_ws) {
+        drop_graphs(kv.second.get());
+        if (kv.second->capture) hipStreamDestroy(kv.second->capture);
         if (kv.second->block) hipFree(kv.second->block);
         if (kv.second->st_host) hipHostFree(kv.second->st_host);
     }

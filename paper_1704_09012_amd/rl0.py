@@ -102,7 +102,7 @@ def lib() -> ctypes.CDLL:
                                ctypes.POINTER(I64), ctypes.POINTER(I32), P, P, P, P, V]
         L.rl0_profile_enable.argtypes = [I32]
         L.rl0_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
-        L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double)]
+        L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
@@ -260,10 +260,14 @@ def profile_read() -> tuple[float, int]:
 
 
 def profile_read_kernels() -> dict:
-    """Total milliseconds per kernel of the timed iterations since profile_enable."""
-    arr = (ctypes.c_double * 3)()
-    _check(lib().rl0_profile_read_kernels(arr))
-    return {"sweep": arr[0], "select_apply": arr[1], "finish_rows": arr[2]}
+    """Total milliseconds per kernel since profile_enable: over every launched iteration
+    ("all") and over the iterations that ran before the stopping condition ("executed")."""
+    arr = (ctypes.c_double * 6)()
+    cnt = (ctypes.c_int64 * 2)()
+    _check(lib().rl0_profile_read_kernels(arr, cnt))
+    names = ("sweep", "select_apply", "finish_rows")
+    return {"all": {k: arr[i] for i, k in enumerate(names)}, "all_launches": cnt[0],
+            "executed": {k: arr[3 + i] for i, k in enumerate(names)}, "executed_launches": cnt[1]}
 
 
 def release() -> None:

@@ -237,6 +237,27 @@ def test_decode_zero_signal_and_determinism():
     assert np.array_equal(a, b) and sa == sb
 
 
+def test_decode_replay_into_the_same_buffers():
+    """A decode into the same buffers replays the captured launch sequence: new contents
+    of A and y between replays, eager work in between, every replay against the oracle."""
+    n, m, k, d = 8192, 1024, 120, 7
+    A_t = torch.empty((n, d), dtype=torch.int32, device="cuda")
+    y_t = torch.empty(m, dtype=torch.float32, device="cuda")
+    x_t = torch.empty(n, dtype=torch.float32, device="cuda")
+    cases = [problem(n, m, k, d, snr, seed) for snr, seed in ((40, 31), (20, 32), (60, 33))]
+    for rep, (inst, x, y, sig) in enumerate(cases + cases[:1]):
+        print(f"replay {rep}", flush=True)
+        A_t.copy_(dev(inst.A_cols))
+        y_t.copy_(dev(y))
+        params = R.params_default(n, m, d, k, float(np.float32(I.sigma_for_snr(40, n, m, k, d))))
+        _, st = R.decode(A_t, y_t, params=params, out=x_t)
+        junk = torch.randn(4096, device="cuda").sum()      # eager work between replays
+        C = D.make_constants(n, m, d, k, params.sigma)
+        res = D.decode(inst.A_cols, y, C)
+        assert_same_decode(host(x_t), st, res)
+        assert math.isfinite(float(junk))
+
+
 def _golden_cases():
     if not os.path.isdir(GOLDEN):
         return []
