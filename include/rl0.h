@@ -136,6 +136,60 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
              int32_t* accepted_h, int32_t* updated, float* omega, float* x_trial,
              float* r_trial, void* stream);
 
+/* ---------------------------------------------------------------- batched decoding
+ *
+ * Many independent Robust-l0 decodes (Alg. 1) of uneven n, m and k in one persistent
+ * launch, replayed from a captured hipGraph.  Every workgroup takes the next instance
+ * from a queue ordered largest first and decodes it alone; each instance's x_hat and
+ * statistics are bit-identical to what rl0_decode returns for it. */
+
+#define RL0_SIZE_CLASSES 12     /* schedule classes by n: class c holds n in [2^(10+c),
+                                   2^(11+c)); class 0 also n < 2^10, class 11 n >= 2^21 */
+#define RL0_BATCH_MAX_M 524288  /* rows per instance (its outer-test bitmask sits in LDS) */
+
+/* One instance.  A_cols [n][d] (16-byte aligned), y [m] and x_out [n] are device
+ * pointers; params as for rl0_decode (posterior = 0). */
+typedef struct rl0_problem {
+    const int32_t* A_cols;
+    int32_t n, m, d;
+    const float* y;
+    rl0_params params;
+    float* x_out;
+} rl0_problem;
+
+/* How a batch runs: the launch shape, and per size class the columns each thread takes
+ * per tile of the column sweep.  Results do not depend on it. */
+typedef struct rl0_batch_schedule {
+    int32_t block;                      /* threads per workgroup: 256, 512 or 1024 */
+    int32_t per_cu;                     /* resident workgroups per compute unit the
+                                           persistent grid is sized for, 1..8 */
+    int32_t cols[RL0_SIZE_CLASSES];     /* 1, 2 or 4 */
+} rl0_batch_schedule;
+
+/* Decode count instances (probs_h: host array).  Every instance is checked as in
+ * rl0_decode before anything runs (RL0_EINVAL names the first bad one in
+ * rl0_last_error); m must be <= RL0_BATCH_MAX_M.  st_h (host, count entries, may be
+ * NULL) receives each instance's statistics; the stream is synchronised.  When a
+ * decode fails on the device (malformed A_cols with validate = 1, non-finite y,
+ * fixed-point range), that instance's x_out and stats.error_flags say so, the others
+ * are unaffected, and the call returns the first such error's code.  Uses the
+ * calling device's current schedule. */
+int rl0_decode_batched(const rl0_problem* probs_h, int32_t count, rl0_stats* st_h, void* stream);
+
+/* The calling device's batch schedule (a default until set or tuned). */
+int rl0_batch_schedule_get(rl0_batch_schedule* out_h);
+/* Install a schedule for the calling device; RL0_EINVAL if a field is out of range. */
+int rl0_batch_schedule_set(const rl0_batch_schedule* s_h);
+
+/* Autotuner: decodes the given batch under candidate schedules, timing each persistent
+ * launch with HIP events (median of `reps` runs): first the launch shape (block, per_cu)
+ * over the feasible candidates, then for each size class present, largest first, the
+ * columns per thread.  Installs the fastest schedule for the calling device and writes
+ * it to best_h (may be NULL); ms_h (may be NULL) receives its median time.  The x_out
+ * buffers hold valid decodes afterwards. */
+int rl0_autotune_batched(const rl0_problem* probs_h, int32_t count, int32_t reps,
+                         rl0_batch_schedule* best_h, double* ms_h, void* stream);
+
 /* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of
  * replaying its captured graph), each loop kernel with a pair of HIP events that take
  * the dispatch's own start and end times on the decode stream; once the decode has

@@ -1,0 +1,595 @@
+// Persistent batched Robust-l0 decoder for gfx950.
+//
+// One launch decodes many independent instances.  Every workgroup repeatedly takes the
+// next instance from a queue (the host orders it largest first) and runs Alg. 1 for that
+// instance alone, so the only synchronisation is the workgroup barrier and the launch
+// drains when the queue is empty.  Per iteration a workgroup
+//   1. writes the outer-test bitmask |r_i| >= tau_it of its instance into LDS (ballot);
+//   2. sweeps its columns in tiles (the next tile's indices load while the current one is
+//      tested): a column whose rows hit the bitmask gathers its exact residuals and runs
+//      the consensus test; an update goes to x' and to the change list;
+//   3. applies H_k: when x' has more than k nonzeros, the k-th largest key by a radix
+//      select over x', and the dropped columns join the change list;
+//   4. adds the exact fixed-point residual change of every changed column with 64-bit
+//      atomics, accumulating the change of ||r||_1 from the values the atomics return
+//      (the per-row differences telescope, whatever the order of the atomics);
+//   5. accepts (x_hat <- x') or undoes the residual change.
+// The arithmetic is the single-decode kernels' (column_math.h), so every instance's
+// result is bit-identical to rl0_decode's on the same input.
+#include "batched.h"
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "column_math.h"
+
+#pragma clang fp contract(off)
+
+namespace rl0 {
+
+namespace {
+
+constexpr int kBins = 2048;
+constexpr int kTabStride = kTableStrideFloats;   // floats from the start of Tz to Te in LDS
+
+template <int BLOCK>
+struct BatchShared {
+    unsigned hist[kBins];
+    int queue[BLOCK * 5];      // queued columns: fewer than BLOCK carried over plus one tile
+    unsigned scan[BLOCK / 64];
+    long long red[BLOCK / 64];
+    int idx, nq, nchg, nupd, nzd, nkeys, err, digit;
+    unsigned above, bucket;
+};
+
+// Sum over the workgroup, returned to every thread.
+template <int BLOCK>
+__device__ __forceinline__ long long wg_sum(long long v, long long* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long t = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// The digit (among kBins, highest first) of the bucket holding the rem-th largest of the
+// counted keys, the count above that bucket and the bucket's own count.  Needs
+// 1 <= rem <= total count.
+template <int BLOCK>
+__device__ void wg_find_digit(const unsigned* hist, unsigned rem, BatchShared<BLOCK>& sh) {
+    constexpr int B = kBins / BLOCK;
+    const int tid = threadIdx.x;
+    unsigned c = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) c += hist[kBins - 1 - tid * B - i];
+    unsigned incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned t = __shfl_up(incl, off);
+        if ((tid & 63) >= off) incl += t;
+    }
+    if ((tid & 63) == 63) sh.scan[tid >> 6] = incl;
+    __syncthreads();
+    unsigned before = incl - c;
+    for (int w = 0; w < (tid >> 6); ++w) before += sh.scan[w];
+    if (before < rem && rem <= before + c) {
+        unsigned acc = before;
+        for (int i = 0; i < B; ++i) {
+            const int dg = kBins - 1 - tid * B - i;
+            const unsigned h = hist[dg];
+            if (rem <= acc + h) {
+                sh.digit = dg;
+                sh.above = acc;
+                sh.bucket = h;
+                break;
+            }
+            acc += h;
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int kU = 8;   // loads in flight per thread in the streaming loops
+
+// H_k's threshold: the k-th largest key (|x'_j| bits, then smaller j) among the nonzero
+// entries of x', which number more than k.  One pass over x' writes the nonzero keys to
+// the key buffer (and their top-digit histogram); five radix passes over that buffer
+// follow (11, ..., 11, 8 bits), stopping once the bucket is exactly the rest of H_k.
+// Returns the number of keys in the buffer through *nkeys.
+template <int BLOCK>
+__device__ unsigned long long wg_select_kth(const BatchProblem& P, BatchShared<BLOCK>& sh, int* nkeys) {
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kBins; b += BLOCK) sh.hist[b] = 0u;
+    if (tid == 0) sh.nkeys = 0;
+    __syncthreads();
+    for (int base = 0; base < P.n; base += BLOCK * kU) {
+        float v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int j = base + u * BLOCK + tid;
+            v[u] = j < P.n ? P.xp[j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool nz = v[u] != 0.0f;
+            const unsigned long long key = nz ? hk_key(base + u * BLOCK + tid, v[u]) : 0ull;
+            const int slot = wave_append(&sh.nkeys, nz);
+            if (nz) P.keys[slot] = key;
+            hist_add(sh.hist, static_cast<unsigned>(key >> 52), nz);
+        }
+    }
+    __syncthreads();
+    const int nk = sh.nkeys;
+    *nkeys = nk;
+    unsigned long long prefix = 0ull, pmask = 0ull;
+    unsigned rem = static_cast<unsigned>(P.k);
+    for (int pass = 0; pass < 6; ++pass) {
+        const int sft = pass < 5 ? 52 - 11 * pass : 0;
+        const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
+        if (pass > 0) {
+            for (int b = tid; b < kBins; b += BLOCK) sh.hist[b] = 0u;
+            __syncthreads();
+            for (int base = 0; base < nk; base += BLOCK * kU) {
+                unsigned long long kv[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int e = base + u * BLOCK + tid;
+                    kv[u] = e < nk ? P.keys[e] : 0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    hist_add(sh.hist, static_cast<unsigned>((kv[u] >> sft) & dmask),
+                             kv[u] != 0ull && (kv[u] & pmask) == prefix);
+            }
+            __syncthreads();
+        }
+        wg_find_digit<BLOCK>(sh.hist, rem, sh);
+        prefix |= static_cast<unsigned long long>(sh.digit) << sft;
+        pmask |= static_cast<unsigned long long>(dmask) << sft;
+        rem -= sh.above;
+        const bool exact = (rem == sh.bucket);
+        __syncthreads();
+        if (exact) break;
+    }
+    return prefix;
+}
+
+template <int D, int C>
+__device__ __forceinline__ void load_tile(const int32_t* __restrict__ A, int n, int j0, int (&rows)[C][D]) {
+    if (C == 4 && j0 + C <= n) {
+        // C * D ints from a 16-byte aligned start (j0 is a multiple of 4)
+        const int4* __restrict__ p4 = reinterpret_cast<const int4*>(A + static_cast<size_t>(j0) * D);
+        int flat[C * D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int4 t = p4[k];
+            flat[4 * k] = t.x;
+            flat[4 * k + 1] = t.y;
+            flat[4 * k + 2] = t.z;
+            flat[4 * k + 3] = t.w;
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = flat[q * D + p];
+    } else {
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = (j0 + q < n) ? A[static_cast<size_t>(j0 + q) * D + p] : 0;
+    }
+}
+
+// Step 2 for one instance: the column sweep, C consecutive columns per thread per tile.
+// A tile's columns test their rows against the bitmask and those with a candidate row
+// join an LDS queue; the next tile's indices load while the queue is checked.  Once the
+// queue holds a column per thread (or the sweep ends) it is worked off one column per
+// thread, so the consensus test is balanced and its gathers are paid once per BLOCK
+// queued columns rather than once per tile.
+template <int D, int BLOCK, int C>
+__device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uint32_t* bm, int it,
+                         BatchShared<BLOCK>& sh) {
+    const int tid = threadIdx.x;
+    const int n = P.n;
+    constexpr int kTile = BLOCK * C;
+    int cur[C][D];
+    load_tile<D, C>(P.A, n, tid * C, cur);
+    int nupd = 0, nzd = 0;
+    for (int base = 0; base < n; base += kTile) {
+        const int j0 = base + tid * C;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            unsigned hit = 0u;
+            if (j0 + q < n) {
+#pragma unroll
+                for (int p = 0; p < D; ++p) {
+                    const int r = cur[q][p];
+                    hit |= (bm[r >> 5] >> (r & 31)) & 1u;
+                }
+            }
+            const int slot = wave_append(&sh.nq, hit != 0u);
+            if (hit) sh.queue[slot] = j0 + q;
+        }
+        const bool more = base + kTile < n;
+        if (more) load_tile<D, C>(P.A, n, base + kTile + tid * C, cur);
+        __syncthreads();
+        const int nq = sh.nq;
+        __syncthreads();   // every thread has read nq before the next tile appends
+        if (nq < BLOCK && more) continue;
+        for (int e0 = 0; e0 < nq; e0 += BLOCK) {
+            const int e = e0 + tid;
+            bool upd = false;
+            int j = 0;
+            if (e < nq) {
+                j = sh.queue[e];
+                const int32_t* __restrict__ col = P.A + static_cast<size_t>(j) * D;
+                int rows[D];
+#pragma unroll
+                for (int p = 0; p < D; ++p) rows[p] = col[p];
+                float v[D];
+#pragma unroll
+                for (int p = 0; p < D; ++p) v[p] = from_fx(P.S[rows[p]]);
+                unsigned cm = 0u;
+#pragma unroll
+                for (int p = 0; p < D; ++p) cm |= ((bm[rows[p] >> 5] >> (rows[p] & 31)) & 1u) << p;
+                float om = 0.0f;
+                upd = column_update<D>(v, cm, tb, P.alpha, P.l1_test, &om);
+                if (upd) {
+                    const float xh = P.x[j];
+                    const float xn = xh + om;
+                    P.xp[j] = xn;
+                    P.stamp[j] = it;
+                    ++nupd;
+                    nzd += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
+                }
+            }
+            const int slot = wave_append(&sh.nchg, upd);
+            if (upd) P.chg[slot] = j;
+        }
+        if (tid == 0) sh.nq = 0;
+        __syncthreads();
+    }
+    if (nupd) atomicAdd(&sh.nupd, nupd);
+    if (nzd) atomicAdd(&sh.nzd, nzd);
+}
+
+// The fixed-point residual change of changing column j from xh to xn (d rows); with
+// `track`, the change of ||r||_1 that the atomics' returned values give.
+template <int D>
+__device__ __forceinline__ long long apply_change(const BatchProblem& P, int j, float xh, float xn, bool track,
+                                                  int* err) {
+    const long long delta = (xh != 0.0f ? to_fx(xh, err) : 0) - (xn != 0.0f ? to_fx(xn, err) : 0);
+    if (delta == 0) return 0;
+    const int32_t* __restrict__ col = P.A + static_cast<size_t>(j) * D;
+    int rows[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) rows[p] = col[p];
+    long long dl = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        unsigned long long* a = reinterpret_cast<unsigned long long*>(P.S + rows[p]);
+        const long long old = static_cast<long long>(atomicAdd(a, static_cast<unsigned long long>(delta)));
+        if (track) dl += l1_term(from_fx(old + delta)) - l1_term(from_fx(old));
+    }
+    return dl;
+}
+
+template <int D, int BLOCK>
+__device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn, BatchShared<BLOCK>& sh) {
+    const int tid = threadIdx.x;
+    const int n = P.n, m = P.m;
+    float* Tz = dyn;
+    float* Te = dyn + kTabStride;
+    uint32_t* bm = reinterpret_cast<uint32_t*>(dyn + 2 * kTabStride);
+    if (!P.exact)
+        for (int i = tid; i <= kTableN; i += BLOCK) {
+            Tz[i] = P.Tz[i];
+            Te[i] = P.Te[i];
+        }
+    if (tid == 0) sh.err = 0;
+    __syncthreads();
+    const ScoreTables tb{Tz, Te, P.inv_h_z, P.inv_h_e, P.exact};
+
+    // ---- ingest: the columns (rows in range, strictly ascending), y, the state
+    if (P.validate) {
+        for (int j = tid; j < n; j += BLOCK) {
+            const int32_t* __restrict__ col = P.A + static_cast<size_t>(j) * D;
+            int prev = -1;
+            bool bad = false;
+#pragma unroll
+            for (int p = 0; p < D; ++p) {
+                const int r = col[p];
+                bad = bad || r <= prev || r >= m;
+                prev = r;
+            }
+            if (bad) atomicOr(&sh.err, kErrIndex);
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < n; j += BLOCK) {
+        P.x[j] = 0.0f;
+        P.xp[j] = 0.0f;
+        P.stamp[j] = -1;
+    }
+    long long l = 0;
+    for (int base = 0; base < m; base += BLOCK * kU) {
+        float yv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = base + u * BLOCK + tid;
+            yv[u] = i < m ? P.y[i] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = base + u * BLOCK + tid;
+            if (i >= m) continue;
+            long long sfx = 0;
+            if (!isfinite(yv[u]))
+                atomicOr(&sh.err, kErrNonFinite);
+            else
+                sfx = to_fx(yv[u], &sh.err);
+            P.S[i] = sfx;
+            l += l1_term(from_fx(sfx));
+        }
+    }
+    long long L_hat = wg_sum<BLOCK>(l, sh.red);
+
+    int iters = 0, accepted = 0, updates = 0, supp = 0;
+    const int words = (m + 31) >> 5;
+    for (int it = 0;; ++it) {
+        if (sh.err != 0 || static_cast<double>(L_hat) <= P.tol_fx || it >= P.n_iters) break;
+        // ---- 1. outer-test bitmask of this iteration's threshold
+        const uint32_t tau = P.tau[it];
+        for (int base = 0; base < words * 32; base += BLOCK * kU) {
+            long long sv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = base + u * BLOCK + tid;
+                sv[u] = i < m ? P.S[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = base + u * BLOCK + tid;
+                const bool pred = i < m && abs_bits(from_fx(sv[u])) >= tau;
+                const unsigned long long b = __ballot(pred);
+                if ((tid & 63) == 0) {
+                    const int w = i >> 5;
+                    if (w < words) bm[w] = static_cast<uint32_t>(b);
+                    if (w + 1 < words) bm[w + 1] = static_cast<uint32_t>(b >> 32);
+                }
+            }
+        }
+        if (tid == 0) {
+            sh.nq = 0;
+            sh.nchg = 0;
+            sh.nupd = 0;
+            sh.nzd = 0;
+        }
+        __syncthreads();
+        // ---- 2. sweep
+        if (P.cols == 1)
+            wg_sweep<D, BLOCK, 1>(P, tb, bm, it, sh);
+        else if (P.cols == 2)
+            wg_sweep<D, BLOCK, 2>(P, tb, bm, it, sh);
+        else
+            wg_sweep<D, BLOCK, 4>(P, tb, bm, it, sh);
+        __syncthreads();
+        updates += sh.nupd;
+        // ---- 3. H_k
+        if (supp + sh.nzd > P.k) {
+            int nk = 0;
+            const unsigned long long kth = wg_select_kth<BLOCK>(P, sh, &nk);
+            // the dropped columns: keys below the threshold
+            for (int e0 = 0; e0 < nk; e0 += BLOCK) {
+                const int e = e0 + tid;
+                bool add = false;
+                int j = 0;
+                if (e < nk) {
+                    const unsigned long long key = P.keys[e];
+                    if (key < kth) {
+                        j = static_cast<int>(0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull));
+                        P.xp[j] = 0.0f;
+                        add = P.stamp[j] != it;
+                        if (add) P.stamp[j] = it;
+                    }
+                }
+                const int slot = wave_append(&sh.nchg, add);
+                if (add) P.chg[slot] = j;
+            }
+            __syncthreads();
+        }
+        // ---- 4. exact residual change and ||r||_1 of the trial iterate
+        const int nchg = sh.nchg;
+        long long dl = 0, dsupp = 0;
+        for (int base = 0; base < nchg; base += BLOCK * 4) {
+            int jj[4];
+            float xh[4], xn[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = base + u * BLOCK + tid;
+                jj[u] = c < nchg ? P.chg[c] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xh[u] = jj[u] >= 0 ? P.x[jj[u]] : 0.0f;
+                xn[u] = jj[u] >= 0 ? P.xp[jj[u]] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (jj[u] < 0 || xh[u] == xn[u]) continue;
+                dsupp += (xn[u] != 0.0f ? 1 : 0) - (xh[u] != 0.0f ? 1 : 0);
+                dl += apply_change<D>(P, jj[u], xh[u], xn[u], true, &sh.err);
+            }
+        }
+        const long long Lt = L_hat + wg_sum<BLOCK>(dl, sh.red);
+        const long long ds = wg_sum<BLOCK>(dsupp, sh.red);
+        // ---- 5. accept or undo
+        const bool acc = (Lt < L_hat) && (sh.err == 0);
+        ++iters;
+        if (acc) {
+            for (int c = tid; c < nchg; c += BLOCK) {
+                const int j = P.chg[c];
+                P.x[j] = P.xp[j];
+            }
+            L_hat = Lt;
+            supp += static_cast<int>(ds);
+            ++accepted;
+        } else {
+            for (int c = tid; c < nchg; c += BLOCK) {
+                const int j = P.chg[c];
+                const float xh = P.x[j], xn = P.xp[j];
+                if (xh == xn) continue;
+                P.xp[j] = xh;
+                apply_change<D>(P, j, xn, xh, false, &sh.err);
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        R->L_hat = L_hat;
+        R->iterations = iters;
+        R->accepted = accepted;
+        R->updates_total = updates;
+        R->err = sh.err;
+    }
+    __syncthreads();
+}
+
+template <int D, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_decode_batched(const BatchProblem* __restrict__ probs,
+                                                          const int* __restrict__ order, int count,
+                                                          BatchResult* __restrict__ res, int* __restrict__ counter) {
+    extern __shared__ float dyn[];
+    __shared__ BatchShared<BLOCK> sh;
+    for (;;) {
+        if (threadIdx.x == 0) sh.idx = atomicAdd(counter, 1);
+        __syncthreads();
+        // the instance index is uniform over the workgroup: keep it (and so the
+        // descriptor loads) scalar
+        const int q = __builtin_amdgcn_readfirstlane(sh.idx);
+        __syncthreads();
+        if (q >= count) return;
+        const int pi = __builtin_amdgcn_readfirstlane(order[q]);
+        decode_instance<D, BLOCK>(probs[pi], res + pi, dyn, sh);
+    }
+}
+
+__global__ void k_zero_counter(int* counter) { *counter = 0; }
+
+template <int D, int BLOCK>
+hipError_t launch_db(int grid, size_t lds, const BatchProblem* probs, const int* order, int count,
+                     BatchResult* res, int* counter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (e0) {
+        hipExtLaunchKernelGGL(k_decode_batched<D, BLOCK>, dim3(grid), dim3(BLOCK), static_cast<uint32_t>(lds), s,
+                              e0, e1, 0, probs, order, count, res, counter);
+    } else {
+        k_decode_batched<D, BLOCK><<<grid, BLOCK, lds, s>>>(probs, order, count, res, counter);
+    }
+    return hipGetLastError();
+}
+
+template <int D, int BLOCK>
+hipError_t set_lds_limit() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_decode_batched<D, BLOCK>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(batched_lds_bytes(kBatchMaxRows)));
+}
+
+template <int D>
+hipError_t set_lds_limits_d() {
+    hipError_t e = set_lds_limit<D, 256>();
+    if (e == hipSuccess) e = set_lds_limit<D, 512>();
+    if (e == hipSuccess) e = set_lds_limit<D, 1024>();
+    return e;
+}
+
+template <int... Ds>
+hipError_t set_lds_limits_all(std::integer_sequence<int, Ds...>) {
+    hipError_t e = hipSuccess;
+    ((e = (e == hipSuccess ? set_lds_limits_d<Ds + 1>() : e)), ...);
+    return e;
+}
+
+template <int D, int BLOCK>
+int max_resident_db(size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_decode_batched<D, BLOCK>, BLOCK, lds) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+template <int D>
+int max_resident_d(int block, size_t lds) {
+    switch (block) {
+        case 256: return max_resident_db<D, 256>(lds);
+        case 512: return max_resident_db<D, 512>(lds);
+        case 1024: return max_resident_db<D, 1024>(lds);
+        default: return 0;
+    }
+}
+
+template <int... Ds>
+int max_resident_any(int d, int block, size_t lds, std::integer_sequence<int, Ds...>) {
+    int r = 0;
+    ((r = (d == Ds + 1 ? max_resident_d<Ds + 1>(block, lds) : r)), ...);
+    return r;
+}
+
+template <int D>
+hipError_t launch_d(const BatchLaunch& L, int grid, size_t lds, const BatchProblem* probs, const int* order,
+                    int count, BatchResult* res, int* counter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    switch (L.block) {
+        case 256: return launch_db<D, 256>(grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 512: return launch_db<D, 512>(grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 1024: return launch_db<D, 1024>(grid, lds, probs, order, count, res, counter, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t batched_set_lds_limits() {
+    return set_lds_limits_all(std::make_integer_sequence<int, kMaxD>{});
+}
+
+int batched_max_resident(int d, int block, size_t lds_bytes) {
+    return max_resident_any(d, block, lds_bytes, std::make_integer_sequence<int, kMaxD>{});
+}
+
+size_t batched_lds_bytes(int max_m) {
+    const size_t words = (static_cast<size_t>(max_m) + 31) / 32;
+    return (2 * static_cast<size_t>(kTabStride)) * sizeof(float) + 4 * words;
+}
+
+hipError_t launch_batched(int d, const BatchLaunch& L, int grid, size_t lds, const BatchProblem* probs,
+                          const int* order, int count, BatchResult* res, int* counter, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
+    k_zero_counter<<<1, 1, 0, s>>>(counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (d) {
+        case 1: return launch_d<1>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 2: return launch_d<2>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 3: return launch_d<3>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 4: return launch_d<4>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 5: return launch_d<5>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 6: return launch_d<6>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 7: return launch_d<7>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 8: return launch_d<8>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 9: return launch_d<9>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 10: return launch_d<10>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 11: return launch_d<11>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 12: return launch_d<12>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 13: return launch_d<13>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 14: return launch_d<14>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 15: return launch_d<15>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 16: return launch_d<16>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rl0

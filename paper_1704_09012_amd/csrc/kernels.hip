@@ -18,6 +18,7 @@
 // float32 operations in the written order, no contraction (-ffp-contract=off and the
 // pragma below), IEEE division; residuals and ||r||_1 are integer sums.
 #include "kernels.h"
+#include "column_math.h"
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -28,12 +29,7 @@ namespace rl0 {
 
 namespace {
 
-constexpr int kTableN = 4096;
 constexpr int kTableStride = kTableStrideFloats;       // table_e starts 16-byte aligned
-constexpr double kTwo40 = 1099511627776.0;          // 2^40
-constexpr double kTwoM40 = 1.0 / 1099511627776.0;   // 2^-40
-constexpr double kTwo30 = 1073741824.0;             // 2^30
-constexpr double kFxLimit = 4611686018427387904.0;  // 2^62
 constexpr int kSweepBlock = 1024;
 constexpr int kSweepCols = 4;                     // columns per sweep thread per chunk
 constexpr int kSweepChunk = kSweepBlock * kSweepCols;
@@ -44,44 +40,6 @@ constexpr int kSelectBlock = 1024;
 constexpr int kSelectGrid = 64;
 constexpr int kRowBlock = 1024;
 
-__device__ __forceinline__ long long to_fx(float v, int* err) {
-    const double s = static_cast<double>(v) * kTwo40;
-    if (!(fabs(s) < kFxLimit)) {
-        atomicOr(err, kErrRange);
-        return 0;
-    }
-    return __double2ll_rn(s);
-}
-
-__device__ __forceinline__ float from_fx(long long S) {
-    return static_cast<float>(static_cast<double>(S) * kTwoM40);
-}
-
-__device__ __forceinline__ long long l1_term(float r) {
-    return __double2ll_rn(static_cast<double>(fabsf(r)) * kTwo30);
-}
-
-__device__ __forceinline__ uint32_t abs_bits(float v) { return __float_as_uint(v) & 0x7FFFFFFFu; }
-
-__device__ __forceinline__ float table_score(const float* __restrict__ T, float inv_h, float a) {
-    const float u = a * inv_h;
-    if (!(u < static_cast<float>(kTableN))) return 0.0f;
-    const int i = static_cast<int>(u);
-    const float f = u - static_cast<float>(i);
-    const float t0 = T[i];
-    const float t1 = T[i + 1];
-    return t0 + f * (t1 - t0);
-}
-
-__device__ __forceinline__ float score(const float* __restrict__ T, float inv_h, int exact, float a) {
-    if (exact) return a == 0.0f ? 1.0f : 0.0f;
-    return table_score(T, inv_h, a);
-}
-
-__device__ __forceinline__ unsigned long long hk_key(int j, float x) {
-    return (static_cast<unsigned long long>(abs_bits(x)) << 32) |
-           static_cast<unsigned long long>(0xFFFFFFFFu - static_cast<unsigned int>(j));
-}
 
 template <int BLOCK>
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
@@ -302,58 +260,6 @@ struct SweepArgs {
     DebugOut dbg;
 };
 
-// Column body of Alg. 1 on the snapshot r_hat, float32 contract.  cmask marks the rows
-// that pass the outer test; they are visited in ascending row order, so the first row
-// with the strictly largest n_e wins.  Returns whether the column proposes an update
-// and its omega.
-template <int D>
-__device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int cmask,
-                                              const ScoreTables& tb, float alpha, int l1_test,
-                                              float* omega_out) {
-    float n_z = 0.0f;
-    float S1 = 0.0f;
-#pragma unroll
-    for (int p = 0; p < D; ++p) {
-        n_z = n_z + score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v[p]));
-        S1 = S1 + fabsf(v[p]);
-    }
-    bool has = false;
-    float best_ne = 0.0f, best_om = 0.0f;
-    unsigned int rem = cmask;
-    while (rem) {
-        const int p = __builtin_ctz(rem);
-        rem &= rem - 1u;
-        float vp = v[0];
-#pragma unroll
-        for (int q = 1; q < D; ++q)
-            if (p == q) vp = v[q];
-        float n_e = 0.0f, s = 0.0f;
-#pragma unroll
-        for (int l = 0; l < D; ++l) {
-            const float w = (l == p) ? 1.0f : score(tb.Te, tb.inv_h_e, tb.exact, fabsf(vp - v[l]));
-            n_e = n_e + w;
-            s = s + v[l] * w;
-        }
-        const float om = s / n_e;
-        bool l1_ok;
-        if (l1_test == 0) {
-            float Lp = 0.0f;
-#pragma unroll
-            for (int l = 0; l < D; ++l) Lp = Lp + fabsf(v[l] - om);
-            l1_ok = Lp <= S1;
-        } else {
-            l1_ok = fabsf(vp - om) <= fabsf(vp);
-        }
-        const bool pass = ((n_e - n_z) >= alpha) && l1_ok;
-        if (pass && (!has || n_e > best_ne)) {
-            has = true;
-            best_ne = n_e;
-            best_om = om;
-        }
-    }
-    *omega_out = best_om;
-    return has;
-}
 
 // H_k's value of candidate j in an iteration whose k-th key was kth (zero if dropped).
 __device__ __forceinline__ float hk_value(int j, float xp, unsigned long long kth) {
@@ -687,20 +593,6 @@ __device__ __forceinline__ void apply_candidate(const SelectArgs& a, int tr, uns
     }
 }
 
-// hist[bin] += 1 for every lane with valid set; lanes of a wave that hit the same bin
-// add together (the magnitudes of a support cluster in a few bins).  Every lane of the
-// wave must call.
-__device__ __forceinline__ void hist_add(unsigned* hist, unsigned bin, bool valid) {
-    unsigned long long active = __ballot(valid);
-    const int lane = __lane_id();
-    while (active) {
-        const int leader = __ffsll(static_cast<long long>(active)) - 1;
-        const unsigned b = __shfl(bin, leader);
-        const unsigned long long same = __ballot(valid && bin == b);
-        if (lane == leader) atomicAdd(&hist[b], static_cast<unsigned>(__popcll(same)));
-        active &= ~same;
-    }
-}
 
 // Within one workgroup: exclusive prefix sums of one int per segment (threads < nseg
 // hold their value in v) by wave scans; returns the total.  start[] gets the sums.

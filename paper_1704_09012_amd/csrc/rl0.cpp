@@ -13,11 +13,14 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <algorithm>
 #include <tuple>
 #include <vector>
 
 #include "constants.h"
 #include "kernels.h"
+#include "batched.h"
 
 namespace {
 
@@ -81,7 +84,8 @@ void profile_collect(int launched, int executed) {
 
 struct DeviceConstants {
     rl0::HostConstants hc;
-    float* d_tables = nullptr;  // table_z then table_e, kTableN + 1 each
+    float* d_tables = nullptr;        // table_z, table_e (kTableStrideFloats apart), then tau
+    const uint32_t* d_tau = nullptr;  // outer-test threshold bits per iteration
 };
 
 using ConstKey = std::tuple<int, int, int, int, int, uint32_t, uint32_t, double, int, int>;
@@ -91,9 +95,30 @@ uint32_t fbits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 
 // Looks up (or builds and uploads) the constants of a problem; the device copy is
 // written with a blocking copy, so it is ready before any later launch.
+ConstKey key_of(const rl0::Problem& pr, int device) {
+    return ConstKey{device, pr.n, pr.m, pr.d, pr.k, fbits(static_cast<float>(pr.sigma)),
+                    fbits(static_cast<float>(pr.sigma_s)), pr.c, pr.ell, pr.max_iters};
+}
+
+// Device copy of computed constants: both tables and the thresholds in one allocation,
+// written with a blocking copy, so they are ready before any later launch.
+int upload_constants(DeviceConstants* dc) {
+    const size_t tab = 2 * rl0::kTableStrideFloats * sizeof(float);
+    const size_t ntau = dc->hc.tau_bits.size();
+    std::vector<char> staging(tab + sizeof(uint32_t) * (ntau ? ntau : 1), 0);
+    std::memcpy(staging.data(), dc->hc.table_z, (rl0::kTableN + 1) * sizeof(float));
+    std::memcpy(staging.data() + rl0::kTableStrideFloats * sizeof(float), dc->hc.table_e,
+                (rl0::kTableN + 1) * sizeof(float));
+    if (ntau) std::memcpy(staging.data() + tab, dc->hc.tau_bits.data(), ntau * sizeof(uint32_t));
+    if (hipMalloc(&dc->d_tables, staging.size()) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(tables)");
+    HIP_TRY(hipMemcpy(dc->d_tables, staging.data(), staging.size(), hipMemcpyHostToDevice));
+    dc->d_tau = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(dc->d_tables) + tab);
+    return RL0_OK;
+}
+
+// Looks up (or builds and uploads) the constants of a problem.
 int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
-    ConstKey key{device, pr.n, pr.m, pr.d, pr.k, fbits(static_cast<float>(pr.sigma)),
-                 fbits(static_cast<float>(pr.sigma_s)), pr.c, pr.ell, pr.max_iters};
+    const ConstKey key = key_of(pr, device);
     auto it = g_consts.find(key);
     if (it != g_consts.end()) {
         *out = it->second.get();
@@ -101,13 +126,41 @@ int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
     }
     auto dc = std::make_unique<DeviceConstants>();
     rl0::compute_constants(pr, &dc->hc);
-    const size_t bytes = 2 * rl0::kTableStrideFloats * sizeof(float);
-    if (hipMalloc(&dc->d_tables, bytes) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(tables)");
-    HIP_TRY(hipMemcpy(dc->d_tables, dc->hc.table_z, (rl0::kTableN + 1) * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dc->d_tables + rl0::kTableStrideFloats, dc->hc.table_e, (rl0::kTableN + 1) * sizeof(float),
-                      hipMemcpyHostToDevice));
+    if (int rc = upload_constants(dc.get())) return rc;
     *out = dc.get();
     g_consts.emplace(key, std::move(dc));
+    return RL0_OK;
+}
+
+// The same for many problems; the ones not cached yet are computed on host threads.
+int get_constants_many(const std::vector<rl0::Problem>& prs, int device, std::vector<DeviceConstants*>* out) {
+    out->assign(prs.size(), nullptr);
+    std::map<ConstKey, size_t> fresh_of;   // key -> index into fresh
+    std::vector<size_t> fresh_src;          // a problem index per fresh entry
+    for (size_t i = 0; i < prs.size(); ++i) {
+        const ConstKey key = key_of(prs[i], device);
+        auto it = g_consts.find(key);
+        if (it != g_consts.end()) {
+            (*out)[i] = it->second.get();
+        } else if (!fresh_of.count(key)) {
+            fresh_of.emplace(key, fresh_src.size());
+            fresh_src.push_back(i);
+        }
+    }
+    std::vector<std::unique_ptr<DeviceConstants>> fresh(fresh_src.size());
+    for (auto& f : fresh) f = std::make_unique<DeviceConstants>();
+    const size_t nt = std::min<size_t>(fresh.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            for (size_t f = t; f < fresh.size(); f += nt) rl0::compute_constants(prs[fresh_src[f]], &fresh[f]->hc);
+        });
+    for (auto& th : pool) th.join();
+    for (size_t f = 0; f < fresh.size(); ++f)
+        if (int rc = upload_constants(fresh[f].get())) return rc;
+    for (auto& kv : fresh_of) g_consts.emplace(kv.first, std::move(fresh[kv.second]));
+    for (size_t i = 0; i < prs.size(); ++i)
+        if (!(*out)[i]) (*out)[i] = g_consts.at(key_of(prs[i], device)).get();
     return RL0_OK;
 }
 
@@ -294,6 +347,345 @@ rl0::IterParams iter_params(const DeviceConstants* dc, const rl0_params* p, int 
     return ip;
 }
 
+
+// ---------------------------------------------------------------- batched decoding
+
+struct BatchKey {
+    int32_t count, d, block, per_cu, grid;
+    size_t lds;
+    const void* meta;
+};
+
+struct BatchGraph {
+    BatchKey key;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long last_use = 0;
+};
+
+// Working memory of batched decodes on one (device, stream).
+struct BatchBuffers {
+    void* block = nullptr;           // per-instance S, x', stamps, change lists
+    size_t block_bytes = 0;
+    void* meta = nullptr;            // descriptors, order, results, queue counter
+    size_t meta_count = 0;
+    void* host = nullptr;            // pinned staging of descriptors, order and results
+    hipStream_t capture = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<BatchGraph> graphs;
+    unsigned long long uses = 0;
+    rl0::BatchProblem* desc_d() const { return static_cast<rl0::BatchProblem*>(meta); }
+};
+
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<BatchBuffers>> g_bws;
+std::map<int, rl0_batch_schedule> g_sched;
+std::map<int, bool> g_lds_ready;
+
+size_t meta_bytes(size_t count) {
+    return rl0::al_host(count * sizeof(rl0::BatchProblem)) + rl0::al_host(count * sizeof(int)) +
+           rl0::al_host(count * sizeof(rl0::BatchResult)) + 256;
+}
+
+struct MetaView {
+    rl0::BatchProblem* desc;
+    int* order;
+    rl0::BatchResult* res;
+    int* counter;
+};
+
+MetaView meta_view(void* base, size_t count) {
+    char* p = static_cast<char*>(base);
+    MetaView v;
+    v.desc = reinterpret_cast<rl0::BatchProblem*>(p);
+    p += rl0::al_host(count * sizeof(rl0::BatchProblem));
+    v.order = reinterpret_cast<int*>(p);
+    p += rl0::al_host(count * sizeof(int));
+    v.res = reinterpret_cast<rl0::BatchResult*>(p);
+    p += rl0::al_host(count * sizeof(rl0::BatchResult));
+    v.counter = reinterpret_cast<int*>(p);
+    return v;
+}
+
+void drop_batch_graphs(BatchBuffers* b) {
+    for (BatchGraph& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
+int get_batch_buffers(int device, hipStream_t s, size_t block_bytes, size_t count, BatchBuffers** out) {
+    auto& slot = g_bws[{device, s}];
+    if (!slot) slot = std::make_unique<BatchBuffers>();
+    BatchBuffers* b = slot.get();
+    if (b->block_bytes < block_bytes) {
+        HIP_TRY(hipStreamSynchronize(s));
+        if (b->block) HIP_TRY(hipFree(b->block));
+        b->block = nullptr;
+        b->block_bytes = 0;
+        if (hipMalloc(&b->block, block_bytes) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(batch workspace)");
+        b->block_bytes = block_bytes;
+    }
+    if (b->meta_count < count) {
+        HIP_TRY(hipStreamSynchronize(s));
+        drop_batch_graphs(b);   // they point into the old block
+        if (b->meta) HIP_TRY(hipFree(b->meta));
+        if (b->host) HIP_TRY(hipHostFree(b->host));
+        b->meta = nullptr;
+        b->host = nullptr;
+        b->meta_count = 0;
+        if (hipMalloc(&b->meta, meta_bytes(count)) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(batch meta)");
+        if (hipHostMalloc(&b->host, meta_bytes(count), hipHostMallocDefault) != hipSuccess)
+            return fail(RL0_ENOMEM, "hipHostMalloc(batch meta)");
+        b->meta_count = count;
+    }
+    if (!b->ev[0]) {
+        HIP_TRY(hipEventCreate(&b->ev[0]));
+        HIP_TRY(hipEventCreate(&b->ev[1]));
+    }
+    *out = b;
+    return RL0_OK;
+}
+
+int size_class(int n) {
+    int c = 0;
+    while (c < RL0_SIZE_CLASSES - 1 && n >= (1 << (11 + c))) ++c;
+    return c;
+}
+
+rl0_batch_schedule default_schedule() {
+    rl0_batch_schedule s;
+    s.block = 256;
+    s.per_cu = 3;
+    for (int c = 0; c < RL0_SIZE_CLASSES; ++c) s.cols[c] = 4;
+    return s;
+}
+
+int check_schedule(const rl0_batch_schedule& s) {
+    if (s.block != 256 && s.block != 512 && s.block != 1024) return fail(RL0_EINVAL, "schedule: block must be 256, 512 or 1024");
+    if (s.per_cu < 1 || s.per_cu > 8) return fail(RL0_EINVAL, "schedule: per_cu must be in [1, 8]");
+    for (int c = 0; c < RL0_SIZE_CLASSES; ++c)
+        if (s.cols[c] != 1 && s.cols[c] != 2 && s.cols[c] != 4) return fail(RL0_EINVAL, "schedule: cols must be 1, 2 or 4");
+    return RL0_OK;
+}
+
+rl0_batch_schedule& schedule_of(int device) {
+    auto it = g_sched.find(device);
+    if (it == g_sched.end()) it = g_sched.emplace(device, default_schedule()).first;
+    return it->second;
+}
+
+// A batch checked, with its constants and working memory, ready to launch.
+struct BatchPlan {
+    int device = 0, count = 0, d = 0, max_m = 0;
+    bool uniform_d = true;
+    BatchBuffers* b = nullptr;
+    std::vector<DeviceConstants*> dc;
+    std::vector<size_t> offs;      // per instance: byte offset of its working memory
+    std::vector<int> order;        // largest first
+};
+
+int plan_batch(const rl0_problem* probs, int count, hipStream_t s, BatchPlan* plan) {
+    if (count < 0) return fail(RL0_EINVAL, "count must be >= 0");
+    if (count > 0 && !probs) return fail(RL0_EINVAL, "probs_h is NULL");
+    std::vector<rl0::Problem> prs(count);
+    for (int i = 0; i < count; ++i) {
+        const rl0_problem& q = probs[i];
+        auto bad = [&](int rc) { return fail(rc, "instance " + std::to_string(i) + ": " + g_last_error); };
+        if (int rc = check_params(&q.params, q.n, q.m, q.d)) return bad(rc);
+        if (!q.A_cols || !q.y || !q.x_out) return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": NULL pointer");
+        if (reinterpret_cast<uintptr_t>(q.A_cols) % 16)
+            return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": A_cols must be 16-byte aligned");
+        if (q.m > rl0::kBatchMaxRows)
+            return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": m exceeds RL0_BATCH_MAX_M");
+        prs[i] = problem_of(&q.params, q.n, q.m, q.d);
+    }
+    plan->count = count;
+    if (count == 0) return RL0_OK;
+    HIP_TRY(hipGetDevice(&plan->device));
+    if (int rc = get_constants_many(prs, plan->device, &plan->dc)) return rc;
+    plan->offs.resize(count);
+    size_t total = 0;
+    plan->d = probs[0].d;
+    for (int i = 0; i < count; ++i) {
+        plan->offs[i] = total;
+        total += rl0::al_host(8ull * probs[i].m) + 3 * rl0::al_host(4ull * probs[i].n) + rl0::al_host(8ull * probs[i].n);
+        plan->max_m = std::max(plan->max_m, probs[i].m);
+        plan->uniform_d = plan->uniform_d && probs[i].d == plan->d;
+    }
+    plan->order.resize(count);
+    for (int i = 0; i < count; ++i) plan->order[i] = i;
+    // grouped by d (one launch each), largest first within a group
+    std::stable_sort(plan->order.begin(), plan->order.end(), [&](int a, int c) {
+        if (probs[a].d != probs[c].d) return probs[a].d < probs[c].d;
+        return static_cast<long long>(probs[a].n) * probs[a].d > static_cast<long long>(probs[c].n) * probs[c].d;
+    });
+    if (!g_lds_ready[plan->device]) {
+        HIP_TRY(rl0::batched_set_lds_limits());
+        g_lds_ready[plan->device] = true;
+    }
+    return get_batch_buffers(plan->device, s, total, count, &plan->b);
+}
+
+// Descriptors (with the schedule's columns per tile) and order to the device.
+int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_schedule& sc, hipStream_t s) {
+    const MetaView h = meta_view(P.b->host, P.count);
+    char* ws = static_cast<char*>(P.b->block);
+    for (int i = 0; i < P.count; ++i) {
+        const rl0_problem& q = probs[i];
+        const DeviceConstants* dc = P.dc[i];
+        rl0::BatchProblem& B = h.desc[i];
+        std::memset(&B, 0, sizeof(B));
+        char* w = ws + P.offs[i];
+        B.A = q.A_cols;
+        B.y = q.y;
+        B.x = q.x_out;
+        B.S = reinterpret_cast<long long*>(w);
+        w += rl0::al_host(8ull * q.m);
+        B.xp = reinterpret_cast<float*>(w);
+        w += rl0::al_host(4ull * q.n);
+        B.stamp = reinterpret_cast<int*>(w);
+        w += rl0::al_host(4ull * q.n);
+        B.chg = reinterpret_cast<int*>(w);
+        w += rl0::al_host(4ull * q.n);
+        B.keys = reinterpret_cast<unsigned long long*>(w);
+        B.Tz = dc->d_tables;
+        B.Te = dc->d_tables + rl0::kTableStrideFloats;
+        B.tau = dc->d_tau;
+        B.tol_fx = dc->hc.tol * 1073741824.0;
+        B.n = q.n;
+        B.m = q.m;
+        B.d = q.d;
+        B.k = q.params.k;
+        B.alpha = q.params.alpha;
+        B.inv_h_z = dc->hc.inv_h_z;
+        B.inv_h_e = dc->hc.inv_h_e;
+        B.exact = dc->hc.exact ? 1 : 0;
+        B.l1_test = q.params.l1_test;
+        B.validate = q.params.validate;
+        B.n_iters = dc->hc.n_iters;
+        B.cols = sc.cols[size_class(q.n)];
+    }
+    std::memcpy(h.order, P.order.data(), sizeof(int) * P.count);
+    const MetaView dv = meta_view(P.b->meta, P.count);
+    HIP_TRY(hipMemcpyAsync(dv.desc, h.desc, sizeof(rl0::BatchProblem) * P.count, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dv.order, h.order, sizeof(int) * P.count, hipMemcpyHostToDevice, s));
+    return RL0_OK;
+}
+
+int batch_grid(const BatchPlan& P, const rl0_batch_schedule& sc, int count) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, P.device) != hipSuccess) return std::min(count, 256 * sc.per_cu);
+    return std::max(1, std::min(count, prop.multiProcessorCount * sc.per_cu));
+}
+
+size_t batch_lds(const BatchPlan& P) {
+    // rounded up so that batches of similar sizes share a captured graph
+    const int m = ((P.max_m + 32767) / 32768) * 32768;
+    return rl0::batched_lds_bytes(std::min(m, rl0::kBatchMaxRows));
+}
+
+// Every launch of the plan (one per distinct d, in order), optionally timed.
+int issue_batch(const BatchPlan& P, const rl0_batch_schedule& sc, const rl0_problem* probs, hipStream_t q,
+                bool timed) {
+    const MetaView dv = meta_view(P.b->meta, P.count);
+    const rl0::BatchLaunch L{sc.block, sc.per_cu};
+    const size_t lds = batch_lds(P);
+    int start = 0;
+    bool first = true;
+    while (start < P.count) {
+        const int d = probs[P.order[start]].d;
+        int end = start;
+        while (end < P.count && probs[P.order[end]].d == d) ++end;
+        const int cnt = end - start;
+        const bool last = end == P.count;
+        HIP_TRY(rl0::launch_batched(d, L, batch_grid(P, sc, cnt), lds, dv.desc, dv.order + start, cnt, dv.res,
+                                    dv.counter, q, timed && first ? P.b->ev[0] : nullptr,
+                                    timed && last ? P.b->ev[1] : nullptr));
+        first = false;
+        start = end;
+    }
+    return RL0_OK;
+}
+
+int run_batch(const BatchPlan& P, const rl0_batch_schedule& sc, const rl0_problem* probs, hipStream_t s,
+              bool timed) {
+    if (timed || !P.uniform_d || !graphs_enabled()) return issue_batch(P, sc, probs, s, timed);
+    BatchKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.count = P.count;
+    key.d = P.d;
+    key.block = sc.block;
+    key.per_cu = sc.per_cu;
+    key.grid = batch_grid(P, sc, P.count);
+    key.lds = batch_lds(P);
+    key.meta = P.b->meta;
+    BatchBuffers* b = P.b;
+    BatchGraph* hit = nullptr;
+    for (BatchGraph& g : b->graphs)
+        if (std::memcmp(&g.key, &key, sizeof(key)) == 0) hit = &g;
+    if (!hit) {
+        if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
+        const int rc = issue_batch(P, sc, probs, b->capture, false);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->capture, &graph);
+        if (rc != RL0_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(RL0_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(RL0_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        if (b->graphs.size() >= kMaxGraphs) {
+            size_t lru = 0;
+            for (size_t i = 1; i < b->graphs.size(); ++i)
+                if (b->graphs[i].last_use < b->graphs[lru].last_use) lru = i;
+            (void)hipGraphExecDestroy(b->graphs[lru].exec);
+            b->graphs.erase(b->graphs.begin() + static_cast<std::ptrdiff_t>(lru));
+        }
+        BatchGraph g;
+        g.key = key;
+        g.exec = exec;
+        b->graphs.push_back(g);
+        hit = &b->graphs.back();
+    }
+    hit->last_use = ++b->uses;
+    HIP_TRY(hipGraphLaunch(hit->exec, s));
+    return RL0_OK;
+}
+
+// Results to the host (synchronising the stream) and into the stats; the first failed
+// instance's code is returned.
+int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, hipStream_t s) {
+    const MetaView h = meta_view(P.b->host, P.count);
+    const MetaView dv = meta_view(P.b->meta, P.count);
+    HIP_TRY(hipMemcpyAsync(h.res, dv.res, sizeof(rl0::BatchResult) * P.count, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int first_rc = RL0_OK;
+    std::string first_msg;
+    for (int i = 0; i < P.count; ++i) {
+        const rl0::BatchResult& R = h.res[i];
+        const DeviceConstants* dc = P.dc[i];
+        if (st) {
+            rl0_stats& o = st[i];
+            o.iterations = R.iterations;
+            o.accepted = R.accepted;
+            o.l1_final_fx = R.L_hat;
+            o.l1_final = static_cast<double>(R.L_hat) / 1073741824.0;
+            o.l1_tol = dc->hc.tol;
+            o.converged = (static_cast<double>(R.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
+            o.updates_total = R.updates_total;
+            o.t_final = R.iterations > 0 ? dc->hc.t[R.iterations - 1] : 1.0f;
+            o.error_flags = R.err;
+        }
+        if (R.err && first_rc == RL0_OK) {
+            first_rc = err_code_of(R.err);
+            first_msg = "instance " + std::to_string(i) + ": " + g_last_error;
+        }
+    }
+    (void)probs;
+    if (first_rc != RL0_OK) return fail(first_rc, first_msg);
+    return RL0_OK;
+}
 
 }  // namespace
 
@@ -482,6 +874,110 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
     return RL0_OK;
 }
 
+int rl0_decode_batched(const rl0_problem* probs_h, int32_t count, rl0_stats* st_h, void* stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchPlan plan;
+    if (int rc = plan_batch(probs_h, count, s, &plan)) return rc;
+    if (count == 0) return RL0_OK;
+    const rl0_batch_schedule sc = schedule_of(plan.device);
+    if (int rc = upload_batch(probs_h, plan, sc, s)) return rc;
+    if (int rc = run_batch(plan, sc, probs_h, s, false)) return rc;
+    return collect_batch(probs_h, plan, st_h, s);
+}
+
+int rl0_batch_schedule_get(rl0_batch_schedule* out_h) {
+    if (!out_h) return fail(RL0_EINVAL, "out_h is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    *out_h = schedule_of(dev);
+    return RL0_OK;
+}
+
+int rl0_batch_schedule_set(const rl0_batch_schedule* s_h) {
+    if (!s_h) return fail(RL0_EINVAL, "s_h is NULL");
+    if (int rc = check_schedule(*s_h)) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    schedule_of(dev) = *s_h;
+    return RL0_OK;
+}
+
+int rl0_autotune_batched(const rl0_problem* probs_h, int32_t count, int32_t reps, rl0_batch_schedule* best_h,
+                         double* ms_h, void* stream) {
+    if (reps < 1) return fail(RL0_EINVAL, "reps must be >= 1");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchPlan plan;
+    if (int rc = plan_batch(probs_h, count, s, &plan)) return rc;
+    if (count == 0) return fail(RL0_EINVAL, "nothing to tune on: count is 0");
+    // median time of the persistent launches under a schedule
+    auto time_of = [&](const rl0_batch_schedule& sc, double* ms) -> int {
+        if (int rc = upload_batch(probs_h, plan, sc, s)) return rc;
+        std::vector<double> t;
+        for (int r = 0; r < reps; ++r) {
+            if (int rc = run_batch(plan, sc, probs_h, s, true)) return rc;
+            HIP_TRY(hipStreamSynchronize(s));
+            float e = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&e, plan.b->ev[0], plan.b->ev[1]));
+            t.push_back(e);
+        }
+        std::sort(t.begin(), t.end());
+        *ms = t[t.size() / 2];
+        return RL0_OK;
+    };
+    rl0_batch_schedule best = schedule_of(plan.device);
+    double best_ms = 0.0;
+    if (int rc = time_of(best, &best_ms)) return rc;
+    // 1. launch shape, over the shapes the device can hold
+    const size_t lds = batch_lds(plan);
+    for (int block : {256, 512, 1024}) {
+        const int fit = rl0::batched_max_resident(plan.d, block, lds);
+        for (int per_cu : {1, 2, 3, 4, 6, 8}) {
+            if (per_cu > fit) continue;
+            rl0_batch_schedule c = best;
+            c.block = block;
+            c.per_cu = per_cu;
+            if (c.block == best.block && c.per_cu == best.per_cu) continue;
+            double ms = 0.0;
+            if (int rc = time_of(c, &ms)) return rc;
+            if (ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+    }
+    // 2. columns per tile, size class by size class, the classes with most columns first
+    std::vector<long long> cls_cols(RL0_SIZE_CLASSES, 0);
+    for (int i = 0; i < count; ++i) cls_cols[size_class(probs_h[i].n)] += probs_h[i].n;
+    std::vector<int> cls;
+    for (int c = 0; c < RL0_SIZE_CLASSES; ++c)
+        if (cls_cols[c] > 0) cls.push_back(c);
+    std::stable_sort(cls.begin(), cls.end(), [&](int a, int b) { return cls_cols[a] > cls_cols[b]; });
+    for (int c : cls) {
+        for (int cols : {1, 2, 4}) {
+            if (cols == best.cols[c]) continue;
+            rl0_batch_schedule cand = best;
+            cand.cols[c] = cols;
+            double ms = 0.0;
+            if (int rc = time_of(cand, &ms)) return rc;
+            if (ms < best_ms) {
+                best = cand;
+                best_ms = ms;
+            }
+        }
+    }
+    schedule_of(plan.device) = best;
+    if (best_h) *best_h = best;
+    if (ms_h) *ms_h = best_ms;
+    // leave every x_out holding the decode under the installed schedule
+    if (int rc = upload_batch(probs_h, plan, best, s)) return rc;
+    if (int rc = run_batch(plan, best, probs_h, s, false)) return rc;
+    return collect_batch(probs_h, plan, nullptr, s);
+}
+
 int rl0_profile_enable(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof.enabled = enable != 0;
@@ -519,6 +1015,17 @@ void rl0_release(void) {
         if (kv.second->st_host) hipHostFree(kv.second->st_host);
     }
     g_ws.clear();
+    for (auto& kv : g_bws) {
+        BatchBuffers* b = kv.second.get();
+        drop_batch_graphs(b);
+        if (b->capture) hipStreamDestroy(b->capture);
+        for (hipEvent_t e : b->ev)
+            if (e) hipEventDestroy(e);
+        if (b->block) hipFree(b->block);
+        if (b->meta) hipFree(b->meta);
+        if (b->host) hipHostFree(b->host);
+    }
+    g_bws.clear();
     for (auto& kv : g_consts)
         if (kv.second->d_tables) hipFree(kv.second->d_tables);
     g_consts.clear();

@@ -25,6 +25,8 @@ import numpy as np
 
 __all__ = [
     "Instance",
+    "draw_batch_shapes",
+    "draw_batch",
     "sigma_for_snr",
     "draw_columns",
     "draw_signal",
@@ -125,3 +127,27 @@ def draw_instance(n: int, m: int, k: int, d: int, sigma: float, seed: int,
     eta = draw_noise(rng, m, sigma)
     return Instance(n=n, m=m, k=k, d=d, sigma=float(sigma), sigma_s=float(sigma_s),
                     A_cols=A_cols, support=support, values=values, eta=eta)
+
+
+def draw_batch_shapes(count: int, seed: int, d: int = 7, log2_n=(12, 18), delta=(0.05, 0.5),
+                      rho=(0.05, 0.3), snr_db=(20.0, 60.0)) -> list[tuple[int, int, int, float]]:
+    """Shapes of a batch of uneven instances: n log-uniform in [2^a, 2^b], m = n * U(delta),
+    k = m * U(rho) (at least 1), SNR uniform; returns (n, m, k, snr_db) per instance."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        n = int(round(2.0 ** rng.uniform(*log2_n)))
+        m = max(d + 1, int(round(n * rng.uniform(*delta))))
+        k = min(m - 1, max(1, int(round(m * rng.uniform(*rho)))))
+        out.append((n, m, k, float(rng.uniform(*snr_db))))
+    return out
+
+
+def draw_batch(count: int, seed: int, d: int = 7, **shape_kw) -> list[Instance]:
+    """A batch of instances with the shapes of draw_batch_shapes, each drawn from its own
+    seed (seed * 100000 + i) with sigma_n from its SNR."""
+    out = []
+    for i, (n, m, k, snr) in enumerate(draw_batch_shapes(count, seed, d, **shape_kw)):
+        sig = float(np.float32(sigma_for_snr(snr, n, m, k, d)))
+        out.append(draw_instance(n, m, k, d, sig, seed * 100000 + i))
+    return out

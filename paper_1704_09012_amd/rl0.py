@@ -76,6 +76,42 @@ class Constants(ctypes.Structure):
     ]
 
 
+RL0_SIZE_CLASSES = 12
+RL0_BATCH_MAX_M = 524288
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("A_cols", ctypes.c_void_p),
+        ("n", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("y", ctypes.c_void_p),
+        ("params", Params),
+        ("x_out", ctypes.c_void_p),
+    ]
+
+
+class BatchSchedule(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32),
+        ("per_cu", ctypes.c_int32),
+        ("cols", ctypes.c_int32 * RL0_SIZE_CLASSES),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"block": self.block, "per_cu": self.per_cu, "cols": list(self.cols)}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "BatchSchedule":
+        s = cls()
+        s.block = d["block"]
+        s.per_cu = d["per_cu"]
+        for i, c in enumerate(d["cols"]):
+            s.cols[i] = c
+        return s
+
+
 class Rl0Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -103,10 +139,16 @@ def lib() -> ctypes.CDLL:
         L.rl0_profile_enable.argtypes = [I32]
         L.rl0_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+        L.rl0_decode_batched.argtypes = [ctypes.POINTER(Problem), I32, ctypes.POINTER(Stats), V]
+        L.rl0_batch_schedule_get.argtypes = [ctypes.POINTER(BatchSchedule)]
+        L.rl0_batch_schedule_set.argtypes = [ctypes.POINTER(BatchSchedule)]
+        L.rl0_autotune_batched.argtypes = [ctypes.POINTER(Problem), I32, I32, ctypes.POINTER(BatchSchedule),
+                                           ctypes.POINTER(ctypes.c_double), V]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
-                     "rl0_decode", "rl0_step"):
+                     "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get",
+                     "rl0_batch_schedule_set", "rl0_autotune_batched"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -272,3 +314,61 @@ def profile_read_kernels() -> dict:
 
 def release() -> None:
     lib().rl0_release()
+
+
+# ---------------------------------------------------------------- batched decoding
+
+def _problems(problems):
+    """Marshal a list of dicts {A, y, out, params} (or {A, y, out, sigma, k, **overrides})
+    into an rl0_problem array; returns (array, kept tensors)."""
+    torch = _torch()
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, pr in enumerate(problems):
+        A, y = pr["A"], pr["y"]
+        n, d = A.shape
+        m = y.shape[0]
+        out = pr.get("out")
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=y.device)
+            pr["out"] = out
+        params = pr.get("params")
+        if params is None:
+            extra = {k: v for k, v in pr.items() if k not in ("A", "y", "out", "params", "sigma", "k")}
+            params = params_default(n, m, d, pr["k"], pr["sigma"], **extra)
+        arr[i].A_cols = _dev_ptr(A, torch.int32, (n, d), f"problems[{i}].A").value
+        arr[i].n, arr[i].m, arr[i].d = n, m, d
+        arr[i].y = _dev_ptr(y, torch.float32, (m,), f"problems[{i}].y").value
+        arr[i].params = params
+        arr[i].x_out = _dev_ptr(out, torch.float32, (n,), f"problems[{i}].out").value
+        keep.append((A, y, out))
+    return arr, keep
+
+
+def decode_batched(problems) -> list:
+    """rl0_decode_batched over a list of problem dicts; each dict's "out" (created if
+    absent) receives x_hat.  Returns the per-instance stats dicts."""
+    arr, _keep = _problems(problems)
+    st = (Stats * max(len(problems), 1))()
+    _check(lib().rl0_decode_batched(arr, len(problems), st, _stream()))
+    return [st[i].as_dict() for i in range(len(problems))]
+
+
+def batch_schedule_get() -> dict:
+    s = BatchSchedule()
+    _check(lib().rl0_batch_schedule_get(ctypes.byref(s)))
+    return s.as_dict()
+
+
+def batch_schedule_set(sched: dict) -> None:
+    s = BatchSchedule.from_dict(sched)
+    _check(lib().rl0_batch_schedule_set(ctypes.byref(s)))
+
+
+def autotune_batched(problems, reps: int = 3) -> tuple[dict, float]:
+    """rl0_autotune_batched: installs and returns (best schedule, its median ms)."""
+    arr, _keep = _problems(problems)
+    best = BatchSchedule()
+    ms = ctypes.c_double(0.0)
+    _check(lib().rl0_autotune_batched(arr, len(problems), reps, ctypes.byref(best), ctypes.byref(ms), _stream()))
+    return best.as_dict(), ms.value

@@ -1,6 +1,7 @@
 """The C-ABI library on the CPU: it loads, exports every declared symbol, rejects bad
 arguments before touching a device, and computes its host constants (score tables,
 t-sweep, outer-test thresholds) exactly as the oracle does.  No device work."""
+import ctypes
 import os
 import re
 
@@ -117,3 +118,43 @@ def test_exact_mode_constants():
     hc = R.compute_constants(p, 1024, 256, 7)
     assert hc.exact and hc.tol == 0.0
     assert np.all(hc.tau == np.float32(1e-45))
+
+
+# ---------------------------------------------------------------- batched: host checks
+
+def _fake_problem(n=1000, m=200, d=7, k=10, sigma=0.01, align=0):
+    p = R.Problem()
+    p.A_cols = 4096 + align
+    p.n, p.m, p.d = n, m, d
+    p.y = 8192
+    p.x_out = 16384
+    R.lib().rl0_params_default(ctypes.byref(p.params), n, m, d, k, ctypes.c_float(sigma))
+    return p
+
+
+def test_batched_rejects_bad_instances_before_device_work():
+    L = R.lib()
+    arr = (R.Problem * 3)(_fake_problem(), _fake_problem(), _fake_problem())
+    assert L.rl0_decode_batched(arr, -1, None, None) == -1
+    assert L.rl0_decode_batched(arr, 0, None, None) == 0
+    arr[1].params.alpha = 9.0
+    assert L.rl0_decode_batched(arr, 3, None, None) == -1
+    assert b"instance 1" in L.rl0_last_error()
+    arr[1] = _fake_problem(align=4)
+    assert L.rl0_decode_batched(arr, 3, None, None) == -1
+    assert b"aligned" in L.rl0_last_error()
+    arr[1] = _fake_problem(m=R.RL0_BATCH_MAX_M + 1, n=R.RL0_BATCH_MAX_M * 2)
+    assert L.rl0_decode_batched(arr, 3, None, None) == -1
+    assert b"RL0_BATCH_MAX_M" in L.rl0_last_error()
+    arr[2].y = 0
+    arr[1] = _fake_problem()
+    assert L.rl0_decode_batched(arr, 3, None, None) == -1
+    assert b"instance 2" in L.rl0_last_error()
+
+
+def test_batch_schedule_rejects_bad_fields():
+    L = R.lib()
+    for bad in ({"block": 128, "per_cu": 1, "cols": [4] * 12}, {"block": 256, "per_cu": 0, "cols": [4] * 12},
+                {"block": 256, "per_cu": 9, "cols": [4] * 12}, {"block": 256, "per_cu": 1, "cols": [3] * 12}):
+        s = R.BatchSchedule.from_dict(bad)
+        assert L.rl0_batch_schedule_set(ctypes.byref(s)) == -1
