@@ -59,7 +59,8 @@ typedef struct rl0_params {
     int32_t l1_test;        /* 0 = column reading sum_{N(j)}|r-omega| <= sum_{N(j)}|r|,
                                1 = literal |r_i - omega| <= |r_i| */
     int32_t posterior;      /* 0 = analytic scores, 1 = learned network (mlp != NULL) */
-    const void* mlp;        /* device pointer to packed network weights (posterior = 1) */
+    const void* mlp;        /* device pointer to the network's fp32 parameters
+                               (posterior = 1; see rl0_mlp_num_params) */
     int32_t validate;       /* 1 = check A_cols on the device before decoding */
 } rl0_params;
 
@@ -189,6 +190,65 @@ int rl0_batch_schedule_set(const rl0_batch_schedule* s_h);
  * buffers hold valid decodes afterwards. */
 int rl0_autotune_batched(const rl0_problem* probs_h, int32_t count, int32_t reps,
                          rl0_batch_schedule* best_h, double* ms_h, void* stream);
+
+/* ---------------------------------------------------------------- learned decision
+ *
+ * Not in the paper: a network of a column's residual neighbourhood takes the place of
+ * the analytic column test of Alg. 1 (the scores built from eq:pz_approx/eq:pe_approx);
+ * H_k, the residual and the acceptance test are unchanged.  Features of column j: its d
+ * residual entries sorted ascending, then sigma_n.  Network: d+1 -> 64 (GELU) -> 64
+ * (GELU) -> 2 = (logit, value), GELU in its exact erf form.  Column j updates, by
+ * x'_j = x_hat_j + value, iff logit >= log(t / (1 - t)).  Parameters: one fp32 device
+ * vector of rl0_mlp_num_params(d) values, W1 [64][d+1], b1 [64], W2 [64][64], b2 [64],
+ * W3 [2][64], b3 [2], owned by the caller.
+ *
+ * rl0_decode with params.posterior = 1 and params.mlp = that vector (d <= 15) runs, at
+ * every t of the schedule, an iteration with the learned decision and, when it is not
+ * accepted, one with the analytic decision at the same t (stats.iterations counts both);
+ * inference runs on the matrix cores with bf16 operands and fp32 accumulation.
+ * rl0_step with posterior = 1 runs one learned iteration. */
+
+int32_t rl0_mlp_num_params(int32_t d);
+
+/* w [rl0_mlp_num_params(d)] (device) <- weights uniform in +-sqrt(3 / fan_in), zero
+ * biases, from a SplitMix64 stream seeded with `seed`.  Synchronises the stream. */
+int rl0_mlp_init(float* w, int32_t d, uint64_t seed, void* stream);
+
+/* feats [n][d+1] (device) <- the features of every column on the residual r [m]. */
+int rl0_mlp_features(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* r, float sigma,
+                     float* feats, void* stream);
+
+/* Training targets for iterate x_hat of a signal x_true (both [n], device): labels
+ * [n][2] <- (1 if x_true_j != 0 and |x_true_j - x_hat_j| > 3 sigma / sqrt(d) else 0,
+ * x_true_j - x_hat_j). */
+int rl0_mlp_labels(const float* x_true, const float* x_hat, int32_t n, int32_t d, float sigma, float* labels,
+                   void* stream);
+
+/* Loss over N samples (feats [N][d+1], labels [N][2]): the mean of
+ * BCE(logit, y_acc) + lam * y_acc * (value - y_val)^2.  grad [P] (device) <- its
+ * gradient at w (fp32 backpropagation); *loss_h <- the loss.  Synchronises. */
+int rl0_mlp_grad(const float* feats, const float* labels, int32_t N, int32_t d, const float* w, float lam,
+                 float* grad, float* loss_h, void* stream);
+
+typedef struct rl0_train_cfg {
+    float lr, beta1, beta2, eps;  /* Adam (defaults 1e-3, 0.9, 0.999, 1e-8) */
+    float lam;                    /* weight of the value loss (default 1) */
+    int32_t batch;                /* samples per step (default 4096) */
+    int32_t steps;                /* Adam steps of this call */
+    int32_t t0;                   /* steps already taken (Adam's bias correction; batch order) */
+} rl0_train_cfg;
+
+/* `steps` Adam steps on (feats, labels) [N] (device, already shuffled): step i takes the
+ * (t0 + i) mod floor(N / batch)-th block of `batch` samples.  w, adam_m, adam_v [P]
+ * (device) are updated in place (zero m and v before the first call).  *loss_h (may be
+ * NULL) <- the mean loss of the last min(steps, 50) steps.  Synchronises. */
+int rl0_mlp_train(const float* feats, const float* labels, int64_t N, int32_t d, float* w, float* adam_m,
+                  float* adam_v, const rl0_train_cfg* cfg, float* loss_h, void* stream);
+
+/* out [N][2] (device) <- (logit, value) of the N samples: fp32 (bf16 = 0) or on the
+ * matrix cores as the decoder runs it (bf16 = 1, d <= 15). */
+int rl0_mlp_forward(const float* feats, int32_t N, int32_t d, const float* w, float* out, int32_t bf16,
+                    void* stream);
 
 /* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of
  * replaying its captured graph), each loop kernel with a pair of HIP events that take

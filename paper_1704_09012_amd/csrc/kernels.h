@@ -79,6 +79,7 @@ struct Workspace {
     int* cand_j[2];       // candidate list per iteration parity, one segment per sweep
     float* cand_x[2];     //   workgroup of seg_cap entries: column j, x'_j and
     float* cand_h[2];     //   x_hat_j (0 if j was not in the support)
+    float* learned;       // [n] learned decisions of the current iteration (NaN: none)
     int seg_cap;          // entries per segment
     int sweep_grid;       // sweep workgroups (= segments)
     DevState* st;
@@ -106,10 +107,12 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0,
                           hipStream_t s);
 // One loop iteration (sweep, H_k and residual, finish).  ev (optional, 6 events) gets
-// the start and end of the sweep, select and row dispatches, in that order.
+// the start and end of the sweep, select and row dispatches, in that order.  With
+// `learned` (per column: the update, NaN for none) the sweep takes those decisions in
+// place of the analytic column test.
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
-                            hipStream_t s, const hipEvent_t* ev = nullptr);
+                            hipStream_t s, const hipEvent_t* ev = nullptr, const float* learned = nullptr);
 // Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat (the run
 // started at iteration it0).
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,

@@ -258,6 +258,7 @@ struct SweepArgs {
     ScoreTables tb;
     IterParams ip;
     DebugOut dbg;
+    const float* learned;   // learned decisions per column (NaN: no update), or nullptr
 };
 
 
@@ -455,9 +456,37 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             if (v != 0.0f && j >= cbase && j < cbase + kSweepChunk) supv[j - cbase] = v;
         }
         __syncthreads();
-        // outer test of every row of my columns: one bit each from the bitmask
         const float4 sv4 = reinterpret_cast<const float4*>(supv)[tid];
         const float svq[kSweepCols] = {sv4.x, sv4.y, sv4.z, sv4.w};
+        if (a.learned) {
+            // the learned decision replaces the column test: x'_j = x_hat_j + value
+#pragma unroll
+            for (int q = 0; q < kSweepCols; ++q) {
+                const int j = jb + q;
+                if (j >= a.n) continue;
+                const float lv = a.learned[j];
+                const bool upd = lv == lv;
+                if (a.dbg.updated) a.dbg.updated[j] = upd ? 1 : 0;
+                if (a.dbg.omega) a.dbg.omega[j] = upd ? lv : 0.0f;
+                if (upd) {
+                    atomicAdd(&seg_upd, 1);
+                    const float xp = svq[q] + lv;
+                    const int o = atomicAdd(&seg_f, 1);
+                    out_j[o] = j;
+                    out_x[o] = xp;
+                    out_h[o] = svq[q];
+                    if (xp != 0.0f) atomicAdd(&seg_z, 1);
+                } else if (svq[q] != 0.0f) {
+                    const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                    out_j[o] = j;
+                    out_x[o] = svq[q];
+                    out_h[o] = svq[q];
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        // outer test of every row of my columns: one bit each from the bitmask
 #pragma unroll
         for (int q = 0; q < kSweepCols; ++q) {
             const int j = jb + q;
@@ -926,7 +955,8 @@ size_t workspace_bytes(int n, int m) {
     const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
     (void)wn;
-    return 3 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(sizeof(DevState));
+    return 3 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(4ull * n) +
+           al(sizeof(DevState));
 }
 
 void carve_workspace(void* base, int n, int m, Workspace* w) {
@@ -946,6 +976,7 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     }
     w->seg_cap = seg_capacity(n);
     w->sweep_grid = sweep_grid(n);
+    w->learned = reinterpret_cast<float*>(take(4ull * n));
     w->st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
 }
 
@@ -1000,7 +1031,7 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
 
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
-                            hipStream_t s, const hipEvent_t* ev) {
+                            hipStream_t s, const hipEvent_t* ev, const float* learned) {
     SweepArgs a;
     a.A = A;
     a.n = dm.n;
@@ -1011,6 +1042,7 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     a.tb = tb;
     a.ip = ip;
     a.dbg = dbg;
+    a.learned = learned;
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
     const SelectArgs sa{A, dm.d, dm.k, w, ip.it};

@@ -1,0 +1,46 @@
+// The learned column decision: a 2-hidden-layer network of a column's residual
+// neighbourhood, its training kernels (fp32 forward, backward, Adam) and its inference
+// on the matrix cores (bf16 operands, fp32 accumulation).
+//
+// Parameters: one flat fp32 vector, W1 [64][d+1], b1 [64], W2 [64][64], b2 [64],
+// W3 [2][64], b3 [2].  Features of column j: its d residual entries sorted ascending,
+// then sigma_n.  Output: (logit, value); the column updates iff logit >= log(t/(1-t)),
+// by x'_j = x_hat_j + value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rl0 {
+
+constexpr int kHidden = 64;
+constexpr int kMlpMaxFeatures = 16;   // d + 1 for the matrix-core inference (d <= 15)
+
+inline int mlp_params(int d) {
+    const int f = d + 1;
+    return kHidden * f + kHidden + kHidden * kHidden + kHidden + 2 * kHidden + 2;
+}
+
+// feats [n][d+1]: sorted residual entries of each column's rows, then sigma.
+hipError_t launch_mlp_features(const int32_t* A, int n, int d, const float* r, float sigma, float* feats,
+                               hipStream_t s);
+// labels [n][2]: (1 if x_true_j != 0 and |x_true_j - x_hat_j| > thr else 0, x_true_j - x_hat_j).
+hipError_t launch_mlp_labels(const float* x_true, const float* x_hat, int n, double thr, float* labels,
+                             hipStream_t s);
+// grad [P] = d(mean loss)/dw over the N samples, loss[0] = the mean loss (both
+// accumulated into zeroed buffers by this call).
+hipError_t launch_mlp_grad(const float* feats, const float* labels, int N, int d, const float* w, float lam,
+                           float* grad, float* loss, hipStream_t s);
+// One Adam step in place; c1 = 1 - beta1^t and c2 = 1 - beta2^t are the bias corrections.
+hipError_t launch_mlp_adam(float* w, const float* grad, float* m, float* v, int P, float lr, float b1, float b2,
+                           float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_zero_floats(float* p, long long count, hipStream_t s);
+// out [N][2]: fp32 (bf16 = 0) or matrix-core bf16 (bf16 = 1) inference.
+hipError_t launch_mlp_forward(const float* feats, int N, int d, const float* w, float* out, int bf16,
+                              hipStream_t s);
+// The learned decision of every column on the residual r: value[j] = the network's
+// value if its logit >= logit_t, else NaN (no update).  d <= 15.
+hipError_t launch_learned_cols(const int32_t* A, int n, int d, const float* r, float sigma, float logit_t,
+                               const float* w, float* value, hipStream_t s);
+
+}  // namespace rl0

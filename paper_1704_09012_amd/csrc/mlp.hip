@@ -1,0 +1,549 @@
+// Kernels of the learned column decision (see mlp.h for the network and its layout).
+//
+// Training runs in fp32: one workgroup takes 64 samples, keeps the weights and every
+// activation of its samples in LDS, and adds its share of the gradient of the mean
+// loss to a global buffer; Adam then updates the weights elementwise.
+//
+// Inference on the matrix cores: a wave evaluates the network for its 64 samples with
+// v_mfma_f32_16x16x32_bf16.  The products are laid out transposed (hidden units along
+// M, samples along N), so each layer's accumulators already sit in the lanes and
+// registers that the next layer's B operand needs; the K order of a layer is permuted to
+// match and the weights are read from LDS in that order.
+#include "mlp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "column_math.h"
+
+#pragma clang fp contract(off)
+
+namespace rl0 {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGradSamples = 64;     // samples per training workgroup
+constexpr int kGradBlock = 256;
+constexpr float kInvSqrt2 = 0.70710678118654752f;
+constexpr float kInvSqrt2Pi = 0.39894228040143268f;
+
+__device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(u * kInvSqrt2)); }
+
+__device__ __forceinline__ float gelu_grad(float u) {
+    return 0.5f * (1.0f + erff(u * kInvSqrt2)) + u * expf(-0.5f * u * u) * kInvSqrt2Pi;
+}
+
+// ------------------------------------------------------------------ features, labels
+
+template <int D>
+__global__ void k_mlp_features(const int32_t* __restrict__ A, int n, const float* __restrict__ r, float sigma,
+                               float* __restrict__ feats) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float v[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) v[p] = r[A[static_cast<size_t>(j) * D + p]];
+    // insertion sort, ascending
+#pragma unroll
+    for (int a = 1; a < D; ++a)
+#pragma unroll
+        for (int b = a; b > 0; --b) {
+            const float lo = fminf(v[b - 1], v[b]), hi = fmaxf(v[b - 1], v[b]);
+            v[b - 1] = lo;
+            v[b] = hi;
+        }
+    float* out = feats + static_cast<size_t>(j) * (D + 1);
+#pragma unroll
+    for (int p = 0; p < D; ++p) out[p] = v[p];
+    out[D] = sigma;
+}
+
+__global__ void k_mlp_labels(const float* __restrict__ x_true, const float* __restrict__ x_hat, int n, double thr,
+                             float* __restrict__ labels) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float xt = x_true[j];
+    const float diff = xt - x_hat[j];
+    const bool acc = xt != 0.0f && static_cast<double>(fabsf(diff)) > thr;
+    labels[2 * static_cast<size_t>(j)] = acc ? 1.0f : 0.0f;
+    labels[2 * static_cast<size_t>(j) + 1] = diff;
+}
+
+// ------------------------------------------------------------------ training
+
+// One workgroup: 64 samples.  LDS: the weights, the features, the labels and the
+// pre-activations and activations of both hidden layers.
+__global__ __launch_bounds__(kGradBlock) void k_mlp_grad(const float* __restrict__ feats,
+                                                         const float* __restrict__ labels, int N, int F,
+                                                         const float* __restrict__ w, float lam, float inv_n,
+                                                         float* __restrict__ grad, float* __restrict__ loss) {
+    extern __shared__ float lds[];
+    __shared__ float red[kGradBlock / 64];
+    const int P = kHidden * F + kHidden + kHidden * kHidden + kHidden + 2 * kHidden + 2;
+    float* W = lds;
+    float* Fs = W + P;
+    float* Z1 = Fs + kGradSamples * F;
+    float* H1 = Z1 + kGradSamples * kHidden;
+    float* Z2 = H1 + kGradSamples * kHidden;
+    float* H2 = Z2 + kGradSamples * kHidden;
+    float* dO = H2 + kGradSamples * kHidden;
+    float* Ys = dO + 2 * kGradSamples;
+    const float* W1 = W;
+    const float* b1 = W1 + kHidden * F;
+    const float* W2 = b1 + kHidden;
+    const float* b2 = W2 + kHidden * kHidden;
+    const float* W3 = b2 + kHidden;
+    const float* b3 = W3 + 2 * kHidden;
+    const int tid = threadIdx.x;
+    const int s0 = blockIdx.x * kGradSamples;
+    const int ns = min(kGradSamples, N - s0);
+    for (int i = tid; i < P; i += kGradBlock) W[i] = w[i];
+    for (int i = tid; i < kGradSamples * F; i += kGradBlock) {
+        const int sm = i / F;
+        Fs[i] = sm < ns ? feats[static_cast<size_t>(s0) * F + i] : 0.0f;
+    }
+    for (int i = tid; i < 2 * kGradSamples; i += kGradBlock) {
+        const int sm = i >> 1;
+        Ys[i] = sm < ns ? labels[2 * static_cast<size_t>(s0) + i] : 0.0f;
+    }
+    __syncthreads();
+    constexpr int kAct = kGradSamples * kHidden;
+    // layer 1: element e = (sample, hidden)
+    for (int e = tid; e < kAct; e += kGradBlock) {
+        const int sm = e / kHidden, h = e % kHidden;
+        float a = 0.0f;
+        for (int k = 0; k < F; ++k) a = a + W1[h * F + k] * Fs[sm * F + k];
+        a = a + b1[h];
+        Z1[e] = a;
+        H1[e] = gelu(a);
+    }
+    __syncthreads();
+    for (int e = tid; e < kAct; e += kGradBlock) {
+        const int sm = e / kHidden, h = e % kHidden;
+        float a = 0.0f;
+        for (int k = 0; k < kHidden; ++k) a = a + W2[h * kHidden + k] * H1[sm * kHidden + k];
+        a = a + b2[h];
+        Z2[e] = a;
+        H2[e] = gelu(a);
+    }
+    __syncthreads();
+    // outputs, loss and the gradient at the outputs (one thread per sample)
+    float l = 0.0f;
+    if (tid < kGradSamples) {
+        const int sm = tid;
+        float o0 = 0.0f, o1 = 0.0f;
+        for (int k = 0; k < kHidden; ++k) {
+            o0 = o0 + W3[k] * H2[sm * kHidden + k];
+            o1 = o1 + W3[kHidden + k] * H2[sm * kHidden + k];
+        }
+        o0 = o0 + b3[0];
+        o1 = o1 + b3[1];
+        float g0 = 0.0f, g1 = 0.0f;
+        if (sm < ns) {
+            const float ya = Ys[2 * sm], yv = Ys[2 * sm + 1];
+            const float dv = o1 - yv;
+            l = fmaxf(o0, 0.0f) - ya * o0 + log1pf(expf(-fabsf(o0))) + lam * ya * dv * dv;
+            const float sig = 1.0f / (1.0f + expf(-o0));
+            g0 = (sig - ya) * inv_n;
+            g1 = 2.0f * lam * ya * dv * inv_n;
+        }
+        dO[2 * sm] = g0;
+        dO[2 * sm + 1] = g1;
+    }
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
+    if ((tid & 63) == 0) red[tid >> 6] = l;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int wv = 0; wv < kGradBlock / 64; ++wv) t += red[wv];
+        atomicAdd(loss, t * inv_n);
+    }
+    // dZ2 = (dO W3) * gelu'(Z2), in place of Z2
+    for (int e = tid; e < kAct; e += kGradBlock) {
+        const int sm = e / kHidden, h = e % kHidden;
+        const float g = dO[2 * sm] * W3[h] + dO[2 * sm + 1] * W3[kHidden + h];
+        Z2[e] = g * gelu_grad(Z2[e]);
+    }
+    __syncthreads();
+    const int oW1 = 0, ob1 = kHidden * F, oW2 = ob1 + kHidden, ob2 = oW2 + kHidden * kHidden,
+              oW3 = ob2 + kHidden, ob3 = oW3 + 2 * kHidden;
+    // W3, b3
+    for (int i = tid; i < 2 * kHidden + 2; i += kGradBlock) {
+        float g = 0.0f;
+        if (i < 2 * kHidden) {
+            const int o = i / kHidden, k = i % kHidden;
+            for (int sm = 0; sm < kGradSamples; ++sm) g = g + dO[2 * sm + o] * H2[sm * kHidden + k];
+            atomicAdd(&grad[oW3 + i], g);
+        } else {
+            const int o = i - 2 * kHidden;
+            for (int sm = 0; sm < kGradSamples; ++sm) g = g + dO[2 * sm + o];
+            atomicAdd(&grad[ob3 + o], g);
+        }
+    }
+    // W2 [h][k] = sum_s dZ2[s][h] H1[s][k]; b2
+    for (int i = tid; i < kHidden * kHidden; i += kGradBlock) {
+        const int h = i / kHidden, k = i % kHidden;
+        float g = 0.0f;
+        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z2[sm * kHidden + h] * H1[sm * kHidden + k];
+        atomicAdd(&grad[oW2 + i], g);
+    }
+    for (int h = tid; h < kHidden; h += kGradBlock) {
+        float g = 0.0f;
+        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z2[sm * kHidden + h];
+        atomicAdd(&grad[ob2 + h], g);
+    }
+    // dZ1 = (dZ2 W2) * gelu'(Z1), in place of Z1
+    for (int e = tid; e < kAct; e += kGradBlock) {
+        const int sm = e / kHidden, k = e % kHidden;
+        float g = 0.0f;
+        for (int h = 0; h < kHidden; ++h) g = g + Z2[sm * kHidden + h] * W2[h * kHidden + k];
+        Z1[e] = g * gelu_grad(Z1[e]);
+    }
+    __syncthreads();
+    // W1 [h][k] = sum_s dZ1[s][h] F[s][k]; b1
+    for (int i = tid; i < kHidden * F; i += kGradBlock) {
+        const int h = i / F, k = i % F;
+        float g = 0.0f;
+        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z1[sm * kHidden + h] * Fs[sm * F + k];
+        atomicAdd(&grad[oW1 + i], g);
+    }
+    for (int h = tid; h < kHidden; h += kGradBlock) {
+        float g = 0.0f;
+        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z1[sm * kHidden + h];
+        atomicAdd(&grad[ob1 + h], g);
+    }
+}
+
+__global__ void k_mlp_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                           float* __restrict__ v, int P, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_zero_floats(float* __restrict__ p, long long count) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0f;
+}
+
+// ------------------------------------------------------------------ fp32 inference
+
+__global__ void k_mlp_forward_f32(const float* __restrict__ feats, int N, int F, const float* __restrict__ w,
+                                  float* __restrict__ out) {
+    extern __shared__ float W[];
+    const int P = kHidden * F + kHidden + kHidden * kHidden + kHidden + 2 * kHidden + 2;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) W[i] = w[i];
+    __syncthreads();
+    const int sm = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sm >= N) return;
+    const float* W1 = W;
+    const float* b1 = W1 + kHidden * F;
+    const float* W2 = b1 + kHidden;
+    const float* b2 = W2 + kHidden * kHidden;
+    const float* W3 = b2 + kHidden;
+    const float* b3 = W3 + 2 * kHidden;
+    float f[kMlpMaxFeatures + 1];
+    for (int k = 0; k < F; ++k) f[k] = feats[static_cast<size_t>(sm) * F + k];
+    float h1[kHidden];
+    for (int h = 0; h < kHidden; ++h) {
+        float a = 0.0f;
+        for (int k = 0; k < F; ++k) a = a + W1[h * F + k] * f[k];
+        h1[h] = gelu(a + b1[h]);
+    }
+    float o0 = 0.0f, o1 = 0.0f;
+    for (int h = 0; h < kHidden; ++h) {
+        float a = 0.0f;
+        for (int k = 0; k < kHidden; ++k) a = a + W2[h * kHidden + k] * h1[k];
+        const float h2 = gelu(a + b2[h]);
+        o0 = o0 + W3[h] * h2;
+        o1 = o1 + W3[kHidden + h] * h2;
+    }
+    out[2 * static_cast<size_t>(sm)] = o0 + b3[0];
+    out[2 * static_cast<size_t>(sm) + 1] = o1 + b3[1];
+}
+
+// ------------------------------------------------------------------ matrix-core inference
+
+// The network in LDS for the matrix cores: bf16 weights (W1 zero-padded to 16 inputs),
+// fp32 biases.
+struct MlpLds {
+    __bf16 W1[kHidden][kMlpMaxFeatures];
+    __bf16 W2[kHidden][kHidden];
+    __bf16 W3[2][kHidden];
+    float b1[kHidden], b2[kHidden], b3[2];
+};
+
+__device__ void load_mlp_lds(MlpLds& L, const float* __restrict__ w, int F) {
+    const float* W1 = w;
+    const float* b1 = W1 + kHidden * F;
+    const float* W2 = b1 + kHidden;
+    const float* b2 = W2 + kHidden * kHidden;
+    const float* W3 = b2 + kHidden;
+    const float* b3 = W3 + 2 * kHidden;
+    for (int i = threadIdx.x; i < kHidden * kMlpMaxFeatures; i += blockDim.x) {
+        const int h = i / kMlpMaxFeatures, k = i % kMlpMaxFeatures;
+        L.W1[h][k] = static_cast<__bf16>(k < F ? W1[h * F + k] : 0.0f);
+    }
+    for (int i = threadIdx.x; i < kHidden * kHidden; i += blockDim.x) L.W2[i / kHidden][i % kHidden] = static_cast<__bf16>(W2[i]);
+    for (int i = threadIdx.x; i < 2 * kHidden; i += blockDim.x) L.W3[i / kHidden][i % kHidden] = static_cast<__bf16>(W3[i]);
+    for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
+        L.b1[i] = b1[i];
+        L.b2[i] = b2[i];
+    }
+    if (threadIdx.x < 2) L.b3[threadIdx.x] = b3[threadIdx.x];
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = static_cast<__bf16>(0.0f);
+    return z;
+}
+
+// The 8 weights row `row` of W (row-major, `stride` columns) contributes to the k-step
+// kt of lane group g: columns 32 kt + 4 g + (0..3) and 32 kt + 16 + 4 g + (0..3).
+__device__ __forceinline__ bf16x8 perm_row(const __bf16* W, int stride, int row, int kt, int g) {
+    bf16x8 a;
+    const __bf16* p = W + row * stride + 32 * kt + 4 * g;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j] = p[j];
+        a[4 + j] = p[16 + j];
+    }
+    return a;
+}
+
+// The next layer's B operand from this layer's accumulators acc[mt][nt] (hidden unit
+// 16 mt + 4 g + i of sample 16 nt + c in lane 16 g + c): bias, GELU, bf16, in the
+// permuted K order of perm_row.
+__device__ __forceinline__ void activations(const floatx4 (&acc)[4][4], const float* bias, int g,
+                                            bf16x8 (&b)[2][4]) {
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                b[kt][nt][i] = static_cast<__bf16>(gelu(acc[2 * kt][nt][i] + bias[32 * kt + 4 * g + i]));
+                b[kt][nt][4 + i] = static_cast<__bf16>(gelu(acc[2 * kt + 1][nt][i] + bias[32 * kt + 16 + 4 * g + i]));
+            }
+}
+
+// The network for the 64 samples of a wave, one per lane (f: this lane's F <= 16
+// features).  stage: this wave's 64 x 16 bf16 LDS scratch.  Every lane must call.
+__device__ void mlp_wave_bf16(const MlpLds& L, const float* f, int F, __bf16* stage, float& logit, float& value) {
+    const int lane = __lane_id();
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int k = 0; k < kMlpMaxFeatures; ++k) stage[lane * kMlpMaxFeatures + k] = static_cast<__bf16>(k < F ? f[k] : 0.0f);
+    __builtin_amdgcn_wave_barrier();
+    // layer 1 (K = 16 inputs in lane groups 0 and 1, zero in groups 2 and 3)
+    bf16x8 bf[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        if (g < 2) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bf[nt][j] = stage[(16 * nt + c) * kMlpMaxFeatures + 8 * g + j];
+        } else {
+            bf[nt] = zero8();
+        }
+    }
+    const floatx4 z4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        bf16x8 a = zero8();
+        if (g < 2) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = L.W1[16 * mt + c][8 * g + j];
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[nt], z4, 0, 0, 0);
+    }
+    bf16x8 h[2][4];
+    activations(acc, L.b1, g, h);
+    // layer 2
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = z4;
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            const bf16x8 a = perm_row(&L.W2[0][0], kHidden, 16 * mt + c, kt, g);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h[kt][nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+    activations(acc, L.b2, g, h);
+    // layer 3 (M = 2 outputs in rows 0 and 1 of a 16-row tile)
+    floatx4 out[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) out[nt] = z4;
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+        const bf16x8 a = c < 2 ? perm_row(&L.W3[0][0], kHidden, c, kt, g) : zero8();
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) out[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h[kt][nt], out[nt], 0, 0, 0);
+    }
+    // outputs of sample 16 nt + c sit in lane c (rows 0 and 1); bring them to lane 16 nt + c
+    const int my_nt = lane >> 4, src = lane & 15;
+    float lg = 0.0f, vl = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const float t0 = __shfl(out[nt][0], src);
+        const float t1 = __shfl(out[nt][1], src);
+        if (nt == my_nt) {
+            lg = t0;
+            vl = t1;
+        }
+    }
+    logit = lg + L.b3[0];
+    value = vl + L.b3[1];
+    __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kInferBlock = 256;
+
+__global__ __launch_bounds__(kInferBlock) void k_mlp_forward_bf16(const float* __restrict__ feats, int N, int F,
+                                                                  const float* __restrict__ w, float* __restrict__ out) {
+    __shared__ MlpLds L;
+    __shared__ __bf16 stage[kInferBlock / 64][64 * kMlpMaxFeatures];
+    load_mlp_lds(L, w, F);
+    __syncthreads();
+    const int sm = blockIdx.x * kInferBlock + threadIdx.x;
+    float f[kMlpMaxFeatures];
+#pragma unroll
+    for (int k = 0; k < kMlpMaxFeatures; ++k) f[k] = (sm < N && k < F) ? feats[static_cast<size_t>(sm) * F + k] : 0.0f;
+    float logit, value;
+    mlp_wave_bf16(L, f, F, stage[threadIdx.x >> 6], logit, value);
+    if (sm < N) {
+        out[2 * static_cast<size_t>(sm)] = logit;
+        out[2 * static_cast<size_t>(sm) + 1] = value;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kInferBlock) void k_learned_cols(const int32_t* __restrict__ A, int n,
+                                                              const float* __restrict__ r, float sigma, float logit_t,
+                                                              const float* __restrict__ w, float* __restrict__ value) {
+    __shared__ MlpLds L;
+    __shared__ __bf16 stage[kInferBlock / 64][64 * kMlpMaxFeatures];
+    load_mlp_lds(L, w, D + 1);
+    __syncthreads();
+    const int j = blockIdx.x * kInferBlock + threadIdx.x;
+    float v[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) v[p] = j < n ? r[A[static_cast<size_t>(j) * D + p]] : 0.0f;
+#pragma unroll
+    for (int a = 1; a < D; ++a)
+#pragma unroll
+        for (int b = a; b > 0; --b) {
+            const float lo = fminf(v[b - 1], v[b]), hi = fmaxf(v[b - 1], v[b]);
+            v[b - 1] = lo;
+            v[b] = hi;
+        }
+    float f[kMlpMaxFeatures];
+#pragma unroll
+    for (int k = 0; k < kMlpMaxFeatures; ++k) f[k] = k < D ? v[k < D ? k : 0] : (k == D ? sigma : 0.0f);
+    float logit, val;
+    mlp_wave_bf16(L, f, D + 1, stage[threadIdx.x >> 6], logit, val);
+    if (j < n) value[j] = logit >= logit_t ? val : __builtin_nanf("");
+}
+
+int blocks_of(long long count, int block) { return static_cast<int>((count + block - 1) / block); }
+
+}  // namespace
+
+hipError_t launch_mlp_features(const int32_t* A, int n, int d, const float* r, float sigma, float* feats,
+                               hipStream_t s) {
+    const int g = blocks_of(n, 256);
+    switch (d) {
+#define RL0_FEAT(D) \
+    case D: k_mlp_features<D><<<g, 256, 0, s>>>(A, n, r, sigma, feats); break;
+        RL0_FEAT(1) RL0_FEAT(2) RL0_FEAT(3) RL0_FEAT(4) RL0_FEAT(5) RL0_FEAT(6) RL0_FEAT(7) RL0_FEAT(8)
+        RL0_FEAT(9) RL0_FEAT(10) RL0_FEAT(11) RL0_FEAT(12) RL0_FEAT(13) RL0_FEAT(14) RL0_FEAT(15) RL0_FEAT(16)
+#undef RL0_FEAT
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_labels(const float* x_true, const float* x_hat, int n, double thr, float* labels,
+                             hipStream_t s) {
+    k_mlp_labels<<<blocks_of(n, 256), 256, 0, s>>>(x_true, x_hat, n, thr, labels);
+    return hipGetLastError();
+}
+
+size_t mlp_grad_lds(int F) {
+    const size_t P = static_cast<size_t>(mlp_params(F - 1));
+    return sizeof(float) * (P + kGradSamples * F + 4 * kGradSamples * kHidden + 4 * kGradSamples);
+}
+
+hipError_t launch_mlp_grad(const float* feats, const float* labels, int N, int d, const float* w, float lam,
+                           float* grad, float* loss, hipStream_t s) {
+    const int F = d + 1;
+    const size_t lds = mlp_grad_lds(F);
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_grad),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(mlp_grad_lds(kMaxD + 1)));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    k_zero_floats<<<blocks_of(mlp_params(d), 256), 256, 0, s>>>(grad, mlp_params(d));
+    k_zero_floats<<<1, 64, 0, s>>>(loss, 1);
+    k_mlp_grad<<<blocks_of(N, kGradSamples), kGradBlock, lds, s>>>(feats, labels, N, F, w, lam,
+                                                                    1.0f / static_cast<float>(N), grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* w, const float* grad, float* m, float* v, int P, float lr, float b1, float b2,
+                           float eps, float c1, float c2, hipStream_t s) {
+    k_mlp_adam<<<blocks_of(P, 256), 256, 0, s>>>(w, grad, m, v, P, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_floats(float* p, long long count, hipStream_t s) {
+    if (count > 0) k_zero_floats<<<blocks_of(count, 256), 256, 0, s>>>(p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* feats, int N, int d, const float* w, float* out, int bf16,
+                              hipStream_t s) {
+    const int F = d + 1;
+    if (bf16) {
+        if (F > kMlpMaxFeatures) return hipErrorInvalidValue;
+        k_mlp_forward_bf16<<<blocks_of(N, kInferBlock), kInferBlock, 0, s>>>(feats, N, F, w, out);
+    } else {
+        const size_t lds = sizeof(float) * mlp_params(d);
+        k_mlp_forward_f32<<<blocks_of(N, 128), 128, lds, s>>>(feats, N, F, w, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_cols(const int32_t* A, int n, int d, const float* r, float sigma, float logit_t,
+                               const float* w, float* value, hipStream_t s) {
+    const int g = blocks_of(n, kInferBlock);
+    switch (d) {
+#define RL0_LC(D) \
+    case D: k_learned_cols<D><<<g, kInferBlock, 0, s>>>(A, n, r, sigma, logit_t, w, value); break;
+        RL0_LC(1) RL0_LC(2) RL0_LC(3) RL0_LC(4) RL0_LC(5) RL0_LC(6) RL0_LC(7) RL0_LC(8)
+        RL0_LC(9) RL0_LC(10) RL0_LC(11) RL0_LC(12) RL0_LC(13) RL0_LC(14) RL0_LC(15)
+#undef RL0_LC
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rl0

@@ -21,6 +21,7 @@
 #include "constants.h"
 #include "kernels.h"
 #include "batched.h"
+#include "mlp.h"
 
 namespace {
 
@@ -260,7 +261,8 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     if (p->l1_test != 0 && p->l1_test != 1) return fail(RL0_EINVAL, "l1_test must be 0 or 1");
     if (p->posterior != 0 && p->posterior != 1) return fail(RL0_EINVAL, "posterior must be 0 or 1");
     if (p->posterior == 1 && !p->mlp) return fail(RL0_ENOWEIGHTS, "learned posterior requested without weights");
-    if (p->posterior == 1) return fail(RL0_EINVAL, "learned posterior is not available in this build");
+    if (p->posterior == 1 && d + 1 > rl0::kMlpMaxFeatures)
+        return fail(RL0_EINVAL, "the learned posterior supports d <= 15");
     return RL0_OK;
 }
 
@@ -687,6 +689,126 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
     return RL0_OK;
 }
 
+// ---------------------------------------------------------------- one iteration from x_hat
+
+struct StepResult {
+    int accepted = 0;
+    int updates = 0;
+    long long L_hat = 0;   // after the decision
+    int cur = 0;           // buffer holding r_hat afterwards
+};
+
+// fl32(log(t / (1 - t))): the learned decision's threshold on the logit (+inf at t = 1).
+float logit_threshold(float t) {
+    if (!(t < 1.0f)) return INFINITY;
+    return static_cast<float>(std::log(static_cast<double>(t) / (1.0 - static_cast<double>(t))));
+}
+
+// Iteration `it` of Alg. 1's loop from x_hat (device, updated in place when accepted):
+// the residual is rebuilt from y and x_hat, the column decisions are the learned ones
+// when `learned`, and the stream is synchronised.
+int step_core(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, const int32_t* A, const float* y,
+              const rl0_params* p, int it, bool learned, float* x_hat, const rl0::DebugOut& dbg, hipStream_t s,
+              StepResult* out) {
+    const rl0::Workspace& w = b->w;
+    rl0::IterParams ip = iter_params(dc, p, it);
+    ip.n_iters = it + 1;
+    ip.tol_fx = -1.0;  // a single step never stops early
+    rl0::IterParams ip_end = iter_params(dc, p, it + 1);
+    ip_end.n_iters = it + 1;
+    ip_end.tol_fx = -1.0;
+    HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, x_hat, w, ip, s));
+    const float* lv = nullptr;
+    if (learned) {
+        HIP_TRY(rl0::launch_learned_cols(A, dm.n, dm.d, w.r[0], p->sigma, logit_threshold(ip.t),
+                                         static_cast<const float*>(p->mlp), w.learned, s));
+        lv = w.learned;
+    }
+    HIP_TRY(rl0::launch_iteration(dm, A, w, tables_of(dc), ip, dbg, s, nullptr, lv));
+    HIP_TRY(rl0::launch_finish(dm, w, ip_end, it, x_hat, s));
+    HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const rl0::DevState& ds = *b->st_host;
+    if (int rc = err_code_of(ds.err)) return rc;
+    const rl0::Slot& fin = ds.slot[(it + 1) & 1];
+    out->accepted = fin.accepted_last;
+    out->L_hat = fin.L_hat;
+    out->cur = fin.cur;
+    out->updates = ds.updates_total;
+    return RL0_OK;
+}
+
+// Alg. 1 with the learned column decision: at each t a learned iteration, and when it
+// is not accepted, an iteration with the analytic decision at the same t.
+int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, const int32_t* A,
+                   const float* y, const rl0_params* p, float* x_out, rl0_stats* st_h, hipStream_t s) {
+    HIP_TRY(rl0::launch_zero_f32(x_out, dm.n, s));
+    HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, x_out, b->w, iter_params(dc, p, 0), s));
+    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (int rc = err_code_of(b->st_host->err)) return rc;
+    long long L_hat = b->st_host->slot[1].L_hat;
+    const double tol_fx = dc->hc.tol * 1073741824.0;
+    int iters = 0, accepted = 0, updates = 0;
+    float t_final = 1.0f;
+    const rl0::DebugOut dbg{nullptr, nullptr};
+    for (int it = 0; it < dc->hc.n_iters; ++it) {
+        if (static_cast<double>(L_hat) <= tol_fx) break;
+        for (int pass = 0; pass < 2; ++pass) {
+            StepResult r;
+            if (int rc = step_core(b, dc, dm, A, y, p, it, pass == 0, x_out, dbg, s, &r)) return rc;
+            ++iters;
+            updates += r.updates;
+            t_final = dc->hc.t[it];
+            L_hat = r.L_hat;
+            if (r.accepted) {
+                ++accepted;
+                break;
+            }
+        }
+    }
+    if (st_h) {
+        st_h->iterations = iters;
+        st_h->accepted = accepted;
+        st_h->l1_final_fx = L_hat;
+        st_h->l1_final = static_cast<double>(L_hat) / 1073741824.0;
+        st_h->l1_tol = dc->hc.tol;
+        st_h->converged = static_cast<double>(L_hat) <= tol_fx ? 1 : 0;
+        st_h->updates_total = updates;
+        st_h->t_final = t_final;
+        st_h->error_flags = 0;
+    }
+    return RL0_OK;
+}
+
+// ---------------------------------------------------------------- network training memory
+
+struct MlpBuffers {
+    float* grad = nullptr;
+    float* losses = nullptr;
+    size_t cap_p = 0, cap_steps = 0;
+    std::vector<float> host_losses;
+};
+
+std::map<std::pair<int, hipStream_t>, MlpBuffers> g_mlp;
+
+int get_mlp_buffers(int device, hipStream_t s, size_t P, size_t steps, MlpBuffers** out) {
+    MlpBuffers& mb = g_mlp[{device, s}];
+    if (mb.cap_p < P || mb.cap_steps < steps) {
+        HIP_TRY(hipStreamSynchronize(s));
+        if (mb.grad) HIP_TRY(hipFree(mb.grad));
+        mb.grad = nullptr;
+        mb.cap_p = mb.cap_steps = 0;
+        const size_t np = std::max(P, mb.cap_p), ns = std::max<size_t>(std::max(steps, mb.cap_steps), 1);
+        if (hipMalloc(&mb.grad, sizeof(float) * (np + ns)) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(mlp)");
+        mb.losses = mb.grad + np;
+        mb.cap_p = np;
+        mb.cap_steps = ns;
+    }
+    *out = &mb;
+    return RL0_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -782,6 +904,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     Buffers* b = nullptr;
     if (int rc = get_workspace(dev, s, n, m, &b)) return rc;
     const rl0::DecodeDims dm{n, m, d, p->k};
+    if (p->posterior == 1) return decode_learned(b, dc, dm, A_cols, y, p, x_out, st_h, s);
     const rl0::ScoreTables tb = tables_of(dc);
     const int N = dc->hc.n_iters;
     auto issue = [&](hipStream_t q) -> int {
@@ -847,29 +970,17 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
     if (int rc = get_workspace(dev, s, n, m, &b)) return rc;
     const rl0::DecodeDims dm{n, m, d, p->k};
     const rl0::Workspace& w = b->w;
-    rl0::IterParams ip = iter_params(dc, p, it);
-    ip.n_iters = it + 1;
-    ip.tol_fx = -1.0;  // a single step never stops early
-    rl0::IterParams ip_end = iter_params(dc, p, it + 1);
-    ip_end.n_iters = it + 1;
-    ip_end.tol_fx = -1.0;
     if (updated) HIP_TRY(rl0::launch_zero_i32(updated, n, s));
     if (omega) HIP_TRY(rl0::launch_zero_f32(omega, n, s));
-    HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, x_hat, w, ip, s));
     const rl0::DebugOut dbg{updated, omega};
-    HIP_TRY(rl0::launch_iteration(dm, A_cols, w, tables_of(dc), ip, dbg, s));
-    HIP_TRY(rl0::launch_finish(dm, w, ip_end, it, x_hat, s));
+    StepResult r;
+    if (int rc = step_core(b, dc, dm, A_cols, y, p, it, p->posterior == 1, x_hat, dbg, s, &r)) return rc;
     // the iteration ran from buffer 0; its trial iterate sits in buffer 1
     if (x_trial) HIP_TRY(rl0::launch_trial_out(dm, w, it + 1, it, x_trial, s));
     if (r_trial) HIP_TRY(rl0::launch_copy_f32(w.r[1], r_trial, m, s));
-    HIP_TRY(hipMemcpyAsync(b->st_host, w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const rl0::DevState& ds = *b->st_host;
-    if (int rc = err_code_of(ds.err)) return rc;
-    const rl0::Slot& fin = ds.slot[(it + 1) & 1];
-    if (accepted_h) *accepted_h = fin.accepted_last;
-    *L_hat_h = fin.L_hat;
-    HIP_TRY(rl0::launch_copy_f32(w.r[fin.cur], r_hat, m, s));
+    if (accepted_h) *accepted_h = r.accepted;
+    *L_hat_h = r.L_hat;
+    HIP_TRY(rl0::launch_copy_f32(w.r[r.cur], r_hat, m, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RL0_OK;
 }
@@ -978,6 +1089,127 @@ int rl0_autotune_batched(const rl0_problem* probs_h, int32_t count, int32_t reps
     return collect_batch(probs_h, plan, nullptr, s);
 }
 
+int32_t rl0_mlp_num_params(int32_t d) { return d >= 1 && d <= RL0_MAX_D ? rl0::mlp_params(d) : -1; }
+
+int rl0_mlp_init(float* w, int32_t d, uint64_t seed, void* stream) {
+    if (!w) return fail(RL0_EINVAL, "w is NULL");
+    if (d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "d must be in [1, 16]");
+    const int F = d + 1, H = rl0::kHidden;
+    std::vector<float> h(rl0::mlp_params(d), 0.0f);
+    uint64_t st = seed;
+    auto next = [&]() {   // SplitMix64
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    size_t o = 0;
+    const int shapes[3][2] = {{H, F}, {H, H}, {2, H}};
+    for (const auto& sh : shapes) {
+        const double bound = std::sqrt(3.0 / sh[1]);
+        for (int i = 0; i < sh[0] * sh[1]; ++i) {
+            const double u = static_cast<double>(next() >> 11) * (1.0 / 9007199254740992.0);
+            h[o++] = static_cast<float>((2.0 * u - 1.0) * bound);
+        }
+        o += sh[0];   // biases stay 0
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(w, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RL0_OK;
+}
+
+int rl0_mlp_features(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* r, float sigma,
+                     float* feats, void* stream) {
+    if (int rc = check_dims(n, m, d)) return rc;
+    if (!A_cols || !r || !feats) return fail(RL0_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    HIP_TRY(rl0::launch_mlp_features(A_cols, n, d, r, sigma, feats, static_cast<hipStream_t>(stream)));
+    return RL0_OK;
+}
+
+int rl0_mlp_labels(const float* x_true, const float* x_hat, int32_t n, int32_t d, float sigma, float* labels,
+                   void* stream) {
+    if (n < 1 || d < 1) return fail(RL0_EINVAL, "n and d must be >= 1");
+    if (!x_true || !x_hat || !labels) return fail(RL0_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    const double thr = 3.0 * static_cast<double>(sigma) / std::sqrt(static_cast<double>(d));
+    HIP_TRY(rl0::launch_mlp_labels(x_true, x_hat, n, thr, labels, static_cast<hipStream_t>(stream)));
+    return RL0_OK;
+}
+
+int rl0_mlp_grad(const float* feats, const float* labels, int32_t N, int32_t d, const float* w, float lam,
+                 float* grad, float* loss_h, void* stream) {
+    if (N < 1 || d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "N >= 1 and d in [1, 16] required");
+    if (!feats || !labels || !w || !grad) return fail(RL0_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    MlpBuffers* mb = nullptr;
+    if (int rc = get_mlp_buffers(dev, s, rl0::mlp_params(d), 1, &mb)) return rc;
+    HIP_TRY(rl0::launch_mlp_grad(feats, labels, N, d, w, lam, grad, mb->losses, s));
+    float l = 0.0f;
+    HIP_TRY(hipMemcpyAsync(&l, mb->losses, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_h) *loss_h = l;
+    return RL0_OK;
+}
+
+int rl0_mlp_train(const float* feats, const float* labels, int64_t N, int32_t d, float* w, float* adam_m,
+                  float* adam_v, const rl0_train_cfg* cfg, float* loss_h, void* stream) {
+    if (!cfg) return fail(RL0_EINVAL, "cfg is NULL");
+    if (d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "d must be in [1, 16]");
+    if (cfg->batch < 1 || cfg->steps < 0 || cfg->t0 < 0 || N < cfg->batch)
+        return fail(RL0_EINVAL, "need batch >= 1, steps >= 0, t0 >= 0 and N >= batch");
+    if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+        !(cfg->eps > 0.0f))
+        return fail(RL0_EINVAL, "Adam settings out of range");
+    if (!feats || !labels || !w || !adam_m || !adam_v) return fail(RL0_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const int P = rl0::mlp_params(d), F = d + 1;
+    MlpBuffers* mb = nullptr;
+    if (int rc = get_mlp_buffers(dev, s, P, cfg->steps, &mb)) return rc;
+    const int64_t nb = N / cfg->batch;
+    for (int i = 0; i < cfg->steps; ++i) {
+        const int64_t blk = (static_cast<int64_t>(cfg->t0) + i) % nb;
+        const size_t off = static_cast<size_t>(blk) * cfg->batch;
+        HIP_TRY(rl0::launch_mlp_grad(feats + off * F, labels + off * 2, cfg->batch, d, w, cfg->lam, mb->grad,
+                                     mb->losses + i, s));
+        const double t = static_cast<double>(cfg->t0) + i + 1;
+        const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), t));
+        const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), t));
+        HIP_TRY(rl0::launch_mlp_adam(w, mb->grad, adam_m, adam_v, P, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, c1,
+                                     c2, s));
+    }
+    if (cfg->steps > 0) {
+        mb->host_losses.resize(cfg->steps);
+        HIP_TRY(hipMemcpyAsync(mb->host_losses.data(), mb->losses, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_h) {
+        const int tail = std::min(cfg->steps, 50);
+        double acc = 0.0;
+        for (int i = cfg->steps - tail; i < cfg->steps; ++i) acc += mb->host_losses[i];
+        *loss_h = tail > 0 ? static_cast<float>(acc / tail) : 0.0f;
+    }
+    return RL0_OK;
+}
+
+int rl0_mlp_forward(const float* feats, int32_t N, int32_t d, const float* w, float* out, int32_t bf16,
+                    void* stream) {
+    if (N < 1 || d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "N >= 1 and d in [1, 16] required");
+    if (bf16 && d + 1 > rl0::kMlpMaxFeatures) return fail(RL0_EINVAL, "bf16 inference supports d <= 15");
+    if (!feats || !w || !out) return fail(RL0_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    HIP_TRY(rl0::launch_mlp_forward(feats, N, d, w, out, bf16 ? 1 : 0, static_cast<hipStream_t>(stream)));
+    return RL0_OK;
+}
+
 int rl0_profile_enable(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof.enabled = enable != 0;
@@ -1026,6 +1258,9 @@ void rl0_release(void) {
         if (b->host) hipHostFree(b->host);
     }
     g_bws.clear();
+    for (auto& kv : g_mlp)
+        if (kv.second.grad) hipFree(kv.second.grad);
+    g_mlp.clear();
     for (auto& kv : g_consts)
         if (kv.second->d_tables) hipFree(kv.second->d_tables);
     g_consts.clear();

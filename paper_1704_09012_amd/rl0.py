@@ -112,6 +112,19 @@ class BatchSchedule(ctypes.Structure):
         return s
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [
+        ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("lam", ctypes.c_float),
+        ("batch", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("t0", ctypes.c_int32),
+    ]
+
+
 class Rl0Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -144,11 +157,21 @@ def lib() -> ctypes.CDLL:
         L.rl0_batch_schedule_set.argtypes = [ctypes.POINTER(BatchSchedule)]
         L.rl0_autotune_batched.argtypes = [ctypes.POINTER(Problem), I32, I32, ctypes.POINTER(BatchSchedule),
                                            ctypes.POINTER(ctypes.c_double), V]
+        L.rl0_mlp_num_params.argtypes = [I32]
+        L.rl0_mlp_num_params.restype = I32
+        L.rl0_mlp_init.argtypes = [P, I32, ctypes.c_uint64, V]
+        L.rl0_mlp_features.argtypes = [P, I32, I32, I32, P, ctypes.c_float, P, V]
+        L.rl0_mlp_labels.argtypes = [P, P, I32, I32, ctypes.c_float, P, V]
+        L.rl0_mlp_grad.argtypes = [P, P, I32, I32, P, ctypes.c_float, P, ctypes.POINTER(ctypes.c_float), V]
+        L.rl0_mlp_train.argtypes = [P, P, I64, I32, P, P, P, ctypes.POINTER(TrainCfg),
+                                    ctypes.POINTER(ctypes.c_float), V]
+        L.rl0_mlp_forward.argtypes = [P, I32, I32, P, P, I32, V]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
                      "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get",
-                     "rl0_batch_schedule_set", "rl0_autotune_batched"):
+                     "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_mlp_init", "rl0_mlp_features",
+                     "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -188,6 +211,10 @@ def params_default(n: int, m: int, d: int, k: int, sigma: float, **overrides) ->
     for key, val in overrides.items():
         if not hasattr(p, key):
             raise KeyError(key)
+        if key == "mlp" and hasattr(val, "data_ptr"):
+            # a parameter tensor: the learned decision
+            val = val.data_ptr()
+            p.posterior = 1
         setattr(p, key, val)
     return p
 
@@ -253,6 +280,9 @@ def decode(A_cols, y, sigma: float | None = None, d: int | None = None, params: 
         params = params_default(n, m, dd, k, sigma, **overrides)
     else:
         for key, val in overrides.items():
+            if key == "mlp" and hasattr(val, "data_ptr"):
+                val = val.data_ptr()
+                params.posterior = 1
             setattr(params, key, val)
     x = out if out is not None else torch.empty(n, dtype=torch.float32, device=y.device)
     st = Stats()
@@ -372,3 +402,79 @@ def autotune_batched(problems, reps: int = 3) -> tuple[dict, float]:
     ms = ctypes.c_double(0.0)
     _check(lib().rl0_autotune_batched(arr, len(problems), reps, ctypes.byref(best), ctypes.byref(ms), _stream()))
     return best.as_dict(), ms.value
+
+
+# ---------------------------------------------------------------- learned decision
+
+def mlp_num_params(d: int) -> int:
+    n = lib().rl0_mlp_num_params(d)
+    if n < 0:
+        raise ValueError("d must be in [1, 16]")
+    return n
+
+
+def mlp_init(d: int, seed: int, device="cuda"):
+    """A new parameter vector (rl0_mlp_init)."""
+    torch = _torch()
+    w = torch.empty(mlp_num_params(d), dtype=torch.float32, device=device)
+    _check(lib().rl0_mlp_init(_dev_ptr(w, torch.float32, None, "w"), d, seed, _stream()))
+    return w
+
+
+def mlp_features(A_cols, r, sigma: float, out=None):
+    torch = _torch()
+    n, d = A_cols.shape
+    m = r.shape[0]
+    f = out if out is not None else torch.empty((n, d + 1), dtype=torch.float32, device=r.device)
+    _check(lib().rl0_mlp_features(_dev_ptr(A_cols, torch.int32, (n, d), "A_cols"), n, m, d,
+                                  _dev_ptr(r, torch.float32, (m,), "r"), ctypes.c_float(sigma),
+                                  _dev_ptr(f, torch.float32, (n, d + 1), "feats"), _stream()))
+    return f
+
+
+def mlp_labels(x_true, x_hat, d: int, sigma: float, out=None):
+    torch = _torch()
+    n = x_true.shape[0]
+    lab = out if out is not None else torch.empty((n, 2), dtype=torch.float32, device=x_true.device)
+    _check(lib().rl0_mlp_labels(_dev_ptr(x_true, torch.float32, (n,), "x_true"),
+                                _dev_ptr(x_hat, torch.float32, (n,), "x_hat"), n, d, ctypes.c_float(sigma),
+                                _dev_ptr(lab, torch.float32, (n, 2), "labels"), _stream()))
+    return lab
+
+
+def mlp_grad(feats, labels, w, lam: float = 1.0):
+    """(gradient tensor, loss) of the mean loss at w."""
+    torch = _torch()
+    N, F = feats.shape
+    g = torch.empty_like(w)
+    loss = ctypes.c_float(0.0)
+    _check(lib().rl0_mlp_grad(_dev_ptr(feats, torch.float32, (N, F), "feats"),
+                              _dev_ptr(labels, torch.float32, (N, 2), "labels"), N, F - 1,
+                              _dev_ptr(w, torch.float32, None, "w"), ctypes.c_float(lam),
+                              _dev_ptr(g, torch.float32, None, "grad"), ctypes.byref(loss), _stream()))
+    return g, loss.value
+
+
+def mlp_train(feats, labels, w, m, v, steps: int, t0: int = 0, lr: float = 1e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, lam: float = 1.0, batch: int = 4096) -> float:
+    """rl0_mlp_train in place on (w, m, v); returns the mean loss of the last steps."""
+    torch = _torch()
+    N, F = feats.shape
+    cfg = TrainCfg(lr, beta1, beta2, eps, lam, batch, steps, t0)
+    loss = ctypes.c_float(0.0)
+    _check(lib().rl0_mlp_train(_dev_ptr(feats, torch.float32, (N, F), "feats"),
+                               _dev_ptr(labels, torch.float32, (N, 2), "labels"), N, F - 1,
+                               _dev_ptr(w, torch.float32, None, "w"), _dev_ptr(m, torch.float32, None, "m"),
+                               _dev_ptr(v, torch.float32, None, "v"), ctypes.byref(cfg), ctypes.byref(loss),
+                               _stream()))
+    return loss.value
+
+
+def mlp_forward(feats, w, bf16: bool = True):
+    torch = _torch()
+    N, F = feats.shape
+    out = torch.empty((N, 2), dtype=torch.float32, device=feats.device)
+    _check(lib().rl0_mlp_forward(_dev_ptr(feats, torch.float32, (N, F), "feats"), N, F - 1,
+                                 _dev_ptr(w, torch.float32, None, "w"),
+                                 _dev_ptr(out, torch.float32, (N, 2), "out"), 1 if bf16 else 0, _stream()))
+    return out

@@ -1,0 +1,139 @@
+"""The learned column decision on the GPU against the oracle (oracle/mlp.py).
+
+Bars: features and labels bitwise; fp32 gradients within 1e-4 of the fp64 oracle's
+(relative to the largest component); fp32 inference within 1e-4; matrix-core bf16
+inference within 1e-2 of the oracle's bf16 emulation (the accumulation order of the
+matrix cores is not specified); the learned iteration's decisions equal the oracle's
+wherever the logit is more than 1e-2 from the threshold; training lowers the loss; and
+a silent network reproduces the analytic decoder bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import decoder as D
+from oracle import mlp as M
+from paper_1704_09012_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_1704_09012_amd.rl0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def net(d, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    w = M.init_params(d, seed)
+    W1, b1, W2, b2, W3, b3 = M.unpack(w, d)
+    W1 *= scale
+    b1[:] = rng.normal(0, 0.2, 64)
+    b2[:] = rng.normal(0, 0.2, 64)
+    b3[:] = rng.normal(0, 0.2, 2)
+    return w.astype(np.float32)
+
+
+def state_after(inst, y, its):
+    C = D.make_constants(inst.n, inst.m, inst.d, inst.k, inst.sigma)
+    st = D.init_state(y, inst.n)
+    for _ in range(its):
+        st = D.step(inst.A_cols, y, st, C).state
+    return st, C
+
+
+def test_features_and_labels_bitwise():
+    inst = I.draw_instance(5000, 700, 60, 7, 0.01, 21)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, inst.m)
+    st, _ = state_after(inst, y, 6)
+    f = R.mlp_features(dev(inst.A_cols), dev(st.r_hat), 0.01)
+    assert np.array_equal(host(f), M.features(inst.A_cols, st.r_hat, 0.01))
+    lab = R.mlp_labels(dev(inst.x_dense()), dev(st.x_hat), 7, 0.01)
+    assert np.array_equal(host(lab), M.labels(inst.x_dense(), st.x_hat, 0.01, 7))
+
+
+@pytest.mark.parametrize("d,N", [(7, 4096), (7, 1000), (3, 130)])
+def test_gradient_matches_fp64_oracle(d, N):
+    rng = np.random.default_rng(N)
+    w = net(d, 7)
+    F = rng.normal(0, 0.3, (N, d + 1)).astype(np.float32)
+    Y = np.stack([(rng.random(N) < 0.3).astype(np.float32), rng.normal(0, 1, N).astype(np.float32)], 1)
+    g, loss = R.mlp_grad(dev(F), dev(Y), dev(w), lam=1.0)
+    lo, go = M.loss_and_grad(w, F, Y, d, lam=1.0)
+    g = host(g)
+    err = np.max(np.abs(g - go)) / np.max(np.abs(go))
+    print(f"d={d} N={N} grad rel err {err:.2e} loss {loss} vs {lo}", flush=True)
+    assert err <= 1e-4
+    assert abs(loss - lo) <= 1e-4 * max(1.0, abs(lo))
+
+
+def test_inference_fp32_and_bf16():
+    d = 7
+    rng = np.random.default_rng(8)
+    w = net(d, 9)
+    F = rng.normal(0, 0.2, (3000, d + 1)).astype(np.float32)
+    exact, _ = M.forward(w, F, d)
+    o32 = host(R.mlp_forward(dev(F), dev(w), bf16=False))
+    assert np.max(np.abs(o32 - exact)) <= 1e-4 * (1 + np.max(np.abs(exact)))
+    o16 = host(R.mlp_forward(dev(F), dev(w), bf16=True))
+    emu = M.forward_bf16(w, F, d)
+    print("bf16 max diff", np.max(np.abs(o16 - emu)), flush=True)
+    assert np.max(np.abs(o16 - emu)) <= 1e-2
+
+
+def test_learned_step_decisions_match_the_oracle():
+    n, m, k, d = 4096, 1024, 100, 7
+    sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, 31)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    w = net(d, 12, scale=4.0)
+    for its in (3, 12):
+        st, C = state_after(inst, y, its)
+        x_prime, upd, value, logit = M.learned_sweep(inst.A_cols, st.r_hat, st.x_hat, D._scores.t_of(its, C.c), sig, w)
+        params = R.params_default(n, m, d, k, sig, mlp=dev(w))
+        x_t, r_t = dev(st.x_hat), dev(st.r_hat)
+        wt = dev(w)
+        params.mlp = wt.data_ptr()
+        out = R.step(dev(inst.A_cols), dev(y), params, its, x_t, r_t, st.L_hat)
+        gu = host(out["updated"]).astype(bool)
+        go = host(out["omega"])
+        lt = M.logit_threshold(D._scores.t_of(its, C.c))
+        clear = np.abs(logit - lt) > 1e-2
+        print(f"its={its}: oracle updates {upd.sum()}, gpu {gu.sum()}, clear {clear.sum()}", flush=True)
+        assert np.array_equal(gu[clear], upd[clear])
+        both = gu & upd
+        assert np.max(np.abs(go[both] - value[both]), initial=0.0) <= 1e-2
+
+
+def test_silent_network_reproduces_the_analytic_decoder():
+    n, m, k, d = 4096, 800, 70, 7
+    sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, 41)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    w = np.zeros(M.n_params(d), np.float32)
+    w[-2] = -1e4
+    wt = dev(w)
+    xg, stg = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=wt)
+    ref = D.decode(inst.A_cols, y, D.make_constants(n, m, d, k, sig))
+    assert np.array_equal(host(xg), ref.x_hat)
+    assert stg["l1_final_fx"] == ref.L_hat and stg["accepted"] == ref.accepted
+
+
+def test_training_lowers_the_loss():
+    from paper_1704_09012_amd import learned as Lrn
+    F, Y = Lrn.trajectories(6, 3)
+    print("samples", F.shape[0], "positives", int(Y[:, 0].sum()), flush=True)
+    w0 = R.mlp_init(7, 5)
+    _, l0 = R.mlp_grad(F, Y, w0)
+    w, l1 = Lrn.train(F, Y, epochs=30, batch=256, w=w0.clone())
+    _, l2 = R.mlp_grad(F, Y, w)
+    print("loss before", l0, "after", l2, flush=True)
+    assert l2 < 0.7 * l0
