@@ -101,6 +101,54 @@ def copy_calibration() -> int:
     return 0
 
 
+def bench_learned(args) -> int:
+    """The learned decision against the analytic one at the headline size: the network
+    is trained on the GPU on trajectories of the n = 1024 workload (2000 decodes, SNR in
+    [20, 60] dB, 30 epochs), then `--seeds` instances per SNR (20, 40, 60 dB) are decoded
+    both ways."""
+    import torch
+    from paper_1704_09012_amd import learned as Lrn
+
+    t0 = time.perf_counter()
+    F, Y = Lrn.trajectories(2000, 1)
+    torch.cuda.synchronize()
+    t_traj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w, loss = Lrn.train(F, Y, epochs=30)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    per_snr = {}
+    for snr in (20, 40, 60):
+        rows = Lrn.compare(w, N, M, K, snr, [I.seed_for(5, i, j) for i, j in [(snr // 20, j) for j in range(args.seeds)]])
+        agg = {}
+        for tag in ("analytic", "learned"):
+            agg[tag] = {
+                "rel_err_median": float(np.median([r[tag]["rel_err"] for r in rows])),
+                "frac_rel_err_below_1e-2": float(np.mean([r[tag]["rel_err"] < 1e-2 for r in rows])),
+                "converged_frac": float(np.mean([r[tag]["converged"] for r in rows])),
+                "iterations_mean": float(np.mean([r[tag]["iterations"] for r in rows])),
+                "ms_median": float(np.median([r[tag]["ms"] for r in rows])),
+            }
+        per_snr[str(snr)] = agg
+    out = {
+        "metric": "learned vs analytic column decision, n=2^20 d=7",
+        "value": per_snr["40"]["learned"]["ms_median"],
+        "unit": "ms per decode (learned, 40 dB)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "bf16 inference (fp32 accumulate), fp32 training",
+        "data": "synthetic",
+        "config": {"workload": "train on n=1024 m=256 k=25 trajectories (2000 decodes, SNR U[20,60]); "
+                               "evaluate n=2^20 m=104857 k=10485 at SNR 20/40/60 dB",
+                   "seeds_per_snr": args.seeds},
+        "training": {"samples": int(F.shape[0]), "positives": int(Y[:, 0].sum()), "loss": loss,
+                     "trajectory_s": t_traj, "train_s": t_train},
+        "per_snr": per_snr,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_batched(args) -> int:
     """Batched decoding: `--batch` instances with n log-uniform in [2^12, 2^18], m/n in
     [0.05, 0.5], k/m in [0.05, 0.3], d = 7, SNR in [20, 60] dB.  The schedule is tuned
@@ -178,7 +226,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "batched"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batched", "learned"], default="headline",
                     help="batched: 512 uneven instances in one persistent launch, against "
                          "sequential single decodes of the same instances")
     ap.add_argument("--batch", type=int, default=512)
@@ -195,6 +243,8 @@ def main() -> int:
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "learned":
+        return bench_learned(args)
 
     import torch
     from paper_1704_09012_amd import rl0 as R

@@ -225,7 +225,7 @@ int rl0_mlp_labels(const float* x_true, const float* x_hat, int32_t n, int32_t d
                    void* stream);
 
 /* Loss over N samples (feats [N][d+1], labels [N][2]): the mean of
- * BCE(logit, y_acc) + lam * y_acc * (value - y_val)^2.  grad [P] (device) <- its
+ * BCE(logit, y_acc) + lam * (value - y_val)^2.  grad [P] (device) <- its
  * gradient at w (fp32 backpropagation); *loss_h <- the loss.  Synchronises. */
 int rl0_mlp_grad(const float* feats, const float* labels, int32_t N, int32_t d, const float* w, float lam,
                  float* grad, float* loss_h, void* stream);

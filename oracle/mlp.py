@@ -18,7 +18,9 @@ the contract the HIP kernels are checked against:
              +inf: nothing updates, as in the analytic loop); x'_j = x_hat_j + value
   labels     y_acc = 1 iff j in supp(x) and |x_j - x_hat_j| > 3 sigma_n / sqrt(d);
              y_val = x_j - x_hat_j
-  loss       mean over the batch of  BCE(logit, y_acc) + lam * y_acc * (value - y_val)^2
+  loss       mean over the batch of  BCE(logit, y_acc) + lam * (value - y_val)^2
+             (the value is fitted on every sample, so that a column the decision lets
+             through by mistake moves by about its true error, usually about 0)
   optimiser  Adam (Kingma and Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
              w <- w - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
 
@@ -142,10 +144,10 @@ def loss_and_grad(w: np.ndarray, F: np.ndarray, Y: np.ndarray, d: int, lam: floa
     N = F.shape[0]
     s, val = out[:, 0], out[:, 1]
     ya, yv = Y[:, 0].astype(np.float64), Y[:, 1].astype(np.float64)
-    loss = float(np.mean(_bce_with_logits(s, ya) + lam * ya * (val - yv) ** 2))
+    loss = float(np.mean(_bce_with_logits(s, ya) + lam * (val - yv) ** 2))
     dout = np.empty_like(out)
     dout[:, 0] = (1.0 / (1.0 + np.exp(-s)) - ya) / N
-    dout[:, 1] = 2.0 * lam * ya * (val - yv) / N
+    dout[:, 1] = 2.0 * lam * (val - yv) / N
     gW3 = dout.T @ h2
     gb3 = dout.sum(axis=0)
     dz2 = (dout @ W3) * gelu_grad(z2)

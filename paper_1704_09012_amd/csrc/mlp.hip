@@ -146,10 +146,10 @@ __global__ __launch_bounds__(kGradBlock) void k_mlp_grad(const float* __restrict
         if (sm < ns) {
             const float ya = Ys[2 * sm], yv = Ys[2 * sm + 1];
             const float dv = o1 - yv;
-            l = fmaxf(o0, 0.0f) - ya * o0 + log1pf(expf(-fabsf(o0))) + lam * ya * dv * dv;
+            l = fmaxf(o0, 0.0f) - ya * o0 + log1pf(expf(-fabsf(o0))) + lam * dv * dv;
             const float sig = 1.0f / (1.0f + expf(-o0));
             g0 = (sig - ya) * inv_n;
-            g1 = 2.0f * lam * ya * dv * inv_n;
+            g1 = 2.0f * lam * dv * inv_n;
         }
         dO[2 * sm] = g0;
         dO[2 * sm + 1] = g1;

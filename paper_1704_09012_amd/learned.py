@@ -75,3 +75,31 @@ def train(F, Y, d: int = 7, epochs: int = 4, batch: int = 4096, lr: float = 1e-3
     steps = max(1, epochs * (F.shape[0] // batch))
     loss = R.mlp_train(F, Y, w, m, v, steps, 0, lr=lr, batch=batch)
     return w, loss
+
+
+def compare(w, n: int, m: int, k: int, snr_db: float, seeds, d: int = 7, device: str = "cuda") -> list[dict]:
+    """Decode each seeded instance of GM(n, m, k, d) at the given SNR with the analytic
+    decision and with the learned one (w); per instance: relative l2 errors, iterations
+    executed and accepted, and the wall time of each decode (inputs already on the GPU)."""
+    import time
+
+    torch = _torch()
+    out = []
+    for seed in seeds:
+        sig = float(np.float32(I.sigma_for_snr(snr_db, n, m, k, d)))
+        inst = I.draw_instance(n, m, k, d, sig, seed)
+        A = torch.from_numpy(inst.A_cols).to(device)
+        x = torch.from_numpy(inst.x_dense()).to(device)
+        y = R.sketch(A, x, m) + torch.from_numpy(inst.eta).to(device)
+        row = {"seed": seed, "sigma": sig}
+        for tag, kw in (("analytic", {}), ("learned", {"mlp": w})):
+            R.decode(A, y, sigma=sig, k=k, **kw)       # warm (constants, graphs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xh, st = R.decode(A, y, sigma=sig, k=k, **kw)
+            torch.cuda.synchronize()
+            row[tag] = {"rel_err": float(torch.linalg.norm(xh - x) / torch.linalg.norm(x)),
+                        "iterations": st["iterations"], "accepted": st["accepted"],
+                        "converged": st["converged"], "ms": 1e3 * (time.perf_counter() - t0)}
+        out.append(row)
+    return out

@@ -70,10 +70,10 @@ def test_loss_special_values():
     F = np.ones((4, d + 1))
     Y = np.array([[1, 2.0], [0, 5.0], [1, -1.0], [0, 0.0]])
     loss, g = M.loss_and_grad(w, F, Y, d, lam=1.0)
-    # BCE(0, y) = log 2 for either label; squared error only on positives: (4 + 1) / 4
-    assert math.isclose(loss, math.log(2) + 5.0 / 4, rel_tol=1e-12)
-    # d loss / d b3 = mean of (sigmoid(0) - y) and of 2 y (0 - y_val)
-    assert np.allclose(g[-2:], [np.mean(0.5 - Y[:, 0]), np.mean(2 * Y[:, 0] * (0 - Y[:, 1]))])
+    # BCE(0, y) = log 2 for either label; squared error of every value: (4 + 25 + 1 + 0) / 4
+    assert math.isclose(loss, math.log(2) + 30.0 / 4, rel_tol=1e-12)
+    # d loss / d b3 = mean of (sigmoid(0) - y) and of 2 (0 - y_val)
+    assert np.allclose(g[-2:], [np.mean(0.5 - Y[:, 0]), np.mean(2 * (0 - Y[:, 1]))])
 
 
 def test_adam_first_step_is_lr_times_sign():
