@@ -62,11 +62,12 @@ __device__ __forceinline__ unsigned long long hk_key(int j, float x) {
 // Column body of Alg. 1 on the snapshot r_hat, float32 contract.  cmask marks the rows
 // that pass the outer test; they are visited in ascending row order, so the first row
 // with the strictly largest n_e wins.  Returns whether the column proposes an update
-// and its omega.
+// and its omega.  Each lane walks its own set bits, so the lanes of a wave stay busy
+// whichever rows their columns flag.
 template <int D>
 __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int cmask,
-                                              const ScoreTables& tb, float alpha, int l1_test,
-                                              float* omega_out) {
+                                                      const ScoreTables& tb, float alpha, int l1_test,
+                                                      float* omega_out) {
     float n_z = 0.0f;
     float S1 = 0.0f;
 #pragma unroll

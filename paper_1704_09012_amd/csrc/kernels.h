@@ -74,12 +74,14 @@ struct IterParams {
 struct Workspace {
     long long* Sy;        // rint(2^40 y) [m]
     long long* S[2];      // fixed-point residual [m]
+    long long* D;         // [m] change of the residual during an iteration (zero between iterations)
     float* r[2];          // float32 residual [m]
     uint32_t* bm[2];      // bit i: |r[b]_i| >= tau of the next sweep [ceil(m/32)]
     int* cand_j[2];       // candidate list per iteration parity, one segment per sweep
     float* cand_x[2];     //   workgroup of seg_cap entries: column j, x'_j and
     float* cand_h[2];     //   x_hat_j (0 if j was not in the support)
     float* learned;       // [n] learned decisions of the current iteration (NaN: none)
+    uint4* Apk;           // [n] A_cols packed into one 16-byte word per column
     int seg_cap;          // entries per segment
     int sweep_grid;       // sweep workgroups (= segments)
     DevState* st;
@@ -106,8 +108,8 @@ hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStr
 hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0,
                           hipStream_t s);
-// One loop iteration (sweep, H_k and residual, finish).  ev (optional, 6 events) gets
-// the start and end of the sweep, select and row dispatches, in that order.  With
+// One loop iteration (the sweep, then H_k with the rows).  ev (optional, 6 events) gets
+// the start and end of the sweep dispatch in ev[0..1] and of the row dispatch in ev[4..5].  With
 // `learned` (per column: the update, NaN for none) the sweep takes those decisions in
 // place of the analytic column test.
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,

@@ -36,8 +36,6 @@ constexpr int kSweepChunk = kSweepBlock * kSweepCols;
 constexpr int kQueueRowInts = 7168;                 // 28 KiB of row indices of queued columns
 constexpr int kBmLdsWords = 12288;                  // 48 KiB: bitmasks of m <= 393216 rows
 constexpr int kBmPer = 4;                           // bitmask words per sweep thread held in registers
-constexpr int kSelectBlock = 1024;
-constexpr int kSelectGrid = 64;
 constexpr int kRowBlock = 1024;
 
 
@@ -180,9 +178,10 @@ __global__ void k_prep_support(const float* __restrict__ x0, int n, Workspace w,
 
 // Sy = rint(2^40 y), S0 = Sy
 __global__ void k_prep_rows(const float* __restrict__ y, long long* __restrict__ Sy, long long* __restrict__ S0,
-                            int m, DevState* st) {
+                            long long* __restrict__ Dl, int m, DevState* st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
+    Dl[i] = 0;
     const float yi = y[i];
     if (!isfinite(yi)) atomicOr(&st->err, kErrNonFinite);
     const long long s = to_fx(yi, &st->err);
@@ -259,6 +258,7 @@ struct SweepArgs {
     IterParams ip;
     DebugOut dbg;
     const float* learned;   // learned decisions per column (NaN: no update), or nullptr
+    const uint4* Apk;       // packed A_cols (Packing<D>), or nullptr
 };
 
 
@@ -276,31 +276,86 @@ __device__ __forceinline__ float current_value(int accepted, int j, float xp, fl
     return accepted ? hk_value(j, xp, kth) : xh;
 }
 
-// Row indices of the kSweepCols consecutive columns jb, jb+1, ... (16-byte loads when
-// all of them exist; A_cols is 16-byte aligned and a chunk starts on a multiple of 4).
+// Packed column indices: the d rows of a column in one 16-byte word, kField bits each
+// (row p in bits [p kField, (p + 1) kField)), usable when m <= 2^kField.
 template <int D>
-__device__ __forceinline__ void load_rows(const int32_t* __restrict__ A, int n, int jb, int (&rows)[kSweepCols][D]) {
-    if (jb + kSweepCols <= n) {
-        const int4* __restrict__ p4 = reinterpret_cast<const int4*>(A + static_cast<size_t>(jb) * D);
-        int flat[kSweepCols * D];
+struct Packing {
+    static constexpr int kField = D <= 4 ? 32 : 128 / D;
+};
+
+template <int D>
+__device__ __forceinline__ void unpack_rows(const uint4 w, int (&rows)[D]) {
+    constexpr int F = Packing<D>::kField;
+    const unsigned long long lo = (static_cast<unsigned long long>(w.y) << 32) | w.x;
+    const unsigned long long hi = (static_cast<unsigned long long>(w.w) << 32) | w.z;
+    constexpr unsigned long long mask = F >= 64 ? ~0ull : ((1ull << F) - 1ull);
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const int4 t = p4[k];
-            flat[4 * k] = t.x;
-            flat[4 * k + 1] = t.y;
-            flat[4 * k + 2] = t.z;
-            flat[4 * k + 3] = t.w;
-        }
-#pragma unroll
-        for (int q = 0; q < kSweepCols; ++q)
-#pragma unroll
-            for (int p = 0; p < D; ++p) rows[q][p] = flat[q * D + p];
-    } else {
-#pragma unroll
-        for (int q = 0; q < kSweepCols; ++q)
-#pragma unroll
-            for (int p = 0; p < D; ++p) rows[q][p] = (jb + q < n) ? A[static_cast<size_t>(jb + q) * D + p] : 0;
+    for (int p = 0; p < D; ++p) {
+        const int o = p * F;
+        unsigned long long v;
+        if (o + F <= 64)
+            v = lo >> o;
+        else if (o >= 64)
+            v = hi >> (o - 64);
+        else
+            v = (lo >> o) | (hi << (64 - o));
+        rows[p] = static_cast<int>(v & mask);
     }
+}
+
+// Row indices of the kSweepCols columns of thread tid in a chunk: column
+// cbase + q kSweepBlock + tid for slot q (consecutive lanes, consecutive columns).
+template <int D>
+__device__ __forceinline__ void load_rows(const int32_t* __restrict__ A, const uint4* __restrict__ Apk, int n,
+                                          int cbase, int tid, int (&rows)[kSweepCols][D]) {
+#pragma unroll
+    for (int q = 0; q < kSweepCols; ++q) {
+        const int j = cbase + q * kSweepBlock + tid;
+        if (j >= n) {
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = 0;
+        } else if (Apk) {
+            unpack_rows<D>(Apk[j], rows[q]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = A[static_cast<size_t>(j) * D + p];
+        }
+    }
+}
+
+// The packed form of A_cols (one 16-byte word per column).
+template <int D>
+__global__ void k_pack_cols(const int32_t* __restrict__ A, int n, uint4* __restrict__ Apk) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    constexpr int F = Packing<D>::kField;
+    unsigned long long lo = 0ull, hi = 0ull;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        const unsigned long long r = static_cast<unsigned int>(A[static_cast<size_t>(j) * D + p]);
+        const int o = p * F;
+        if (o + F <= 64) {
+            lo |= r << o;
+        } else if (o >= 64) {
+            hi |= r << (o - 64);
+        } else {
+            lo |= r << o;
+            hi |= r >> (64 - o);
+        }
+    }
+    Apk[j] = make_uint4(static_cast<unsigned>(lo), static_cast<unsigned>(lo >> 32), static_cast<unsigned>(hi),
+                        static_cast<unsigned>(hi >> 32));
+}
+
+// D[row] += rint(2^40 x_old) - rint(2^40 x_new) on the d rows of a column: the exact
+// change of the fixed-point residual when the column's value goes from x_old to x_new.
+template <int D>
+__device__ __forceinline__ void add_change(long long* Dl, const int (&rows)[D], float x_old, float x_new, int* err) {
+    const long long delta = (x_old != 0.0f ? to_fx(x_old, err) : 0) - (x_new != 0.0f ? to_fx(x_new, err) : 0);
+    if (delta == 0) return;
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+        atomicAdd(reinterpret_cast<unsigned long long*>(Dl + rows[p]), static_cast<unsigned long long>(delta));
 }
 
 // The sweep: one workgroup per CU, each owning chunks of kSweepChunk columns (thread t
@@ -332,7 +387,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 
     // ---- round 1
     int rows[kSweepCols][D];
-    load_rows<D>(a.A, a.n, blockIdx.x * kSweepChunk + kSweepCols * tid, rows);
+    load_rows<D>(a.A, a.Apk, a.n, blockIdx.x * kSweepChunk, tid, rows);
     float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
     float tzl = 0.0f, tel = 0.0f;
     if (!a.tb.exact) {
@@ -370,12 +425,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         bw0 = reinterpret_cast<const uint4*>(a.w.bm[0])[tid];
         bw1 = reinterpret_cast<const uint4*>(a.w.bm[1])[tid];
     }
-    const int i0 = blockIdx.x * kSweepBlock + tid;
-    long long s0v = 0, s1v = 0;
-    if (i0 < a.m) {
-        s0v = a.w.S[0][i0];
-        s1v = a.w.S[1][i0];
-    }
     if (!a.tb.exact) {
         reinterpret_cast<float4*>(Tz)[tid] = tz4;
         reinterpret_cast<float4*>(Te)[tid] = te4;
@@ -400,7 +449,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     const Slot s = s_sh;
     if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
     if (s.done) return;
-    const int c = s.cur, tr = c ^ 1;
+    const int c = s.cur;
     const int acc = s.accepted_last;
     const float* __restrict__ r = a.w.r[c];
     const uint32_t* __restrict__ bmg = a.w.bm[c];
@@ -426,13 +475,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             for (int wi = tid; wi < words; wi += kSweepBlock) bml[wi] = bmg[wi];
         }
     }
-    if (i0 < a.m) a.w.S[tr][i0] = c ? s1v : s0v;
-    for (int i = i0 + gridDim.x * kSweepBlock; i < a.m; i += gridDim.x * kSweepBlock) a.w.S[tr][i] = a.w.S[c][i];
 
     for (int chunk = blockIdx.x; chunk < a.chunks; chunk += gridDim.x) {
         const int cbase = chunk * kSweepChunk;
-        const int jb = cbase + kSweepCols * tid;
-        if (chunk != static_cast<int>(blockIdx.x)) load_rows<D>(a.A, a.n, jb, rows);
+        if (chunk != static_cast<int>(blockIdx.x)) load_rows<D>(a.A, a.Apk, a.n, cbase, tid, rows);
         reinterpret_cast<float4*>(supv)[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (tid == 0) qn = 0;
         __syncthreads();
@@ -456,13 +502,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             if (v != 0.0f && j >= cbase && j < cbase + kSweepChunk) supv[j - cbase] = v;
         }
         __syncthreads();
-        const float4 sv4 = reinterpret_cast<const float4*>(supv)[tid];
-        const float svq[kSweepCols] = {sv4.x, sv4.y, sv4.z, sv4.w};
+        float svq[kSweepCols];
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q) svq[q] = supv[q * kSweepBlock + tid];
         if (a.learned) {
             // the learned decision replaces the column test: x'_j = x_hat_j + value
 #pragma unroll
             for (int q = 0; q < kSweepCols; ++q) {
-                const int j = jb + q;
+                const int j = cbase + q * kSweepBlock + tid;
                 if (j >= a.n) continue;
                 const float lv = a.learned[j];
                 const bool upd = lv == lv;
@@ -476,6 +523,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     out_x[o] = xp;
                     out_h[o] = svq[q];
                     if (xp != 0.0f) atomicAdd(&seg_z, 1);
+                    add_change<D>(a.w.D, rows[q], svq[q], xp, &st->err);
                 } else if (svq[q] != 0.0f) {
                     const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
                     out_j[o] = j;
@@ -489,7 +537,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         // outer test of every row of my columns: one bit each from the bitmask
 #pragma unroll
         for (int q = 0; q < kSweepCols; ++q) {
-            const int j = jb + q;
+            const int j = cbase + q * kSweepBlock + tid;
             if (j >= a.n) continue;
             unsigned int cm = 0u;
 #pragma unroll
@@ -545,13 +593,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             if (a.dbg.omega) a.dbg.omega[jq] = upd ? om : 0.0f;
             if (upd) atomicAdd(&seg_upd, 1);
             if (upd) {
-                // an updated column goes to the front
+                // an updated column goes to the front; its residual change is added at
+                // once, as if H_k keeps it (the select kernel takes back what it drops)
                 const float xp = xhq + om;
                 const int o = atomicAdd(&seg_f, 1);
                 out_j[o] = jq;
                 out_x[o] = xp;
                 out_h[o] = xhq;
                 if (xp != 0.0f) atomicAdd(&seg_z, 1);
+                add_change<D>(a.w.D, rr, xhq, xp, &st->err);
             } else if (xhq != 0.0f) {
                 const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
                 out_j[o] = jq;
@@ -571,12 +621,18 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 
 // ------------------------------------------------------------------ H_k and residual change
 
-struct SelectArgs {
+// ------------------------------------------------------------------ H_k and the rows
+
+struct FinishArgs {
     const int32_t* A;
-    int d, k;
+    int d, k, m;
     Workspace w;
     int it;
+    uint32_t tau_next;
 };
+
+constexpr int kLdsKeys = 12288;   // candidate keys a finish workgroup caches in LDS
+constexpr int kSelPer = 12;       // candidate loads in flight per thread (kLdsKeys / block)
 
 // Within one workgroup: the digit of the bucket (among 2048, highest first) that holds
 // the `rem`-th largest of the counted keys, the count above it and the bucket's count.
@@ -586,7 +642,7 @@ __device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, i
     const unsigned hi = hist[2047 - 2 * tid], lo = hist[2046 - 2 * tid];
     scan[tid] = hi + lo;
     __syncthreads();
-    for (int off = 1; off < kSelectBlock; off <<= 1) {
+    for (int off = 1; off < kRowBlock; off <<= 1) {
         const unsigned add = tid >= off ? scan[tid - off] : 0u;
         __syncthreads();
         scan[tid] += add;
@@ -605,23 +661,6 @@ __device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, i
     }
     __syncthreads();
 }
-
-constexpr int kLdsKeys = 12288;   // candidate keys a select workgroup caches in LDS
-constexpr int kSelPer = 12;       // candidate loads in flight per select thread (kLdsKeys / block)
-
-// H_k's effect on one candidate: the exact change of the residual of column j.
-__device__ __forceinline__ void apply_candidate(const SelectArgs& a, int tr, unsigned long long kth, int j,
-                                                float xp, float xh, int* err) {
-    const float nv = hk_value(j, xp, kth);
-    if (nv == xh) return;
-    const long long delta = (xh != 0.0f ? to_fx(xh, err) : 0) - (nv != 0.0f ? to_fx(nv, err) : 0);
-    if (delta != 0) {
-        const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
-        for (int p = 0; p < a.d; ++p)
-            atomicAdd(reinterpret_cast<unsigned long long*>(a.w.S[tr] + col[p]), static_cast<unsigned long long>(delta));
-    }
-}
-
 
 // Within one workgroup: exclusive prefix sums of one int per segment (threads < nseg
 // hold their value in v) by wave scans; returns the total.  start[] gets the sums.
@@ -654,37 +693,42 @@ __device__ __forceinline__ size_t seg_phys(int seg, int cap, int front, int e) {
     return static_cast<size_t>(seg) * cap + (e < front ? e : cap - 1 - (e - front));
 }
 
-// Every workgroup computes the k-th largest key of H_k (the same value everywhere);
-// workgroup b then applies the candidates of waves w with w % gridDim.x == b.
-// When the nonzero candidates number at most k (the common case once the support has
-// formed), every one is kept, and only the front of each segment -- the columns the
-// sweep updated, x' != x_hat -- can change the residual: then a workgroup reads just
-// the front entries it applies.
-__global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
+// One kernel after the sweep.  H_k: when the nonzero candidates number at most k (the
+// common case once the support has formed) every one is kept and the sweep has already
+// added every residual change to D.  Otherwise every workgroup finds the k-th largest
+// key (|x'_j| bits, then smaller j) by an 11-bit radix select over the candidates and
+// takes back, on its own rows, the columns H_k drops (+rint(2^40 x'_j) per row).
+// Then, on its rows: S_trial = S_hat + D (D cleared for the next iteration), the
+// rounded residual r = fl32(2^-40 S), the partial sum of ||r||_1 and the outer-test
+// bitmasks of the next threshold for both possible outcomes of the decision.
+__global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     __shared__ unsigned long long keys[kLdsKeys];
     __shared__ unsigned short segmap[kLdsKeys];
     __shared__ unsigned hist[kHistBins];
-    __shared__ unsigned scan[kSelectBlock];
+    __shared__ unsigned scan[kRowBlock];
     __shared__ int seg_cnt[kSweepGridMax];
     __shared__ int seg_frt[kSweepGridMax];
     __shared__ int seg_start[kSweepGridMax];
     __shared__ int wtot[kSweepGridMax / 64];
+    __shared__ long long corr[kRowBlock];
+    __shared__ long long sh[kRowBlock / 64];
     __shared__ int digit;
     __shared__ unsigned above, bucket;
     __shared__ int nz_sh, upd_sh;
-    __shared__ Slot s_sh;
     const int me = a.it & 1;
     DevState* st = a.w.st;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int nseg = a.w.sweep_grid;
     const int cap = a.w.seg_cap;
-    const int G = gridDim.x;
-    const int* __restrict__ cj = a.w.cand_j[me];
-    const float* __restrict__ cx = a.w.cand_x[me];
-    const float* __restrict__ ch = a.w.cand_h[me];
+    const int words = (a.m + 31) >> 5;
+    // rows of this workgroup: [row0, row1), whole multiples of the block
+    const int per = ((a.m + gridDim.x * kRowBlock - 1) / (gridDim.x * kRowBlock)) * kRowBlock;
+    const int row0 = blockIdx.x * per;
+    const int row1 = min(a.m, row0 + per);
 
-    // ---- round 1: slot and segment sizes
+    // ---- round 1: slot, segment sizes and this workgroup's first rows
+    const Slot s = st->slot[me];
     int myc = 0, myf = 0, myz = 0, myu = 0;
     if (tid < nseg) {
         myc = st->seg_count[me][tid];
@@ -692,8 +736,16 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
         myz = st->seg_nz[me][tid];
         if (blockIdx.x == 0) myu = st->seg_updates[me][tid];
     }
+    long long s0 = 0, s1 = 0, dl = 0;
+    {
+        const int i = row0 + tid;
+        if (i < row1) {
+            s0 = a.w.S[0][i];
+            s1 = a.w.S[1][i];
+            dl = a.w.D[i];
+        }
+    }
     if (tid == 0) {
-        s_sh = st->slot[me];
         nz_sh = 0;
         upd_sh = 0;
     }
@@ -702,71 +754,49 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
         seg_frt[tid] = myf;
     }
     __syncthreads();
-    if (s_sh.done) return;
-    const int tr = s_sh.cur ^ 1;
+    if (s.done) return;
+    const int c = s.cur, tr = c ^ 1;
     if (myz) atomicAdd(&nz_sh, myz);
     if (myu) atomicAdd(&upd_sh, myu);
     __syncthreads();
     if (blockIdx.x == 0 && tid == 0) st->updates_total += upd_sh;
     const bool all_kept = nz_sh <= a.k;
-    // entries visited: the fronts if everything is kept, else everything
-    const int count = segment_scan(all_kept ? myf : myc, nseg, seg_start, wtot);
-    const bool fast = count <= kLdsKeys;
-    if (fast) {
-        for (int sg = tid >> 6; sg < nseg; sg += kSelectBlock / 64) {
-            const int cnt = all_kept ? seg_frt[sg] : seg_cnt[sg];
-            for (int o = lane; o < cnt; o += 64) segmap[seg_start[sg] + o] = static_cast<unsigned short>(sg);
-        }
-        __syncthreads();
-    }
+    const int* __restrict__ cj = a.w.cand_j[me];
+    const float* __restrict__ cx = a.w.cand_x[me];
 
-    // ---- round 2: candidates (in registers and LDS on the fast path)
-    float xr[kSelPer], hr[kSelPer];
-    int jr[kSelPer];
-    if (fast) {
-#pragma unroll
-        for (int q = 0; q < kSelPer; ++q) {
-            const int e = q * kSelectBlock + tid;
-            xr[q] = 0.0f;
-            hr[q] = 0.0f;
-            jr[q] = 0;
-            // with every entry kept, a workgroup needs only the entries it applies
-            const bool own = ((e >> 6) % G) == static_cast<int>(blockIdx.x);
-            if (e < count && (own || !all_kept)) {
-                const int sg = segmap[e];
-                const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
-                xr[q] = cx[ix];
-                jr[q] = cj[ix];
-                if (own) hr[q] = ch[ix];
-            }
-        }
-        if (!all_kept) {
+    // ---- H_k's threshold, only when something is dropped
+    unsigned long long kth = 1ull << 32;   // every nonzero entry is kept
+    int count = 0;
+    bool fast = true;
+    if (!all_kept) {
+        count = segment_scan(myc, nseg, seg_start, wtot);
+        fast = count <= kLdsKeys;
+        if (fast) {
+            for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64)
+                for (int o = lane; o < seg_cnt[sg]; o += 64) segmap[seg_start[sg] + o] = static_cast<unsigned short>(sg);
+            __syncthreads();
 #pragma unroll
             for (int q = 0; q < kSelPer; ++q) {
-                const int e = q * kSelectBlock + tid;
-                if (e < count) keys[e] = xr[q] != 0.0f ? hk_key(jr[q], xr[q]) : 0ull;
+                const int e = q * kRowBlock + tid;
+                if (e < count) {
+                    const int sg = segmap[e];
+                    const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
+                    const float x = cx[ix];
+                    keys[e] = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
+                }
             }
+            __syncthreads();
         }
-    }
-    __syncthreads();
-
-    // ---- the k-th largest key
-    unsigned long long kth;
-    if (all_kept) {
-        kth = 1ull << 32;   // every nonzero entry is kept
-    } else {
         unsigned long long prefix = 0ull, pmask = 0ull;
         unsigned rem = static_cast<unsigned>(a.k);
         bool exact = false;
-        const int shifts[6] = {52, 41, 30, 19, 8, 0};
-        const int widths[6] = {11, 11, 11, 11, 11, 8};
         for (int pass = 0; pass < 6 && !exact; ++pass) {
-            const int sh = shifts[pass];
-            const unsigned dmask = (1u << widths[pass]) - 1u;
+            const int sft = pass < 5 ? 52 - 11 * pass : 0;
+            const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
             hist[tid] = 0u;
-            hist[tid + kSelectBlock] = 0u;
+            hist[tid + kRowBlock] = 0u;
             __syncthreads();
-            for (int e0 = 0; e0 < count; e0 += kSelectBlock) {
+            for (int e0 = 0; e0 < count; e0 += kRowBlock) {
                 const int e = e0 + tid;
                 unsigned long long key = 0ull;
                 if (e < count) {
@@ -783,13 +813,12 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
                         key = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
                     }
                 }
-                const bool in = key != 0ull && (key & pmask) == prefix;
-                hist_add(hist, static_cast<unsigned>((key >> sh) & dmask), in);
+                hist_add(hist, static_cast<unsigned>((key >> sft) & dmask), key != 0ull && (key & pmask) == prefix);
             }
             __syncthreads();
             find_digit(hist, rem, scan, &digit, &above, &bucket);
-            prefix |= static_cast<unsigned long long>(digit) << sh;
-            pmask |= static_cast<unsigned long long>(dmask) << sh;
+            prefix |= static_cast<unsigned long long>(digit) << sft;
+            pmask |= static_cast<unsigned long long>(dmask) << sft;
             rem -= above;
             exact = (rem == bucket);
         }
@@ -797,74 +826,78 @@ __global__ __launch_bounds__(kSelectBlock) void k_select_apply(SelectArgs a) {
     }
     if (blockIdx.x == 0 && tid == 0) st->kth_key[me] = kth;
 
-    // ---- exact residual change of every changed column
-    if (fast) {
-#pragma unroll
-        for (int q = 0; q < kSelPer; ++q) {
-            const int e = q * kSelectBlock + tid;
-            if (e < count && ((e >> 6) % G) == static_cast<int>(blockIdx.x))
-                apply_candidate(a, tr, kth, jr[q], xr[q], hr[q], &st->err);
-        }
-    } else {
-        for (int e = tid; e < count; e += kSelectBlock) {
-            if (((e >> 6) % G) != static_cast<int>(blockIdx.x)) continue;
-            int lo = 0, hi = nseg - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            const size_t ix = seg_phys(lo, cap, seg_frt[lo], e - seg_start[lo]);
-            apply_candidate(a, tr, kth, cj[ix], cx[ix], ch[ix], &st->err);
-        }
-    }
-}
-
-// ------------------------------------------------------------------ finish rows
-
-struct FinishArgs {
-    int m;
-    Workspace w;
-    int it;
-    uint32_t tau_next;
-};
-
-__global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
-    __shared__ long long sh[kRowBlock / 64];
-    const int me = a.it & 1;
-    DevState* st = a.w.st;
-    const Slot s = st->slot[me];
-    const int words = (a.m + 31) >> 5;
+    // ---- the rows, a block at a time
     long long l = 0;
-    for (int base = blockIdx.x * kRowBlock; base < a.m; base += gridDim.x * kRowBlock) {
-        const int i = base + threadIdx.x;
-        // both buffers are loaded in the same round as the slot that says which is which
-        long long s0 = 0, s1 = 0;
-        if (i < a.m) {
-            s0 = a.w.S[0][i];
-            s1 = a.w.S[1][i];
+    for (int base = row0; base < row1; base += kRowBlock) {
+        const int i = base + tid;
+        if (base != row0) {
+            s0 = s1 = dl = 0;
+            if (i < row1) {
+                s0 = a.w.S[0][i];
+                s1 = a.w.S[1][i];
+                dl = a.w.D[i];
+            }
         }
-        if (s.done) return;
-        const int c = s.cur, tr = c ^ 1;
+        if (!all_kept) {
+            // the dropped columns' rows in [base, base + kRowBlock)
+            corr[tid] = 0;
+            __syncthreads();
+            for (int e = tid; e < count; e += kRowBlock) {
+                int sg;
+                unsigned long long key;
+                if (fast) {
+                    key = keys[e];
+                    sg = segmap[e];
+                } else {
+                    int lo = 0, hi = nseg - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    sg = lo;
+                    key = 1ull;   // decided below from the entry itself
+                }
+                if (key == 0ull || (fast && key >= kth)) continue;
+                const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
+                const float x = cx[ix];
+                const int j = cj[ix];
+                if (x == 0.0f || hk_key(j, x) >= kth) continue;
+                const long long delta = to_fx(x, &st->err);
+                const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
+                for (int p = 0; p < a.d; ++p) {
+                    const int row = col[p];
+                    if (row >= base && row < base + kRowBlock)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(&corr[row - base]),
+                                  static_cast<unsigned long long>(delta));
+                }
+            }
+            __syncthreads();
+            dl += corr[tid];
+        }
         bool bt = false, bc = false;
-        if (i < a.m) {
-            const float v = from_fx(tr ? s1 : s0);
-            const float vc = from_fx(tr ? s0 : s1);
+        if (i < row1) {
+            // the trial residual: the current one plus this iteration's changes
+            const long long sc = c ? s1 : s0;
+            const long long snew = sc + dl;
+            a.w.S[tr][i] = snew;
+            a.w.D[i] = 0;
+            const float v = from_fx(snew);
             a.w.r[tr][i] = v;
             l += l1_term(v);
             bt = abs_bits(v) >= a.tau_next;
-            bc = abs_bits(vc) >= a.tau_next;
+            bc = abs_bits(from_fx(sc)) >= a.tau_next;
         }
         const unsigned long long bmt = __ballot(bt);
         const unsigned long long bmc = __ballot(bc);
-        if ((threadIdx.x & 63) == 0) {
-            const int wb = base + (threadIdx.x & ~63);
+        if (lane == 0) {
+            const int wb = base + (tid & ~63);
             store_bits(a.w.bm[tr], words, wb, bmt);
             store_bits(a.w.bm[c], words, wb, bmc);
         }
+        if (!all_kept) __syncthreads();   // corr is reused by the next block of rows
     }
-    if (s.done) return;
     const long long tot = block_sum_rows(l, sh);
-    if (threadIdx.x == 0) st->L_part[me][blockIdx.x] = tot;
+    if (tid == 0) st->L_part[me][blockIdx.x] = tot;
 }
 
 // ------------------------------------------------------------------ final decision
@@ -923,6 +956,42 @@ hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s, const hipEvent_t* e
     return launch_timed(k_sweep<D>, a.w.sweep_grid, kSweepBlock, s, ev, a);
 }
 
+template <int D>
+bool pack_fits(int m) {
+    constexpr int F = Packing<D>::kField;
+    return F >= 32 || static_cast<long long>(m) <= (1ll << F);
+}
+
+// The packed indices when they fit (d <= 16 and m <= 2^field); false if not.
+template <int D>
+bool launch_pack_d(const int32_t* A, int n, int m, uint4* Apk, hipStream_t s) {
+    if (!pack_fits<D>(m)) return false;
+    k_pack_cols<D><<<blocks(n, 256), 256, 0, s>>>(A, n, Apk);
+    return true;
+}
+
+bool launch_pack(int d, const int32_t* A, int n, int m, uint4* Apk, hipStream_t s) {
+    switch (d) {
+#define RL0_PK(D) \
+    case D: return launch_pack_d<D>(A, n, m, Apk, s);
+        RL0_PK(1) RL0_PK(2) RL0_PK(3) RL0_PK(4) RL0_PK(5) RL0_PK(6) RL0_PK(7) RL0_PK(8)
+        RL0_PK(9) RL0_PK(10) RL0_PK(11) RL0_PK(12) RL0_PK(13) RL0_PK(14) RL0_PK(15) RL0_PK(16)
+#undef RL0_PK
+        default: return false;
+    }
+}
+
+bool pack_usable(int d, int m) {
+    switch (d) {
+#define RL0_PF(D) \
+    case D: return pack_fits<D>(m);
+        RL0_PF(1) RL0_PF(2) RL0_PF(3) RL0_PF(4) RL0_PF(5) RL0_PF(6) RL0_PF(7) RL0_PF(8)
+        RL0_PF(9) RL0_PF(10) RL0_PF(11) RL0_PF(12) RL0_PF(13) RL0_PF(14) RL0_PF(15) RL0_PF(16)
+#undef RL0_PF
+        default: return false;
+    }
+}
+
 hipError_t launch_sweep(int d, const SweepArgs& a, hipStream_t s, const hipEvent_t* ev = nullptr) {
     switch (d) {
         case 1: return launch_sweep_d<1>(a, s, ev);
@@ -955,8 +1024,8 @@ size_t workspace_bytes(int n, int m) {
     const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
     (void)wn;
-    return 3 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(4ull * n) +
-           al(sizeof(DevState));
+    return 4 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(4ull * n) +
+           al(16ull * n) + al(sizeof(DevState));
 }
 
 void carve_workspace(void* base, int n, int m, Workspace* w) {
@@ -966,6 +1035,7 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
     w->Sy = reinterpret_cast<long long*>(take(8ull * m));
     for (int b = 0; b < 2; ++b) w->S[b] = reinterpret_cast<long long*>(take(8ull * m));
+    w->D = reinterpret_cast<long long*>(take(8ull * m));
     for (int b = 0; b < 2; ++b) w->r[b] = reinterpret_cast<float*>(take(4ull * m));
     for (int b = 0; b < 2; ++b) w->bm[b] = reinterpret_cast<uint32_t*>(take(4 * wm + 16));
     (void)wn;
@@ -977,6 +1047,7 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     w->seg_cap = seg_capacity(n);
     w->sweep_grid = sweep_grid(n);
     w->learned = reinterpret_cast<float*>(take(4ull * n));
+    w->Apk = reinterpret_cast<uint4*>(take(16ull * n));
     w->st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
 }
 
@@ -1022,7 +1093,8 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
     k_prep_state<<<1, 256, 0, s>>>(w.st);
     if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
     if (x_hat0) k_prep_support<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, dm.n, w, slot);
-    k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], dm.m, w.st);
+    k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], w.D, dm.m, w.st);
+    launch_pack(dm.d, A, dm.n, dm.m, w.Apk, s);
     if (x_hat0) k_prep_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.d, x_hat0, w.S[0], w.st);
     k_prep_rows2<<<kRowGrid, kRowBlock, 0, s>>>(w.S[0], w.r[0], w.bm[0], dm.m, ip0.tau_bits, w.st, slot);
     k_prep_slot<<<1, 256, 0, s>>>(w.st, slot);
@@ -1043,12 +1115,10 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     a.ip = ip;
     a.dbg = dbg;
     a.learned = learned;
+    a.Apk = pack_usable(dm.d, dm.m) ? w.Apk : nullptr;
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
-    const SelectArgs sa{A, dm.d, dm.k, w, ip.it};
-    e = launch_timed(k_select_apply, kSelectGrid, kSelectBlock, s, ev ? ev + 2 : nullptr, sa);
-    if (e != hipSuccess) return e;
-    const FinishArgs fa{dm.m, w, ip.it, ip.tau_next};
+    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next};
     return launch_timed(k_finish_rows, kRowGrid, kRowBlock, s, ev ? ev + 4 : nullptr, fa);
 }
 

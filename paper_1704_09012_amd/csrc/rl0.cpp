@@ -45,8 +45,8 @@ std::mutex g_mu;
 
 struct SweepProfile {
     bool enabled = false;
-    std::vector<hipEvent_t> pool;   // per iteration: start and end of the sweep, select, finish
-    double total_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // all launched, then executed
+    std::vector<hipEvent_t> pool;   // per iteration: start and end of the sweep, (unused), the row kernel
+    double total_ms[4] = {0.0, 0.0, 0.0, 0.0};   // sweep and row kernel: all launched, then executed
     long long launches = 0, executed = 0;
 };
 SweepProfile g_prof;
@@ -67,15 +67,15 @@ hipEvent_t* profile_events(int it) {
 void profile_collect(int launched, int executed) {
     if (!g_prof.enabled) return;
     for (int it = 0; it < launched && 6 * static_cast<size_t>(it) + 5 < g_prof.pool.size(); ++it) {
-        float ms[3] = {0.0f, 0.0f, 0.0f};
-        bool ok = true;
-        for (int k = 0; k < 3; ++k)
-            ok = ok && hipEventElapsedTime(&ms[k], g_prof.pool[6 * it + 2 * k], g_prof.pool[6 * it + 2 * k + 1]) == hipSuccess;
+        float ms[2] = {0.0f, 0.0f};
+        const bool ok =
+            hipEventElapsedTime(&ms[0], g_prof.pool[6 * it], g_prof.pool[6 * it + 1]) == hipSuccess &&
+            hipEventElapsedTime(&ms[1], g_prof.pool[6 * it + 4], g_prof.pool[6 * it + 5]) == hipSuccess;
         if (!ok) continue;
-        for (int k = 0; k < 3; ++k) g_prof.total_ms[k] += ms[k];
+        for (int k = 0; k < 2; ++k) g_prof.total_ms[k] += ms[k];
         g_prof.launches += 1;
         if (it < executed) {
-            for (int k = 0; k < 3; ++k) g_prof.total_ms[3 + k] += ms[k];
+            for (int k = 0; k < 2; ++k) g_prof.total_ms[2 + k] += ms[k];
             g_prof.executed += 1;
         }
     }
@@ -1229,7 +1229,7 @@ int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h) {
 int rl0_profile_read_kernels(double* ms_total_h, int64_t* counts_h) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!ms_total_h) return fail(RL0_EINVAL, "NULL pointer");
-    for (int k = 0; k < 6; ++k) ms_total_h[k] = g_prof.total_ms[k];
+    for (int k = 0; k < 4; ++k) ms_total_h[k] = g_prof.total_ms[k];
     if (counts_h) {
         counts_h[0] = g_prof.launches;
         counts_h[1] = g_prof.executed;

@@ -334,12 +334,12 @@ def profile_read() -> tuple[float, int]:
 def profile_read_kernels() -> dict:
     """Total milliseconds per kernel since profile_enable: over every launched iteration
     ("all") and over the iterations that ran before the stopping condition ("executed")."""
-    arr = (ctypes.c_double * 6)()
+    arr = (ctypes.c_double * 4)()
     cnt = (ctypes.c_int64 * 2)()
     _check(lib().rl0_profile_read_kernels(arr, cnt))
-    names = ("sweep", "select_apply", "finish_rows")
+    names = ("sweep", "hk_rows")
     return {"all": {k: arr[i] for i, k in enumerate(names)}, "all_launches": cnt[0],
-            "executed": {k: arr[3 + i] for i, k in enumerate(names)}, "executed_launches": cnt[1]}
+            "executed": {k: arr[2 + i] for i, k in enumerate(names)}, "executed_launches": cnt[1]}
 
 
 def release() -> None:
