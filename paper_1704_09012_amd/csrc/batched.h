@@ -29,7 +29,7 @@ struct BatchProblem {
     float alpha, inv_h_z, inv_h_e;
     int exact, l1_test, validate, n_iters;
     int cols;                // columns per thread per tile: 1, 2 or 4 (the schedule)
-    int pad_;
+    uint32_t e_zero_bits;    // |a| >= this (float bits)  =>  e-score 0
 };
 
 // What a decode did (device memory, one per instance).

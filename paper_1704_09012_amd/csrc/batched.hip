@@ -292,7 +292,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         }
     if (tid == 0) sh.err = 0;
     __syncthreads();
-    const ScoreTables tb{Tz, Te, P.inv_h_z, P.inv_h_e, P.exact};
+    const ScoreTables tb{Tz, Te, P.inv_h_z, P.inv_h_e, P.exact, P.e_zero_bits};
 
     // ---- ingest: the columns (rows in range, strictly ascending), y, the state
     if (P.validate) {

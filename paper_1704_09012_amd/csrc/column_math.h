@@ -85,6 +85,13 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
 #pragma unroll
         for (int q = 1; q < D; ++q)
             if (p == q) vp = v[q];
+        // every e-score is at most 1 and is 0 once |v_p - v_l| reaches the end of the
+        // table, so n_e <= 1 + (rows closer than that); when even that bound fails the
+        // test, the candidate fails it (fp32 sums and differences are monotone)
+        int near = 0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) near += (l != p && abs_bits(vp - v[l]) < tb.e_zero_bits) ? 1 : 0;
+        if (!((1.0f + static_cast<float>(near)) - n_z >= alpha)) continue;
         float n_e = 0.0f, s = 0.0f;
 #pragma unroll
         for (int l = 0; l < D; ++l) {

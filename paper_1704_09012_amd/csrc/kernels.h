@@ -56,6 +56,7 @@ struct ScoreTables {
     const float* Te;   // Tz + kTableStrideFloats
     float inv_h_z, inv_h_e;
     int exact;         // indicator scores (sigma = 0)
+    uint32_t e_zero_bits;   // |a| >= this (float bits)  =>  e-score 0
 };
 
 struct IterParams {

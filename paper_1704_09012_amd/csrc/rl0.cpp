@@ -332,6 +332,7 @@ rl0::ScoreTables tables_of(const DeviceConstants* dc) {
     tb.inv_h_z = dc->hc.inv_h_z;
     tb.inv_h_e = dc->hc.inv_h_e;
     tb.exact = dc->hc.exact ? 1 : 0;
+    tb.e_zero_bits = dc->hc.e_zero_bits;
     return tb;
 }
 
@@ -559,6 +560,7 @@ int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_s
         B.inv_h_z = dc->hc.inv_h_z;
         B.inv_h_e = dc->hc.inv_h_e;
         B.exact = dc->hc.exact ? 1 : 0;
+        B.e_zero_bits = dc->hc.e_zero_bits;
         B.l1_test = q.params.l1_test;
         B.validate = q.params.validate;
         B.n_iters = dc->hc.n_iters;
