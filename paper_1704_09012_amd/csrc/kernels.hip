@@ -388,16 +388,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     // ---- round 1
     int rows[kSweepCols][D];
     load_rows<D>(a.A, a.Apk, a.n, blockIdx.x * kSweepChunk, tid, rows);
-    float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
-    float tzl = 0.0f, tel = 0.0f;
-    if (!a.tb.exact) {
-        tz4 = reinterpret_cast<const float4*>(a.tb.Tz)[tid];
-        te4 = reinterpret_cast<const float4*>(a.tb.Te)[tid];
-        if (tid == 0) {
-            tzl = a.tb.Tz[kTableN];
-            tel = a.tb.Te[kTableN];
-        }
-    }
     Slot prev{};
     int err = 0;
     if (tid == 0) {
@@ -425,14 +415,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         bw0 = reinterpret_cast<const uint4*>(a.w.bm[0])[tid];
         bw1 = reinterpret_cast<const uint4*>(a.w.bm[1])[tid];
     }
-    if (!a.tb.exact) {
-        reinterpret_cast<float4*>(Tz)[tid] = tz4;
-        reinterpret_cast<float4*>(Te)[tid] = te4;
-        if (tid == 0) {
-            Tz[kTableN] = tzl;
-            Te[kTableN] = tel;
-        }
-    }
     for (int off = 32; off > 0; off >>= 1) lp += __shfl_down(lp, off);
     if ((tid & 63) == 0) red[tid >> 6] = lp;
     __syncthreads();
@@ -449,6 +431,18 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     const Slot s = s_sh;
     if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
     if (s.done) return;
+    // the score tables are needed only by the consensus test: their loads are issued
+    // now, behind the index stream, and land in LDS with the bit tests
+    float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
+    float tzl = 0.0f, tel = 0.0f;
+    if (!a.tb.exact) {
+        tz4 = reinterpret_cast<const float4*>(a.tb.Tz)[tid];
+        te4 = reinterpret_cast<const float4*>(a.tb.Te)[tid];
+        if (tid == 0) {
+            tzl = a.tb.Tz[kTableN];
+            tel = a.tb.Te[kTableN];
+        }
+    }
     const int c = s.cur;
     const int acc = s.accepted_last;
     const float* __restrict__ r = a.w.r[c];
@@ -560,6 +554,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 out_j[o] = j;
                 out_x[o] = svq[q];
                 out_h[o] = svq[q];
+            }
+        }
+        if (chunk == static_cast<int>(blockIdx.x) && !a.tb.exact) {
+            reinterpret_cast<float4*>(Tz)[tid] = tz4;
+            reinterpret_cast<float4*>(Te)[tid] = te4;
+            if (tid == 0) {
+                Tz[kTableN] = tzl;
+                Te[kTableN] = tel;
             }
         }
         __syncthreads();
