@@ -40,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # per dispatch at this workload) and the factors a 256 MiB plain copy gives each counter;
 # valid only for the kernel source they were taken on.
 SWEEP_COUNTERS = {
-    "kernels_sha256": "910e241d4e5925e1c41894c3d13875622235b74d8f8fa8f29416d9fc16fa4aba",
-    "fetch_kib": 20145.8, "write_kib": 672.3, "fetch_factor": 2.000, "write_factor": 1.000,
+    "kernels_sha256": "7cc5990fc45a05c8982b246a0ff02937ac60405c3a89e9a856a789878ec309d0",
+    "fetch_kib": 13267.5, "write_kib": 171.6, "fetch_factor": 2.000, "write_factor": 1.000,
 }
 
 
