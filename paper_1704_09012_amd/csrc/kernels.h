@@ -31,6 +31,8 @@ struct Slot {
     int accepted;      // accepted iterations so far
     int iterations;    // executed iterations so far
     int accepted_last; // the last decision accepted
+    int t_step;        // schedule step (index of t) of the last executed iteration
+    int last_par;      // parity of the last sweep that ran: its segments hold x_hat
 };
 
 // Nothing here is updated by contended atomics: every workgroup writes its own entry
@@ -40,6 +42,7 @@ struct DevState {
     unsigned long long kth_key[2];        // smallest key H_k keeps
     int updates_total;                    // column updates proposed, summed over iterations
     int err;                              // ErrFlag bits
+    int peek_cur, peek_done;              // the coming decision, evaluated ahead (learned decode)
     int seg_count[2][kSweepGridMax];      // candidates written by each sweep workgroup
     int seg_front[2][kSweepGridMax];      //   of which at the segment's front (tested columns)
     int seg_nz[2][kSweepGridMax];         //   of which with x' != 0
@@ -68,6 +71,8 @@ struct IterParams {
     int it;
     int n_iters;
     double tol_fx;        // tolerance in units of 2^-30 (negative: never converged)
+    int step = 0;         // index of t in the schedule (= it, except in the learned decode)
+    int retry = 0;        // 1: an analytic retry, skipped when the iteration before was accepted
 };
 
 // Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.  x_hat
@@ -82,6 +87,8 @@ struct Workspace {
     float* cand_x[2];     //   workgroup of seg_cap entries: column j, x'_j and
     float* cand_h[2];     //   x_hat_j (0 if j was not in the support)
     float* learned;       // [n] learned decisions of the current iteration (NaN: none)
+    float* lcache;        // [2n] the network's (logit, value) per column at its last evaluation
+    float* reval[2];      // [m] residuals the learned decisions were last evaluated on
     uint4* Apk;           // [n] A_cols packed into one 16-byte word per column
     int seg_cap;          // entries per segment
     int sweep_grid;       // sweep workgroups (= segments)
@@ -116,12 +123,14 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
                             hipStream_t s, const hipEvent_t* ev = nullptr, const float* learned = nullptr);
-// Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat (the run
-// started at iteration it0).
-hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,
+// The decision the next sweep will take, written ahead to DevState::peek_cur/peek_done
+// (ip.it = that sweep's iteration).
+hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s);
+// Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat.
+hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
                          float* x_out, hipStream_t s);
 // After launch_finish: H_k(x') of the last executed iteration, zero elsewhere.
-hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, int it0, float* x_trial,
+hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, float* x_trial,
                             hipStream_t s);
 
 }  // namespace rl0

@@ -244,6 +244,69 @@ __global__ __launch_bounds__(256) void k_prep_slot(DevState* st, int slot) {
     s.accepted = 0;
     s.iterations = 0;
     s.accepted_last = 0;
+    s.t_step = 0;
+    s.last_par = slot;
+}
+
+// ------------------------------------------------------------------ H_k helpers
+
+// Within one workgroup: the digit of the bucket (among 2048, highest first) that holds
+// the `rem`-th largest of the counted keys, the count above it and the bucket's count.
+__device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, int* digit_out,
+                           unsigned* above_out, unsigned* bucket_out) {
+    const int tid = threadIdx.x;
+    const unsigned hi = hist[2047 - 2 * tid], lo = hist[2046 - 2 * tid];
+    scan[tid] = hi + lo;
+    __syncthreads();
+    for (int off = 1; off < kRowBlock; off <<= 1) {
+        const unsigned add = tid >= off ? scan[tid - off] : 0u;
+        __syncthreads();
+        scan[tid] += add;
+        __syncthreads();
+    }
+    const unsigned incl = scan[tid];
+    const unsigned before = incl - hi - lo;
+    if (before < rem && rem <= before + hi) {
+        *digit_out = 2047 - 2 * tid;
+        *above_out = before;
+        *bucket_out = hi;
+    } else if (before + hi < rem && rem <= incl) {
+        *digit_out = 2046 - 2 * tid;
+        *above_out = before + hi;
+        *bucket_out = lo;
+    }
+    __syncthreads();
+}
+
+// Within one workgroup: exclusive prefix sums of one int per segment (threads < nseg
+// hold their value in v) by wave scans; returns the total.  start[] gets the sums.
+__device__ __forceinline__ int segment_scan(int v, int nseg, int* start, int* wtot) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < kSweepGridMax) {
+        int incl = tid < nseg ? v : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        start[tid] = incl - (tid < nseg ? v : 0);
+        if (lane == 63) wtot[tid >> 6] = incl;
+    }
+    __syncthreads();
+    int total = 0;
+    for (int w = 0; w < kSweepGridMax / 64; ++w) total += wtot[w];
+    if (tid < kSweepGridMax) {
+        int add = 0;
+        for (int w = 0; w < (tid >> 6); ++w) add += wtot[w];
+        start[tid] += add;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Physical index of entry e (0 <= e < count) of a segment whose first `front` entries
+// sit at its start and the rest at its end, backwards.
+__device__ __forceinline__ size_t seg_phys(int seg, int cap, int front, int e) {
+    return static_cast<size_t>(seg) * cap + (e < front ? e : cap - 1 - (e - front));
 }
 
 // ------------------------------------------------------------------ sweep
@@ -421,7 +484,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     if (tid == 0) {
         long long Lt = 0;
         for (int w = 0; w < kSweepBlock / 64; ++w) Lt += red[w];
-        s_sh = decide_from(prev, err, it, a.ip.n_iters, a.ip.tol_fx, Lt);
+        Slot d = decide_from(prev, err, it, a.ip.n_iters, a.ip.tol_fx, Lt);
+        // an analytic retry has nothing to do when the iteration before it was accepted:
+        // it only carries x_hat forward and leaves no decision pending
+        if (a.ip.retry && d.pending && d.accepted_last)
+            d.pending = 0;
+        else if (d.pending)
+            d.t_step = a.ip.step;
+        if (!d.done) d.last_par = me;
+        s_sh = d;
         seg_f = 0;
         seg_b = 0;
         seg_z = 0;
@@ -431,6 +502,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     const Slot s = s_sh;
     if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
     if (s.done) return;
+    const bool skip = !s.pending;   // a retry with nothing to retry
     // the score tables are needed only by the consensus test: their loads are issued
     // now, behind the index stream, and land in LDS with the bit tests
     float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
@@ -499,14 +571,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         float svq[kSweepCols];
 #pragma unroll
         for (int q = 0; q < kSweepCols; ++q) svq[q] = supv[q * kSweepBlock + tid];
-        if (a.learned) {
-            // the learned decision replaces the column test: x'_j = x_hat_j + value
+        if (a.learned || skip) {
+            // the learned decision replaces the column test: x'_j = x_hat_j + value (a
+            // skipped retry updates nothing and keeps the support)
 #pragma unroll
             for (int q = 0; q < kSweepCols; ++q) {
                 const int j = cbase + q * kSweepBlock + tid;
                 if (j >= a.n) continue;
-                const float lv = a.learned[j];
-                const bool upd = lv == lv;
+                const float lv = skip ? 0.0f : a.learned[j];
+                const bool upd = !skip && lv == lv;
                 if (a.dbg.updated) a.dbg.updated[j] = upd ? 1 : 0;
                 if (a.dbg.omega) a.dbg.omega[j] = upd ? lv : 0.0f;
                 if (upd) {
@@ -635,65 +708,6 @@ struct FinishArgs {
 
 constexpr int kLdsKeys = 12288;   // candidate keys a finish workgroup caches in LDS
 constexpr int kSelPer = 12;       // candidate loads in flight per thread (kLdsKeys / block)
-
-// Within one workgroup: the digit of the bucket (among 2048, highest first) that holds
-// the `rem`-th largest of the counted keys, the count above it and the bucket's count.
-__device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, int* digit_out,
-                           unsigned* above_out, unsigned* bucket_out) {
-    const int tid = threadIdx.x;
-    const unsigned hi = hist[2047 - 2 * tid], lo = hist[2046 - 2 * tid];
-    scan[tid] = hi + lo;
-    __syncthreads();
-    for (int off = 1; off < kRowBlock; off <<= 1) {
-        const unsigned add = tid >= off ? scan[tid - off] : 0u;
-        __syncthreads();
-        scan[tid] += add;
-        __syncthreads();
-    }
-    const unsigned incl = scan[tid];
-    const unsigned before = incl - hi - lo;
-    if (before < rem && rem <= before + hi) {
-        *digit_out = 2047 - 2 * tid;
-        *above_out = before;
-        *bucket_out = hi;
-    } else if (before + hi < rem && rem <= incl) {
-        *digit_out = 2046 - 2 * tid;
-        *above_out = before + hi;
-        *bucket_out = lo;
-    }
-    __syncthreads();
-}
-
-// Within one workgroup: exclusive prefix sums of one int per segment (threads < nseg
-// hold their value in v) by wave scans; returns the total.  start[] gets the sums.
-__device__ __forceinline__ int segment_scan(int v, int nseg, int* start, int* wtot) {
-    const int tid = threadIdx.x, lane = tid & 63;
-    if (tid < kSweepGridMax) {
-        int incl = tid < nseg ? v : 0;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(incl, off);
-            if (lane >= off) incl += t;
-        }
-        start[tid] = incl - (tid < nseg ? v : 0);
-        if (lane == 63) wtot[tid >> 6] = incl;
-    }
-    __syncthreads();
-    int total = 0;
-    for (int w = 0; w < kSweepGridMax / 64; ++w) total += wtot[w];
-    if (tid < kSweepGridMax) {
-        int add = 0;
-        for (int w = 0; w < (tid >> 6); ++w) add += wtot[w];
-        start[tid] += add;
-    }
-    __syncthreads();
-    return total;
-}
-
-// Physical index of entry e (0 <= e < count) of a segment whose first `front` entries
-// sit at its start and the rest at its end, backwards.
-__device__ __forceinline__ size_t seg_phys(int seg, int cap, int front, int e) {
-    return static_cast<size_t>(seg) * cap + (e < front ? e : cap - 1 - (e - front));
-}
 
 // One kernel after the sweep.  H_k: when the nonzero candidates number at most k (the
 // common case once the support has formed) every one is kept and the sweep has already
@@ -904,6 +918,16 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
 
 // ------------------------------------------------------------------ final decision
 
+__global__ __launch_bounds__(256) void k_peek(DevState* st, int it, int n_iters, double tol_fx) {
+    __shared__ long long red[4];
+    const long long Lt = trial_l1_block(st, (it & 1) ^ 1, red);
+    if (threadIdx.x == 0) {
+        const Slot s = decide(st, it, n_iters, tol_fx, Lt);
+        st->peek_cur = s.cur;
+        st->peek_done = s.done;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n_iters, double tol_fx) {
     __shared__ long long red[4];
     const long long Lt = trial_l1_block(st, (it & 1) ^ 1, red);
@@ -912,10 +936,9 @@ __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n
 
 // x_out = x_hat (or, with trial = 1, H_k(x') of the last executed iteration) from the
 // candidate segments of the last executed iteration.  x_out is zeroed first.
-__global__ void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end, int it0, int trial) {
+__global__ void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end, int trial) {
     const Slot fin = w.st->slot[it_end & 1];
-    const int it_last = it0 + fin.iterations - 1;      // it0 - 1 if nothing ran
-    const int par = it_last & 1;
+    const int par = fin.last_par;   // the parity of it0 - 1 if nothing ran
     const int acc = trial ? 1 : fin.accepted_last;
     const unsigned long long kth = w.st->kth_key[par];
     const int seg = blockIdx.x;
@@ -1027,7 +1050,7 @@ size_t workspace_bytes(int n, int m) {
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
     (void)wn;
     return 4 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(4ull * n) +
-           al(16ull * n) + al(sizeof(DevState));
+           al(8ull * n) + 2 * al(4ull * m) + al(16ull * n) + al(sizeof(DevState));
 }
 
 void carve_workspace(void* base, int n, int m, Workspace* w) {
@@ -1049,6 +1072,8 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     w->seg_cap = seg_capacity(n);
     w->sweep_grid = sweep_grid(n);
     w->learned = reinterpret_cast<float*>(take(4ull * n));
+    w->lcache = reinterpret_cast<float*>(take(8ull * n));
+    for (int b = 0; b < 2; ++b) w->reval[b] = reinterpret_cast<float*>(take(4ull * m));
     w->Apk = reinterpret_cast<uint4*>(take(16ull * n));
     w->st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
 }
@@ -1124,20 +1149,25 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     return launch_timed(k_finish_rows, kRowGrid, kRowBlock, s, ev ? ev + 4 : nullptr, fa);
 }
 
-hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last, int it0,
+hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s) {
+    k_peek<<<1, 256, 0, s>>>(w.st, ip.it, ip.n_iters, ip.tol_fx);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
                          float* x_out, hipStream_t s) {
     k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx);
     if (x_out) {
         k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_out, dm.n);
-        k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, it0, 0);
+        k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, 0);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, int it0, float* x_trial,
+hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, float* x_trial,
                             hipStream_t s) {
     k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_trial, dm.n);
-    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, it0, 1);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, 1);
     return hipGetLastError();
 }
 

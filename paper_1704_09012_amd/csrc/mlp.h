@@ -38,9 +38,22 @@ hipError_t launch_zero_floats(float* p, long long count, hipStream_t s);
 // out [N][2]: fp32 (bf16 = 0) or matrix-core bf16 (bf16 = 1) inference.
 hipError_t launch_mlp_forward(const float* feats, int N, int d, const float* w, float* out, int bf16,
                               hipStream_t s);
-// The learned decision of every column on the residual r: value[j] = the network's
-// value if its logit >= logit_t, else NaN (no update).  d <= 15.
-hipError_t launch_learned_cols(const int32_t* A, int n, int d, const float* r, float sigma, float logit_t,
-                               const float* w, float* value, hipStream_t s);
+// The learned decision of every column: value[j] = the network's value if its logit >=
+// logit_t, else NaN (no update).  d <= 15.
+struct LearnedCols {
+    const int32_t* A;          // [n][d]
+    int n, m, d;
+    const float* r;            // residual [m]
+    const float* r1;           // with pick: the residual if pick[0] != 0
+    const int* pick;           // {use r1, stopped} on the device, or nullptr; nothing runs if stopped
+    const float* reval_in;     // residual of the last evaluation (cache valid), or nullptr: evaluate all
+    float* reval_out;          // <- the residual used, or nullptr
+    float* cache;              // [2n] (logit, value) per column: read where unchanged, written where
+                               // evaluated; nullptr only without reval_in
+    float sigma, logit_t;
+    const float* w;            // parameters (fp32)
+    float* value;              // [n] out
+};
+hipError_t launch_learned_cols(const LearnedCols& lc, hipStream_t s);
 
 }  // namespace rl0

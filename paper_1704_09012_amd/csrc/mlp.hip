@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "column_math.h"
@@ -32,6 +33,27 @@ constexpr float kInvSqrt2 = 0.70710678118654752f;
 constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
 __device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(u * kInvSqrt2)); }
+
+// GELU for the matrix-core inference, whose activations are rounded to bf16 (8
+// significant bits) right after: Phi from Abramowitz & Stegun 7.1.26,
+//   erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2),  t = 1 / (1 + p x),
+// for x = |u| / sqrt(2) >= 0 (absolute error <= 1.5e-7), with the hardware's reciprocal
+// and base-2 exponential.
+__device__ __forceinline__ float gelu_bf16(float u) {
+    constexpr float p = 0.3275911f;
+    constexpr float a1 = 0.254829592f, a2 = -0.284496736f, a3 = 1.421413741f, a4 = -1.453152027f,
+                    a5 = 1.061405429f;
+    constexpr float kHalfLog2e = 0.72134752044448170f;   // log2(e) / 2
+    const float x = fabsf(u) * kInvSqrt2;
+    const float t = __builtin_amdgcn_rcpf(fmaf(p, x, 1.0f));
+    float q = fmaf(t, a5, a4);
+    q = fmaf(t, q, a3);
+    q = fmaf(t, q, a2);
+    q = fmaf(t, q, a1);
+    const float e = __builtin_amdgcn_exp2f(-(u * u) * kHalfLog2e);   // exp(-x^2)
+    const float tail = (0.5f * t) * q * e;                            // 1 - Phi(|u|)
+    return u * (u >= 0.0f ? 1.0f - tail : tail);
+}
 
 __device__ __forceinline__ float gelu_grad(float u) {
     return 0.5f * (1.0f + erff(u * kInvSqrt2)) + u * expf(-0.5f * u * u) * kInvSqrt2Pi;
@@ -273,12 +295,21 @@ __global__ void k_mlp_forward_f32(const float* __restrict__ feats, int N, int F,
 
 // ------------------------------------------------------------------ matrix-core inference
 
-// The network in LDS for the matrix cores: bf16 weights (W1 zero-padded to 16 inputs),
-// fp32 biases.
+constexpr int kInferBlock = 256;
+constexpr int kInferWaves = kInferBlock / 64;
+constexpr int kQueueCap = 128;   // per-wave queue of samples awaiting the network
+
+// The network in LDS for the matrix cores: every lane's A operand of every product as
+// one 16-byte word (bf16), the biases in fp32.  Lane l = 16 g + c of the wave holds
+//   A1[mt][l]: W1[16 mt + c][8 g + 0..7] (inputs zero-padded to 16; zero for g >= 2),
+//   A2[mt][kt][l]: W2[16 mt + c][32 kt + 4 g + 0..3, 32 kt + 16 + 4 g + 0..3],
+//   A3[kt][l]: the same K order of W3 row c (zero for c >= 2).
+// The permuted K order of A2 and A3 is the order in which the previous layer's
+// activations sit in a lane's registers (see activations()).
 struct MlpLds {
-    __bf16 W1[kHidden][kMlpMaxFeatures];
-    __bf16 W2[kHidden][kHidden];
-    __bf16 W3[2][kHidden];
+    bf16x8 A1[4][64];
+    bf16x8 A2[4][2][64];
+    bf16x8 A3[2][64];
     float b1[kHidden], b2[kHidden], b3[2];
 };
 
@@ -289,12 +320,35 @@ __device__ void load_mlp_lds(MlpLds& L, const float* __restrict__ w, int F) {
     const float* b2 = W2 + kHidden * kHidden;
     const float* W3 = b2 + kHidden;
     const float* b3 = W3 + 2 * kHidden;
-    for (int i = threadIdx.x; i < kHidden * kMlpMaxFeatures; i += blockDim.x) {
-        const int h = i / kMlpMaxFeatures, k = i % kMlpMaxFeatures;
-        L.W1[h][k] = static_cast<__bf16>(k < F ? W1[h * F + k] : 0.0f);
+    constexpr int kWords = 4 * 64 + 8 * 64 + 2 * 64;
+    for (int e = threadIdx.x; e < kWords; e += blockDim.x) {
+        const int l = e & 63, g = l >> 4, c = l & 15;
+        bf16x8 v;
+        if (e < 256) {
+            const int mt = e >> 6;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 8 * g + j;
+                v[j] = static_cast<__bf16>(k < F ? W1[(16 * mt + c) * F + k] : 0.0f);
+            }
+            L.A1[mt][l] = v;
+        } else {
+            const bool l2 = e < 768;
+            const int q = l2 ? (e - 256) >> 6 : (e - 768) >> 6;
+            const int kt = q & 1;
+            const float* row = l2 ? W2 + (16 * (q >> 1) + c) * kHidden : W3 + c * kHidden;
+            const bool live = l2 || c < 2;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[j] = static_cast<__bf16>(live ? row[32 * kt + 4 * g + j] : 0.0f);
+                v[4 + j] = static_cast<__bf16>(live ? row[32 * kt + 16 + 4 * g + j] : 0.0f);
+            }
+            if (l2)
+                L.A2[q >> 1][kt][l] = v;
+            else
+                L.A3[kt][l] = v;
+        }
     }
-    for (int i = threadIdx.x; i < kHidden * kHidden; i += blockDim.x) L.W2[i / kHidden][i % kHidden] = static_cast<__bf16>(W2[i]);
-    for (int i = threadIdx.x; i < 2 * kHidden; i += blockDim.x) L.W3[i / kHidden][i % kHidden] = static_cast<__bf16>(W3[i]);
     for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
         L.b1[i] = b1[i];
         L.b2[i] = b2[i];
@@ -309,91 +363,68 @@ __device__ __forceinline__ bf16x8 zero8() {
     return z;
 }
 
-// The 8 weights row `row` of W (row-major, `stride` columns) contributes to the k-step
-// kt of lane group g: columns 32 kt + 4 g + (0..3) and 32 kt + 16 + 4 g + (0..3).
-__device__ __forceinline__ bf16x8 perm_row(const __bf16* W, int stride, int row, int kt, int g) {
-    bf16x8 a;
-    const __bf16* p = W + row * stride + 32 * kt + 4 * g;
+// Half kt of the next layer's B operand from accumulators acc[2 kt], acc[2 kt + 1] (hidden
+// unit 16 mt + 4 g + i of sample 16 nt + c in lane 16 g + c, bias included): GELU, bf16,
+// in the permuted K order of A2 and A3 (hidden 32 kt + 4 g + i, then 32 kt + 16 + 4 g + i).
+__device__ __forceinline__ void activations(const floatx4 (&acc)[2][4], bf16x8 (&b)[4]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        a[j] = p[j];
-        a[4 + j] = p[16 + j];
-    }
-    return a;
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            b[nt][i] = static_cast<__bf16>(gelu_bf16(acc[0][nt][i]));
+            b[nt][4 + i] = static_cast<__bf16>(gelu_bf16(acc[1][nt][i]));
+        }
 }
 
-// The next layer's B operand from this layer's accumulators acc[mt][nt] (hidden unit
-// 16 mt + 4 g + i of sample 16 nt + c in lane 16 g + c): bias, GELU, bf16, in the
-// permuted K order of perm_row.
-__device__ __forceinline__ void activations(const floatx4 (&acc)[4][4], const float* bias, int g,
-                                            bf16x8 (&b)[2][4]) {
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                b[kt][nt][i] = static_cast<__bf16>(gelu(acc[2 * kt][nt][i] + bias[32 * kt + 4 * g + i]));
-                b[kt][nt][4 + i] = static_cast<__bf16>(gelu(acc[2 * kt + 1][nt][i] + bias[32 * kt + 16 + 4 * g + i]));
-            }
-}
-
-// The network for the 64 samples of a wave, one per lane (f: this lane's F <= 16
-// features).  stage: this wave's 64 x 16 bf16 LDS scratch.  Every lane must call.
-__device__ void mlp_wave_bf16(const MlpLds& L, const float* f, int F, __bf16* stage, float& logit, float& value) {
+// The network for 64 samples of a wave: feat holds sample e's inputs in row e (16
+// bf16, zero beyond F).  Returns the logit and value of sample `lane`.  The biases enter
+// as the accumulators' initial values (fp32).  Each layer runs in two halves of 32
+// hidden units, so that only half of its accumulators is live at a time.  Every lane
+// must call.
+__device__ void mlp_tile(const MlpLds& L, const __bf16* feat, float& logit, float& value) {
     const int lane = __lane_id();
     const int g = lane >> 4, c = lane & 15;
+    bf16x8 h1[2][4];
+    {
+        bf16x8 bf[4];
 #pragma unroll
-    for (int k = 0; k < kMlpMaxFeatures; ++k) stage[lane * kMlpMaxFeatures + k] = static_cast<__bf16>(k < F ? f[k] : 0.0f);
-    __builtin_amdgcn_wave_barrier();
-    // layer 1 (K = 16 inputs in lane groups 0 and 1, zero in groups 2 and 3)
-    bf16x8 bf[4];
+        for (int nt = 0; nt < 4; ++nt)
+            bf[nt] = g < 2 ? *reinterpret_cast<const bf16x8*>(feat + (16 * nt + c) * kMlpMaxFeatures + 8 * g) : zero8();
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        if (g < 2) {
+        for (int kt = 0; kt < 2; ++kt) {
+            floatx4 acc[2][4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) bf[nt][j] = stage[(16 * nt + c) * kMlpMaxFeatures + 8 * g + j];
-        } else {
-            bf[nt] = zero8();
+            for (int u = 0; u < 2; ++u) {
+                const int mt = 2 * kt + u;
+                const floatx4 bias = *reinterpret_cast<const floatx4*>(&L.b1[16 * mt + 4 * g]);
+                const bf16x8 a = L.A1[mt][lane];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[u][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[nt], bias, 0, 0, 0);
+            }
+            activations(acc, h1[kt]);
         }
     }
     const floatx4 z4 = {0.0f, 0.0f, 0.0f, 0.0f};
-    floatx4 acc[4][4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        bf16x8 a = zero8();
-        if (g < 2) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = L.W1[16 * mt + c][8 * g + j];
-        }
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[nt], z4, 0, 0, 0);
-    }
-    bf16x8 h[2][4];
-    activations(acc, L.b1, g, h);
-    // layer 2
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = z4;
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
-            const bf16x8 a = perm_row(&L.W2[0][0], kHidden, 16 * mt + c, kt, g);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h[kt][nt], acc[mt][nt], 0, 0, 0);
-        }
-    }
-    activations(acc, L.b2, g, h);
-    // layer 3 (M = 2 outputs in rows 0 and 1 of a 16-row tile)
-    floatx4 out[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) out[nt] = z4;
+    floatx4 out[4] = {z4, z4, z4, z4};
 #pragma unroll
     for (int kt = 0; kt < 2; ++kt) {
-        const bf16x8 a = c < 2 ? perm_row(&L.W3[0][0], kHidden, c, kt, g) : zero8();
+        floatx4 acc[2][4];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) out[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h[kt][nt], out[nt], 0, 0, 0);
+        for (int u = 0; u < 2; ++u) {
+            const int mt = 2 * kt + u;
+            const floatx4 bias = *reinterpret_cast<const floatx4*>(&L.b2[16 * mt + 4 * g]);
+            const bf16x8 a0 = L.A2[mt][0][lane], a1 = L.A2[mt][1][lane];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                acc[u][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, h1[0][nt], bias, 0, 0, 0);
+                acc[u][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, h1[1][nt], acc[u][nt], 0, 0, 0);
+            }
+        }
+        bf16x8 h2[4];
+        activations(acc, h2);
+        const bf16x8 a3 = L.A3[kt][lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) out[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, h2[nt], out[nt], 0, 0, 0);
     }
     // outputs of sample 16 nt + c sit in lane c (rows 0 and 1); bring them to lane 16 nt + c
     const int my_nt = lane >> 4, src = lane & 15;
@@ -409,55 +440,142 @@ __device__ void mlp_wave_bf16(const MlpLds& L, const float* f, int F, __bf16* st
     }
     logit = lg + L.b3[0];
     value = vl + L.b3[1];
-    __builtin_amdgcn_wave_barrier();
 }
-
-constexpr int kInferBlock = 256;
 
 __global__ __launch_bounds__(kInferBlock) void k_mlp_forward_bf16(const float* __restrict__ feats, int N, int F,
                                                                   const float* __restrict__ w, float* __restrict__ out) {
     __shared__ MlpLds L;
-    __shared__ __bf16 stage[kInferBlock / 64][64 * kMlpMaxFeatures];
+    __shared__ __attribute__((aligned(16))) __bf16 stage[kInferWaves][64 * kMlpMaxFeatures];
     load_mlp_lds(L, w, F);
-    __syncthreads();
     const int sm = blockIdx.x * kInferBlock + threadIdx.x;
-    float f[kMlpMaxFeatures];
+    __bf16* st = stage[threadIdx.x >> 6] + __lane_id() * kMlpMaxFeatures;
 #pragma unroll
-    for (int k = 0; k < kMlpMaxFeatures; ++k) f[k] = (sm < N && k < F) ? feats[static_cast<size_t>(sm) * F + k] : 0.0f;
+    for (int k = 0; k < kMlpMaxFeatures; ++k)
+        st[k] = static_cast<__bf16>((sm < N && k < F) ? feats[static_cast<size_t>(sm) * F + k] : 0.0f);
+    __syncthreads();
     float logit, value;
-    mlp_wave_bf16(L, f, F, stage[threadIdx.x >> 6], logit, value);
+    mlp_tile(L, stage[threadIdx.x >> 6], logit, value);
     if (sm < N) {
         out[2 * static_cast<size_t>(sm)] = logit;
         out[2 * static_cast<size_t>(sm) + 1] = value;
     }
 }
 
+struct LearnedArgs {
+    const int32_t* A;
+    int n, m;
+    const float* r0;
+    const float* r1;
+    const int* pick;          // {use r1, stopped} or nullptr (r0)
+    const float* reval_in;    // residual the cached outputs were computed on, or nullptr
+    float* reval_out;         // <- the residual used now, or nullptr
+    float2* cache;            // [n] (logit, value) of the last evaluation, or nullptr
+    float sigma, logit_t;
+    const float* w;
+    float* value;
+};
+
+// The learned decision of every column.  Each wave takes rounds of 64 consecutive
+// columns, one per lane: a column whose d residual entries are bit-identical to those
+// of the last evaluation takes its cached (logit, value); the others queue their
+// sorted features in the wave's LDS queue, which is run through the network 64 at a time.
 template <int D>
-__global__ __launch_bounds__(kInferBlock) void k_learned_cols(const int32_t* __restrict__ A, int n,
-                                                              const float* __restrict__ r, float sigma, float logit_t,
-                                                              const float* __restrict__ w, float* __restrict__ value) {
+__global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) {
     __shared__ MlpLds L;
-    __shared__ __bf16 stage[kInferBlock / 64][64 * kMlpMaxFeatures];
-    load_mlp_lds(L, w, D + 1);
+    __shared__ __attribute__((aligned(16))) __bf16 qf[kInferWaves][kQueueCap * kMlpMaxFeatures];
+    __shared__ int qj[kInferWaves][kQueueCap];
+    if (a.pick && a.pick[1]) return;
+    const float* __restrict__ r = (a.pick && a.pick[0]) ? a.r1 : a.r0;
+    load_mlp_lds(L, a.w, D + 1);
+    if (a.reval_out) {
+        for (int i = blockIdx.x * kInferBlock + threadIdx.x; i < a.m; i += gridDim.x * kInferBlock)
+            a.reval_out[i] = r[i];
+    }
     __syncthreads();
-    const int j = blockIdx.x * kInferBlock + threadIdx.x;
-    float v[D];
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
+    __bf16* __restrict__ myf = qf[wave];
+    int* __restrict__ myj = qj[wave];
+    const float nan = __builtin_nanf("");
+    const int rounds = (a.n + 63) >> 6;
+    const int nw = gridDim.x * kInferWaves;
+    int qn = 0;
+    for (int rd = blockIdx.x * kInferWaves + wave; rd < rounds; rd += nw) {
+        const int j = rd * 64 + lane;
+        bool need = false;
+        float v[D];
+        if (j < a.n) {
+            int rows[D];
 #pragma unroll
-    for (int p = 0; p < D; ++p) v[p] = j < n ? r[A[static_cast<size_t>(j) * D + p]] : 0.0f;
+            for (int p = 0; p < D; ++p) rows[p] = a.A[static_cast<size_t>(j) * D + p];
 #pragma unroll
-    for (int a = 1; a < D; ++a)
+            for (int p = 0; p < D; ++p) v[p] = r[rows[p]];
+            need = true;
+            if (a.reval_in) {
+                bool same = true;
 #pragma unroll
-        for (int b = a; b > 0; --b) {
-            const float lo = fminf(v[b - 1], v[b]), hi = fmaxf(v[b - 1], v[b]);
-            v[b - 1] = lo;
-            v[b] = hi;
+                for (int p = 0; p < D; ++p) same = same && (__float_as_uint(a.reval_in[rows[p]]) == __float_as_uint(v[p]));
+                if (same) {
+                    const float2 cc = a.cache[j];
+                    a.value[j] = cc.x >= a.logit_t ? cc.y : nan;
+                    need = false;
+                }
+            }
         }
-    float f[kMlpMaxFeatures];
+        const unsigned long long bal = __ballot(need);
+        if (need) {
 #pragma unroll
-    for (int k = 0; k < kMlpMaxFeatures; ++k) f[k] = k < D ? v[k < D ? k : 0] : (k == D ? sigma : 0.0f);
-    float logit, val;
-    mlp_wave_bf16(L, f, D + 1, stage[threadIdx.x >> 6], logit, val);
-    if (j < n) value[j] = logit >= logit_t ? val : __builtin_nanf("");
+            for (int x = 1; x < D; ++x)
+#pragma unroll
+                for (int y = x; y > 0; --y) {
+                    const float lo = fminf(v[y - 1], v[y]), hi = fmaxf(v[y - 1], v[y]);
+                    v[y - 1] = lo;
+                    v[y] = hi;
+                }
+            const int slot = qn + __popcll(bal & ((1ull << lane) - 1ull));
+            bf16x8 f0, f1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                f0[k] = static_cast<__bf16>(k < D ? v[k < D ? k : 0] : (k == D ? a.sigma : 0.0f));
+                f1[k] = static_cast<__bf16>(k + 8 < D ? v[k + 8 < D ? k + 8 : 0] : (k + 8 == D ? a.sigma : 0.0f));
+            }
+            bf16x8* dst = reinterpret_cast<bf16x8*>(myf + slot * kMlpMaxFeatures);
+            dst[0] = f0;
+            dst[1] = f1;
+            myj[slot] = j;
+        }
+        qn += __popcll(bal);
+        if (qn >= 64) {
+            __builtin_amdgcn_wave_barrier();
+            float lg, vl;
+            mlp_tile(L, myf, lg, vl);
+            const int jj = myj[lane];
+            if (a.cache) a.cache[jj] = make_float2(lg, vl);
+            a.value[jj] = lg >= a.logit_t ? vl : nan;
+            // entries 64.. move to the front of the queue
+            qn -= 64;
+            if (lane < qn) {
+                const bf16x8* src = reinterpret_cast<const bf16x8*>(myf + (64 + lane) * kMlpMaxFeatures);
+                bf16x8* dst = reinterpret_cast<bf16x8*>(myf + lane * kMlpMaxFeatures);
+                const bf16x8 s0 = src[0], s1 = src[1];
+                const int sj = myj[64 + lane];
+                dst[0] = s0;
+                dst[1] = s1;
+                myj[lane] = sj;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (qn > 0) {
+        // the rest; rows qn..63 of the tile hold stale samples whose outputs are unused
+        __builtin_amdgcn_wave_barrier();
+        float lg, vl;
+        mlp_tile(L, myf, lg, vl);
+        if (lane < qn) {
+            const int jj = myj[lane];
+            if (a.cache) a.cache[jj] = make_float2(lg, vl);
+            a.value[jj] = lg >= a.logit_t ? vl : nan;
+        }
+    }
 }
 
 int blocks_of(long long count, int block) { return static_cast<int>((count + block - 1) / block); }
@@ -532,12 +650,32 @@ hipError_t launch_mlp_forward(const float* feats, int N, int d, const float* w, 
     return hipGetLastError();
 }
 
-hipError_t launch_learned_cols(const int32_t* A, int n, int d, const float* r, float sigma, float logit_t,
-                               const float* w, float* value, hipStream_t s) {
-    const int g = blocks_of(n, kInferBlock);
-    switch (d) {
+hipError_t launch_learned_cols(const LearnedCols& lc, hipStream_t s) {
+    LearnedArgs a;
+    a.A = lc.A;
+    a.n = lc.n;
+    a.m = lc.m;
+    a.r0 = lc.r;
+    a.r1 = lc.r1;
+    a.pick = lc.pick;
+    a.reval_in = lc.reval_in;
+    a.reval_out = lc.reval_out;
+    a.cache = reinterpret_cast<float2*>(lc.cache);
+    a.sigma = lc.sigma;
+    a.logit_t = lc.logit_t;
+    a.w = lc.w;
+    a.value = lc.value;
+    if (a.reval_in && !a.cache) return hipErrorInvalidValue;
+    int cus = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    const int rounds = blocks_of(lc.n, 64);
+    const int g = std::max(1, std::min(blocks_of(rounds, kInferWaves), 4 * cus));
+    switch (lc.d) {
 #define RL0_LC(D) \
-    case D: k_learned_cols<D><<<g, kInferBlock, 0, s>>>(A, n, r, sigma, logit_t, w, value); break;
+    case D: k_learned_cols<D><<<g, kInferBlock, 0, s>>>(a); break;
         RL0_LC(1) RL0_LC(2) RL0_LC(3) RL0_LC(4) RL0_LC(5) RL0_LC(6) RL0_LC(7) RL0_LC(8)
         RL0_LC(9) RL0_LC(10) RL0_LC(11) RL0_LC(12) RL0_LC(13) RL0_LC(14) RL0_LC(15)
 #undef RL0_LC

@@ -722,12 +722,21 @@ int step_core(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, 
     HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, x_hat, w, ip, s));
     const float* lv = nullptr;
     if (learned) {
-        HIP_TRY(rl0::launch_learned_cols(A, dm.n, dm.d, w.r[0], p->sigma, logit_threshold(ip.t),
-                                         static_cast<const float*>(p->mlp), w.learned, s));
+        rl0::LearnedCols lc{};
+        lc.A = A;
+        lc.n = dm.n;
+        lc.m = dm.m;
+        lc.d = dm.d;
+        lc.r = w.r[0];
+        lc.sigma = p->sigma;
+        lc.logit_t = logit_threshold(ip.t);
+        lc.w = static_cast<const float*>(p->mlp);
+        lc.value = w.learned;
+        HIP_TRY(rl0::launch_learned_cols(lc, s));
         lv = w.learned;
     }
     HIP_TRY(rl0::launch_iteration(dm, A, w, tables_of(dc), ip, dbg, s, nullptr, lv));
-    HIP_TRY(rl0::launch_finish(dm, w, ip_end, it, x_hat, s));
+    HIP_TRY(rl0::launch_finish(dm, w, ip_end, x_hat, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
@@ -741,46 +750,89 @@ int step_core(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, 
 }
 
 // Alg. 1 with the learned column decision: at each t a learned iteration, and when it
-// is not accepted, an iteration with the analytic decision at the same t.
+// is not accepted, an iteration with the analytic decision at the same t.  The whole
+// decode stays on the device: t-step j is sub-iteration 2j (learned) and 2j + 1 (the
+// analytic retry, which the sweep skips when 2j was accepted).  The learned decisions
+// of 2j need r_hat after the decision on 2j - 1, which a one-workgroup kernel evaluates
+// ahead; the sweep of 2j takes the same decision again.
+rl0::IterParams learned_sub_params(const DeviceConstants* dc, const rl0_params* p, int u) {
+    const int N = dc->hc.n_iters;
+    rl0::IterParams ip = iter_params(dc, p, u >> 1);
+    ip.tau_next = iter_params(dc, p, (u + 1) >> 1).tau_bits;   // the next sweep's t
+    ip.it = u;
+    ip.n_iters = 2 * N;
+    ip.step = u >> 1;
+    ip.retry = u & 1;
+    return ip;
+}
+
 int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, const int32_t* A,
                    const float* y, const rl0_params* p, float* x_out, rl0_stats* st_h, hipStream_t s) {
-    HIP_TRY(rl0::launch_zero_f32(x_out, dm.n, s));
-    HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, x_out, b->w, iter_params(dc, p, 0), s));
-    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (int rc = err_code_of(b->st_host->err)) return rc;
-    long long L_hat = b->st_host->slot[1].L_hat;
-    const double tol_fx = dc->hc.tol * 1073741824.0;
-    int iters = 0, accepted = 0, updates = 0;
-    float t_final = 1.0f;
-    const rl0::DebugOut dbg{nullptr, nullptr};
-    for (int it = 0; it < dc->hc.n_iters; ++it) {
-        if (static_cast<double>(L_hat) <= tol_fx) break;
-        for (int pass = 0; pass < 2; ++pass) {
-            StepResult r;
-            if (int rc = step_core(b, dc, dm, A, y, p, it, pass == 0, x_out, dbg, s, &r)) return rc;
-            ++iters;
-            updates += r.updates;
-            t_final = dc->hc.t[it];
-            L_hat = r.L_hat;
-            if (r.accepted) {
-                ++accepted;
-                break;
-            }
+    const rl0::ScoreTables tb = tables_of(dc);
+    const int N = dc->hc.n_iters;
+    const rl0::Workspace& w = b->w;
+    const float* mlp = static_cast<const float*>(p->mlp);
+    auto issue = [&](hipStream_t q) -> int {
+        HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, nullptr, w, learned_sub_params(dc, p, 0), q));
+        const rl0::DebugOut dbg{nullptr, nullptr};
+        for (int j = 0; j < N; ++j) {
+            const rl0::IterParams ipl = learned_sub_params(dc, p, 2 * j);
+            HIP_TRY(rl0::launch_peek(w, ipl, q));
+            // columns whose residual entries are unchanged since the last t keep the
+            // network's outputs of then
+            rl0::LearnedCols lc{};
+            lc.A = A;
+            lc.n = dm.n;
+            lc.m = dm.m;
+            lc.d = dm.d;
+            lc.r = w.r[0];
+            lc.r1 = w.r[1];
+            lc.pick = &w.st->peek_cur;
+            lc.reval_in = j > 0 ? w.reval[(j + 1) & 1] : nullptr;
+            lc.reval_out = w.reval[j & 1];
+            lc.cache = w.lcache;
+            lc.sigma = p->sigma;
+            lc.logit_t = logit_threshold(ipl.t);
+            lc.w = mlp;
+            lc.value = w.learned;
+            HIP_TRY(rl0::launch_learned_cols(lc, q));
+            HIP_TRY(rl0::launch_iteration(dm, A, w, tb, ipl, dbg, q, nullptr, w.learned));
+            HIP_TRY(rl0::launch_iteration(dm, A, w, tb, learned_sub_params(dc, p, 2 * j + 1), dbg, q));
         }
+        HIP_TRY(rl0::launch_finish(dm, w, learned_sub_params(dc, p, 2 * N), x_out, q));
+        return RL0_OK;
+    };
+    if (graphs_enabled()) {
+        DecodeKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.A = A;
+        key.y = y;
+        key.x = x_out;
+        key.dc = dc;
+        key.n = dm.n;
+        key.m = dm.m;
+        key.d = dm.d;
+        std::memcpy(&key.p, p, sizeof(*p));
+        if (int rc = replay_decode(b, key, s, issue)) return rc;
+    } else {
+        if (int rc = issue(s)) return rc;
     }
+    HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const rl0::DevState& ds = *b->st_host;
+    const rl0::Slot& fin = ds.slot[0];   // sub-iteration 2N decides last
     if (st_h) {
-        st_h->iterations = iters;
-        st_h->accepted = accepted;
-        st_h->l1_final_fx = L_hat;
-        st_h->l1_final = static_cast<double>(L_hat) / 1073741824.0;
+        st_h->iterations = fin.iterations;
+        st_h->accepted = fin.accepted;
+        st_h->l1_final_fx = fin.L_hat;
+        st_h->l1_final = static_cast<double>(fin.L_hat) / 1073741824.0;
         st_h->l1_tol = dc->hc.tol;
-        st_h->converged = static_cast<double>(L_hat) <= tol_fx ? 1 : 0;
-        st_h->updates_total = updates;
-        st_h->t_final = t_final;
-        st_h->error_flags = 0;
+        st_h->converged = (static_cast<double>(fin.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
+        st_h->updates_total = ds.updates_total;
+        st_h->t_final = fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f;
+        st_h->error_flags = ds.err;
     }
-    return RL0_OK;
+    return err_code_of(ds.err);
 }
 
 // ---------------------------------------------------------------- network training memory
@@ -914,7 +966,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
         const rl0::DebugOut dbg{nullptr, nullptr};
         for (int it = 0; it < N; ++it)
             HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, q, profile_events(it)));
-        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), 0, x_out, q));
+        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), x_out, q));
         return RL0_OK;
     };
     // per-iteration timing events cannot be recorded into a captured graph: a profiled
@@ -978,7 +1030,7 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
     StepResult r;
     if (int rc = step_core(b, dc, dm, A_cols, y, p, it, p->posterior == 1, x_hat, dbg, s, &r)) return rc;
     // the iteration ran from buffer 0; its trial iterate sits in buffer 1
-    if (x_trial) HIP_TRY(rl0::launch_trial_out(dm, w, it + 1, it, x_trial, s));
+    if (x_trial) HIP_TRY(rl0::launch_trial_out(dm, w, it + 1, x_trial, s));
     if (r_trial) HIP_TRY(rl0::launch_copy_f32(w.r[1], r_trial, m, s));
     if (accepted_h) *accepted_h = r.accepted;
     *L_hat_h = r.L_hat;

@@ -167,3 +167,66 @@ def test_trained_network_gain_over_the_analytic_rule():
                 assert r["learned"]["rel_err"] < 1e-2 and r["analytic"]["rel_err"] < 1e-2
     print("converged (of 8):", conv, "train loss", loss, flush=True)
     assert conv["learned"] > conv["analytic"]
+
+
+def median_net(d, sigma, bias):
+    """A hand-set network: value = the median residual of the column, logit =
+    s|r_med| (2 Phi(s r_med) - 1) - bias with s = 1/sigma.  Hidden units come in pairs
+    gelu(u), gelu(-u), whose difference is u, so the value survives both layers."""
+    w = np.zeros(M.n_params(d), np.float32)
+    W1, b1, W2, b2, W3, b3 = M.unpack(w, d)
+    s = 1.0 / sigma
+    mid = d // 2
+    W1[0, mid], W1[1, mid] = s, -s
+    W2[0, 0], W2[0, 1] = 1.0, -1.0
+    W2[1, 0], W2[1, 1] = -1.0, 1.0
+    W3[0, 0], W3[0, 1] = 1.0, 1.0
+    b3[0] = -bias
+    W3[1, 0], W3[1, 1] = 1.0 / s, -1.0 / s
+    return w
+
+
+def stepwise_learned(A, y, n, m, d, k, sig, wt):
+    """The learned loop through rl0_step: at each t a learned iteration, then the
+    analytic one at the same t when it is not accepted."""
+    pa = R.params_default(n, m, d, k, sig)
+    pl = R.params_default(n, m, d, k, sig, mlp=wt)
+    C = R.compute_constants(pa, n, m, d)
+    tol = C.tol * 2.0 ** 30
+    x = torch.zeros(n, dtype=torch.float32, device="cuda")
+    r = torch.empty(m, dtype=torch.float32, device="cuda")
+    L = None
+    iters = acc = learned_acc = retries = 0
+    for it in range(C.n_iters):
+        if L is not None and L <= tol:
+            break
+        out = R.step(A, y, pl, it, x, r, 0, debug=False)
+        iters += 1
+        L = out["L_hat"]
+        if out["accepted"]:
+            acc += 1
+            learned_acc += 1
+            continue
+        out = R.step(A, y, pa, it, x, r, 0, debug=False)
+        iters += 1
+        retries += 1
+        L = out["L_hat"]
+        acc += int(out["accepted"])
+    return host(x), L, iters, acc, learned_acc, retries
+
+
+@pytest.mark.parametrize("n,m,k,snr,seed", [(8192, 2048, 160, 40, 51), (20000, 3000, 250, 25, 52)])
+def test_device_learned_decode_matches_the_stepwise_loop(n, m, k, snr, seed):
+    d = 7
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, seed)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    A, yt = dev(inst.A_cols), dev(y)
+    wt = dev(median_net(d, sig, 1.5))
+    xe, Le, ie, ae, la, rt = stepwise_learned(A, yt, n, m, d, k, sig, wt)
+    print(f"n={n}: iterations {ie}, accepted {ae} (learned {la}), retries {rt}", flush=True)
+    assert la > 0 and rt > 0          # both branches of the schedule ran
+    for _ in range(2):                # captured, then replayed
+        xg, st = R.decode(A, yt, sigma=sig, k=k, mlp=wt)
+        assert np.array_equal(host(xg), xe)
+        assert st["l1_final_fx"] == Le and st["iterations"] == ie and st["accepted"] == ae
