@@ -10,6 +10,7 @@ constexpr int kMaxD = 16;
 constexpr int kFxShift = 40;   // residual / sketch fixed point: 40 fractional bits
 constexpr int kL1Shift = 30;   // ||r||_1 fixed point: 30 fractional bits
 constexpr int kHistBins = 2048;
+constexpr int kHistCopies = 8;        // one per XCD: workgroup b adds into copy b % 8
 constexpr int kTableStrideFloats = 4100;  // floats between the starts of the two score tables
 constexpr int kSweepGridMax = 256;   // workgroups of the sweep (each owns a candidate segment)
 constexpr int kRowGrid = 256;        // workgroups of the row kernels (each owns a partial sum)
@@ -48,6 +49,8 @@ struct DevState {
     int seg_nz[2][kSweepGridMax];         //   of which with x' != 0
     int seg_updates[2][kSweepGridMax];    // updates proposed by each sweep workgroup
     long long L_part[2][kRowGrid];        // partial ||r||_1 of the trial residual
+    unsigned hk_hist[2][kHistCopies][kHistBins];   // nonzero candidates by the top 11 bits of
+                                                   // |x'_j|, one copy per XCD (added up by H_k)
 };
 
 struct DecodeDims {

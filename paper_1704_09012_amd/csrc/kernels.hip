@@ -155,10 +155,11 @@ __global__ void k_sketch_finish(const long long* __restrict__ S, float* __restri
 
 // ------------------------------------------------------------------ prepare
 
+constexpr int kStateWords = static_cast<int>(sizeof(DevState) / sizeof(int));
+
 __global__ void k_prep_state(DevState* st) {
     int* p = reinterpret_cast<int*>(st);
-    const int words = static_cast<int>(sizeof(DevState) / sizeof(int));
-    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kStateWords; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // The starting support x0 as the candidate segments of the iteration before it0, in
@@ -249,6 +250,12 @@ __global__ __launch_bounds__(256) void k_prep_slot(DevState* st, int slot) {
 }
 
 // ------------------------------------------------------------------ H_k helpers
+
+// The top 11 bits of hk_key(j, x) (x != 0): bits 30..20 of |x|.
+__device__ __forceinline__ unsigned top_digit(float x) { return abs_bits(x) >> 20; }
+static_assert(kHistBins == 2048 && (kHistCopies * kHistBins) % kRowGrid == 0 &&
+                  kHistCopies * kHistBins / kRowGrid <= kRowBlock,
+              "H_k's radix digits are 11 bits; the finish grid clears the histograms");
 
 // Within one workgroup: the digit of the bucket (among 2048, highest first) that holds
 // the `rem`-th largest of the counted keys, the count above it and the bucket's count.
@@ -438,6 +445,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     __shared__ int queue[kSweepChunk];
     __shared__ int qrows[kQueueRowInts];
     __shared__ int qn, seg_f, seg_b, seg_z, seg_upd;
+    __shared__ unsigned lhist[kHistBins];   // this workgroup's nonzero candidates by top digit
     __shared__ Slot s_sh;
     __shared__ long long red[kSweepBlock / 64];
     const int it = a.ip.it, me = it & 1, pv = me ^ 1;
@@ -449,6 +457,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     const bool bm_regs = words <= kBmPer * kSweepBlock;
 
     // ---- round 1
+    for (int b = threadIdx.x; b < kHistBins; b += kSweepBlock) lhist[b] = 0u;
     int rows[kSweepCols][D];
     load_rows<D>(a.A, a.Apk, a.n, blockIdx.x * kSweepChunk, tid, rows);
     Slot prev{};
@@ -589,13 +598,17 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     out_j[o] = j;
                     out_x[o] = xp;
                     out_h[o] = svq[q];
-                    if (xp != 0.0f) atomicAdd(&seg_z, 1);
+                    if (xp != 0.0f) {
+                        atomicAdd(&seg_z, 1);
+                        atomicAdd(&lhist[top_digit(xp)], 1u);
+                    }
                     add_change<D>(a.w.D, rows[q], svq[q], xp, &st->err);
                 } else if (svq[q] != 0.0f) {
                     const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
                     out_j[o] = j;
                     out_x[o] = svq[q];
                     out_h[o] = svq[q];
+                    atomicAdd(&lhist[top_digit(svq[q])], 1u);
                 }
             }
             __syncthreads();
@@ -627,6 +640,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 out_j[o] = j;
                 out_x[o] = svq[q];
                 out_h[o] = svq[q];
+                atomicAdd(&lhist[top_digit(svq[q])], 1u);
             }
         }
         if (chunk == static_cast<int>(blockIdx.x) && !a.tb.exact) {
@@ -675,13 +689,17 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 out_j[o] = jq;
                 out_x[o] = xp;
                 out_h[o] = xhq;
-                if (xp != 0.0f) atomicAdd(&seg_z, 1);
+                if (xp != 0.0f) {
+                    atomicAdd(&seg_z, 1);
+                    atomicAdd(&lhist[top_digit(xp)], 1u);
+                }
                 add_change<D>(a.w.D, rr, xhq, xp, &st->err);
             } else if (xhq != 0.0f) {
                 const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
                 out_j[o] = jq;
                 out_x[o] = xhq;
                 out_h[o] = xhq;
+                atomicAdd(&lhist[top_digit(xhq)], 1u);
             }
         }
         __syncthreads();
@@ -691,6 +709,11 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         st->seg_front[me][seg] = seg_f;
         st->seg_nz[me][seg] = seg_z + seg_b;
         st->seg_updates[me][seg] = seg_upd;
+    }
+    // H_k's first radix digit, counted for every workgroup at once
+    for (int b = tid; b < kHistBins; b += kSweepBlock) {
+        const unsigned v = lhist[b];
+        if (v) atomicAdd(&st->hk_hist[me][blockIdx.x % kHistCopies][b], v);
     }
 }
 
@@ -761,6 +784,9 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             dl = a.w.D[i];
         }
     }
+    // the next iteration's first-digit histograms are cleared here, a slice per workgroup
+    if (tid < kHistCopies * kHistBins / kRowGrid)
+        (&st->hk_hist[me ^ 1][0][0])[blockIdx.x * (kHistCopies * kHistBins / kRowGrid) + tid] = 0u;
     if (tid == 0) {
         nz_sh = 0;
         upd_sh = 0;
@@ -809,29 +835,47 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         for (int pass = 0; pass < 6 && !exact; ++pass) {
             const int sft = pass < 5 ? 52 - 11 * pass : 0;
             const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
-            hist[tid] = 0u;
-            hist[tid + kRowBlock] = 0u;
-            __syncthreads();
-            for (int e0 = 0; e0 < count; e0 += kRowBlock) {
-                const int e = e0 + tid;
-                unsigned long long key = 0ull;
-                if (e < count) {
-                    if (fast) {
-                        key = keys[e];
-                    } else {
-                        int lo = 0, hi = nseg - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
+            if (pass == 0) {
+                // the first digit's histogram, counted by the sweep
+                unsigned h_hi = 0u, h_lo = 0u;
+#pragma unroll
+                for (int cp = 0; cp < kHistCopies; ++cp) {
+                    h_hi += st->hk_hist[me][cp][tid];
+                    h_lo += st->hk_hist[me][cp][tid + kRowBlock];
+                }
+                hist[tid] = h_hi;
+                hist[tid + kRowBlock] = h_lo;
+                __syncthreads();
+            } else {
+                hist[tid] = 0u;
+                hist[tid + kRowBlock] = 0u;
+                __syncthreads();
+                if (fast) {
+                    for (int e0 = 0; e0 < count; e0 += kRowBlock) {
+                        const int e = e0 + tid;
+                        const unsigned long long key = e < count ? keys[e] : 0ull;
+                        hist_add(hist, static_cast<unsigned>((key >> sft) & dmask),
+                                 key != 0ull && (key & pmask) == prefix);
+                    }
+                } else {
+                    // a wave per segment
+                    for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64) {
+                        const int cnt = seg_cnt[sg], fr = seg_frt[sg];
+                        for (int o0 = 0; o0 < cnt; o0 += 64) {
+                            const int o = o0 + lane;
+                            unsigned long long key = 0ull;
+                            if (o < cnt) {
+                                const size_t ix = seg_phys(sg, cap, fr, o);
+                                const float x = cx[ix];
+                                key = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
+                            }
+                            hist_add(hist, static_cast<unsigned>((key >> sft) & dmask),
+                                     key != 0ull && (key & pmask) == prefix);
                         }
-                        const size_t ix = seg_phys(lo, cap, seg_frt[lo], e - seg_start[lo]);
-                        const float x = cx[ix];
-                        key = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
                     }
                 }
-                hist_add(hist, static_cast<unsigned>((key >> sft) & dmask), key != 0ull && (key & pmask) == prefix);
+                __syncthreads();
             }
-            __syncthreads();
             find_digit(hist, rem, scan, &digit, &above, &bucket);
             prefix |= static_cast<unsigned long long>(digit) << sft;
             pmask |= static_cast<unsigned long long>(dmask) << sft;
@@ -858,26 +902,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             // the dropped columns' rows in [base, base + kRowBlock)
             corr[tid] = 0;
             __syncthreads();
-            for (int e = tid; e < count; e += kRowBlock) {
-                int sg;
-                unsigned long long key;
-                if (fast) {
-                    key = keys[e];
-                    sg = segmap[e];
-                } else {
-                    int lo = 0, hi = nseg - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
-                    }
-                    sg = lo;
-                    key = 1ull;   // decided below from the entry itself
-                }
-                if (key == 0ull || (fast && key >= kth)) continue;
-                const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
-                const float x = cx[ix];
-                const int j = cj[ix];
-                if (x == 0.0f || hk_key(j, x) >= kth) continue;
+            auto take_back = [&](int j, float x) {
                 const long long delta = to_fx(x, &st->err);
                 const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
                 for (int p = 0; p < a.d; ++p) {
@@ -885,6 +910,26 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
                     if (row >= base && row < base + kRowBlock)
                         atomicAdd(reinterpret_cast<unsigned long long*>(&corr[row - base]),
                                   static_cast<unsigned long long>(delta));
+                }
+            };
+            if (fast) {
+                for (int e = tid; e < count; e += kRowBlock) {
+                    const unsigned long long key = keys[e];
+                    if (key == 0ull || key >= kth) continue;
+                    const int sg = segmap[e];
+                    const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
+                    take_back(cj[ix], cx[ix]);
+                }
+            } else {
+                for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64) {
+                    const int cnt = seg_cnt[sg], fr = seg_frt[sg];
+                    for (int o = lane; o < cnt; o += 64) {
+                        const size_t ix = seg_phys(sg, cap, fr, o);
+                        const float x = cx[ix];
+                        if (x == 0.0f) continue;
+                        const int j = cj[ix];
+                        if (hk_key(j, x) < kth) take_back(j, x);
+                    }
                 }
             }
             __syncthreads();
@@ -1095,7 +1140,7 @@ hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, 
 }
 
 hipError_t launch_clear_state(DevState* st, hipStream_t s) {
-    k_prep_state<<<1, 256, 0, s>>>(st);
+    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(st);
     return hipGetLastError();
 }
 
@@ -1117,7 +1162,7 @@ hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStr
 hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0, hipStream_t s) {
     const int slot = (ip0.it & 1) ^ 1;   // the slot iteration it0 reads as "previous"
-    k_prep_state<<<1, 256, 0, s>>>(w.st);
+    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(w.st);
     if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
     if (x_hat0) k_prep_support<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, dm.n, w, slot);
     k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], w.D, dm.m, w.st);
