@@ -128,6 +128,7 @@ def bench_learned(args) -> int:
                 "converged_frac": float(np.mean([r[tag]["converged"] for r in rows])),
                 "iterations_mean": float(np.mean([r[tag]["iterations"] for r in rows])),
                 "ms_median": float(np.median([r[tag]["ms"] for r in rows])),
+                "ms_each": [round(r[tag]["ms"], 3) for r in rows],
             }
         per_snr[str(snr)] = agg
     out = {

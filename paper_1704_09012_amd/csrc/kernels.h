@@ -92,6 +92,8 @@ struct Workspace {
     float* learned;       // [n] learned decisions of the current iteration (NaN: none)
     float* lcache;        // [2n] the network's (logit, value) per column at its last evaluation
     float* reval[2];      // [m] residuals the learned decisions were last evaluated on
+    float* ystage;        // [m] y of a decode replayed on staging buffers
+    float* xstage;        // [n] its x_hat before the copy out
     uint4* Apk;           // [n] A_cols packed into one 16-byte word per column
     int seg_cap;          // entries per segment
     int sweep_grid;       // sweep workgroups (= segments)

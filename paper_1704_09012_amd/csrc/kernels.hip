@@ -1095,7 +1095,7 @@ size_t workspace_bytes(int n, int m) {
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
     (void)wn;
     return 4 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(4ull * n) +
-           al(8ull * n) + 2 * al(4ull * m) + al(16ull * n) + al(sizeof(DevState));
+           al(8ull * n) + 2 * al(4ull * m) + al(4ull * m) + al(4ull * n) + al(16ull * n) + al(sizeof(DevState));
 }
 
 void carve_workspace(void* base, int n, int m, Workspace* w) {
@@ -1119,6 +1119,8 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     w->learned = reinterpret_cast<float*>(take(4ull * n));
     w->lcache = reinterpret_cast<float*>(take(8ull * n));
     for (int b = 0; b < 2; ++b) w->reval[b] = reinterpret_cast<float*>(take(4ull * m));
+    w->ystage = reinterpret_cast<float*>(take(4ull * m));
+    w->xstage = reinterpret_cast<float*>(take(4ull * n));
     w->Apk = reinterpret_cast<uint4*>(take(16ull * n));
     w->st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
 }

@@ -325,6 +325,39 @@ int replay_decode(Buffers* b, const DecodeKey& key, hipStream_t s, Issue&& issue
     return RL0_OK;
 }
 
+// The key with the buffers of y and x_out left out.
+DecodeKey without_io(DecodeKey k) {
+    k.y = nullptr;
+    k.x = nullptr;
+    return k;
+}
+
+// Replays a decode whose launches issue(q, y, x) makes.  A graph bakes the buffers it
+// was captured with, so a call with other y / x_out buffers than the cached graph's
+// (the same matrix and parameters otherwise) would capture and instantiate anew.  Such
+// a call runs the graph captured once on the workspace's staging buffers instead: y is
+// copied in before it and x copied out after it.
+template <class Issue>
+int replay_decode_io(Buffers* b, DecodeKey key, const float* y, float* x_out, int n, int m, hipStream_t s,
+                     Issue&& issue) {
+    key.y = y;
+    key.x = x_out;
+    const DecodeKey staged = without_io(key);
+    bool direct = false, seen = false;
+    for (const GraphEntry& g : b->graphs) {
+        if (std::memcmp(&g.key, &key, sizeof(key)) == 0) direct = true;
+        const DecodeKey gk = without_io(g.key);
+        if (std::memcmp(&gk, &staged, sizeof(staged)) == 0) seen = true;
+    }
+    if (direct || !seen)
+        return replay_decode(b, key, s, [&](hipStream_t q) { return issue(q, y, x_out); });
+    HIP_TRY(hipMemcpyAsync(b->w.ystage, y, sizeof(float) * m, hipMemcpyDeviceToDevice, s));
+    if (int rc = replay_decode(b, staged, s, [&](hipStream_t q) { return issue(q, b->w.ystage, b->w.xstage); }))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(x_out, b->w.xstage, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    return RL0_OK;
+}
+
 rl0::ScoreTables tables_of(const DeviceConstants* dc) {
     rl0::ScoreTables tb;
     tb.Tz = dc->d_tables;
@@ -772,8 +805,8 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
     const int N = dc->hc.n_iters;
     const rl0::Workspace& w = b->w;
     const float* mlp = static_cast<const float*>(p->mlp);
-    auto issue = [&](hipStream_t q) -> int {
-        HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, nullptr, w, learned_sub_params(dc, p, 0), q));
+    auto issue = [&](hipStream_t q, const float* yq, float* xq) -> int {
+        HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, yq, nullptr, w, learned_sub_params(dc, p, 0), q));
         const rl0::DebugOut dbg{nullptr, nullptr};
         for (int j = 0; j < N; ++j) {
             const rl0::IterParams ipl = learned_sub_params(dc, p, 2 * j);
@@ -799,23 +832,21 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
             HIP_TRY(rl0::launch_iteration(dm, A, w, tb, ipl, dbg, q, nullptr, w.learned));
             HIP_TRY(rl0::launch_iteration(dm, A, w, tb, learned_sub_params(dc, p, 2 * j + 1), dbg, q));
         }
-        HIP_TRY(rl0::launch_finish(dm, w, learned_sub_params(dc, p, 2 * N), x_out, q));
+        HIP_TRY(rl0::launch_finish(dm, w, learned_sub_params(dc, p, 2 * N), xq, q));
         return RL0_OK;
     };
     if (graphs_enabled()) {
         DecodeKey key;
         std::memset(&key, 0, sizeof(key));
         key.A = A;
-        key.y = y;
-        key.x = x_out;
         key.dc = dc;
         key.n = dm.n;
         key.m = dm.m;
         key.d = dm.d;
         std::memcpy(&key.p, p, sizeof(*p));
-        if (int rc = replay_decode(b, key, s, issue)) return rc;
+        if (int rc = replay_decode_io(b, key, y, x_out, dm.n, dm.m, s, issue)) return rc;
     } else {
-        if (int rc = issue(s)) return rc;
+        if (int rc = issue(s, y, x_out)) return rc;
     }
     HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -961,12 +992,12 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     if (p->posterior == 1) return decode_learned(b, dc, dm, A_cols, y, p, x_out, st_h, s);
     const rl0::ScoreTables tb = tables_of(dc);
     const int N = dc->hc.n_iters;
-    auto issue = [&](hipStream_t q) -> int {
-        HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, y, nullptr, b->w, iter_params(dc, p, 0), q));
+    auto issue = [&](hipStream_t q, const float* yq, float* xq) -> int {
+        HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, yq, nullptr, b->w, iter_params(dc, p, 0), q));
         const rl0::DebugOut dbg{nullptr, nullptr};
         for (int it = 0; it < N; ++it)
             HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, q, profile_events(it)));
-        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), x_out, q));
+        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), xq, q));
         return RL0_OK;
     };
     // per-iteration timing events cannot be recorded into a captured graph: a profiled
@@ -975,16 +1006,14 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
         DecodeKey key;
         std::memset(&key, 0, sizeof(key));
         key.A = A_cols;
-        key.y = y;
-        key.x = x_out;
         key.dc = dc;
         key.n = n;
         key.m = m;
         key.d = d;
         std::memcpy(&key.p, p, sizeof(*p));
-        if (int rc = replay_decode(b, key, s, issue)) return rc;
+        if (int rc = replay_decode_io(b, key, y, x_out, n, m, s, issue)) return rc;
     } else {
-        if (int rc = issue(s)) return rc;
+        if (int rc = issue(s, y, x_out)) return rc;
     }
     // the slots, counters and flags lead the device state
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));

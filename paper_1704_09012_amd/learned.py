@@ -98,8 +98,9 @@ def compare(w, n: int, m: int, k: int, snr_db: float, seeds, d: int = 7, device:
             t0 = time.perf_counter()
             xh, st = R.decode(A, y, sigma=sig, k=k, **kw)
             torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
             row[tag] = {"rel_err": float(torch.linalg.norm(xh - x) / torch.linalg.norm(x)),
                         "iterations": st["iterations"], "accepted": st["accepted"],
-                        "converged": st["converged"], "ms": 1e3 * (time.perf_counter() - t0)}
+                        "converged": st["converged"], "ms": ms}
         out.append(row)
     return out

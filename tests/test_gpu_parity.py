@@ -258,6 +258,36 @@ def test_decode_replay_into_the_same_buffers():
         assert math.isfinite(float(junk))
 
 
+def test_decode_into_new_buffers_replays_through_staging():
+    """Decodes of one matrix with y and x_out in fresh buffers on every call: the first
+    call captures on its own buffers, later ones replay a graph on the workspace's
+    staging buffers.  Every result against the oracle, also after the buffers of an
+    earlier call are reused."""
+    n, m, k, d = 8192, 1024, 120, 7
+    inst0, _, _, _ = problem(n, m, k, d, 40, 41)
+    A_t = dev(inst0.A_cols)
+    params = R.params_default(n, m, d, k, float(np.float32(I.sigma_for_snr(40, n, m, k, d))))
+    C = D.make_constants(n, m, d, k, params.sigma)
+    keep = []
+    for rep, seed in enumerate((41, 42, 43, 44)):
+        print(f"call {rep}", flush=True)
+        rng = np.random.default_rng(seed)
+        x = np.zeros(n, np.float32)
+        x[rng.choice(n, k, replace=False)] = rng.normal(0, 1, k).astype(np.float32)
+        eta = rng.normal(0, params.sigma, m).astype(np.float32)
+        y = D.measure(inst0.A_cols, x, eta, m)
+        y_t = dev(y)
+        x_t = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+        _, st = R.decode(A_t, y_t, params=params, out=x_t)
+        res = D.decode(inst0.A_cols, y, C)
+        assert_same_decode(host(x_t), st, res)
+        keep.append((y_t, x_t, y, res))
+    y_t, x_t, y, res = keep[0]          # the first call's own buffers again: its direct graph
+    x_t.fill_(float("nan"))
+    _, st = R.decode(A_t, y_t, params=params, out=x_t)
+    assert_same_decode(host(x_t), st, res)
+
+
 def _golden_cases():
     if not os.path.isdir(GOLDEN):
         return []
