@@ -253,25 +253,24 @@ __global__ __launch_bounds__(256) void k_prep_slot(DevState* st, int slot) {
 
 // The top 11 bits of hk_key(j, x) (x != 0): bits 30..20 of |x|.
 __device__ __forceinline__ unsigned top_digit(float x) { return abs_bits(x) >> 20; }
-static_assert(kHistBins == 2048 && (kHistCopies * kHistBins) % kRowGrid == 0 &&
-                  kHistCopies * kHistBins / kRowGrid <= kRowBlock,
-              "H_k's radix digits are 11 bits; the finish grid clears the histograms");
+static_assert(kHistBins == 2048, "H_k's radix digits are 11 bits");
 
-// Within one workgroup: the digit of the bucket (among 2048, highest first) that holds
-// the `rem`-th largest of the counted keys, the count above it and the bucket's count.
+// Within one workgroup of kRowBlock threads: the digit of the bucket (among 2048,
+// highest first) that holds the `rem`-th largest of the counted keys, the count above it
+// and the bucket's count.  Thread t holds digits 2047 - 2t and 2046 - 2t; the prefix
+// counts come from wave scans and one exchange of the wave totals (scan: >= 16 entries).
 __device__ void find_digit(const unsigned* hist, unsigned rem, unsigned* scan, int* digit_out,
                            unsigned* above_out, unsigned* bucket_out) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned hi = hist[2047 - 2 * tid], lo = hist[2046 - 2 * tid];
-    scan[tid] = hi + lo;
-    __syncthreads();
-    for (int off = 1; off < kRowBlock; off <<= 1) {
-        const unsigned add = tid >= off ? scan[tid - off] : 0u;
-        __syncthreads();
-        scan[tid] += add;
-        __syncthreads();
+    unsigned incl = hi + lo;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
     }
-    const unsigned incl = scan[tid];
+    if (lane == 63) scan[wave] = incl;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) incl += scan[w];
     const unsigned before = incl - hi - lo;
     if (before < rem && rem <= before + hi) {
         *digit_out = 2047 - 2 * tid;
@@ -744,7 +743,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     __shared__ unsigned long long keys[kLdsKeys];
     __shared__ unsigned short segmap[kLdsKeys];
     __shared__ unsigned hist[kHistBins];
-    __shared__ unsigned scan[kRowBlock];
+    __shared__ unsigned scan[kRowBlock / 64];
     __shared__ int seg_cnt[kSweepGridMax];
     __shared__ int seg_frt[kSweepGridMax];
     __shared__ int seg_start[kSweepGridMax];
@@ -785,8 +784,8 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     }
     // the next iteration's first-digit histograms are cleared here, a slice per workgroup
-    if (tid < kHistCopies * kHistBins / kRowGrid)
-        (&st->hk_hist[me ^ 1][0][0])[blockIdx.x * (kHistCopies * kHistBins / kRowGrid) + tid] = 0u;
+    for (int i = blockIdx.x * kRowBlock + tid; i < kHistCopies * kHistBins; i += gridDim.x * kRowBlock)
+        (&st->hk_hist[me ^ 1][0][0])[i] = 0u;
     if (tid == 0) {
         nz_sh = 0;
         upd_sh = 0;
@@ -798,10 +797,19 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     __syncthreads();
     if (s.done) return;
     const int c = s.cur, tr = c ^ 1;
-    if (myz) atomicAdd(&nz_sh, myz);
-    if (myu) atomicAdd(&upd_sh, myu);
+    if (tid < kSweepGridMax) {
+        int z = myz, u = myu;
+        for (int off = 32; off > 0; off >>= 1) {
+            z += __shfl_down(z, off);
+            u += __shfl_down(u, off);
+        }
+        if (lane == 0) {
+            if (z) atomicAdd(&nz_sh, z);
+            if (u) atomicAdd(&upd_sh, u);
+        }
+    }
     __syncthreads();
-    if (blockIdx.x == 0 && tid == 0) st->updates_total += upd_sh;
+    if (blockIdx.x == 0 && tid == 0 && upd_sh) atomicAdd(&st->updates_total, upd_sh);
     const bool all_kept = nz_sh <= a.k;
     const int* __restrict__ cj = a.w.cand_j[me];
     const float* __restrict__ cx = a.w.cand_x[me];
@@ -810,22 +818,48 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     unsigned long long kth = 1ull << 32;   // every nonzero entry is kept
     int count = 0;
     bool fast = true;
+    // the first digit's histogram, counted by the sweep (its loads overlap the key loads)
+    unsigned h_hi = 0u, h_lo = 0u;
+    if (!all_kept) {
+#pragma unroll
+        for (int cp = 0; cp < kHistCopies; ++cp) {
+            h_hi += st->hk_hist[me][cp][tid];
+            h_lo += st->hk_hist[me][cp][tid + kRowBlock];
+        }
+    }
     if (!all_kept) {
         count = segment_scan(myc, nseg, seg_start, wtot);
         fast = count <= kLdsKeys;
         if (fast) {
-            for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64)
-                for (int o = lane; o < seg_cnt[sg]; o += 64) segmap[seg_start[sg] + o] = static_cast<unsigned short>(sg);
+            // entry -> segment map: a thread per segment writes its run
+            if (tid < nseg) {
+                const int st0 = seg_start[tid];
+                for (int o = 0; o < myc; ++o) segmap[st0 + o] = static_cast<unsigned short>(tid);
+            }
             __syncthreads();
+            // every load is issued before any is used (entries past the count read the
+            // first candidate and are discarded)
+            size_t ixs[kSelPer];
 #pragma unroll
             for (int q = 0; q < kSelPer; ++q) {
                 const int e = q * kRowBlock + tid;
+                ixs[q] = 0;
                 if (e < count) {
                     const int sg = segmap[e];
-                    const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
-                    const float x = cx[ix];
-                    keys[e] = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
+                    ixs[q] = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
                 }
+            }
+            float xs[kSelPer];
+            int js[kSelPer];
+#pragma unroll
+            for (int q = 0; q < kSelPer; ++q) {
+                xs[q] = cx[ixs[q]];
+                js[q] = cj[ixs[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < kSelPer; ++q) {
+                const int e = q * kRowBlock + tid;
+                if (e < count) keys[e] = xs[q] != 0.0f ? hk_key(js[q], xs[q]) : 0ull;
             }
             __syncthreads();
         }
@@ -836,13 +870,6 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             const int sft = pass < 5 ? 52 - 11 * pass : 0;
             const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
             if (pass == 0) {
-                // the first digit's histogram, counted by the sweep
-                unsigned h_hi = 0u, h_lo = 0u;
-#pragma unroll
-                for (int cp = 0; cp < kHistCopies; ++cp) {
-                    h_hi += st->hk_hist[me][cp][tid];
-                    h_lo += st->hk_hist[me][cp][tid + kRowBlock];
-                }
                 hist[tid] = h_hi;
                 hist[tid + kRowBlock] = h_lo;
                 __syncthreads();
@@ -916,9 +943,10 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
                 for (int e = tid; e < count; e += kRowBlock) {
                     const unsigned long long key = keys[e];
                     if (key == 0ull || key >= kth) continue;
+                    // the key holds j; x'_j (for its sign) loads beside the column's rows
                     const int sg = segmap[e];
                     const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
-                    take_back(cj[ix], cx[ix]);
+                    take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), cx[ix]);
                 }
             } else {
                 for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64) {
@@ -1003,6 +1031,14 @@ int sweep_grid(int n) {
     // one workgroup per CU, persistent over chunks of kSweepChunk columns
     const int chunks = blocks(n, kSweepChunk);
     return chunks < kSweepGridMax ? chunks : kSweepGridMax;
+}
+
+// Workgroups of the row kernel after the sweep: one per kRowBlock rows, at most kRowGrid
+// (each holds a partial sum; the unused ones stay zero).  Every workgroup runs H_k's
+// selection for itself, so fewer of them read the candidates fewer times.
+int finish_grid(int m) {
+    const int g = blocks(m, kRowBlock);
+    return g < 1 ? 1 : (g > kRowGrid ? kRowGrid : g);
 }
 
 int seg_capacity(int n) {
@@ -1193,7 +1229,7 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
     const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next};
-    return launch_timed(k_finish_rows, kRowGrid, kRowBlock, s, ev ? ev + 4 : nullptr, fa);
+    return launch_timed(k_finish_rows, finish_grid(dm.m), kRowBlock, s, ev ? ev + 4 : nullptr, fa);
 }
 
 hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s) {

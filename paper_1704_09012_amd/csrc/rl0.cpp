@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -117,8 +118,15 @@ int upload_constants(DeviceConstants* dc) {
     return RL0_OK;
 }
 
+// At most this many problems' constants are kept; past it the cache is emptied (rare:
+// every distinct sigma of a problem size is an entry).
+constexpr size_t kMaxConstants = 4096;
+int drop_all_constants();   // after the working memory's definitions
+
 // Looks up (or builds and uploads) the constants of a problem.
 int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
+    if (g_consts.size() >= kMaxConstants)
+        if (int rc = drop_all_constants()) return rc;
     const ConstKey key = key_of(pr, device);
     auto it = g_consts.find(key);
     if (it != g_consts.end()) {
@@ -135,6 +143,8 @@ int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
 
 // The same for many problems; the ones not cached yet are computed on host threads.
 int get_constants_many(const std::vector<rl0::Problem>& prs, int device, std::vector<DeviceConstants*>* out) {
+    if (g_consts.size() + prs.size() > kMaxConstants)
+        if (int rc = drop_all_constants()) return rc;
     out->assign(prs.size(), nullptr);
     std::map<ConstKey, size_t> fresh_of;   // key -> index into fresh
     std::vector<size_t> fresh_src;          // a problem index per fresh entry
@@ -234,6 +244,26 @@ int get_workspace(int device, hipStream_t s, int n, int m, Buffers** out) {
             return fail(RL0_ENOMEM, "hipHostMalloc(state)");
     }
     *out = b;
+    return RL0_OK;
+}
+
+// Frees every cached constant set.  Decode graphs bake their constants' device
+// pointers, so they go too, once all work on every device that holds a workspace is done.
+int drop_all_constants() {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    std::set<int> devices;
+    for (auto& kv : g_ws) devices.insert(kv.first.first);
+    for (auto& kv : g_consts) devices.insert(std::get<0>(kv.first));
+    for (int dev : devices) {
+        HIP_TRY(hipSetDevice(dev));
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    HIP_TRY(hipSetDevice(cur));
+    for (auto& kv : g_ws) drop_graphs(kv.second.get());
+    for (auto& kv : g_consts)
+        if (kv.second->d_tables) HIP_TRY(hipFree(kv.second->d_tables));
+    g_consts.clear();
     return RL0_OK;
 }
 
