@@ -728,8 +728,49 @@ struct FinishArgs {
     uint32_t tau_next;
 };
 
-constexpr int kLdsKeys = 12288;   // candidate keys a finish workgroup caches in LDS
-constexpr int kSelPer = 12;       // candidate loads in flight per thread (kLdsKeys / block)
+constexpr int kWinKeys = 12288;   // candidates a window of the row kernel maps in LDS
+constexpr int kWinPer = kWinKeys / kRowBlock;   // their loads in flight per thread
+constexpr int kBucketCap = 4096;  // entries of H_k's boundary bucket kept in LDS
+constexpr int kCorrRows = 8192;   // rows a correction window of the row kernel covers
+
+// Calls fn(j, x'_j, ok) for every candidate of the iteration, in windows of kWinKeys: an
+// entry -> segment map is written in LDS by a thread per segment, then every thread issues
+// its kWinPer loads before it uses any.  Every lane of the workgroup calls fn the same
+// number of times (ok = false past the count), so fn may use wave-wide operations.
+template <class F>
+__device__ __forceinline__ void for_candidates(int count, int nseg, int cap, const int* seg_start, const int* seg_cnt,
+                                               const int* seg_frt, unsigned short* segmap, const int* __restrict__ cj,
+                                               const float* __restrict__ cx, F&& fn) {
+    const int tid = threadIdx.x;
+    for (int w0 = 0; w0 < count; w0 += kWinKeys) {
+        if (tid < nseg) {
+            const int st0 = seg_start[tid], c = seg_cnt[tid];
+            const int lo = max(0, w0 - st0), hi = min(c, w0 + kWinKeys - st0);
+            for (int o = lo; o < hi; ++o) segmap[st0 + o - w0] = static_cast<unsigned short>(tid);
+        }
+        __syncthreads();
+        size_t ixs[kWinPer];
+#pragma unroll
+        for (int q = 0; q < kWinPer; ++q) {
+            const int e = q * kRowBlock + tid;
+            ixs[q] = 0;
+            if (w0 + e < count) {
+                const int sg = segmap[e];
+                ixs[q] = seg_phys(sg, cap, seg_frt[sg], w0 + e - seg_start[sg]);
+            }
+        }
+        float xs[kWinPer];
+        int js[kWinPer];
+#pragma unroll
+        for (int q = 0; q < kWinPer; ++q) {
+            xs[q] = cx[ixs[q]];
+            js[q] = cj[ixs[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < kWinPer; ++q) fn(js[q], xs[q], w0 + q * kRowBlock + tid < count);
+        __syncthreads();   // the map is rewritten by the next window
+    }
+}
 
 // One kernel after the sweep.  H_k: when the nonzero candidates number at most k (the
 // common case once the support has formed) every one is kept and the sweep has already
@@ -740,19 +781,20 @@ constexpr int kSelPer = 12;       // candidate loads in flight per thread (kLdsK
 // rounded residual r = fl32(2^-40 S), the partial sum of ||r||_1 and the outer-test
 // bitmasks of the next threshold for both possible outcomes of the decision.
 __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
-    __shared__ unsigned long long keys[kLdsKeys];
-    __shared__ unsigned short segmap[kLdsKeys];
+    __shared__ unsigned short segmap[kWinKeys];
+    __shared__ unsigned long long bkey[kBucketCap];
+    __shared__ float bx[kBucketCap];
+    __shared__ long long corr[kCorrRows];
     __shared__ unsigned hist[kHistBins];
     __shared__ unsigned scan[kRowBlock / 64];
     __shared__ int seg_cnt[kSweepGridMax];
     __shared__ int seg_frt[kSweepGridMax];
     __shared__ int seg_start[kSweepGridMax];
     __shared__ int wtot[kSweepGridMax / 64];
-    __shared__ long long corr[kRowBlock];
     __shared__ long long sh[kRowBlock / 64];
     __shared__ int digit;
     __shared__ unsigned above, bucket;
-    __shared__ int nz_sh, upd_sh;
+    __shared__ int nz_sh, upd_sh, bn;
     const int me = a.it & 1;
     DevState* st = a.w.st;
     const int tid = threadIdx.x;
@@ -814,11 +856,15 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     const int* __restrict__ cj = a.w.cand_j[me];
     const float* __restrict__ cx = a.w.cand_x[me];
 
-    // ---- H_k's threshold, only when something is dropped
+    // ---- H_k, only when something is dropped.  The first radix digit's histogram is the
+    // sweep's (summed over its copies).  Candidates below the boundary bucket are dropped
+    // and those above it kept.  One pass over the candidates takes back the dropped ones on
+    // the first correction window of rows and, when the bucket is not kept whole, collects
+    // the bucket's entries in LDS; the later digits are then selected among them alone.
     unsigned long long kth = 1ull << 32;   // every nonzero entry is kept
     int count = 0;
-    bool fast = true;
-    // the first digit's histogram, counted by the sweep (its loads overlap the key loads)
+    unsigned d1 = 0u;
+    int nbk = 0;
     unsigned h_hi = 0u, h_lo = 0u;
     if (!all_kept) {
 #pragma unroll
@@ -827,81 +873,66 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             h_lo += st->hk_hist[me][cp][tid + kRowBlock];
         }
     }
+    // +rint(2^40 x'_j) on the rows [cb, ce) of a column H_k drops
+    int cb = row0, ce = min(row1, row0 + kCorrRows);
+    auto take_back = [&](int j, float x) {
+        const long long delta = to_fx(x, &st->err);
+        const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
+        for (int p = 0; p < a.d; ++p) {
+            const int row = col[p];
+            if (row >= cb && row < ce)
+                atomicAdd(reinterpret_cast<unsigned long long*>(&corr[row - cb]), static_cast<unsigned long long>(delta));
+        }
+    };
     if (!all_kept) {
         count = segment_scan(myc, nseg, seg_start, wtot);
-        fast = count <= kLdsKeys;
-        if (fast) {
-            // entry -> segment map: a thread per segment writes its run
-            if (tid < nseg) {
-                const int st0 = seg_start[tid];
-                for (int o = 0; o < myc; ++o) segmap[st0 + o] = static_cast<unsigned short>(tid);
-            }
-            __syncthreads();
-            // every load is issued before any is used (entries past the count read the
-            // first candidate and are discarded)
-            size_t ixs[kSelPer];
-#pragma unroll
-            for (int q = 0; q < kSelPer; ++q) {
-                const int e = q * kRowBlock + tid;
-                ixs[q] = 0;
-                if (e < count) {
-                    const int sg = segmap[e];
-                    ixs[q] = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
+        if (tid == 0) bn = 0;
+        for (int i = tid; i < ce - cb; i += kRowBlock) corr[i] = 0;
+        hist[tid] = h_hi;
+        hist[tid + kRowBlock] = h_lo;
+        __syncthreads();
+        find_digit(hist, static_cast<unsigned>(a.k), scan, &digit, &above, &bucket);
+        d1 = static_cast<unsigned>(digit);
+        unsigned long long prefix = static_cast<unsigned long long>(d1) << 52;
+        unsigned long long pmask = 0x7FFull << 52;
+        unsigned rem = static_cast<unsigned>(a.k) - above;
+        bool exact = (rem == bucket);
+        const bool gather = !exact;
+        for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx, [&](int j, float x, bool ok) {
+            if (!ok || x == 0.0f) return;
+            const unsigned dg = top_digit(x);
+            if (dg < d1) {
+                take_back(j, x);
+            } else if (gather && dg == d1) {
+                const int slot = atomicAdd(&bn, 1);
+                if (slot < kBucketCap) {
+                    bkey[slot] = hk_key(j, x);
+                    bx[slot] = x;
                 }
             }
-            float xs[kSelPer];
-            int js[kSelPer];
-#pragma unroll
-            for (int q = 0; q < kSelPer; ++q) {
-                xs[q] = cx[ixs[q]];
-                js[q] = cj[ixs[q]];
-            }
-#pragma unroll
-            for (int q = 0; q < kSelPer; ++q) {
-                const int e = q * kRowBlock + tid;
-                if (e < count) keys[e] = xs[q] != 0.0f ? hk_key(js[q], xs[q]) : 0ull;
-            }
-            __syncthreads();
-        }
-        unsigned long long prefix = 0ull, pmask = 0ull;
-        unsigned rem = static_cast<unsigned>(a.k);
-        bool exact = false;
-        for (int pass = 0; pass < 6 && !exact; ++pass) {
+        });
+        nbk = bn;
+        for (int pass = 1; pass < 6 && !exact; ++pass) {
             const int sft = pass < 5 ? 52 - 11 * pass : 0;
             const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
-            if (pass == 0) {
-                hist[tid] = h_hi;
-                hist[tid + kRowBlock] = h_lo;
-                __syncthreads();
-            } else {
-                hist[tid] = 0u;
-                hist[tid + kRowBlock] = 0u;
-                __syncthreads();
-                if (fast) {
-                    for (int e0 = 0; e0 < count; e0 += kRowBlock) {
-                        const int e = e0 + tid;
-                        const unsigned long long key = e < count ? keys[e] : 0ull;
-                        hist_add(hist, static_cast<unsigned>((key >> sft) & dmask),
-                                 key != 0ull && (key & pmask) == prefix);
-                    }
-                } else {
-                    // a wave per segment
-                    for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64) {
-                        const int cnt = seg_cnt[sg], fr = seg_frt[sg];
-                        for (int o0 = 0; o0 < cnt; o0 += 64) {
-                            const int o = o0 + lane;
-                            unsigned long long key = 0ull;
-                            if (o < cnt) {
-                                const size_t ix = seg_phys(sg, cap, fr, o);
-                                const float x = cx[ix];
-                                key = x != 0.0f ? hk_key(cj[ix], x) : 0ull;
-                            }
-                            hist_add(hist, static_cast<unsigned>((key >> sft) & dmask),
-                                     key != 0ull && (key & pmask) == prefix);
-                        }
-                    }
+            hist[tid] = 0u;
+            hist[tid + kRowBlock] = 0u;
+            __syncthreads();
+            if (nbk <= kBucketCap) {
+                for (int e0 = 0; e0 < nbk; e0 += kRowBlock) {
+                    const int e = e0 + tid;
+                    const unsigned long long key = e < nbk ? bkey[e] : 0ull;
+                    hist_add(hist, static_cast<unsigned>((key >> sft) & dmask), e < nbk && (key & pmask) == prefix);
                 }
                 __syncthreads();
+            } else {
+                // the bucket did not fit: the pass reads every candidate
+                for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx,
+                               [&](int j, float x, bool ok) {
+                                   const unsigned long long key = (ok && x != 0.0f) ? hk_key(j, x) : 0ull;
+                                   hist_add(hist, static_cast<unsigned>((key >> sft) & dmask),
+                                            key != 0ull && (key & pmask) == prefix);
+                               });
             }
             find_digit(hist, rem, scan, &digit, &above, &bucket);
             prefix |= static_cast<unsigned long long>(digit) << sft;
@@ -910,80 +941,79 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             exact = (rem == bucket);
         }
         kth = prefix;
+        // the bucket's dropped entries
+        if (gather) {
+            if (nbk <= kBucketCap) {
+                for (int e = tid; e < nbk; e += kRowBlock) {
+                    const unsigned long long key = bkey[e];
+                    if (key < kth) take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), bx[e]);
+                }
+            } else {
+                for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx,
+                               [&](int j, float x, bool ok) {
+                                   if (ok && x != 0.0f && top_digit(x) == d1 && hk_key(j, x) < kth) take_back(j, x);
+                               });
+            }
+        }
+        __syncthreads();
     }
     if (blockIdx.x == 0 && tid == 0) st->kth_key[me] = kth;
 
-    // ---- the rows, a block at a time
+    // ---- the rows, a correction window of kCorrRows rows at a time
     long long l = 0;
-    for (int base = row0; base < row1; base += kRowBlock) {
-        const int i = base + tid;
-        if (base != row0) {
-            s0 = s1 = dl = 0;
+    for (; cb < row1; cb += kCorrRows) {
+        ce = min(row1, cb + kCorrRows);
+        if (!all_kept && cb != row0) {
+            // a later window: the dropped columns' rows in it
+            for (int i = tid; i < ce - cb; i += kRowBlock) corr[i] = 0;
+            __syncthreads();
+            const bool bucket_in_lds = nbk <= kBucketCap;
+            for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx, [&](int j, float x, bool ok) {
+                if (!ok || x == 0.0f) return;
+                const unsigned dg = top_digit(x);
+                if (dg < d1 || (dg == d1 && !bucket_in_lds && hk_key(j, x) < kth)) take_back(j, x);
+            });
+            if (bucket_in_lds) {
+                for (int e = tid; e < nbk; e += kRowBlock) {
+                    const unsigned long long key = bkey[e];
+                    if (key < kth) take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), bx[e]);
+                }
+            }
+            __syncthreads();
+        }
+        for (int base = cb; base < ce; base += kRowBlock) {
+            const int i = base + tid;
+            if (base != row0) {
+                s0 = s1 = dl = 0;
+                if (i < row1) {
+                    s0 = a.w.S[0][i];
+                    s1 = a.w.S[1][i];
+                    dl = a.w.D[i];
+                }
+            }
+            if (!all_kept && i < ce) dl += corr[i - cb];
+            bool bt = false, bc = false;
             if (i < row1) {
-                s0 = a.w.S[0][i];
-                s1 = a.w.S[1][i];
-                dl = a.w.D[i];
+                // the trial residual: the current one plus this iteration's changes
+                const long long sc = c ? s1 : s0;
+                const long long snew = sc + dl;
+                a.w.S[tr][i] = snew;
+                a.w.D[i] = 0;
+                const float v = from_fx(snew);
+                a.w.r[tr][i] = v;
+                l += l1_term(v);
+                bt = abs_bits(v) >= a.tau_next;
+                bc = abs_bits(from_fx(sc)) >= a.tau_next;
+            }
+            const unsigned long long bmt = __ballot(bt);
+            const unsigned long long bmc = __ballot(bc);
+            if (lane == 0) {
+                const int wb = base + (tid & ~63);
+                store_bits(a.w.bm[tr], words, wb, bmt);
+                store_bits(a.w.bm[c], words, wb, bmc);
             }
         }
-        if (!all_kept) {
-            // the dropped columns' rows in [base, base + kRowBlock)
-            corr[tid] = 0;
-            __syncthreads();
-            auto take_back = [&](int j, float x) {
-                const long long delta = to_fx(x, &st->err);
-                const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
-                for (int p = 0; p < a.d; ++p) {
-                    const int row = col[p];
-                    if (row >= base && row < base + kRowBlock)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(&corr[row - base]),
-                                  static_cast<unsigned long long>(delta));
-                }
-            };
-            if (fast) {
-                for (int e = tid; e < count; e += kRowBlock) {
-                    const unsigned long long key = keys[e];
-                    if (key == 0ull || key >= kth) continue;
-                    // the key holds j; x'_j (for its sign) loads beside the column's rows
-                    const int sg = segmap[e];
-                    const size_t ix = seg_phys(sg, cap, seg_frt[sg], e - seg_start[sg]);
-                    take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), cx[ix]);
-                }
-            } else {
-                for (int sg = tid >> 6; sg < nseg; sg += kRowBlock / 64) {
-                    const int cnt = seg_cnt[sg], fr = seg_frt[sg];
-                    for (int o = lane; o < cnt; o += 64) {
-                        const size_t ix = seg_phys(sg, cap, fr, o);
-                        const float x = cx[ix];
-                        if (x == 0.0f) continue;
-                        const int j = cj[ix];
-                        if (hk_key(j, x) < kth) take_back(j, x);
-                    }
-                }
-            }
-            __syncthreads();
-            dl += corr[tid];
-        }
-        bool bt = false, bc = false;
-        if (i < row1) {
-            // the trial residual: the current one plus this iteration's changes
-            const long long sc = c ? s1 : s0;
-            const long long snew = sc + dl;
-            a.w.S[tr][i] = snew;
-            a.w.D[i] = 0;
-            const float v = from_fx(snew);
-            a.w.r[tr][i] = v;
-            l += l1_term(v);
-            bt = abs_bits(v) >= a.tau_next;
-            bc = abs_bits(from_fx(sc)) >= a.tau_next;
-        }
-        const unsigned long long bmt = __ballot(bt);
-        const unsigned long long bmc = __ballot(bc);
-        if (lane == 0) {
-            const int wb = base + (tid & ~63);
-            store_bits(a.w.bm[tr], words, wb, bmt);
-            store_bits(a.w.bm[c], words, wb, bmc);
-        }
-        if (!all_kept) __syncthreads();   // corr is reused by the next block of rows
+        if (!all_kept) __syncthreads();   // corr is reused by the next window
     }
     const long long tot = block_sum_rows(l, sh);
     if (tid == 0) st->L_part[me][blockIdx.x] = tot;
