@@ -116,11 +116,12 @@ hipError_t launch_zero_i32(int* p, long long count, hipStream_t s);
 hipError_t launch_zero_f32(float* p, long long count, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStream_t s);
 
-// Prepare a run that starts at iteration it0 from x_hat0 (nullptr: x = 0).
+// Prepare a run that starts at iteration it0 from x_hat0 (nullptr: x = 0); x_zero, when
+// given, is cleared on the way (the decode's output, written at its end).
 // validate: check A_cols first (a malformed A stops the run before any sweep).
 hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0,
-                          hipStream_t s);
+                          hipStream_t s, float* x_zero = nullptr);
 // One loop iteration (the sweep, then H_k with the rows).  ev (optional, 6 events) gets
 // the start and end of the sweep dispatch in ev[0..1] and of the row dispatch in ev[4..5].  With
 // `learned` (per column: the update, NaN for none) the sweep takes those decisions in
@@ -131,9 +132,10 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
 // The decision the next sweep will take, written ahead to DevState::peek_cur/peek_done
 // (ip.it = that sweep's iteration).
 hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s);
-// Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat.
+// Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat (x_zeroed: x_out
+// already holds zeros).
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
-                         float* x_out, hipStream_t s);
+                         float* x_out, hipStream_t s, bool x_zeroed = false);
 // After launch_finish: H_k(x') of the last executed iteration, zero elsewhere.
 hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, float* x_trial,
                             hipStream_t s);

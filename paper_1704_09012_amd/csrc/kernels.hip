@@ -392,16 +392,24 @@ __device__ __forceinline__ void load_rows(const int32_t* __restrict__ A, const u
     }
 }
 
-// The packed form of A_cols (one 16-byte word per column).
+// The packed form of A_cols (one 16-byte word per column).  With err, the columns are
+// validated on the way (rows strictly ascending in [0, m)); with x_zero, x_zero[j] = 0.
 template <int D>
-__global__ void k_pack_cols(const int32_t* __restrict__ A, int n, uint4* __restrict__ Apk) {
+__global__ void k_pack_cols(const int32_t* __restrict__ A, int n, int m, uint4* __restrict__ Apk, int* err,
+                            float* __restrict__ x_zero) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    if (x_zero) x_zero[j] = 0.0f;
     constexpr int F = Packing<D>::kField;
     unsigned long long lo = 0ull, hi = 0ull;
+    int prev = -1;
+    bool bad = false;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
-        const unsigned long long r = static_cast<unsigned int>(A[static_cast<size_t>(j) * D + p]);
+        const int rp = A[static_cast<size_t>(j) * D + p];
+        bad |= (rp <= prev) | (rp >= m);
+        prev = rp;
+        const unsigned long long r = static_cast<unsigned int>(rp);
         const int o = p * F;
         if (o + F <= 64) {
             lo |= r << o;
@@ -414,6 +422,7 @@ __global__ void k_pack_cols(const int32_t* __restrict__ A, int n, uint4* __restr
     }
     Apk[j] = make_uint4(static_cast<unsigned>(lo), static_cast<unsigned>(lo >> 32), static_cast<unsigned>(hi),
                         static_cast<unsigned>(hi >> 32));
+    if (err && bad) atomicOr(err, kErrIndex);
 }
 
 // D[row] += rint(2^40 x_old) - rint(2^40 x_new) on the d rows of a column: the exact
@@ -1038,9 +1047,23 @@ __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n
 }
 
 // x_out = x_hat (or, with trial = 1, H_k(x') of the last executed iteration) from the
-// candidate segments of the last executed iteration.  x_out is zeroed first.
-__global__ void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end, int trial) {
-    const Slot fin = w.st->slot[it_end & 1];
+// candidate segments of the last executed iteration; x_out holds zeros beforehand.  With decide = 1 every workgroup first takes the
+// decision on the last iteration (it_end = n_iters) itself, and workgroup 0 records it.
+__global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end,
+                                                  int trial, int decide_last, int n_iters, double tol_fx) {
+    __shared__ long long red[4];
+    __shared__ Slot fin_sh;
+    if (decide_last) {
+        const long long Lt = trial_l1_block(w.st, (it_end & 1) ^ 1, red);
+        if (threadIdx.x == 0) {
+            fin_sh = decide(w.st, it_end, n_iters, tol_fx, Lt);
+            if (blockIdx.x == 0) w.st->slot[it_end & 1] = fin_sh;
+        }
+    } else if (threadIdx.x == 0) {
+        fin_sh = w.st->slot[it_end & 1];
+    }
+    __syncthreads();
+    const Slot fin = fin_sh;
     const int par = fin.last_par;   // the parity of it0 - 1 if nothing ran
     const int acc = trial ? 1 : fin.accepted_last;
     const unsigned long long kth = w.st->kth_key[par];
@@ -1100,16 +1123,18 @@ bool pack_fits(int m) {
 
 // The packed indices when they fit (d <= 16 and m <= 2^field); false if not.
 template <int D>
-bool launch_pack_d(const int32_t* A, int n, int m, uint4* Apk, hipStream_t s) {
+bool launch_pack_d(const int32_t* A, int n, int m, uint4* Apk, int* err, float* x_zero, hipStream_t s) {
     if (!pack_fits<D>(m)) return false;
-    k_pack_cols<D><<<blocks(n, 256), 256, 0, s>>>(A, n, Apk);
+    k_pack_cols<D><<<blocks(n, 256), 256, 0, s>>>(A, n, m, Apk, err, x_zero);
     return true;
 }
 
-bool launch_pack(int d, const int32_t* A, int n, int m, uint4* Apk, hipStream_t s) {
+// Packs A_cols when its rows fit the packed fields (false otherwise: nothing ran), and
+// validates it and zeroes x_zero on the way when those are given.
+bool launch_pack(int d, const int32_t* A, int n, int m, uint4* Apk, int* err, float* x_zero, hipStream_t s) {
     switch (d) {
 #define RL0_PK(D) \
-    case D: return launch_pack_d<D>(A, n, m, Apk, s);
+    case D: return launch_pack_d<D>(A, n, m, Apk, err, x_zero, s);
         RL0_PK(1) RL0_PK(2) RL0_PK(3) RL0_PK(4) RL0_PK(5) RL0_PK(6) RL0_PK(7) RL0_PK(8)
         RL0_PK(9) RL0_PK(10) RL0_PK(11) RL0_PK(12) RL0_PK(13) RL0_PK(14) RL0_PK(15) RL0_PK(16)
 #undef RL0_PK
@@ -1228,13 +1253,18 @@ hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStr
 }
 
 hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
-                          const float* x_hat0, const Workspace& w, const IterParams& ip0, hipStream_t s) {
+                          const float* x_hat0, const Workspace& w, const IterParams& ip0, hipStream_t s,
+                          float* x_zero) {
     const int slot = (ip0.it & 1) ^ 1;   // the slot iteration it0 reads as "previous"
     k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(w.st);
-    if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
     if (x_hat0) k_prep_support<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, dm.n, w, slot);
     k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], w.D, dm.m, w.st);
-    launch_pack(dm.d, A, dm.n, dm.m, w.Apk, s);
+    // the packing pass validates the columns and clears x_zero; without packing they
+    // run on their own
+    if (!launch_pack(dm.d, A, dm.n, dm.m, w.Apk, validate ? &w.st->err : nullptr, x_zero, s)) {
+        if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
+        if (x_zero) k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_zero, dm.n);
+    }
     if (x_hat0) k_prep_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.d, x_hat0, w.S[0], w.st);
     k_prep_rows2<<<kRowGrid, kRowBlock, 0, s>>>(w.S[0], w.r[0], w.bm[0], dm.m, ip0.tau_bits, w.st, slot);
     k_prep_slot<<<1, 256, 0, s>>>(w.st, slot);
@@ -1268,19 +1298,20 @@ hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s) 
 }
 
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
-                         float* x_out, hipStream_t s) {
-    k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx);
-    if (x_out) {
-        k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_out, dm.n);
-        k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, 0);
+                         float* x_out, hipStream_t s, bool x_zeroed) {
+    if (!x_out) {
+        k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx);
+        return hipGetLastError();
     }
+    if (!x_zeroed) k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_out, dm.n);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, 0, 1, ip_last.n_iters, ip_last.tol_fx);
     return hipGetLastError();
 }
 
 hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, float* x_trial,
                             hipStream_t s) {
     k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_trial, dm.n);
-    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, 1);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, 1, 0, 0, 0.0);
     return hipGetLastError();
 }
 

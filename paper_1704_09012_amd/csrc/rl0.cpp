@@ -836,7 +836,7 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
     const rl0::Workspace& w = b->w;
     const float* mlp = static_cast<const float*>(p->mlp);
     auto issue = [&](hipStream_t q, const float* yq, float* xq) -> int {
-        HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, yq, nullptr, w, learned_sub_params(dc, p, 0), q));
+        HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, yq, nullptr, w, learned_sub_params(dc, p, 0), q, xq));
         const rl0::DebugOut dbg{nullptr, nullptr};
         for (int j = 0; j < N; ++j) {
             const rl0::IterParams ipl = learned_sub_params(dc, p, 2 * j);
@@ -862,7 +862,7 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
             HIP_TRY(rl0::launch_iteration(dm, A, w, tb, ipl, dbg, q, nullptr, w.learned));
             HIP_TRY(rl0::launch_iteration(dm, A, w, tb, learned_sub_params(dc, p, 2 * j + 1), dbg, q));
         }
-        HIP_TRY(rl0::launch_finish(dm, w, learned_sub_params(dc, p, 2 * N), xq, q));
+        HIP_TRY(rl0::launch_finish(dm, w, learned_sub_params(dc, p, 2 * N), xq, q, true));
         return RL0_OK;
     };
     if (graphs_enabled()) {
@@ -1023,11 +1023,11 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     const rl0::ScoreTables tb = tables_of(dc);
     const int N = dc->hc.n_iters;
     auto issue = [&](hipStream_t q, const float* yq, float* xq) -> int {
-        HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, yq, nullptr, b->w, iter_params(dc, p, 0), q));
+        HIP_TRY(rl0::launch_prepare(dm, A_cols, p->validate != 0, yq, nullptr, b->w, iter_params(dc, p, 0), q, xq));
         const rl0::DebugOut dbg{nullptr, nullptr};
         for (int it = 0; it < N; ++it)
             HIP_TRY(rl0::launch_iteration(dm, A_cols, b->w, tb, iter_params(dc, p, it), dbg, q, profile_events(it)));
-        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), xq, q));
+        HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), xq, q, true));
         return RL0_OK;
     };
     // per-iteration timing events cannot be recorded into a captured graph: a profiled
