@@ -86,6 +86,7 @@ struct Workspace {
     long long* D;         // [m] change of the residual during an iteration (zero between iterations)
     float* r[2];          // float32 residual [m]
     uint32_t* bm[2];      // bit i: |r[b]_i| >= tau of the next sweep [ceil(m/32)]
+    uint32_t* bs[2];      // bit g: some row of 8g .. 8g + 7 has its bit set in bm[b] [ceil(m/256)]
     int* cand_j[2];       // candidate list per iteration parity, one segment per sweep
     float* cand_x[2];     //   workgroup of seg_cap entries: column j, x'_j and
     float* cand_h[2];     //   x_hat_j (0 if j was not in the support)

@@ -34,7 +34,8 @@ constexpr int kSweepBlock = 1024;
 constexpr int kSweepCols = 4;                     // columns per sweep thread per chunk
 constexpr int kSweepChunk = kSweepBlock * kSweepCols;
 constexpr int kQueueRowInts = 7168;                 // 28 KiB of row indices of queued columns
-constexpr int kBmLdsWords = 12288;                  // 48 KiB: bitmasks of m <= 393216 rows
+constexpr int kBmLdsWords = 12288;                  // 48 KiB: bitmasks of m <= 393216 rows, or
+                                                    // their 8-row summaries for m <= 3145728
 constexpr int kBmPer = 4;                           // bitmask words per sweep thread held in registers
 constexpr int kRowBlock = 1024;
 
@@ -203,6 +204,14 @@ __global__ void k_prep_scatter(const int32_t* __restrict__ A, int n, int d, cons
         atomicAdd(reinterpret_cast<unsigned long long*>(S0 + col[p]), static_cast<unsigned long long>(-fx));
 }
 
+// Bit g of the result: some bit of 8g .. 8g + 7 is set in b.
+__device__ __forceinline__ uint8_t summary8(unsigned long long b) {
+    uint32_t s = 0u;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) s |= ((b >> (8 * g)) & 0xFFull) ? (1u << g) : 0u;
+    return static_cast<uint8_t>(s);
+}
+
 // Bits of rows [base, base + 64) (base a multiple of 64) from a wave ballot.
 __device__ __forceinline__ void store_bits(uint32_t* bm, int words, int base, unsigned long long b) {
     const int w0 = base >> 5;
@@ -210,10 +219,11 @@ __device__ __forceinline__ void store_bits(uint32_t* bm, int words, int base, un
     if (w0 + 1 < words) bm[w0 + 1] = static_cast<uint32_t>(b >> 32);
 }
 
-// r0 = fl32(2^-40 S0), partial L(r0) into L_part[slot], outer-test bitmask of r0
+// r0 = fl32(2^-40 S0), partial L(r0) into L_part[slot], outer-test bitmask of r0 (and,
+// with bs0, its 8-row summary)
 __global__ __launch_bounds__(kRowBlock) void k_prep_rows2(const long long* __restrict__ S0, float* __restrict__ r0,
-                                                          uint32_t* __restrict__ bm0, int m, uint32_t tau,
-                                                          DevState* st, int slot) {
+                                                          uint32_t* __restrict__ bm0, uint8_t* __restrict__ bs0,
+                                                          int m, uint32_t tau, DevState* st, int slot) {
     __shared__ long long sh[kRowBlock / 64];
     const int words = (m + 31) >> 5;
     long long l = 0;
@@ -227,7 +237,11 @@ __global__ __launch_bounds__(kRowBlock) void k_prep_rows2(const long long* __res
             bit = abs_bits(v) >= tau;
         }
         const unsigned long long b = __ballot(bit);
-        if ((threadIdx.x & 63) == 0) store_bits(bm0, words, base + (threadIdx.x & ~63), b);
+        if ((threadIdx.x & 63) == 0) {
+            const int wb = base + (threadIdx.x & ~63);
+            store_bits(bm0, words, wb, b);
+            if (bs0 && wb < m) bs0[wb >> 6] = summary8(b);
+        }
     }
     const long long tot = block_sum_rows(l, sh);
     if (threadIdx.x == 0) st->L_part[slot][blockIdx.x] = tot;
@@ -322,6 +336,8 @@ struct SweepArgs {
     int n, m;
     int chunks;      // ceil(n / kSweepChunk)
     int bm_lds;      // the outer-test bitmask fits in LDS
+    int bs_lds;      // otherwise its 8-row summary does: a row's bit is read from global
+                     // memory only where its group's summary bit is set
     Workspace w;
     ScoreTables tb;
     IterParams ip;
@@ -557,6 +573,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         } else {
             for (int wi = tid; wi < words; wi += kSweepBlock) bml[wi] = bmg[wi];
         }
+    } else if (a.bs_lds) {
+        const uint32_t* __restrict__ bsg = a.w.bs[c];
+        for (int wi = tid; wi < ((a.m + 255) >> 8); wi += kSweepBlock) bml[wi] = bsg[wi];
     }
 
     for (int chunk = blockIdx.x; chunk < a.chunks; chunk += gridDim.x) {
@@ -631,7 +650,13 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 #pragma unroll
             for (int p = 0; p < D; ++p) {
                 const int row = rows[q][p];
-                const uint32_t word = a.bm_lds ? bml[row >> 5] : bmg[row >> 5];
+                uint32_t word;
+                if (a.bm_lds)
+                    word = bml[row >> 5];
+                else if (a.bs_lds)
+                    word = ((bml[row >> 8] >> ((row >> 3) & 31)) & 1u) ? bmg[row >> 5] : 0u;
+                else
+                    word = bmg[row >> 5];
                 cm |= ((word >> (row & 31)) & 1u) << p;
             }
             if (cm) {
@@ -735,7 +760,9 @@ struct FinishArgs {
     Workspace w;
     int it;
     uint32_t tau_next;
+    int summary;    // also write the 8-row summaries of both bitmasks
 };
+
 
 constexpr int kWinKeys = 12288;   // candidates a window of the row kernel maps in LDS
 constexpr int kWinPer = kWinKeys / kRowBlock;   // their loads in flight per thread
@@ -1020,6 +1047,11 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
                 const int wb = base + (tid & ~63);
                 store_bits(a.w.bm[tr], words, wb, bmt);
                 store_bits(a.w.bm[c], words, wb, bmc);
+                if (a.summary && wb < a.m) {
+                    // 8 summary bits for the wave's 64 rows, one byte
+                    reinterpret_cast<uint8_t*>(a.w.bs[tr])[wb >> 6] = summary8(bmt);
+                    reinterpret_cast<uint8_t*>(a.w.bs[c])[wb >> 6] = summary8(bmc);
+                }
             }
         }
         if (!all_kept) __syncthreads();   // corr is reused by the next window
@@ -1185,7 +1217,8 @@ size_t workspace_bytes(int n, int m) {
     const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
     (void)wn;
-    return 4 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 6 * al(4 * cand) + al(4ull * n) +
+    return 4 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 2 * al(4 * ((m + 255) / 256) + 16) +
+           6 * al(4 * cand) + al(4ull * n) +
            al(8ull * n) + 2 * al(4ull * m) + al(4ull * m) + al(4ull * n) + al(16ull * n) + al(sizeof(DevState));
 }
 
@@ -1199,6 +1232,7 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     w->D = reinterpret_cast<long long*>(take(8ull * m));
     for (int b = 0; b < 2; ++b) w->r[b] = reinterpret_cast<float*>(take(4ull * m));
     for (int b = 0; b < 2; ++b) w->bm[b] = reinterpret_cast<uint32_t*>(take(4 * wm + 16));
+    for (int b = 0; b < 2; ++b) w->bs[b] = reinterpret_cast<uint32_t*>(take(4 * ((static_cast<size_t>(m) + 255) / 256) + 16));
     (void)wn;
     for (int b = 0; b < 2; ++b) {
         w->cand_j[b] = reinterpret_cast<int*>(take(4 * cand));
@@ -1266,7 +1300,10 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
         if (x_zero) k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_zero, dm.n);
     }
     if (x_hat0) k_prep_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.d, x_hat0, w.S[0], w.st);
-    k_prep_rows2<<<kRowGrid, kRowBlock, 0, s>>>(w.S[0], w.r[0], w.bm[0], dm.m, ip0.tau_bits, w.st, slot);
+    const bool summary = ((dm.m + 31) / 32) > kBmLdsWords && ((dm.m + 255) / 256) <= kBmLdsWords;
+    k_prep_rows2<<<kRowGrid, kRowBlock, 0, s>>>(w.S[0], w.r[0], w.bm[0],
+                                                summary ? reinterpret_cast<uint8_t*>(w.bs[0]) : nullptr, dm.m,
+                                                ip0.tau_bits, w.st, slot);
     k_prep_slot<<<1, 256, 0, s>>>(w.st, slot);
     return hipGetLastError();
 }
@@ -1280,6 +1317,7 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     a.m = dm.m;
     a.chunks = blocks(dm.n, kSweepChunk);
     a.bm_lds = ((dm.m + 31) / 32) <= kBmLdsWords ? 1 : 0;
+    a.bs_lds = (!a.bm_lds && ((dm.m + 255) / 256) <= kBmLdsWords) ? 1 : 0;
     a.w = w;
     a.tb = tb;
     a.ip = ip;
@@ -1288,7 +1326,7 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     a.Apk = pack_usable(dm.d, dm.m) ? w.Apk : nullptr;
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
-    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next};
+    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds};
     return launch_timed(k_finish_rows, finish_grid(dm.m), kRowBlock, s, ev ? ev + 4 : nullptr, fa);
 }
 
