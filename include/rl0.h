@@ -264,7 +264,8 @@ int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h);
 
 /* Totals since the last rl0_profile_enable.  ms_total_h (4 doubles): [0] the column
  * sweep, [1] the row kernel (H_k, the trial residual, ||r||_1, the next outer-test
- * bitmasks), over every launched iteration; [2..3] the same over the iterations that ran
+ * bitmasks; for m > 393216 plus the kernel that classifies H_k's candidates before it),
+ * over every launched iteration; [2..3] the same over the iterations that ran
  * before the stopping condition.  counts_h (2 int64, may be NULL): the two iteration
  * counts. */
 int rl0_profile_read_kernels(double* ms_total_h, int64_t* counts_h);

@@ -14,6 +14,7 @@ constexpr int kHistCopies = 8;        // one per XCD: workgroup b adds into copy
 constexpr int kTableStrideFloats = 4100;  // floats between the starts of the two score tables
 constexpr int kSweepGridMax = 256;   // workgroups of the sweep (each owns a candidate segment)
 constexpr int kRowGrid = 256;        // workgroups of the row kernels (each owns a partial sum)
+constexpr int kPreRows = 393216;     // above this m, H_k classifies the candidates in a kernel of its own
 
 enum ErrFlag : int {
     kErrRange = 1,      // a value left the fixed-point range
@@ -44,6 +45,7 @@ struct DevState {
     int updates_total;                    // column updates proposed, summed over iterations
     int err;                              // ErrFlag bits
     int peek_cur, peek_done;              // the coming decision, evaluated ahead (learned decode)
+    int bucket_n[2];                      // entries of H_k's boundary bucket listed by k_hk_classify
     int seg_count[2][kSweepGridMax];      // candidates written by each sweep workgroup
     int seg_front[2][kSweepGridMax];      //   of which at the segment's front (tested columns)
     int seg_nz[2][kSweepGridMax];         //   of which with x' != 0
@@ -96,6 +98,8 @@ struct Workspace {
     float* ystage;        // [m] y of a decode replayed on staging buffers
     float* xstage;        // [n] its x_hat before the copy out
     uint4* Apk;           // [n] A_cols packed into one 16-byte word per column
+    unsigned long long* bkey[2];   // H_k's boundary bucket (key, x'_j) per iteration parity,
+    float* bx[2];                  //   one entry per candidate at most (large m only, else null)
     int seg_cap;          // entries per segment
     int sweep_grid;       // sweep workgroups (= segments)
     DevState* st;
@@ -123,8 +127,10 @@ hipError_t launch_copy_f32(const float* src, float* dst, long long count, hipStr
 hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate, const float* y,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0,
                           hipStream_t s, float* x_zero = nullptr);
-// One loop iteration (the sweep, then H_k with the rows).  ev (optional, 6 events) gets
-// the start and end of the sweep dispatch in ev[0..1] and of the row dispatch in ev[4..5].  With
+// One loop iteration (the sweep, then H_k with the rows; for m > kPreRows H_k's
+// classification kernel between them).  ev (optional, 6 events) gets the start and end of
+// the sweep dispatch in ev[0..1], of the classification in ev[2..3] and of the row dispatch
+// in ev[4..5].  With
 // `learned` (per column: the update, NaN for none) the sweep takes those decisions in
 // place of the analytic column test.
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,

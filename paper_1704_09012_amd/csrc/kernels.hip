@@ -761,28 +761,51 @@ struct FinishArgs {
     int it;
     uint32_t tau_next;
     int summary;    // also write the 8-row summaries of both bitmasks
+    int pre;        // k_hk_classify ran before: drops below the boundary bucket are in D and
+                    // the bucket's entries are listed in w.bkey / w.bx
 };
 
 
 constexpr int kWinKeys = 12288;   // candidates a window of the row kernel maps in LDS
 constexpr int kWinPer = kWinKeys / kRowBlock;   // their loads in flight per thread
+constexpr int kShortSegs = 256;  // mean candidates per segment up to which a thread maps a segment
 constexpr int kBucketCap = 4096;  // entries of H_k's boundary bucket kept in LDS
 constexpr int kCorrRows = 8192;   // rows a correction window of the row kernel covers
 
 // Calls fn(j, x'_j, ok) for every candidate of the iteration, in windows of kWinKeys: an
-// entry -> segment map is written in LDS by a thread per segment, then every thread issues
-// its kWinPer loads before it uses any.  Every lane of the workgroup calls fn the same
-// number of times (ok = false past the count), so fn may use wave-wide operations.
+// entry -> segment map is written in LDS (by a thread per segment when segments are short,
+// else thread t maps kWinPer consecutive entries from one binary search over the segments'
+// starts), then every thread issues its kWinPer loads before it uses any.  Every lane of the workgroup calls fn the same number of times
+// (ok = false past the count), so fn may use wave-wide operations.
 template <class F>
 __device__ __forceinline__ void for_candidates(int count, int nseg, int cap, const int* seg_start, const int* seg_cnt,
                                                const int* seg_frt, unsigned short* segmap, const int* __restrict__ cj,
                                                const float* __restrict__ cx, F&& fn) {
     const int tid = threadIdx.x;
+    // short segments: a thread per segment writes its own entries; long ones would make
+    // that serial, so then each thread maps a run of entries instead
+    const bool per_segment = count <= kShortSegs * nseg;
     for (int w0 = 0; w0 < count; w0 += kWinKeys) {
-        if (tid < nseg) {
-            const int st0 = seg_start[tid], c = seg_cnt[tid];
-            const int lo = max(0, w0 - st0), hi = min(c, w0 + kWinKeys - st0);
-            for (int o = lo; o < hi; ++o) segmap[st0 + o - w0] = static_cast<unsigned short>(tid);
+        const int e_lo = w0 + tid * kWinPer;
+        if (per_segment) {
+            if (tid < nseg) {
+                const int st0 = seg_start[tid], c = seg_cnt[tid];
+                const int lo = max(0, w0 - st0), hi = min(c, w0 + kWinKeys - st0);
+                for (int o = lo; o < hi; ++o) segmap[st0 + o - w0] = static_cast<unsigned short>(tid);
+            }
+        } else if (e_lo < count) {
+            // the segment holding e_lo: the last one that starts at or before it (empty
+            // segments share their start with the next one, which wins)
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (seg_start[mid] <= e_lo) lo = mid; else hi = mid - 1;
+            }
+            int sg = lo;
+            for (int k = 0; k < kWinPer && e_lo + k < count; ++k) {
+                while (sg + 1 < nseg && seg_start[sg + 1] <= e_lo + k) ++sg;
+                segmap[e_lo + k - w0] = static_cast<unsigned short>(sg);
+            }
         }
         __syncthreads();
         size_t ixs[kWinPer];
@@ -805,6 +828,90 @@ __device__ __forceinline__ void for_candidates(int count, int nseg, int cap, con
 #pragma unroll
         for (int q = 0; q < kWinPer; ++q) fn(js[q], xs[q], w0 + q * kRowBlock + tid < count);
         __syncthreads();   // the map is rewritten by the next window
+    }
+}
+
+// For m > kPreRows, H_k's first step runs once here instead of in every workgroup of the
+// row kernel.  The boundary digit d1 of the first radix digit comes from the sweep's
+// histogram.  Workgroup b takes a contiguous slice of the candidates.  A column below
+// bucket d1 is dropped, and its change is taken back on all of its rows at once with 64-bit
+// atomics on D (exact, so the order does not matter).  When bucket d1 is not kept whole,
+// its entries are listed with their keys for the row kernel's later digits.
+__global__ __launch_bounds__(kRowBlock) void k_hk_classify(FinishArgs a) {
+    __shared__ unsigned hist[kHistBins];
+    __shared__ unsigned scan[kRowBlock / 64];
+    __shared__ int seg_start[kSweepGridMax];
+    __shared__ int seg_frt[kSweepGridMax];
+    __shared__ int wtot[kSweepGridMax / 64];
+    __shared__ int digit;
+    __shared__ unsigned above, bucket;
+    __shared__ int nz_sh;
+    const int me = a.it & 1;
+    DevState* st = a.w.st;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int nseg = a.w.sweep_grid;
+    const int cap = a.w.seg_cap;
+    const Slot s = st->slot[me];
+    int myc = 0, myz = 0;
+    if (tid < nseg) {
+        myc = st->seg_count[me][tid];
+        myz = st->seg_nz[me][tid];
+        seg_frt[tid] = st->seg_front[me][tid];
+    }
+    if (tid == 0) nz_sh = 0;
+    __syncthreads();
+    if (s.done) return;
+    if (tid < kSweepGridMax) {
+        int z = myz;
+        for (int off = 32; off > 0; off >>= 1) z += __shfl_down(z, off);
+        if (lane == 0 && z) atomicAdd(&nz_sh, z);
+    }
+    __syncthreads();
+    if (nz_sh <= a.k) return;   // every candidate is kept
+    unsigned h_hi = 0u, h_lo = 0u;
+#pragma unroll
+    for (int cp = 0; cp < kHistCopies; ++cp) {
+        h_hi += st->hk_hist[me][cp][tid];
+        h_lo += st->hk_hist[me][cp][tid + kRowBlock];
+    }
+    hist[tid] = h_hi;
+    hist[tid + kRowBlock] = h_lo;
+    const int count = segment_scan(myc, nseg, seg_start, wtot);   // its barriers publish hist
+    find_digit(hist, static_cast<unsigned>(a.k), scan, &digit, &above, &bucket);
+    const unsigned d1 = static_cast<unsigned>(digit);
+    const bool gather = static_cast<unsigned>(a.k) - above != bucket;
+    const int* __restrict__ cj = a.w.cand_j[me];
+    const float* __restrict__ cx = a.w.cand_x[me];
+    const int per = (count + gridDim.x - 1) / gridDim.x;
+    const int e0 = blockIdx.x * per, e1 = min(count, e0 + per);
+    for (int base = e0; base < e1; base += kRowBlock) {
+        const int e = base + tid;
+        float x = 0.0f;
+        int j = 0;
+        if (e < e1) {
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (seg_start[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const size_t ix = seg_phys(lo, cap, seg_frt[lo], e - seg_start[lo]);
+            x = cx[ix];
+            j = cj[ix];
+        }
+        const unsigned dg = x != 0.0f ? top_digit(x) : 0u;
+        if (x != 0.0f && dg < d1) {
+            const long long delta = to_fx(x, &st->err);
+            const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
+            for (int p = 0; p < a.d; ++p)
+                atomicAdd(reinterpret_cast<unsigned long long*>(&a.w.D[col[p]]), static_cast<unsigned long long>(delta));
+        }
+        const bool put = gather && x != 0.0f && dg == d1;
+        const int slot = wave_append(&st->bucket_n[me], put);
+        if (put) {
+            a.w.bkey[me][slot] = hk_key(j, x);
+            a.w.bx[me][slot] = x;
+        }
     }
 }
 
@@ -864,6 +971,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     // the next iteration's first-digit histograms are cleared here, a slice per workgroup
     for (int i = blockIdx.x * kRowBlock + tid; i < kHistCopies * kHistBins; i += gridDim.x * kRowBlock)
         (&st->hk_hist[me ^ 1][0][0])[i] = 0u;
+    if (blockIdx.x == 0 && tid == 0) st->bucket_n[me ^ 1] = 0;
     if (tid == 0) {
         nz_sh = 0;
         upd_sh = 0;
@@ -921,7 +1029,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     };
     if (!all_kept) {
-        count = segment_scan(myc, nseg, seg_start, wtot);
+        if (!a.pre) count = segment_scan(myc, nseg, seg_start, wtot);
         if (tid == 0) bn = 0;
         for (int i = tid; i < ce - cb; i += kRowBlock) corr[i] = 0;
         hist[tid] = h_hi;
@@ -934,20 +1042,32 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         unsigned rem = static_cast<unsigned>(a.k) - above;
         bool exact = (rem == bucket);
         const bool gather = !exact;
-        for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx, [&](int j, float x, bool ok) {
-            if (!ok || x == 0.0f) return;
-            const unsigned dg = top_digit(x);
-            if (dg < d1) {
-                take_back(j, x);
-            } else if (gather && dg == d1) {
-                const int slot = atomicAdd(&bn, 1);
-                if (slot < kBucketCap) {
-                    bkey[slot] = hk_key(j, x);
-                    bx[slot] = x;
+        if (a.pre) {
+            // the columns below the bucket are already taken back; the bucket is listed
+            nbk = gather ? st->bucket_n[me] : 0;
+            if (nbk <= kBucketCap) {
+                for (int e = tid; e < nbk; e += kRowBlock) {
+                    bkey[e] = a.w.bkey[me][e];
+                    bx[e] = a.w.bx[me][e];
                 }
             }
-        });
-        nbk = bn;
+            __syncthreads();
+        } else {
+            for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx, [&](int j, float x, bool ok) {
+                if (!ok || x == 0.0f) return;
+                const unsigned dg = top_digit(x);
+                if (dg < d1) {
+                    take_back(j, x);
+                } else if (gather && dg == d1) {
+                    const int slot = atomicAdd(&bn, 1);
+                    if (slot < kBucketCap) {
+                        bkey[slot] = hk_key(j, x);
+                        bx[slot] = x;
+                    }
+                }
+            });
+            nbk = bn;
+        }
         for (int pass = 1; pass < 6 && !exact; ++pass) {
             const int sft = pass < 5 ? 52 - 11 * pass : 0;
             const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
@@ -958,6 +1078,14 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
                 for (int e0 = 0; e0 < nbk; e0 += kRowBlock) {
                     const int e = e0 + tid;
                     const unsigned long long key = e < nbk ? bkey[e] : 0ull;
+                    hist_add(hist, static_cast<unsigned>((key >> sft) & dmask), e < nbk && (key & pmask) == prefix);
+                }
+                __syncthreads();
+            } else if (a.pre) {
+                // the bucket's list in global memory
+                for (int e0 = 0; e0 < nbk; e0 += kRowBlock) {
+                    const int e = e0 + tid;
+                    const unsigned long long key = e < nbk ? a.w.bkey[me][e] : 0ull;
                     hist_add(hist, static_cast<unsigned>((key >> sft) & dmask), e < nbk && (key & pmask) == prefix);
                 }
                 __syncthreads();
@@ -984,6 +1112,11 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
                     const unsigned long long key = bkey[e];
                     if (key < kth) take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), bx[e]);
                 }
+            } else if (a.pre) {
+                for (int e = tid; e < nbk; e += kRowBlock) {
+                    const unsigned long long key = a.w.bkey[me][e];
+                    if (key < kth) take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), a.w.bx[me][e]);
+                }
             } else {
                 for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx,
                                [&](int j, float x, bool ok) {
@@ -1004,11 +1137,18 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             for (int i = tid; i < ce - cb; i += kRowBlock) corr[i] = 0;
             __syncthreads();
             const bool bucket_in_lds = nbk <= kBucketCap;
-            for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx, [&](int j, float x, bool ok) {
-                if (!ok || x == 0.0f) return;
-                const unsigned dg = top_digit(x);
-                if (dg < d1 || (dg == d1 && !bucket_in_lds && hk_key(j, x) < kth)) take_back(j, x);
-            });
+            if (!a.pre) {
+                for_candidates(count, nseg, cap, seg_start, seg_cnt, seg_frt, segmap, cj, cx, [&](int j, float x, bool ok) {
+                    if (!ok || x == 0.0f) return;
+                    const unsigned dg = top_digit(x);
+                    if (dg < d1 || (dg == d1 && !bucket_in_lds && hk_key(j, x) < kth)) take_back(j, x);
+                });
+            } else if (!bucket_in_lds) {
+                for (int e = tid; e < nbk; e += kRowBlock) {
+                    const unsigned long long key = a.w.bkey[me][e];
+                    if (key < kth) take_back(static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key)), a.w.bx[me][e]);
+                }
+            }
             if (bucket_in_lds) {
                 for (int e = tid; e < nbk; e += kRowBlock) {
                     const unsigned long long key = bkey[e];
@@ -1217,9 +1357,10 @@ size_t workspace_bytes(int n, int m) {
     const size_t wm = (static_cast<size_t>(m) + 31) / 32, wn = (static_cast<size_t>(n) + 31) / 32;
     const size_t cand = static_cast<size_t>(sweep_grid(n)) * seg_capacity(n);
     (void)wn;
+    const size_t bucket = m > kPreRows ? 2 * (al(8 * cand) + al(4 * cand)) : 0;
     return 4 * al(8ull * m) + 2 * al(4ull * m) + 2 * al(4 * wm + 16) + 2 * al(4 * ((m + 255) / 256) + 16) +
            6 * al(4 * cand) + al(4ull * n) +
-           al(8ull * n) + 2 * al(4ull * m) + al(4ull * m) + al(4ull * n) + al(16ull * n) + al(sizeof(DevState));
+           al(8ull * n) + 2 * al(4ull * m) + al(4ull * m) + al(4ull * n) + al(16ull * n) + al(sizeof(DevState)) + bucket;
 }
 
 void carve_workspace(void* base, int n, int m, Workspace* w) {
@@ -1248,6 +1389,10 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
     w->xstage = reinterpret_cast<float*>(take(4ull * n));
     w->Apk = reinterpret_cast<uint4*>(take(16ull * n));
     w->st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
+    for (int b = 0; b < 2; ++b) {
+        w->bkey[b] = m > kPreRows ? reinterpret_cast<unsigned long long*>(take(8 * cand)) : nullptr;
+        w->bx[b] = m > kPreRows ? reinterpret_cast<float*>(take(4 * cand)) : nullptr;
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1326,7 +1471,12 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     a.Apk = pack_usable(dm.d, dm.m) ? w.Apk : nullptr;
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
-    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds};
+    const int pre = dm.m > kPreRows ? 1 : 0;
+    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, pre};
+    if (pre) {
+        e = launch_timed(k_hk_classify, kRowGrid, kRowBlock, s, ev ? ev + 2 : nullptr, fa);
+        if (e != hipSuccess) return e;
+    }
     return launch_timed(k_finish_rows, finish_grid(dm.m), kRowBlock, s, ev ? ev + 4 : nullptr, fa);
 }
 

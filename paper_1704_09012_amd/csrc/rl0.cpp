@@ -46,7 +46,8 @@ std::mutex g_mu;
 
 struct SweepProfile {
     bool enabled = false;
-    std::vector<hipEvent_t> pool;   // per iteration: start and end of the sweep, (unused), the row kernel
+    std::vector<hipEvent_t> pool;   // per iteration: start and end of the sweep, H_k's classification
+                                    // (large m only), the row kernel
     double total_ms[4] = {0.0, 0.0, 0.0, 0.0};   // sweep and row kernel: all launched, then executed
     long long launches = 0, executed = 0;
 };
@@ -64,15 +65,18 @@ hipEvent_t* profile_events(int it) {
 }
 
 // after a synchronised decode: add the kernels of the launched iterations (the first
-// `executed` of which ran before the stopping condition)
-void profile_collect(int launched, int executed) {
+// `executed` of which ran before the stopping condition); with `pre` the row kernel's time
+// includes H_k's classification kernel
+void profile_collect(int launched, int executed, bool pre) {
     if (!g_prof.enabled) return;
     for (int it = 0; it < launched && 6 * static_cast<size_t>(it) + 5 < g_prof.pool.size(); ++it) {
-        float ms[2] = {0.0f, 0.0f};
+        float ms[2] = {0.0f, 0.0f}, mc = 0.0f;
         const bool ok =
             hipEventElapsedTime(&ms[0], g_prof.pool[6 * it], g_prof.pool[6 * it + 1]) == hipSuccess &&
-            hipEventElapsedTime(&ms[1], g_prof.pool[6 * it + 4], g_prof.pool[6 * it + 5]) == hipSuccess;
+            hipEventElapsedTime(&ms[1], g_prof.pool[6 * it + 4], g_prof.pool[6 * it + 5]) == hipSuccess &&
+            (!pre || hipEventElapsedTime(&mc, g_prof.pool[6 * it + 2], g_prof.pool[6 * it + 3]) == hipSuccess);
         if (!ok) continue;
+        ms[1] += mc;
         for (int k = 0; k < 2; ++k) g_prof.total_ms[k] += ms[k];
         g_prof.launches += 1;
         if (it < executed) {
@@ -1050,7 +1054,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[N & 1];
-    profile_collect(N, fin.iterations);
+    profile_collect(N, fin.iterations, m > rl0::kPreRows);
     if (st_h) {
         st_h->iterations = fin.iterations;
         st_h->accepted = fin.accepted;

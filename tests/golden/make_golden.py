@@ -1,11 +1,17 @@
 """Write the oracle's full-size decodes used by the GPU parity tests.
 
-    python tests/golden/make_golden.py [--jobs 6]
+    python tests/golden/make_golden.py [--jobs 6] [--only NAME_PREFIX]
 
 Only the CPU oracle (oracle/) and the seeded instance generator are called.  Each file
-holds, for one seeded instance of the n = 2^20, m = n/10, k = m/10, d = 7 workload
-(Gaussian N(0,1) signal, Gaussian noise at the stated SNR), the oracle's recovered
-x_hat (support and values) and its loop statistics.
+holds, for one seeded instance (Gaussian N(0,1) signal, Gaussian noise at the stated
+SNR), the oracle's recovered x_hat (support and values) and its loop statistics.  The
+workloads:
+  * n = 2^20, m = n/10, k = m/10, d = 7 at 20, 40 and 60 dB, two seeds each;
+  * n = 2^20, m = n/2, k = m/8, d = 8 at 40 dB: the large workload's d and k/m at 1/16 of
+    its n, with m above 393216 rows (the decoder's large-m paths);
+  * n = 2^21, m = n/2, a signal of m/8 nonzeros decoded with k = m/16, d = 8 at 40 dB:
+    every iteration then has more candidates than k, so H_k selects on the large-m
+    path, with boundary buckets of about 2 100 and 5 000 entries.
 """
 from __future__ import annotations
 
@@ -35,18 +41,25 @@ def case_name(snr: int, i: int) -> str:
     return f"decode_n1048576_d7_snr{snr}_i{i}.npz"
 
 
-def one(args):
-    snr_idx, snr, i = args
-    seed = I.seed_for(2, snr_idx, i)
-    sig = float(np.float32(I.sigma_for_snr(snr, N, M, K, DD)))
-    inst = I.draw_instance(N, M, K, DD, sig, seed)
+# (file name, n, m, k of the signal, d, snr, seed, k of the decoder)
+CASES = [(case_name(snr, i), N, M, K, DD, snr, I.seed_for(2, si, i), K)
+         for si, snr in enumerate(SNRS) for i in range(SEEDS_PER_SNR)]
+CASES.append(("decode_n1048576_m524288_d8_snr40_i0.npz", N, N // 2, N // 16, 8, 40, I.seed_for(3, 1, 10), N // 16))
+CASES.append(("decode_n2097152_m1048576_d8_snr40_kdec65536_i0.npz", 2 * N, N, N // 8, 8, 40, I.seed_for(3, 1, 10),
+              N // 16))
+
+
+def one(case):
+    name, n, m, k, d, snr, seed, k_dec = case
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, seed)
     x = inst.x_dense()
-    y = D.measure(inst.A_cols, x, inst.eta, M)
-    C = D.make_constants(N, M, DD, K, sig)
+    y = D.measure(inst.A_cols, x, inst.eta, m)
+    C = D.make_constants(n, m, d, k_dec, sig)
     res = D.decode(inst.A_cols, y, C)
     supp = np.nonzero(res.x_hat)[0].astype(np.int32)
-    path = os.path.join(HERE, case_name(snr, i))
-    np.savez_compressed(path, n=N, m=M, k=K, d=DD, snr=snr, seed=seed, sigma=np.float32(sig),
+    path = os.path.join(HERE, name)
+    np.savez_compressed(path, n=n, m=m, k=k, k_decode=k_dec, d=d, snr=snr, seed=seed, sigma=np.float32(sig),
                         support=supp, values=res.x_hat[supp].astype(np.float32),
                         iterations=res.iterations, accepted=res.accepted, L_hat=np.int64(res.L_hat),
                         converged=int(res.converged), updates_total=res.updates_total)
@@ -57,8 +70,9 @@ def one(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)
+    ap.add_argument("--only", default="", help="write only the files whose name starts with this")
     a = ap.parse_args()
-    work = [(si, snr, i) for si, snr in enumerate(SNRS) for i in range(SEEDS_PER_SNR)]
+    work = [c for c in CASES if c[0].startswith(a.only)]
     with ProcessPoolExecutor(a.jobs) as ex:
         for path, it, acc, err in ex.map(one, work):
             print(os.path.basename(path), "iterations", it, "accepted", acc, "rel_l2_vs_truth", f"{err:.3e}", flush=True)

@@ -291,22 +291,25 @@ def test_decode_into_new_buffers_replays_through_staging():
 def _golden_cases():
     if not os.path.isdir(GOLDEN):
         return []
-    return sorted(f for f in os.listdir(GOLDEN) if f.startswith("decode_n1048576") and f.endswith(".npz"))
+    return sorted(f for f in os.listdir(GOLDEN) if f.startswith("decode_n") and f.endswith(".npz"))
 
 
 @pytest.mark.parametrize("fname", _golden_cases())
 def test_decode_full_size_against_stored_oracle(fname):
-    """n = 2^20, m = n/10, k = m/10, d = 7 at 20/40/60 dB: identical support and
-    rel-l2 <= 1e-5 against the oracle's decode (stored by tests/golden/make_golden.py);
-    the contract makes it bitwise."""
+    """n = 2^20, m = n/10, k = m/10, d = 7 at 20/40/60 dB, and the large-m cases (m above
+    393216, d = 8; one decoded with k below the signal's sparsity so that H_k selects):
+    identical support and rel-l2 <= 1e-5 against the oracle's decode (stored by
+    tests/golden/make_golden.py); the contract makes it bitwise."""
     g = np.load(os.path.join(GOLDEN, fname))
     n, m, k, d = int(g["n"]), int(g["m"]), int(g["k"]), int(g["d"])
+    k_dec = int(g["k_decode"]) if "k_decode" in g else k
     sig = float(g["sigma"])
     print(f"golden {fname}", flush=True)
     inst = I.draw_instance(n, m, k, d, sig, int(g["seed"]))
     x = inst.x_dense()
     y = D.measure(inst.A_cols, x, inst.eta, m)
-    xg, stg = gpu_decode(inst, y, sig)
+    x_hat, stg = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k_dec)
+    xg = host(x_hat)
     supp = np.nonzero(xg)[0]
     assert np.array_equal(supp, g["support"])
     ref = np.zeros(n, np.float32)
@@ -316,5 +319,5 @@ def test_decode_full_size_against_stored_oracle(fname):
     assert np.array_equal(xg, ref)
     assert stg["iterations"] == int(g["iterations"]) and stg["accepted"] == int(g["accepted"])
     assert stg["l1_final_fx"] == int(g["L_hat"])
-    if int(g["snr"]) >= 40:
+    if int(g["snr"]) >= 40 and k_dec == k:
         assert np.linalg.norm(xg - x) / np.linalg.norm(x) < 1e-2
