@@ -584,18 +584,25 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         reinterpret_cast<float4*>(supv)[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (tid == 0) qn = 0;
         __syncthreads();
-        // x_hat on this chunk's columns, from the previous segment (front, then back)
-        for (int e = tid; e < pc; e += kSweepBlock) {
-            const bool front = e < pf;
-            const int o = front ? e : e - pf;
-            int j;
-            float xp, xh;
-            if (o == tid) {
-                j = front ? pj : qj;
-                xp = front ? pxp : qxp;
-                xh = front ? pxh : qxh;
-            } else {
-                const size_t ix = seg_base + (front ? o : a.w.seg_cap - 1 - o);
+        // x_hat on this chunk's columns, from the previous segment: its front part and its
+        // back part, each walked from entry tid, whose values this thread loaded in round 1
+        for (int o = tid; o < pf; o += kSweepBlock) {
+            int j = pj;
+            float xp = pxp, xh = pxh;
+            if (o != tid) {
+                const size_t ix = seg_base + o;
+                j = a.w.cand_j[pv][ix];
+                xp = a.w.cand_x[pv][ix];
+                xh = a.w.cand_h[pv][ix];
+            }
+            const float v = current_value(acc, j, xp, xh, kthp);
+            if (v != 0.0f && j >= cbase && j < cbase + kSweepChunk) supv[j - cbase] = v;
+        }
+        for (int o = tid; o < pc - pf; o += kSweepBlock) {
+            int j = qj;
+            float xp = qxp, xh = qxh;
+            if (o != tid) {
+                const size_t ix = seg_base + (a.w.seg_cap - 1 - o);
                 j = a.w.cand_j[pv][ix];
                 xp = a.w.cand_x[pv][ix];
                 xh = a.w.cand_h[pv][ix];
