@@ -40,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # per dispatch at this workload) and the factors a 256 MiB plain copy gives each counter;
 # valid only for the kernel source they were taken on.
 SWEEP_COUNTERS = {
-    "kernels_sha256": "6f0b15f58b7c2ee3da3f7bdb6f92f11966606f514e82b1f54e7fb9d07910bea0",
-    "fetch_kib": 13273.3, "write_kib": 214.0, "fetch_factor": 2.000, "write_factor": 1.000,
+    "kernels_sha256": "7eb92697dd5aa4990ffdab80b94bbb412999b8c149f72c327d542e8676ce1756",
+    "fetch_kib": 13293.5, "write_kib": 213.6, "fetch_factor": 2.000, "write_factor": 1.000,
 }
 
 
