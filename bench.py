@@ -306,7 +306,8 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": sweep_traffic() if (N, M, DD) == (2 ** 20, 104857, 7) else None,
-                     "kernel": f"k_sweep<{DD}>", "avg_launch_us": sweep_avg_s * 1e6,
+                     "kernel": f"k_sweep<{DD}, {'true' if (M + 31) // 32 > 12288 else 'false'}>",
+                     "avg_launch_us": sweep_avg_s * 1e6,
                      "launches": sweep_launches, "bytes_per_launch": sweep_bytes(N, M, DD)},
         "kernels_us_per_iteration": {k: 1e3 * v / max(sweep_launches, 1) for k, v in kern["executed"].items()},
         "kernels_us_per_launch_all": {k: 1e3 * v / max(kern["all_launches"], 1) for k, v in kern["all"].items()},

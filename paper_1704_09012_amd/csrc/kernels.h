@@ -51,6 +51,9 @@ struct DevState {
     int seg_nz[2][kSweepGridMax];         //   of which with x' != 0
     int seg_updates[2][kSweepGridMax];    // updates proposed by each sweep workgroup
     long long L_part[2][kRowGrid];        // partial ||r||_1 of the trial residual
+    unsigned flag_part[2][2][kRowGrid];   // rows passing the next outer test, per iteration parity,
+                                          // bitmask buffer and row workgroup (selects the sweep's
+                                          // dense mode)
     unsigned hk_hist[2][kHistCopies][kHistBins];   // nonzero candidates by the top 11 bits of
                                                    // |x'_j|, one copy per XCD (added up by H_k)
 };

@@ -225,8 +225,10 @@ __global__ __launch_bounds__(kRowBlock) void k_prep_rows2(const long long* __res
                                                           uint32_t* __restrict__ bm0, uint8_t* __restrict__ bs0,
                                                           int m, uint32_t tau, DevState* st, int slot) {
     __shared__ long long sh[kRowBlock / 64];
+    __shared__ unsigned flw[kRowBlock / 64];
     const int words = (m + 31) >> 5;
     long long l = 0;
+    unsigned fl = 0u;
     for (int base = blockIdx.x * kRowBlock; base < m; base += gridDim.x * kRowBlock) {
         const int i = base + threadIdx.x;
         bool bit = false;
@@ -237,14 +239,21 @@ __global__ __launch_bounds__(kRowBlock) void k_prep_rows2(const long long* __res
             bit = abs_bits(v) >= tau;
         }
         const unsigned long long b = __ballot(bit);
+        fl += static_cast<unsigned>(__popcll(b));
         if ((threadIdx.x & 63) == 0) {
             const int wb = base + (threadIdx.x & ~63);
             store_bits(bm0, words, wb, b);
             if (bs0 && wb < m) bs0[wb >> 6] = summary8(b);
         }
     }
-    const long long tot = block_sum_rows(l, sh);
-    if (threadIdx.x == 0) st->L_part[slot][blockIdx.x] = tot;
+    if ((threadIdx.x & 63) == 0) flw[threadIdx.x >> 6] = fl;
+    const long long tot = block_sum_rows(l, sh);   // its barrier also publishes flw
+    if (threadIdx.x == 0) {
+        st->L_part[slot][blockIdx.x] = tot;
+        unsigned f = 0u;
+        for (int w = 0; w < kRowBlock / 64; ++w) f += flw[w];
+        st->flag_part[slot][0][blockIdx.x] = f;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_prep_slot(DevState* st, int slot) {
@@ -458,8 +467,10 @@ __device__ __forceinline__ void add_change(long long* Dl, const int (&rows)[D], 
 // iteration are issued in one round before it: this workgroup's column indices, the
 // score tables, the partial sums of ||r||_1, the previous segment, and both candidates
 // for the outer-test bitmask and for the S copy (the decision picks one).  A second
-// round gathers the exact residuals of the columns with a candidate row.
-template <int D>
+// round gathers the exact residuals of the columns with a candidate row.  DENSE (used
+// where the bitmask does not fit in LDS) adds the dense mode: when the row kernel counted
+// enough flagged rows, every thread tests its own columns without the bitmask and queue.
+template <int D, bool DENSE>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     constexpr int kQueueRows = kQueueRowInts / D;
     __shared__ uint32_t bml[kBmLdsWords];
@@ -472,6 +483,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     __shared__ unsigned lhist[kHistBins];   // this workgroup's nonzero candidates by top digit
     __shared__ Slot s_sh;
     __shared__ long long red[kSweepBlock / 64];
+    __shared__ unsigned redf[kSweepBlock / 64][2];
+    __shared__ bool dense_sh;
     const int it = a.ip.it, me = it & 1, pv = me ^ 1;
     const int tid = threadIdx.x;
     const int seg = blockIdx.x;
@@ -494,6 +507,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     const int pf = st->seg_front[pv][seg];
     const unsigned long long kthp = st->kth_key[pv];
     long long lp = tid < kRowGrid ? st->L_part[pv][tid] : 0;
+    // flagged-row counts exist only where the bitmask does not fit in LDS
+    unsigned fp0 = (DENSE && tid < kRowGrid) ? st->flag_part[pv][0][tid] : 0u;
+    unsigned fp1 = (DENSE && tid < kRowGrid) ? st->flag_part[pv][1][tid] : 0u;
     // the previous segment's first front and first back entry of this thread
     int pj = 0, qj = 0;
     float pxp = 0.0f, pxh = 0.0f, qxp = 0.0f, qxh = 0.0f;
@@ -512,12 +528,31 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         bw1 = reinterpret_cast<const uint4*>(a.w.bm[1])[tid];
     }
     for (int off = 32; off > 0; off >>= 1) lp += __shfl_down(lp, off);
+    if (DENSE) {
+        for (int off = 32; off > 0; off >>= 1) {
+            fp0 += __shfl_down(fp0, off);
+            fp1 += __shfl_down(fp1, off);
+        }
+        if ((tid & 63) == 0) {
+            redf[tid >> 6][0] = fp0;
+            redf[tid >> 6][1] = fp1;
+        }
+    }
     if ((tid & 63) == 0) red[tid >> 6] = lp;
     __syncthreads();
     if (tid == 0) {
         long long Lt = 0;
+        unsigned f0 = 0u, f1 = 0u;
         for (int w = 0; w < kSweepBlock / 64; ++w) Lt += red[w];
+        if (DENSE) {
+            for (int w = 0; w < kSweepBlock / 64; ++w) {
+                f0 += redf[w][0];
+                f1 += redf[w][1];
+            }
+        }
         Slot d = decide_from(prev, err, it, a.ip.n_iters, a.ip.tol_fx, Lt);
+        // rows flagged in the bitmask the decision selects
+        if (DENSE) dense_sh = 4ull * (d.cur ? f1 : f0) >= static_cast<unsigned long long>(a.m);
         // an analytic retry has nothing to do when the iteration before it was accepted:
         // it only carries x_hat forward and leaves no decision pending
         if (a.ip.retry && d.pending && d.accepted_last)
@@ -550,6 +585,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     }
     const int c = s.cur;
     const int acc = s.accepted_last;
+    // when a quarter of the rows or more pass the outer test, nearly every column has such
+    // a row: then every thread tests its own columns directly, without the bitmask filter
+    // and the queue (the consensus test recomputes the outer test from the residuals)
+    const bool dense = DENSE && !a.learned && !skip && dense_sh;
     const float* __restrict__ r = a.w.r[c];
     const uint32_t* __restrict__ bmg = a.w.bm[c];
     int* __restrict__ out_j = a.w.cand_j[me] + seg_base;
@@ -643,6 +682,70 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     out_x[o] = svq[q];
                     out_h[o] = svq[q];
                     atomicAdd(&lhist[top_digit(svq[q])], 1u);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        if (dense) {
+            if (chunk == static_cast<int>(blockIdx.x) && !a.tb.exact) {
+                reinterpret_cast<float4*>(Tz)[tid] = tz4;
+                reinterpret_cast<float4*>(Te)[tid] = te4;
+                if (tid == 0) {
+                    Tz[kTableN] = tzl;
+                    Te[kTableN] = tel;
+                }
+            }
+            __syncthreads();
+            // one column at a time, its rows picked by selects (one copy of the test's code)
+#pragma unroll 1
+            for (int q = 0; q < kSweepCols; ++q) {
+                const int j = cbase + q * kSweepBlock + tid;
+                if (j >= a.n) continue;
+                int rq[D];
+                float xhq = svq[0];
+#pragma unroll
+                for (int p = 0; p < D; ++p) rq[p] = rows[0][p];
+#pragma unroll
+                for (int qq = 1; qq < kSweepCols; ++qq) {
+                    if (q == qq) {
+#pragma unroll
+                        for (int p = 0; p < D; ++p) rq[p] = rows[qq][p];
+                        xhq = svq[qq];
+                    }
+                }
+                float v[D];
+#pragma unroll
+                for (int p = 0; p < D; ++p) v[p] = r[rq[p]];
+                unsigned int cm = 0u;
+#pragma unroll
+                for (int p = 0; p < D; ++p)
+                    if (abs_bits(v[p]) >= a.ip.tau_bits) cm |= 1u << p;
+                float om = 0.0f;
+                bool upd = false;
+                if (cm) {
+                    upd = column_update<D>(v, cm, lt, a.ip.alpha, a.ip.l1_test, &om);
+                    if (a.dbg.updated) a.dbg.updated[j] = upd ? 1 : 0;
+                    if (a.dbg.omega) a.dbg.omega[j] = upd ? om : 0.0f;
+                }
+                if (upd) {
+                    atomicAdd(&seg_upd, 1);
+                    const float xp = xhq + om;
+                    const int o = atomicAdd(&seg_f, 1);
+                    out_j[o] = j;
+                    out_x[o] = xp;
+                    out_h[o] = xhq;
+                    if (xp != 0.0f) {
+                        atomicAdd(&seg_z, 1);
+                        atomicAdd(&lhist[top_digit(xp)], 1u);
+                    }
+                    add_change<D>(a.w.D, rq, xhq, xp, &st->err);
+                } else if (xhq != 0.0f) {
+                    const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                    out_j[o] = j;
+                    out_x[o] = xhq;
+                    out_h[o] = xhq;
+                    atomicAdd(&lhist[top_digit(xhq)], 1u);
                 }
             }
             __syncthreads();
@@ -768,6 +871,8 @@ struct FinishArgs {
     int it;
     uint32_t tau_next;
     int summary;    // also write the 8-row summaries of both bitmasks
+    int count_flags;   // also count the flagged rows of both bitmasks (the bitmask does not
+                       // fit in the sweep's LDS; the counts select its dense mode)
     int pre;        // k_hk_classify ran before: drops below the boundary bucket are in D and
                     // the bucket's entries are listed in w.bkey / w.bx
 };
@@ -942,6 +1047,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     __shared__ int seg_start[kSweepGridMax];
     __shared__ int wtot[kSweepGridMax / 64];
     __shared__ long long sh[kRowBlock / 64];
+    __shared__ unsigned flw[kRowBlock / 64][2];
     __shared__ int digit;
     __shared__ unsigned above, bucket;
     __shared__ int nz_sh, upd_sh, bn;
@@ -1137,6 +1243,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
 
     // ---- the rows, a correction window of kCorrRows rows at a time
     long long l = 0;
+    unsigned ft = 0u, fc = 0u;   // rows flagged in the two bitmasks (wave-uniform)
     for (; cb < row1; cb += kCorrRows) {
         ce = min(row1, cb + kCorrRows);
         if (!all_kept && cb != row0) {
@@ -1190,6 +1297,10 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             }
             const unsigned long long bmt = __ballot(bt);
             const unsigned long long bmc = __ballot(bc);
+            if (a.count_flags) {
+                ft += static_cast<unsigned>(__popcll(bmt));
+                fc += static_cast<unsigned>(__popcll(bmc));
+            }
             if (lane == 0) {
                 const int wb = base + (tid & ~63);
                 store_bits(a.w.bm[tr], words, wb, bmt);
@@ -1203,8 +1314,23 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
         if (!all_kept) __syncthreads();   // corr is reused by the next window
     }
-    const long long tot = block_sum_rows(l, sh);
-    if (tid == 0) st->L_part[me][blockIdx.x] = tot;
+    if (a.count_flags && lane == 0) {
+        flw[tid >> 6][0] = ft;
+        flw[tid >> 6][1] = fc;
+    }
+    const long long tot = block_sum_rows(l, sh);   // its barrier also publishes flw
+    if (tid == 0) {
+        st->L_part[me][blockIdx.x] = tot;
+        if (a.count_flags) {
+            unsigned st_t = 0u, st_c = 0u;
+            for (int w = 0; w < kRowBlock / 64; ++w) {
+                st_t += flw[w][0];
+                st_c += flw[w][1];
+            }
+            st->flag_part[me][tr][blockIdx.x] = st_t;
+            st->flag_part[me][c][blockIdx.x] = st_c;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ final decision
@@ -1291,7 +1417,9 @@ hipError_t launch_timed(K kernel, int grid, int block, hipStream_t s, const hipE
 
 template <int D>
 hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s, const hipEvent_t* ev) {
-    return launch_timed(k_sweep<D>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+    // the flagged-row counts exist where the bitmask does not fit in LDS
+    if (a.bm_lds) return launch_timed(k_sweep<D, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+    return launch_timed(k_sweep<D, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
 }
 
 template <int D>
@@ -1479,7 +1607,7 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
     const int pre = dm.m > kPreRows ? 1 : 0;
-    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, pre};
+    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, !a.bm_lds, pre};
     if (pre) {
         e = launch_timed(k_hk_classify, kRowGrid, kRowBlock, s, ev ? ev + 2 : nullptr, fa);
         if (e != hipSuccess) return e;
