@@ -399,21 +399,39 @@ __device__ __forceinline__ void unpack_rows(const uint4 w, int (&rows)[D]) {
 
 // Row indices of the kSweepCols columns of thread tid in a chunk: column
 // cbase + q kSweepBlock + tid for slot q (consecutive lanes, consecutive columns).
-template <int D>
-__device__ __forceinline__ void load_rows(const int32_t* __restrict__ A, const uint4* __restrict__ Apk, int n,
-                                          int cbase, int tid, int (&rows)[kSweepCols][D]) {
+// issue_rows starts the loads (the packed words into w, or A_cols' rows into rows) and
+// unpack_chunk turns packed words into rows; between the two the loads are in flight
+// while other work goes on.  A column past n loads column n - 1 (n >= 1), so no per-lane
+// branch separates the loads (a branch makes the compiler wait for each load before the
+// next); every use of the rows checks the column against n.
+template <int D, bool PACKED>
+__device__ __forceinline__ void issue_rows(const int32_t* __restrict__ A, const uint4* __restrict__ Apk, int n,
+                                           int cbase, int tid, uint4 (&w)[kSweepCols], int (&rows)[kSweepCols][D]) {
+    if constexpr (PACKED) {
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q) w[q] = Apk[min(cbase + q * kSweepBlock + tid, n - 1)];
+    } else {
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q) {
+            const size_t jj = static_cast<size_t>(min(cbase + q * kSweepBlock + tid, n - 1));
+#pragma unroll
+            for (int p = 0; p < D; ++p) rows[q][p] = A[jj * D + p];
+        }
+    }
+}
+
+template <int D, bool PACKED>
+__device__ __forceinline__ void unpack_chunk(const uint4 (&w)[kSweepCols], int (&rows)[kSweepCols][D],
+                                             int n, int cbase, int tid) {
+    if constexpr (PACKED) {
+#pragma unroll
+        for (int q = 0; q < kSweepCols; ++q) unpack_rows<D>(w[q], rows[q]);
+    }
 #pragma unroll
     for (int q = 0; q < kSweepCols; ++q) {
-        const int j = cbase + q * kSweepBlock + tid;
-        if (j >= n) {
+        const bool valid = cbase + q * kSweepBlock + tid < n;
 #pragma unroll
-            for (int p = 0; p < D; ++p) rows[q][p] = 0;
-        } else if (Apk) {
-            unpack_rows<D>(Apk[j], rows[q]);
-        } else {
-#pragma unroll
-            for (int p = 0; p < D; ++p) rows[q][p] = A[static_cast<size_t>(j) * D + p];
-        }
+        for (int p = 0; p < D; ++p) rows[q][p] = valid ? rows[q][p] : 0;
     }
 }
 
@@ -470,7 +488,10 @@ __device__ __forceinline__ void add_change(long long* Dl, const int (&rows)[D], 
 // round gathers the exact residuals of the columns with a candidate row.  DENSE (used
 // where the bitmask does not fit in LDS) adds the dense mode: when the row kernel counted
 // enough flagged rows, every thread tests its own columns without the bitmask and queue.
-template <int D, bool DENSE>
+// PACKED: the indices come from the packed words (a.Apk), else from A_cols.  Both are
+// template parameters, so that no branch separates the index loads from the loads
+// before them (the compiler then waits for all of them at the first use of any).
+template <int D, bool DENSE, bool PACKED>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     constexpr int kQueueRows = kQueueRowInts / D;
     __shared__ uint32_t bml[kBmLdsWords];
@@ -495,8 +516,18 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 
     // ---- round 1
     for (int b = threadIdx.x; b < kHistBins; b += kSweepBlock) lhist[b] = 0u;
-    int rows[kSweepCols][D];
-    load_rows<D>(a.A, a.Apk, a.n, blockIdx.x * kSweepChunk, tid, rows);
+    // the score tables (read only by the consensus test) are loaded first and stored to
+    // LDS before the decision, so they hold no registers past it
+    float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
+    float tzl = 0.0f, tel = 0.0f;
+    if (!a.tb.exact) {
+        tz4 = reinterpret_cast<const float4*>(a.tb.Tz)[tid];
+        te4 = reinterpret_cast<const float4*>(a.tb.Te)[tid];
+        if (tid == 0) {
+            tzl = a.tb.Tz[kTableN];
+            tel = a.tb.Te[kTableN];
+        }
+    }
     Slot prev{};
     int err = 0;
     if (tid == 0) {
@@ -526,6 +557,19 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     if (bm_regs && kBmPer * tid < words) {
         bw0 = reinterpret_cast<const uint4*>(a.w.bm[0])[tid];
         bw1 = reinterpret_cast<const uint4*>(a.w.bm[1])[tid];
+    }
+    // the chunk's indices are loaded last: loads complete in order, so the table stores
+    // and the decision below wait only for the loads before them
+    int rows[kSweepCols][D];
+    uint4 pw[kSweepCols];
+    issue_rows<D, PACKED>(a.A, a.Apk, a.n, blockIdx.x * kSweepChunk, tid, pw, rows);
+    if (!a.tb.exact) {
+        reinterpret_cast<float4*>(Tz)[tid] = tz4;
+        reinterpret_cast<float4*>(Te)[tid] = te4;
+        if (tid == 0) {
+            Tz[kTableN] = tzl;
+            Te[kTableN] = tel;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) lp += __shfl_down(lp, off);
     if (DENSE) {
@@ -568,21 +612,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     }
     __syncthreads();
     const Slot s = s_sh;
+    unpack_chunk<D, PACKED>(pw, rows, a.n, blockIdx.x * kSweepChunk, tid);   // the first chunk's indices
     if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
     if (s.done) return;
     const bool skip = !s.pending;   // a retry with nothing to retry
-    // the score tables are needed only by the consensus test: their loads are issued
-    // now, behind the index stream, and land in LDS with the bit tests
-    float4 tz4 = make_float4(0.f, 0.f, 0.f, 0.f), te4 = tz4;
-    float tzl = 0.0f, tel = 0.0f;
-    if (!a.tb.exact) {
-        tz4 = reinterpret_cast<const float4*>(a.tb.Tz)[tid];
-        te4 = reinterpret_cast<const float4*>(a.tb.Te)[tid];
-        if (tid == 0) {
-            tzl = a.tb.Tz[kTableN];
-            tel = a.tb.Te[kTableN];
-        }
-    }
     const int c = s.cur;
     const int acc = s.accepted_last;
     // when a quarter of the rows or more pass the outer test, nearly every column has such
@@ -619,7 +652,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 
     for (int chunk = blockIdx.x; chunk < a.chunks; chunk += gridDim.x) {
         const int cbase = chunk * kSweepChunk;
-        if (chunk != static_cast<int>(blockIdx.x)) load_rows<D>(a.A, a.Apk, a.n, cbase, tid, rows);
+        if (chunk != static_cast<int>(blockIdx.x)) {
+            issue_rows<D, PACKED>(a.A, a.Apk, a.n, cbase, tid, pw, rows);
+            unpack_chunk<D, PACKED>(pw, rows, a.n, cbase, tid);
+        }
         reinterpret_cast<float4*>(supv)[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (tid == 0) qn = 0;
         __syncthreads();
@@ -688,15 +724,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             continue;
         }
         if (dense) {
-            if (chunk == static_cast<int>(blockIdx.x) && !a.tb.exact) {
-                reinterpret_cast<float4*>(Tz)[tid] = tz4;
-                reinterpret_cast<float4*>(Te)[tid] = te4;
-                if (tid == 0) {
-                    Tz[kTableN] = tzl;
-                    Te[kTableN] = tel;
-                }
-            }
-            __syncthreads();
             // one column at a time, its rows picked by selects (one copy of the test's code)
 #pragma unroll 1
             for (int q = 0; q < kSweepCols; ++q) {
@@ -784,14 +811,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 out_x[o] = svq[q];
                 out_h[o] = svq[q];
                 atomicAdd(&lhist[top_digit(svq[q])], 1u);
-            }
-        }
-        if (chunk == static_cast<int>(blockIdx.x) && !a.tb.exact) {
-            reinterpret_cast<float4*>(Tz)[tid] = tz4;
-            reinterpret_cast<float4*>(Te)[tid] = te4;
-            if (tid == 0) {
-                Tz[kTableN] = tzl;
-                Te[kTableN] = tel;
             }
         }
         __syncthreads();
@@ -1417,9 +1436,15 @@ hipError_t launch_timed(K kernel, int grid, int block, hipStream_t s, const hipE
 
 template <int D>
 hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s, const hipEvent_t* ev) {
-    // the flagged-row counts exist where the bitmask does not fit in LDS
-    if (a.bm_lds) return launch_timed(k_sweep<D, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
-    return launch_timed(k_sweep<D, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+    // the flagged-row counts exist where the bitmask does not fit in LDS; packing fits
+    // such an m only for d <= 6 (18 bits a row or more)
+    if (a.Apk) {
+        if (a.bm_lds) return launch_timed(k_sweep<D, false, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+        if constexpr (D <= 6) return launch_timed(k_sweep<D, true, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+        return hipErrorInvalidValue;
+    }
+    if (a.bm_lds) return launch_timed(k_sweep<D, false, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+    return launch_timed(k_sweep<D, true, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
 }
 
 template <int D>
