@@ -784,17 +784,25 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             const int j = cbase + q * kSweepBlock + tid;
             if (j >= a.n) continue;
             unsigned int cm = 0u;
+            if (a.bm_lds) {
 #pragma unroll
-            for (int p = 0; p < D; ++p) {
-                const int row = rows[q][p];
-                uint32_t word;
-                if (a.bm_lds)
-                    word = bml[row >> 5];
-                else if (a.bs_lds)
-                    word = ((bml[row >> 8] >> ((row >> 3) & 31)) & 1u) ? bmg[row >> 5] : 0u;
-                else
-                    word = bmg[row >> 5];
-                cm |= ((word >> (row & 31)) & 1u) << p;
+                for (int p = 0; p < D; ++p) {
+                    const int row = rows[q][p];
+                    cm |= ((bml[row >> 5] >> (row & 31)) & 1u) << p;
+                }
+            } else {
+                // the column's bitmask words from global memory (only under a set summary
+                // bit when the summary is in LDS), all loaded before any is used
+                uint32_t word[D];
+#pragma unroll
+                for (int p = 0; p < D; ++p) {
+                    const int row = rows[q][p];
+                    const bool need = !a.bs_lds || ((bml[row >> 8] >> ((row >> 3) & 31)) & 1u);
+                    word[p] = 0u;
+                    if (need) word[p] = bmg[row >> 5];
+                }
+#pragma unroll
+                for (int p = 0; p < D; ++p) cm |= ((word[p] >> (rows[q][p] & 31)) & 1u) << p;
             }
             if (cm) {
                 const int qi = atomicAdd(&qn, 1);
