@@ -40,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # per dispatch at this workload) and the factors a 256 MiB plain copy gives each counter;
 # valid only for the kernel source they were taken on.
 SWEEP_COUNTERS = {
-    "kernels_sha256": "7eb92697dd5aa4990ffdab80b94bbb412999b8c149f72c327d542e8676ce1756",
-    "fetch_kib": 13293.5, "write_kib": 213.6, "fetch_factor": 2.000, "write_factor": 1.000,
+    "kernels_sha256": "6a764342e5608fd5ba6c1f14b5deb61b0c712777d27b2303b1278cc9cdf6f545",
+    "fetch_kib": 13324.0, "write_kib": 213.9, "fetch_factor": 2.000, "write_factor": 1.000,
 }
 
 
@@ -306,7 +306,8 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": sweep_traffic() if (N, M, DD) == (2 ** 20, 104857, 7) else None,
-                     "kernel": f"k_sweep<{DD}, {'true' if (M + 31) // 32 > 12288 else 'false'}>",
+                     "kernel": f"k_sweep<{DD}, {'true' if (M + 31) // 32 > 12288 else 'false'}, "
+                               f"{'true' if DD <= 4 or M <= 2 ** (128 // DD) else 'false'}>",
                      "avg_launch_us": sweep_avg_s * 1e6,
                      "launches": sweep_launches, "bytes_per_launch": sweep_bytes(N, M, DD)},
         "kernels_us_per_iteration": {k: 1e3 * v / max(sweep_launches, 1) for k, v in kern["executed"].items()},
