@@ -191,6 +191,10 @@ def test_decode_small_bitwise(seed):
     (20000, 5000, 900, 16, 40, 5),      # d = 16 (largest supported)
     (30000, 3000, 1, 7, 40, 6),         # k = 1
     (4096, 1024, 300, 2, 40, 7),        # d = 2, above the phase transition
+    # m above 393216 rows with packed indices (d = 6): the bitmask does not fit in LDS, about
+    # 43% of the rows pass the first outer test (the sweep's dense mode), and H_k's
+    # candidates are classified by their own kernel
+    (200000, 400003, 40000, 6, 40, 8),
 ])
 def test_decode_mid_size_bitwise(n, m, k, d, snr, seed):
     print(f"decode n={n} m={m} k={k} d={d} snr={snr}", flush=True)
