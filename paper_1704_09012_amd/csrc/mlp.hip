@@ -321,27 +321,36 @@ __device__ void load_mlp_lds(MlpLds& L, const float* __restrict__ w, int F) {
     const float* W3 = b2 + kHidden;
     const float* b3 = W3 + 2 * kHidden;
     constexpr int kWords = 4 * 64 + 8 * 64 + 2 * 64;
+    // every load reads an address inside w (a padding entry reads a clamped one and is
+    // then replaced by 0), so no per-lane branch makes the loads wait for each other
     for (int e = threadIdx.x; e < kWords; e += blockDim.x) {
         const int l = e & 63, g = l >> 4, c = l & 15;
         bf16x8 v;
         if (e < 256) {
             const int mt = e >> 6;
+            const float* __restrict__ wr = W1 + (16 * mt + c) * F;
+            float t[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 8 * g + j;
-                v[j] = static_cast<__bf16>(k < F ? W1[(16 * mt + c) * F + k] : 0.0f);
-            }
+            for (int j = 0; j < 8; ++j) t[j] = wr[min(8 * g + j, F - 1)];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = static_cast<__bf16>(8 * g + j < F ? t[j] : 0.0f);
             L.A1[mt][l] = v;
         } else {
             const bool l2 = e < 768;
             const int q = l2 ? (e - 256) >> 6 : (e - 768) >> 6;
             const int kt = q & 1;
-            const float* row = l2 ? W2 + (16 * (q >> 1) + c) * kHidden : W3 + c * kHidden;
             const bool live = l2 || c < 2;
+            const float* row = l2 ? W2 + (16 * (q >> 1) + c) * kHidden : W3 + (live ? c : 0) * kHidden;
+            float t0[4], t1[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                v[j] = static_cast<__bf16>(live ? row[32 * kt + 4 * g + j] : 0.0f);
-                v[4 + j] = static_cast<__bf16>(live ? row[32 * kt + 16 + 4 * g + j] : 0.0f);
+                t0[j] = row[32 * kt + 4 * g + j];
+                t1[j] = row[32 * kt + 16 + 4 * g + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[j] = static_cast<__bf16>(live ? t0[j] : 0.0f);
+                v[4 + j] = static_cast<__bf16>(live ? t1[j] : 0.0f);
             }
             if (l2)
                 L.A2[q >> 1][kt][l] = v;
@@ -511,9 +520,14 @@ __global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) 
             for (int p = 0; p < D; ++p) v[p] = r[rows[p]];
             need = true;
             if (a.reval_in) {
+                // all d earlier residuals are loaded before any comparison (a comparison
+                // that could skip the next load makes every load wait for the one before)
+                float rv[D];
+#pragma unroll
+                for (int p = 0; p < D; ++p) rv[p] = a.reval_in[rows[p]];
                 bool same = true;
 #pragma unroll
-                for (int p = 0; p < D; ++p) same = same && (__float_as_uint(a.reval_in[rows[p]]) == __float_as_uint(v[p]));
+                for (int p = 0; p < D; ++p) same = same & (__float_as_uint(rv[p]) == __float_as_uint(v[p]));
                 if (same) {
                     const float2 cc = a.cache[j];
                     a.value[j] = cc.x >= a.logit_t ? cc.y : nan;
