@@ -137,21 +137,35 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
     if (i < count) dst[i] = src[i];
 }
 
-__global__ void k_sketch_scatter(const int32_t* __restrict__ A, int n, int d,
+// Validates every column (rows strictly ascending in [0, m)) and scatters the nonzero
+// ones: a malformed column flags kErrIndex and adds nothing, so no write leaves S.
+__global__ void k_sketch_scatter(const int32_t* __restrict__ A, int n, int m, int d,
                                  const float* __restrict__ x, long long* __restrict__ S, int* err) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n || *err) return;
+    if (j >= n) return;
+    const int32_t* col = A + static_cast<size_t>(j) * d;
     const float xj = x[j];
+    int prev = -1;
+    bool bad = false;
+    for (int p = 0; p < d; ++p) {
+        const int r = col[p];
+        bad |= (r <= prev) | (r >= m);
+        prev = r;
+    }
+    if (bad) {
+        atomicOr(err, kErrIndex);
+        return;
+    }
     if (xj == 0.0f) return;
     const long long fx = to_fx(xj, err);
-    const int32_t* col = A + static_cast<size_t>(j) * d;
     for (int p = 0; p < d; ++p)
         atomicAdd(reinterpret_cast<unsigned long long*>(S + col[p]), static_cast<unsigned long long>(fx));
 }
 
-__global__ void k_sketch_finish(const long long* __restrict__ S, float* __restrict__ y, int m) {
+// y = fl32(2^-40 S), unless the scatter flagged an error (then y is left unwritten).
+__global__ void k_sketch_finish(const long long* __restrict__ S, float* __restrict__ y, int m, const int* err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) y[i] = from_fx(S[i]);
+    if (i < m && *err == 0) y[i] = from_fx(S[i]);
 }
 
 // ------------------------------------------------------------------ prepare
@@ -1572,10 +1586,9 @@ hipError_t launch_validate(const int32_t* A, int n, int m, int d, int* err, hipS
 
 hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, float* y,
                          long long* S, int* err, hipStream_t s) {
-    k_validate<<<blocks(n, 256), 256, 0, s>>>(A, n, m, d, err);
     k_zero_ll<<<blocks(m, 256), 256, 0, s>>>(S, m);
-    if (n > 0) k_sketch_scatter<<<blocks(n, 256), 256, 0, s>>>(A, n, d, x, S, err);
-    k_sketch_finish<<<blocks(m, 256), 256, 0, s>>>(S, y, m);
+    if (n > 0) k_sketch_scatter<<<blocks(n, 256), 256, 0, s>>>(A, n, m, d, x, S, err);
+    k_sketch_finish<<<blocks(m, 256), 256, 0, s>>>(S, y, m, err);
     return hipGetLastError();
 }
 

@@ -987,7 +987,7 @@ int rl0_validate(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, void* s
     if (int rc = get_workspace(dev, s, 1, 1, &b)) return rc;
     HIP_TRY(rl0::launch_clear_state(b->w.st, s));
     HIP_TRY(rl0::launch_validate(A_cols, n, m, d, &b->w.st->err, s));
-    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return err_code_of(b->st_host->err);
 }
@@ -1004,7 +1004,8 @@ int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     if (int rc = get_workspace(dev, s, 1, m, &b)) return rc;
     HIP_TRY(rl0::launch_clear_state(b->w.st, s));
     HIP_TRY(rl0::launch_sketch(A_cols, n, m, d, x, y, b->w.S[0], &b->w.st->err, s));
-    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, sizeof(rl0::DevState), hipMemcpyDeviceToHost, s));
+    // the flags lead the device state
+    HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return err_code_of(b->st_host->err);
 }
