@@ -86,6 +86,13 @@ def test_sketch_errors():
     assert e.value.code == -6
     bad = A.copy()
     bad[3, 1] = 40           # out of range
+    y_out = torch.full((40,), 7.0, dtype=torch.float32, device="cuda")
+    with pytest.raises(R.Rl0Error) as e:
+        R.sketch(dev(bad), dev(np.ones(100, np.float32)), 40, out=y_out)
+    assert e.value.code == -2
+    assert bool(torch.all(y_out == 7.0))      # y is left unwritten
+    bad = A.copy()
+    bad[9, [0, 1]] = bad[9, [1, 0]]           # not ascending
     with pytest.raises(R.Rl0Error) as e:
         R.sketch(dev(bad), dev(np.ones(100, np.float32)), 40)
     assert e.value.code == -2
