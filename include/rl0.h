@@ -107,8 +107,9 @@ int rl0_compute_constants(const rl0_params* p_h, int32_t n, int32_t m, int32_t d
 /* y = A x (Sec. 1; the measurement map of Definition "Generating model").
  * y_i = fl32(2^-40 * sum_{j : i in N(j)} rint(2^40 x_j)), an order-independent integer
  * sum that equals the exactly rounded A x whenever every x_j is a multiple of 2^-40.
- * A_cols [n][d], x [n], y [m] on the device.  A_cols is validated first (RL0_EINDEX, and y
- * is left unwritten); RL0_ERANGE if some |x_j| >= 2^22.  Synchronises the stream. */
+ * A_cols [n][d], x [n], y [m] on the device.  Every column of A_cols is validated on the
+ * way (RL0_EINDEX, and y is left unwritten); RL0_ERANGE if some |x_j| >= 2^22 (y is then
+ * left unwritten too).  Synchronises the stream. */
 int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* x,
                float* y, void* stream);
 
