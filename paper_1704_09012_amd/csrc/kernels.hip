@@ -1314,13 +1314,16 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
         for (int base = cb; base < ce; base += kRowBlock) {
             const int i = base + tid;
-            if (base != row0) {
-                s0 = s1 = dl = 0;
-                if (i < row1) {
-                    s0 = a.w.S[0][i];
-                    s1 = a.w.S[1][i];
-                    dl = a.w.D[i];
-                }
+            // the next block's rows are loaded before this block's work (its values are
+            // in s0, s1, dl: the first block's from round 1); a clamped row, no per-lane
+            // branch, so the loads overlap this block rather than wait for it
+            const int nb = base + kRowBlock;
+            long long n0 = 0, n1 = 0, nd = 0;
+            if (nb < row1) {
+                const int ni = min(nb + tid, a.m - 1);
+                n0 = a.w.S[0][ni];
+                n1 = a.w.S[1][ni];
+                nd = a.w.D[ni];
             }
             if (!all_kept && i < ce) dl += corr[i - cb];
             bool bt = false, bc = false;
@@ -1352,6 +1355,9 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
                     reinterpret_cast<uint8_t*>(a.w.bs[c])[wb >> 6] = summary8(bmc);
                 }
             }
+            s0 = n0;
+            s1 = n1;
+            dl = nd;
         }
         if (!all_kept) __syncthreads();   // corr is reused by the next window
     }
