@@ -215,7 +215,12 @@ def stepwise_learned(A, y, n, m, d, k, sig, wt):
     return host(x), L, iters, acc, learned_acc, retries
 
 
-@pytest.mark.parametrize("n,m,k,snr,seed", [(8192, 2048, 160, 40, 51), (20000, 3000, 250, 25, 52)])
+@pytest.mark.parametrize("n,m,k,snr,seed", [
+    (8192, 2048, 160, 40, 51), (20000, 3000, 250, 25, 52),
+    # m above 393216: the 8-row bitmask summary, H_k's classification kernel and the
+    # dense-capable sweep instance (whose dense mode the learned branch never takes)
+    (200000, 400003, 20000, 30, 53),
+])
 def test_device_learned_decode_matches_the_stepwise_loop(n, m, k, snr, seed):
     d = 7
     sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
