@@ -182,6 +182,29 @@ def test_step_teacher_forced_full_size():
         st = out.state
 
 
+def test_step_teacher_forced_large_m_dense():
+    """m = 400003 > 393216 rows, d = 6 (packed indices), k/m = 0.1: about 43% of the rows
+    pass the first outer test, so the sweep runs its dense mode; the first three
+    iterations, bitwise, per column."""
+    n, m, k, d = 200000, 400003, 40000, 6
+    inst, x, y, sig = problem(n, m, k, d, 40, 8)
+    C = D.make_constants(n, m, d, k, sig)
+    p = R.params_default(n, m, d, k, sig)
+    A_d, y_d = dev(inst.A_cols), dev(y)
+    st = D.init_state(y, n)
+    for it in range(3):
+        print(f"step large-m it={it}", flush=True)
+        out = D.step(inst.A_cols, y, st, C)
+        xh, rh = dev(st.x_hat), dev(st.r_hat)
+        g = R.step(A_d, y_d, p, it, xh, rh, st.L_hat)
+        assert np.array_equal(host(g["updated"]).astype(bool), out.sweep.updated)
+        assert np.array_equal(host(g["omega"]), out.sweep.omega)
+        assert np.array_equal(host(g["x_trial"]), out.x_trial)
+        assert np.array_equal(host(g["r_trial"]), out.r_trial)
+        assert g["accepted"] == out.accepted and g["L_hat"] == out.state.L_hat
+        st = out.state
+
+
 # ------------------------------------------------------------------ end to end
 
 @pytest.mark.parametrize("seed", range(20))
