@@ -117,6 +117,17 @@ int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
  * is not strictly ascending.  Synchronises the stream. */
 int rl0_validate(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, void* stream);
 
+/* The same check on a host copy of A_cols [n][d] (no device work).  RL0_EINVAL for bad
+ * sizes or a NULL pointer. */
+int rl0_validate_host(const int32_t* A_cols_h, int32_t n, int32_t m, int32_t d);
+
+/* Bytes of the device workspace a decode of this size allocates (the library allocates
+ * it at the first decode and keeps it per device and stream): the fixed-point and
+ * rounded residuals, bitmasks, candidate segments, packed indices and loop state
+ * described with Alg. 1's data.  0 for invalid sizes (d outside [1, 16] or d > m,
+ * k outside [1, m)). */
+size_t rl0_workspace_bytes(int32_t n, int32_t m, int32_t d, int32_t k);
+
 /* Robust-l0 (Alg. 1): recover x_hat ~ x from y_hat = A x + eta.
  * A_cols [n][d] and y [m] on the device; x_out [n] (device) receives x_hat, the best
  * accepted iterate.  If st_h != NULL the stream is synchronised and *st_h filled.
@@ -245,6 +256,12 @@ typedef struct rl0_train_cfg {
  * NULL) <- the mean loss of the last min(steps, 50) steps.  Synchronises. */
 int rl0_mlp_train(const float* feats, const float* labels, int64_t N, int32_t d, float* w, float* adam_m,
                   float* adam_v, const rl0_train_cfg* cfg, float* loss_h, void* stream);
+
+/* packed_h [rl0_mlp_num_params(d)] <- the parameters w_h (host, fp32) as bf16 bit
+ * patterns, rounded to nearest even: the weights the matrix-core inference multiplies
+ * with (it keeps the biases in fp32; their entries here are the bf16 roundings).  The
+ * decoder packs its device copy itself; this is the same rounding on the host. */
+int rl0_mlp_pack_bf16(const float* w_h, int32_t d, uint16_t* packed_h);
 
 /* out [N][2] (device) <- (logit, value) of the N samples: fp32 (bf16 = 0) or on the
  * matrix cores as the decoder runs it (bf16 = 1, d <= 15). */

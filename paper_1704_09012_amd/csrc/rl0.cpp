@@ -976,6 +976,25 @@ int rl0_compute_constants(const rl0_params* p, int32_t n, int32_t m, int32_t d, 
     return RL0_OK;
 }
 
+int rl0_validate_host(const int32_t* A_cols_h, int32_t n, int32_t m, int32_t d) {
+    if (int rc = check_dims(n, m, d)) return rc;
+    if (!A_cols_h) return fail(RL0_EINVAL, "A_cols_h is NULL");
+    for (int64_t j = 0; j < n; ++j) {
+        int prev = -1;
+        for (int p = 0; p < d; ++p) {
+            const int r = A_cols_h[j * d + p];
+            if (r <= prev || r >= m) return fail(RL0_EINDEX, "column " + std::to_string(j) + " is malformed");
+            prev = r;
+        }
+    }
+    return RL0_OK;
+}
+
+size_t rl0_workspace_bytes(int32_t n, int32_t m, int32_t d, int32_t k) {
+    if (n < 1 || m < 1 || d < 1 || d > RL0_MAX_D || d > m || k < 1 || k >= m) return 0;
+    return rl0::workspace_bytes(n, m);
+}
+
 int rl0_validate(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, void* stream) {
     if (int rc = check_dims(n, m, d)) return rc;
     if (!A_cols) return fail(RL0_EINVAL, "A_cols is NULL");
@@ -1208,6 +1227,23 @@ int rl0_autotune_batched(const rl0_problem* probs_h, int32_t count, int32_t reps
 }
 
 int32_t rl0_mlp_num_params(int32_t d) { return d >= 1 && d <= RL0_MAX_D ? rl0::mlp_params(d) : -1; }
+
+int rl0_mlp_pack_bf16(const float* w_h, int32_t d, uint16_t* packed_h) {
+    if (!w_h || !packed_h) return fail(RL0_EINVAL, "NULL pointer");
+    if (d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "d must be in [1, 16]");
+    const int P = rl0::mlp_params(d);
+    for (int i = 0; i < P; ++i) {
+        uint32_t u;
+        std::memcpy(&u, &w_h[i], 4);
+        if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) {
+            packed_h[i] = static_cast<uint16_t>((u >> 16) | 0x0040u);   // NaN stays NaN
+        } else {
+            const uint32_t lsb = (u >> 16) & 1u;   // round to nearest, ties to even
+            packed_h[i] = static_cast<uint16_t>((u + 0x7FFFu + lsb) >> 16);
+        }
+    }
+    return RL0_OK;
+}
 
 int rl0_mlp_init(float* w, int32_t d, uint64_t seed, void* stream) {
     if (!w) return fail(RL0_EINVAL, "w is NULL");

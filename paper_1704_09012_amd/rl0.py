@@ -159,6 +159,10 @@ def lib() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_double), V]
         L.rl0_mlp_num_params.argtypes = [I32]
         L.rl0_mlp_num_params.restype = I32
+        L.rl0_mlp_pack_bf16.argtypes = [P, I32, P]
+        L.rl0_validate_host.argtypes = [P, I32, I32, I32]
+        L.rl0_workspace_bytes.argtypes = [I32, I32, I32, I32]
+        L.rl0_workspace_bytes.restype = ctypes.c_size_t
         L.rl0_mlp_init.argtypes = [P, I32, ctypes.c_uint64, V]
         L.rl0_mlp_features.argtypes = [P, I32, I32, I32, P, ctypes.c_float, P, V]
         L.rl0_mlp_labels.argtypes = [P, P, I32, I32, ctypes.c_float, P, V]
@@ -340,6 +344,31 @@ def profile_read_kernels() -> dict:
     names = ("sweep", "hk_rows")
     return {"all": {k: arr[i] for i, k in enumerate(names)}, "all_launches": cnt[0],
             "executed": {k: arr[2 + i] for i, k in enumerate(names)}, "executed_launches": cnt[1]}
+
+
+def validate_host(A_cols, m: int) -> None:
+    """rl0_validate_host on a host int32 [n][d] array; raises Rl0Error if malformed."""
+    import numpy as np
+    a = np.ascontiguousarray(A_cols, dtype=np.int32)
+    n, d = a.shape
+    _check(lib().rl0_validate_host(a.ctypes.data, n, m, d))
+
+
+def workspace_bytes(n: int, m: int, d: int, k: int) -> int:
+    """rl0_workspace_bytes: device bytes a decode of this size allocates (0: invalid)."""
+    return int(lib().rl0_workspace_bytes(n, m, d, k))
+
+
+def mlp_pack_bf16(w, d: int):
+    """rl0_mlp_pack_bf16: the fp32 parameters (host) as bf16 bit patterns (uint16)."""
+    import numpy as np
+    wf = np.ascontiguousarray(w, dtype=np.float32)
+    P = mlp_num_params(d)
+    if wf.shape != (P,):
+        raise ValueError(f"w must hold {P} values")
+    out = np.empty(P, dtype=np.uint16)
+    _check(lib().rl0_mlp_pack_bf16(wf.ctypes.data, d, out.ctypes.data))
+    return out
 
 
 def release() -> None:

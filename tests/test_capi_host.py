@@ -158,3 +158,78 @@ def test_batch_schedule_rejects_bad_fields():
                 {"block": 256, "per_cu": 9, "cols": [4] * 12}, {"block": 256, "per_cu": 1, "cols": [3] * 12}):
         s = R.BatchSchedule.from_dict(bad)
         assert L.rl0_batch_schedule_set(ctypes.byref(s)) == -1
+
+
+# ------------------------------------------------------------------ host utilities
+
+def test_validate_host_accepts_good_and_rejects_malformed_columns():
+    rng = np.random.Generator(np.random.PCG64(11))
+    A = I.draw_columns(rng, 300, 50, 5)
+    R.validate_host(A, 50)
+    for mut in ("range", "negative", "order", "repeat"):
+        bad = A.copy()
+        if mut == "range":
+            bad[17, 4] = 50
+        elif mut == "negative":
+            bad[17, 0] = -1
+        elif mut == "order":
+            bad[17, [1, 2]] = bad[17, [2, 1]]
+        else:
+            bad[17, 2] = bad[17, 1]
+        with pytest.raises(R.Rl0Error) as e:
+            R.validate_host(bad, 50)
+        assert e.value.code == -2
+    with pytest.raises(R.Rl0Error) as e:
+        R.validate_host(A, 4)            # d > m
+    assert e.value.code == -1
+
+
+def test_workspace_bytes_grow_with_the_problem_and_reject_bad_sizes():
+    small = R.workspace_bytes(1024, 256, 7, 25)
+    mid = R.workspace_bytes(2 ** 20, 104857, 7, 10485)
+    big = R.workspace_bytes(2 ** 24, 2 ** 21, 8, 2 ** 18)
+    assert 0 < small < mid < big
+    # at least the residual state (int64 S twice, D, and y) and the packed indices
+    assert mid >= 4 * 8 * 104857 + 16 * 2 ** 20
+    for args in [(1024, 256, 17, 25), (1024, 256, 7, 256), (1024, 256, 7, 0), (1024, 6, 7, 2), (0, 256, 7, 25)]:
+        assert R.workspace_bytes(*args) == 0
+
+
+def _bf16_rne(x: float) -> int:
+    """bf16 bits of a float32 value by the definition: the nearer of the two neighbours
+    that keep the top 16 bits, ties to the even one (NaN to a quiet NaN)."""
+    import math
+    import struct
+    u = struct.unpack("<I", struct.pack("<f", x))[0]
+    if math.isnan(x):
+        return (u >> 16) | 0x40
+    lo = u >> 16
+    hi = lo + 1
+    f = lambda b: struct.unpack("<f", struct.pack("<I", (b << 16) & 0xFFFFFFFF))[0]
+    xv = struct.unpack("<f", struct.pack("<I", u))[0]
+    dlo, dhi = abs(xv - f(lo)), abs(f(hi) - xv) if hi & 0x7F80 != 0x7F80 or (hi & 0x7F) == 0 else math.inf
+    if (hi & 0x7F80) == 0x7F80 and (hi & 0x7F) == 0:
+        # the upper neighbour is infinity: halfway is the value 2^128 (1 - 2^-9) in magnitude
+        half = 2.0 ** 128 * (1 - 2.0 ** -9)
+        return hi if abs(xv) >= half and (abs(xv) > half or (lo & 1)) else lo
+    if dlo < dhi:
+        return lo
+    if dhi < dlo:
+        return hi
+    return lo if lo % 2 == 0 else hi
+
+
+def test_mlp_pack_bf16_rounds_to_nearest_even():
+    d = 3
+    P = R.mlp_num_params(d)
+    vals = [1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20, -2.0, 0.0, -0.0,
+            float("inf"), float("-inf"), 3.4028234663852886e38, 1e-40, 0.1, -0.333, 65504.0]
+    rng = np.random.Generator(np.random.PCG64(3))
+    w = np.concatenate([np.array(vals, np.float32), rng.standard_normal(P - len(vals)).astype(np.float32)])
+    got = R.mlp_pack_bf16(w, d)
+    want = np.array([_bf16_rne(float(v)) for v in w], np.uint16)
+    assert np.array_equal(got, want)
+    assert got[0] == 0x3F80 and got[1] == 0x3F80 and got[2] == 0x3F82 and got[3] == 0x3F81
+    assert got[7] == 0x7F80 and got[9] == 0x7F80      # max float rounds up to infinity
+    nan = R.mlp_pack_bf16(np.full(P, np.nan, np.float32), d)
+    assert np.all((nan & 0x7F80) == 0x7F80) and np.all((nan & 0x7F) != 0)
