@@ -233,3 +233,14 @@ def test_mlp_pack_bf16_rounds_to_nearest_even():
     assert got[7] == 0x7F80 and got[9] == 0x7F80      # max float rounds up to infinity
     nan = R.mlp_pack_bf16(np.full(P, np.nan, np.float32), d)
     assert np.all((nan & 0x7F80) == 0x7F80) and np.all((nan & 0x7F) != 0)
+
+
+def test_mlp_pack_bf16_matches_torch_bfloat16_conversion():
+    torch = pytest.importorskip("torch")
+    d = 7
+    P = R.mlp_num_params(d)
+    rng = np.random.Generator(np.random.PCG64(4))
+    w = (rng.standard_normal(P) * np.exp(rng.uniform(-20, 20, P))).astype(np.float32)
+    got = R.mlp_pack_bf16(w, d)
+    ref = torch.from_numpy(w).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, ref)
