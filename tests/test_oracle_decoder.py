@@ -23,6 +23,7 @@ from oracle import bruteforce as B
 from oracle import decoder as D
 from oracle import posterior as P
 from oracle import scores as S
+from oracle import shadow as SH
 from paper_1704_09012_amd import instances as I
 
 
@@ -69,29 +70,6 @@ def test_residual_is_exact_after_every_iteration():
             st.L_hat == D.l1_fixed(st.r_hat)
 
 
-def _scalar_column(v, t, alpha, d, rho, sig):
-    """Alg. 1's column body in fp64 with p_breve evaluated directly; returns
-    (passing candidates with (n_e, omega), margins)."""
-    pz = [float(P.p_breve("z", vi, d, rho, sig)) for vi in v]
-    n_z = sum(pz)
-    S1 = sum(abs(vi) for vi in v)
-    cands = []
-    margin = math.inf
-    for i in range(d):
-        outer = 1.0 - pz[i] - t
-        margin = min(margin, abs(outer))
-        if outer < 0:
-            continue
-        qe = [1.0 if l == i else float(P.p_breve("e", v[i] - v[l], d, rho, sig)) for l in range(d)]
-        n_e = sum(qe)
-        omega = sum(v[l] * qe[l] for l in range(d)) / n_e
-        L = sum(abs(v[l] - omega) for l in range(d))
-        margin = min(margin, abs(n_e - n_z - alpha), abs(L - S1) / max(S1, 1e-30))
-        if L <= S1 and n_e - n_z >= alpha:
-            cands.append((n_e, omega, i))
-    return cands, margin
-
-
 @pytest.mark.parametrize("it", [1, 5, 20, 38])
 def test_sweep_matches_scalar_fp64_transcription(it):
     n, m, k, d = 4096, 1024, 100, 7
@@ -107,18 +85,17 @@ def test_sweep_matches_scalar_fp64_transcription(it):
     cols = np.concatenate([np.nonzero(sw.updated)[0], rng.choice(n, 600, replace=False)])
     for j in cols:
         v = [float(st.r_hat[r]) for r in inst.A_cols[j]]
-        cands, margin = _scalar_column(v, float(t), 2.0, d, k / m, sig)
+        upd, row, omega, margin = SH.decision(v, float(t), 2.0, d, k / m, sig)
         if margin < 1e-5:
             continue
         checked += 1
-        if not cands:
+        if not upd:
             assert not sw.updated[j]
             agree += 1
             continue
         assert sw.updated[j]
-        best = max(cands, key=lambda c: (c[0], -c[2]))
-        assert sw.p_star[j] == best[2]
-        assert abs(float(sw.omega[j]) - best[1]) <= 1e-5 * max(1.0, abs(best[1]))
+        assert sw.p_star[j] == row
+        assert abs(float(sw.omega[j]) - omega) <= 1e-5 * max(1.0, abs(omega))
         agree += 1
     assert checked >= 300 and agree == checked
 
