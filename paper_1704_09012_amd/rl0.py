@@ -284,6 +284,8 @@ def decode(A_cols, y, sigma: float | None = None, d: int | None = None, params: 
         params = params_default(n, m, dd, k, sigma, **overrides)
     else:
         for key, val in overrides.items():
+            if not hasattr(params, key):
+                raise KeyError(key)
             if key == "mlp" and hasattr(val, "data_ptr"):
                 val = val.data_ptr()
                 params.posterior = 1

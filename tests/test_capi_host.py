@@ -54,6 +54,17 @@ def test_bad_params_are_rejected_on_the_host(field, value):
     assert e.value.code == -1
 
 
+def test_unknown_parameter_names_are_rejected():
+    # a misspelt override must not be set on the structure and then ignored by the library
+    import torch
+    with pytest.raises(KeyError):
+        R.params_default(1024, 256, 7, 25, 0.01, alpah=3.0)
+    A = torch.zeros((1024, 7), dtype=torch.int32)
+    y = torch.zeros(256, dtype=torch.float32)
+    with pytest.raises(KeyError):
+        R.decode(A, y, params=R.params_default(1024, 256, 7, 25, 0.01), alpah=3.0)
+
+
 def test_learned_posterior_without_weights():
     p = R.params_default(1024, 256, 7, 25, 0.01)
     p.posterior = 1
