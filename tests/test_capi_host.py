@@ -65,6 +65,14 @@ def test_unknown_parameter_names_are_rejected():
         R.decode(A, y, params=R.params_default(1024, 256, 7, 25, 0.01), alpah=3.0)
 
 
+def test_single_row_columns_are_rejected():
+    # with d = 1 no alpha lies in (1, d], so the library refuses the problem
+    p = R.params_default(3000, 900, 1, 60, 0.01)
+    with pytest.raises(R.Rl0Error) as e:
+        R.compute_constants(p, 3000, 900, 1)
+    assert e.value.code == -1 and "alpha" in str(e.value)
+
+
 def test_learned_posterior_without_weights():
     p = R.params_default(1024, 256, 7, 25, 0.01)
     p.posterior = 1

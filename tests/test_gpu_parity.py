@@ -234,6 +234,21 @@ def test_decode_mid_size_bitwise(n, m, k, d, snr, seed):
     assert_same_decode(xg, stg, res)
 
 
+@pytest.mark.parametrize("n,m,k,d,snr,seed", [
+    (10000, 2000, 150, 3, 40, 11),      # d = 3: three 32-bit fields in the packed word
+    (20000, 1000, 80, 12, 40, 10),      # d = 12, m <= 2^10: packed 10-bit fields
+    (12000, 2500, 200, 9, 30, 12),      # d = 9, m <= 2^14: packed 14-bit fields
+])
+def test_decode_d3_and_narrow_fields_bitwise(n, m, k, d, snr, seed):
+    print(f"decode n={n} m={m} k={k} d={d} snr={snr}", flush=True)
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, I.seed_for(2, 0, seed))
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    xg, stg = gpu_decode(inst, y, sig)
+    res, _ = oracle_decode(inst, y, sig)
+    assert_same_decode(xg, stg, res)
+
+
 @pytest.mark.parametrize("kw", [dict(alpha=3.5), dict(l1_test=1), dict(max_iters=1), dict(c=0.1),
                                 dict(series_terms=1), dict(sigma_signal=2.0)])
 def test_decode_parameter_variants_bitwise(kw):
