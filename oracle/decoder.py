@@ -106,6 +106,9 @@ class Constants:
 def make_constants(n, m, d, k, sigma, sigma_s=1.0, alpha=2.0, c=0.0, ell=4,
                    max_iters=0, l1_test=0) -> Constants:
     """Alg. 1 prologue: p_breve_z, p_breve_e for GM(n, m, k, d, N(0,ss^2), N(0,sn^2))."""
+    # Alg. 1 takes the consensus level alpha from (1, d]
+    if not (1.0 < alpha <= d):
+        raise ValueError("alpha must be in (1, d]")
     rho = k / m
     if c == 0.0:
         c = _scores.c_rule(m / n)

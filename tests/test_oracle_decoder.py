@@ -192,3 +192,11 @@ def test_fixed_point_round_trip_and_l1():
     assert D.l1_fixed(v) == sum(int(round(abs(float(a)) * 2 ** 30)) for a in v)
     with pytest.raises(OverflowError):
         D.to_fixed(np.array([2.0 ** 23], dtype=np.float32))
+
+
+def test_alpha_outside_its_range_is_refused():
+    # Alg. 1's input: alpha in (1, d]; d = 1 leaves no admissible alpha
+    for d, alpha in [(7, 1.0), (7, 7.5), (1, 2.0), (1, 1.0)]:
+        with pytest.raises(ValueError):
+            D.make_constants(1000, 300, d, 20, 0.01, alpha=alpha)
+    assert D.make_constants(1000, 300, 7, 20, 0.01, alpha=7.0).alpha == np.float32(7.0)
