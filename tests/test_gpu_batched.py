@@ -83,6 +83,20 @@ def test_batched_mixed_column_weights():
         same(host(pr["out"]), st, oracle_of(inst))
 
 
+def test_batched_extreme_column_weights():
+    # d = 2 and 3 (few rows per column) and d = 16 (the largest), each in a launch of its own
+    insts = []
+    for i, (n, m, k, d) in enumerate([(4096, 1024, 100, 2), (5000, 1000, 80, 3), (6000, 1500, 200, 16),
+                                      (2500, 700, 30, 16)]):
+        sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
+        insts.append(I.draw_instance(n, m, k, d, sig, 995 + i))
+    probs = problems_of(insts)
+    print("batched d = 2, 3, 16", flush=True)
+    stats = R.decode_batched(probs)
+    for inst, pr, st in zip(insts, probs, stats):
+        same(host(pr["out"]), st, oracle_of(inst))
+
+
 def test_batched_parameter_variants():
     insts = mixed_batch()[:5]
     for kw in (dict(alpha=3.0), dict(l1_test=1), dict(c=0.1), dict(max_iters=3)):
