@@ -50,14 +50,15 @@ def state_after(inst, y, its):
     return st, C
 
 
-def test_features_and_labels_bitwise():
-    inst = I.draw_instance(5000, 700, 60, 7, 0.01, 21)
+@pytest.mark.parametrize("d", [7, 3, 12])
+def test_features_and_labels_bitwise(d):
+    inst = I.draw_instance(5000, 700, 60, d, 0.01, 21)
     y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, inst.m)
     st, _ = state_after(inst, y, 6)
     f = R.mlp_features(dev(inst.A_cols), dev(st.r_hat), 0.01)
     assert np.array_equal(host(f), M.features(inst.A_cols, st.r_hat, 0.01))
-    lab = R.mlp_labels(dev(inst.x_dense()), dev(st.x_hat), 7, 0.01)
-    assert np.array_equal(host(lab), M.labels(inst.x_dense(), st.x_hat, 0.01, 7))
+    lab = R.mlp_labels(dev(inst.x_dense()), dev(st.x_hat), d, 0.01)
+    assert np.array_equal(host(lab), M.labels(inst.x_dense(), st.x_hat, 0.01, d))
 
 
 @pytest.mark.parametrize("d,N", [(7, 4096), (7, 1000), (3, 130)])
@@ -75,8 +76,8 @@ def test_gradient_matches_fp64_oracle(d, N):
     assert abs(loss - lo) <= 1e-4 * max(1.0, abs(lo))
 
 
-def test_inference_fp32_and_bf16():
-    d = 7
+@pytest.mark.parametrize("d", [7, 3, 15])
+def test_inference_fp32_and_bf16(d):
     rng = np.random.default_rng(8)
     w = net(d, 9)
     F = rng.normal(0, 0.2, (3000, d + 1)).astype(np.float32)
