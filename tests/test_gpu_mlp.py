@@ -90,8 +90,9 @@ def test_inference_fp32_and_bf16(d):
     assert np.max(np.abs(o16 - emu)) <= 1e-2
 
 
-def test_learned_step_decisions_match_the_oracle():
-    n, m, k, d = 4096, 1024, 100, 7
+@pytest.mark.parametrize("d", [7, 12])
+def test_learned_step_decisions_match_the_oracle(d):
+    n, m, k = 4096, 1024, 100
     sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
     inst = I.draw_instance(n, m, k, d, sig, 31)
     y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
