@@ -44,7 +44,10 @@ Float32 contract (both this oracle and the GPU follow it, so their bits agree):
       S_i = rint(2^40 y_i) - sum_{j in supp x'} rint(2^40 x'_j) for i in N(j)
       r_i = fl32(fl64(S_i) * 2^-40)
     an exact integer sum, hence independent of summation order; it equals the exactly
-    rounded y - A x' whenever every value is a multiple of 2^-40;
+    rounded y - A x' whenever every value is a multiple of 2^-40, which every float32 of
+    magnitude >= 2^-17 is.  Smaller entries are rounded to the grid first (this also
+    holds for r_hat <- y: rows with |y_i| < 2^-17 start at fl32(2^-40 rint(2^40 y_i)));
+    fx_inexact counts them;
   * ||r||_1 is the integer L(r) = sum_i rint(2^30 |r_i|) (unit 2^-30), accepted on a
     strict decrease.
 
@@ -69,6 +72,7 @@ __all__ = [
     "to_fixed",
     "from_fixed",
     "l1_fixed",
+    "fx_inexact",
     "sketch",
     "measure",
     "sweep",
@@ -135,6 +139,14 @@ def to_fixed(v) -> np.ndarray:
 def from_fixed(S: np.ndarray) -> np.ndarray:
     """fl32(fl64(S) * 2^-40)."""
     return (np.asarray(S, dtype=np.int64).astype(np.float64) * (2.0 ** -FX_SHIFT)).astype(np.float32)
+
+
+def fx_inexact(v) -> int:
+    """Entries of v (float32) that are not multiples of 2^-40, so that rint(2^40 v) rounds.
+    Only such entries make the fixed-point residual differ from the exactly rounded
+    y - A x; a float32 value is a multiple of 2^-40 whenever |v| >= 2^-17."""
+    s = np.asarray(v, dtype=np.float32).astype(np.float64) * (2.0 ** FX_SHIFT)
+    return int(np.count_nonzero(s != np.rint(s)))
 
 
 def l1_fixed(r: np.ndarray) -> int:
@@ -316,6 +328,9 @@ class DecodeResult:
     accepted: int
     converged: bool
     updates_total: int
+    fx_inexact_y: int = 0     # entries of y_hat whose fixed-point conversion rounds
+    fx_inexact_x: int = 0     # nonzero x'_j of updated columns whose conversion rounds,
+                              # summed over the executed iterations
     trace: list = field(default_factory=list)
 
 
@@ -325,12 +340,16 @@ def decode(A_cols, y_hat, C: Constants, keep_trace: bool = False) -> DecodeResul
     st = init_state(y_hat, A_cols.shape[0])
     trace = []
     updates = 0
+    inexact_x = 0
     while st.it < C.n_iters and not converged(st, C):
         out = step(A_cols, y_hat, st, C)
         updates += int(out.sweep.updated.sum())
+        xp = out.sweep.x_prime[out.sweep.updated]
+        inexact_x += fx_inexact(xp[xp != 0])
         if keep_trace:
             trace.append((st.L_hat, out.L_trial, out.accepted))
         st = out.state
     return DecodeResult(x_hat=st.x_hat, r_hat=st.r_hat, L_hat=st.L_hat, iterations=st.it,
                         accepted=st.accepted, converged=converged(st, C),
-                        updates_total=updates, trace=trace)
+                        updates_total=updates, fx_inexact_y=fx_inexact(y_hat), fx_inexact_x=inexact_x,
+                        trace=trace)

@@ -22,36 +22,39 @@ import math
 from oracle import posterior as P
 
 
-def column(v, t: float, alpha: float, d: int, rho: float, sigma: float):
+def column(v, t: float, alpha: float, d: int, rho: float, sigma: float, split: bool = False):
     """One column with residual entries v (its d rows, ascending).  Returns
     (candidates, margin): candidates are the passing rows as (n_e, omega, row), margin
     the smallest distance of any comparison from its threshold (relative for the l1
-    test)."""
+    test).  With split, (candidates, outer margin, margin of the other tests)."""
     pz = [float(P.p_breve("z", vi, d, rho, sigma)) for vi in v]
     n_z = sum(pz)
     S1 = sum(abs(vi) for vi in v)
     cands = []
-    margin = math.inf
+    outer_m = other_m = math.inf
     for i in range(d):
         outer = 1.0 - pz[i] - t
-        margin = min(margin, abs(outer))
+        outer_m = min(outer_m, abs(outer))
         if outer < 0:
             continue
         qe = [1.0 if l == i else float(P.p_breve("e", v[i] - v[l], d, rho, sigma)) for l in range(d)]
         n_e = sum(qe)
         omega = sum(v[l] * qe[l] for l in range(d)) / n_e
         L = sum(abs(v[l] - omega) for l in range(d))
-        margin = min(margin, abs(n_e - n_z - alpha), abs(L - S1) / max(S1, 1e-30))
+        other_m = min(other_m, abs(n_e - n_z - alpha), abs(L - S1) / max(S1, 1e-30))
         if L <= S1 and n_e - n_z >= alpha:
             cands.append((n_e, omega, i))
-    return cands, margin
+    if split:
+        return cands, outer_m, other_m
+    return cands, min(outer_m, other_m)
 
 
-def decision(v, t: float, alpha: float, d: int, rho: float, sigma: float):
+def decision(v, t: float, alpha: float, d: int, rho: float, sigma: float, split: bool = False):
     """(updated, row, omega, margin) of one column: the passing row with the largest
-    n_e, ties to the smaller row."""
-    cands, margin = column(v, t, alpha, d, rho, sigma)
+    n_e, ties to the smaller row.  With split the margin is two values, of the outer test
+    and of the other tests."""
+    cands, *margins = column(v, t, alpha, d, rho, sigma, split)
     if not cands:
-        return False, -1, 0.0, margin
+        return (False, -1, 0.0, *margins)
     n_e, omega, row = max(cands, key=lambda c: (c[0], -c[2]))
-    return True, row, omega, margin
+    return (True, row, omega, *margins)

@@ -112,6 +112,47 @@ def test_bf16_forward_close_to_exact():
     assert not np.array_equal(approx, exact.astype(np.float32))
 
 
+def test_bf16_forward_rounds_every_product_input():
+    """A hand-set chain through one hidden unit per layer, with values worked out by hand.
+    GELU is the identity on these inputs (all above 20, where erf is 1 in float64).
+      input 20.0703125 = 16 x 1.25439453125; 7 fraction bits: 32.5625 / 128 -> 33: 20.125
+      layer 1: 1.75 x 20.125 = 35.21875
+      bf16(35.21875) = 32 x (1 + 12.875 / 128) -> 32 x (1 + 13 / 128) = 35.25
+      layer 2: 1.5 x 35.25 = 52.875
+      bf16(52.875) = 32 x (1 + 83.5 / 128), a tie -> the even 84: 53.0
+      layer 3: logit = 1 x 53.0, value = 0.5 x 53.0 = 26.5
+    Leaving out the rounding of the input of layer 1, 2 or 3 gives a logit of 52.5, 52.75
+    or 52.875 instead, so each of the three roundings is pinned."""
+    d = 3
+    w = np.zeros(M.n_params(d), np.float32)
+    W1, b1, W2, b2, W3, b3 = M.unpack(w, d)
+    W1[0, 0] = 1.75
+    W2[0, 0] = 1.5
+    W3[0, 0] = 1.0
+    W3[1, 0] = 0.5
+    F = np.zeros((1, d + 1), np.float32)
+    F[0, 0] = 20.0703125
+    out = M.forward_bf16(w, F, d)
+    assert out[0, 0] == np.float32(53.0) and out[0, 1] == np.float32(26.5)
+    # planted mistakes: skip the rounding of one product's input (the first of the two
+    # to_bf16 calls of each layer) and the output moves as worked out above
+    real = M.to_bf16
+    for layer, want in ((0, 52.5), (1, 52.75), (2, 52.875)):
+        calls = []
+
+        def skipping(a, _layer=layer, _calls=calls):
+            _calls.append(1)
+            if len(_calls) - 1 == 2 * _layer:
+                return np.asarray(a, dtype=np.float32)
+            return real(a)
+        M.to_bf16 = skipping
+        try:
+            got = M.forward_bf16(w, F, d)[0, 0]
+        finally:
+            M.to_bf16 = real
+        assert got == np.float32(want), (layer, got)
+
+
 def test_logit_threshold_inverts_the_sigmoid():
     for t in (0.975, 0.5, 0.1, 0.025):
         lt = M.logit_threshold(t)
