@@ -62,6 +62,10 @@ typedef struct rl0_params {
     const void* mlp;        /* device pointer to the network's fp32 parameters
                                (posterior = 1; see rl0_mlp_num_params) */
     int32_t validate;       /* 1 = check A_cols on the device before decoding */
+    int32_t variant;        /* scores of Table "scores": 0 = continuous, 1 = quantised
+                               (indicators q_e = 1{p_breve_e >= t}, q_z = 1{p_breve_z >= 1 - t};
+                               c = 0 then selects eq:finetune_c_quant) */
+    int32_t adaptive_k;     /* 0 (Alg. 1's adaptive_k branch is not supported: RL0_EINVAL) */
 } rl0_params;
 
 /* What a decode did.  l1 values are ||r_hat||_1; the fixed-point one is exact. */
@@ -75,6 +79,13 @@ typedef struct rl0_stats {
     double l1_tol;          /* m sigma sqrt(2/pi) (Sec. 4 "Stopping conditions") */
     float t_final;          /* t of the last executed iteration */
     int32_t error_flags;    /* device-side flags; nonzero only with an error return */
+    float ms_total;         /* device time of the call, from the first kernel of the decode to
+                               the copy of x_hat (HIP events on the stream) */
+    int32_t fx_inexact_y;   /* entries of y whose conversion to the 2^-40 fixed point rounds
+                               (|y_i| < 2^-17 and not a multiple of 2^-40); r_hat <- y is not
+                               exact on those rows */
+    int32_t fx_inexact_x;   /* updated entries x'_j != 0 whose conversion rounds, summed over
+                               the executed iterations (0 for batched and learned decodes) */
 } rl0_stats;
 
 /* Host copy of the decoder's constants, for inspection and tests. */
@@ -256,6 +267,15 @@ typedef struct rl0_train_cfg {
  * NULL) <- the mean loss of the last min(steps, 50) steps.  Synchronises. */
 int rl0_mlp_train(const float* feats, const float* labels, int64_t N, int32_t d, float* w, float* adam_m,
                   float* adam_v, const rl0_train_cfg* cfg, float* loss_h, void* stream);
+
+/* One Adam update (Kingma and Ba) of w at step t >= 1 with the gradient grad (all [P]
+ * = rl0_mlp_num_params(d) values on the device, w, adam_m and adam_v updated in place):
+ * m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+ * w <- w - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), in float32 with the bias
+ * corrections taken in double; cfg supplies lr, beta1, beta2 and eps (its other fields are
+ * not used).  This is the update rl0_mlp_train applies after each gradient. */
+int rl0_mlp_adam(float* w, const float* grad, float* adam_m, float* adam_v, int32_t d, int32_t t,
+                 const rl0_train_cfg* cfg, void* stream);
 
 /* packed_h [rl0_mlp_num_params(d)] <- the parameters w_h (host, fp32) as bf16 bit
  * patterns, rounded to nearest even: the weights the matrix-core inference multiplies

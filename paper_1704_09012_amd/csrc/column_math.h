@@ -29,6 +29,12 @@ __device__ __forceinline__ long long to_fx(float v, int* err) {
     return __double2ll_rn(s);
 }
 
+// v is not a multiple of 2^-40, so rint(2^40 v) rounds (only possible for |v| < 2^-17)
+__device__ __forceinline__ bool fx_inexact(float v) {
+    const double s = static_cast<double>(v) * kTwo40;
+    return s != rint(s);
+}
+
 __device__ __forceinline__ float from_fx(long long S) {
     return static_cast<float>(static_cast<double>(S) * kTwoM40);
 }

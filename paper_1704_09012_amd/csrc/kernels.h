@@ -44,6 +44,8 @@ struct DevState {
     unsigned long long kth_key[2];        // smallest key H_k keeps
     int updates_total;                    // column updates proposed, summed over iterations
     int err;                              // ErrFlag bits
+    int inexact_y;                        // entries of y whose fixed-point conversion rounds
+    int inexact_x;                        // updated x'_j != 0 whose conversion rounds (all sweeps)
     int peek_cur, peek_done;              // the coming decision, evaluated ahead (learned decode)
     int bucket_n[2];                      // entries of H_k's boundary bucket listed by k_hk_classify
     int seg_count[2][kSweepGridMax];      // candidates written by each sweep workgroup

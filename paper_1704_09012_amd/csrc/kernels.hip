@@ -201,6 +201,7 @@ __global__ void k_prep_rows(const float* __restrict__ y, long long* __restrict__
     const float yi = y[i];
     if (!isfinite(yi)) atomicOr(&st->err, kErrNonFinite);
     const long long s = to_fx(yi, &st->err);
+    if (fx_inexact(yi)) atomicAdd(&st->inexact_y, 1);
     Sy[i] = s;
     S0[i] = s;
 }
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     __shared__ float supv[kSweepChunk];
     __shared__ int queue[kSweepChunk];
     __shared__ int qrows[kQueueRowInts];
-    __shared__ int qn, seg_f, seg_b, seg_z, seg_upd;
+    __shared__ int qn, seg_f, seg_b, seg_z, seg_upd, seg_inx;
     __shared__ unsigned lhist[kHistBins];   // this workgroup's nonzero candidates by top digit
     __shared__ Slot s_sh;
     __shared__ long long red[kSweepBlock / 64];
@@ -623,6 +624,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         seg_b = 0;
         seg_z = 0;
         seg_upd = 0;
+        seg_inx = 0;
     }
     __syncthreads();
     const Slot s = s_sh;
@@ -723,6 +725,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     out_h[o] = svq[q];
                     if (xp != 0.0f) {
                         atomicAdd(&seg_z, 1);
+                        if (fx_inexact(xp)) atomicAdd(&seg_inx, 1);
                         atomicAdd(&lhist[top_digit(xp)], 1u);
                     }
                     add_change<D>(a.w.D, rows[q], svq[q], xp, &st->err);
@@ -778,6 +781,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     out_h[o] = xhq;
                     if (xp != 0.0f) {
                         atomicAdd(&seg_z, 1);
+                        if (fx_inexact(xp)) atomicAdd(&seg_inx, 1);
                         atomicAdd(&lhist[top_digit(xp)], 1u);
                     }
                     add_change<D>(a.w.D, rq, xhq, xp, &st->err);
@@ -875,6 +879,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 out_h[o] = xhq;
                 if (xp != 0.0f) {
                     atomicAdd(&seg_z, 1);
+                    if (fx_inexact(xp)) atomicAdd(&seg_inx, 1);
                     atomicAdd(&lhist[top_digit(xp)], 1u);
                 }
                 add_change<D>(a.w.D, rr, xhq, xp, &st->err);
@@ -893,6 +898,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         st->seg_front[me][seg] = seg_f;
         st->seg_nz[me][seg] = seg_z + seg_b;
         st->seg_updates[me][seg] = seg_upd;
+        if (seg_inx) atomicAdd(&st->inexact_x, seg_inx);
     }
     // H_k's first radix digit, counted for every workgroup at once
     for (int b = tid; b < kHistBins; b += kSweepBlock) {

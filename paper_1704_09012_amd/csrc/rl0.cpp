@@ -206,6 +206,7 @@ struct Buffers {
     rl0::Workspace w{};
     rl0::DevState* st_host = nullptr;  // pinned copy of the device state
     hipStream_t capture = nullptr;     // private stream the launch sequence is captured on
+    hipEvent_t ev_call[2] = {nullptr, nullptr};   // start and end of a decode (rl0_stats.ms_total)
     std::vector<GraphEntry> graphs;    // replayable decodes on this workspace
     unsigned long long uses = 0;
 };
@@ -246,6 +247,10 @@ int get_workspace(int device, hipStream_t s, int n, int m, Buffers** out) {
     if (!b->st_host) {
         if (hipHostMalloc(&b->st_host, sizeof(rl0::DevState), hipHostMallocDefault) != hipSuccess)
             return fail(RL0_ENOMEM, "hipHostMalloc(state)");
+    }
+    if (!b->ev_call[0]) {
+        HIP_TRY(hipEventCreate(&b->ev_call[0]));
+        HIP_TRY(hipEventCreate(&b->ev_call[1]));
     }
     *out = b;
     return RL0_OK;
@@ -297,7 +302,30 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     if (p->posterior == 1 && !p->mlp) return fail(RL0_ENOWEIGHTS, "learned posterior requested without weights");
     if (p->posterior == 1 && d + 1 > rl0::kMlpMaxFeatures)
         return fail(RL0_EINVAL, "the learned posterior supports d <= 15");
+    if (p->variant != 0) return fail(RL0_EINVAL, "variant must be 0 (continuous scores)");
+    if (p->adaptive_k != 0) return fail(RL0_EINVAL, "adaptive_k is not supported (must be 0)");
     return RL0_OK;
+}
+
+// The parameters as part of a cache key (compared with memcmp): every field copied into
+// *out after zeroing it, so that the padding between fields (whatever the caller's struct
+// holds there) compares equal.
+void params_key(const rl0_params* p, rl0_params* out) {
+    rl0_params& k = *out;
+    std::memset(out, 0, sizeof(*out));
+    k.k = p->k;
+    k.sigma = p->sigma;
+    k.sigma_signal = p->sigma_signal;
+    k.alpha = p->alpha;
+    k.c = p->c;
+    k.series_terms = p->series_terms;
+    k.max_iters = p->max_iters;
+    k.l1_test = p->l1_test;
+    k.posterior = p->posterior;
+    k.mlp = p->mlp;
+    k.validate = p->validate;
+    k.variant = p->variant;
+    k.adaptive_k = p->adaptive_k;
 }
 
 rl0::Problem problem_of(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
@@ -441,6 +469,7 @@ struct BatchBuffers {
     void* host = nullptr;            // pinned staging of descriptors, order and results
     hipStream_t capture = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev_call[2] = {nullptr, nullptr};   // around a whole batched call (ms_total)
     std::vector<BatchGraph> graphs;
     unsigned long long uses = 0;
     rl0::BatchProblem* desc_d() const { return static_cast<rl0::BatchProblem*>(meta); }
@@ -508,6 +537,8 @@ int get_batch_buffers(int device, hipStream_t s, size_t block_bytes, size_t coun
     if (!b->ev[0]) {
         HIP_TRY(hipEventCreate(&b->ev[0]));
         HIP_TRY(hipEventCreate(&b->ev[1]));
+        HIP_TRY(hipEventCreate(&b->ev_call[0]));
+        HIP_TRY(hipEventCreate(&b->ev_call[1]));
     }
     *out = b;
     return RL0_OK;
@@ -731,6 +762,8 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
     const MetaView dv = meta_view(P.b->meta, P.count);
     HIP_TRY(hipMemcpyAsync(h.res, dv.res, sizeof(rl0::BatchResult) * P.count, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    float call_ms = -1.0f;
+    if (hipEventElapsedTime(&call_ms, P.b->ev_call[0], P.b->ev_call[1]) != hipSuccess) call_ms = -1.0f;
     int first_rc = RL0_OK;
     std::string first_msg;
     for (int i = 0; i < P.count; ++i) {
@@ -747,6 +780,9 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
             o.updates_total = R.updates_total;
             o.t_final = R.iterations > 0 ? dc->hc.t[R.iterations - 1] : 1.0f;
             o.error_flags = R.err;
+            o.ms_total = call_ms;   // the whole batched launch
+            o.fx_inexact_y = 0;
+            o.fx_inexact_x = 0;
         }
         if (R.err && first_rc == RL0_OK) {
             first_rc = err_code_of(R.err);
@@ -756,6 +792,25 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
     (void)probs;
     if (first_rc != RL0_OK) return fail(first_rc, first_msg);
     return RL0_OK;
+}
+
+// Fills *st_h from a finished decode's device state (copied to the host) and the
+// workspace's call events (both recorded on the decode's stream, now synchronised).
+void fill_stats(rl0_stats* st_h, const rl0::DevState& ds, const rl0::Slot& fin, const DeviceConstants* dc,
+                float t_final, Buffers* b) {
+    st_h->iterations = fin.iterations;
+    st_h->accepted = fin.accepted;
+    st_h->l1_final_fx = fin.L_hat;
+    st_h->l1_final = static_cast<double>(fin.L_hat) / 1073741824.0;
+    st_h->l1_tol = dc->hc.tol;
+    st_h->converged = (static_cast<double>(fin.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
+    st_h->updates_total = ds.updates_total;
+    st_h->t_final = t_final;
+    st_h->error_flags = ds.err;
+    st_h->fx_inexact_y = ds.inexact_y;
+    st_h->fx_inexact_x = ds.inexact_x;
+    float ms = 0.0f;
+    st_h->ms_total = hipEventElapsedTime(&ms, b->ev_call[0], b->ev_call[1]) == hipSuccess ? ms : -1.0f;
 }
 
 // ---------------------------------------------------------------- one iteration from x_hat
@@ -869,6 +924,7 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
         HIP_TRY(rl0::launch_finish(dm, w, learned_sub_params(dc, p, 2 * N), xq, q, true));
         return RL0_OK;
     };
+    if (st_h) HIP_TRY(hipEventRecord(b->ev_call[0], s));
     if (graphs_enabled()) {
         DecodeKey key;
         std::memset(&key, 0, sizeof(key));
@@ -877,26 +933,17 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
         key.n = dm.n;
         key.m = dm.m;
         key.d = dm.d;
-        std::memcpy(&key.p, p, sizeof(*p));
+        params_key(p, &key.p);
         if (int rc = replay_decode_io(b, key, y, x_out, dm.n, dm.m, s, issue)) return rc;
     } else {
         if (int rc = issue(s, y, x_out)) return rc;
     }
+    if (st_h) HIP_TRY(hipEventRecord(b->ev_call[1], s));
     HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[0];   // sub-iteration 2N decides last
-    if (st_h) {
-        st_h->iterations = fin.iterations;
-        st_h->accepted = fin.accepted;
-        st_h->l1_final_fx = fin.L_hat;
-        st_h->l1_final = static_cast<double>(fin.L_hat) / 1073741824.0;
-        st_h->l1_tol = dc->hc.tol;
-        st_h->converged = (static_cast<double>(fin.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
-        st_h->updates_total = ds.updates_total;
-        st_h->t_final = fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f;
-        st_h->error_flags = ds.err;
-    }
+    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f, b);
     return err_code_of(ds.err);
 }
 
@@ -1054,6 +1101,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
         HIP_TRY(rl0::launch_finish(dm, b->w, iter_params(dc, p, N), xq, q, true));
         return RL0_OK;
     };
+    if (st_h) HIP_TRY(hipEventRecord(b->ev_call[0], s));
     // per-iteration timing events cannot be recorded into a captured graph: a profiled
     // decode launches eagerly
     if (graphs_enabled() && !g_prof.enabled) {
@@ -1064,28 +1112,19 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
         key.n = n;
         key.m = m;
         key.d = d;
-        std::memcpy(&key.p, p, sizeof(*p));
+        params_key(p, &key.p);
         if (int rc = replay_decode_io(b, key, y, x_out, n, m, s, issue)) return rc;
     } else {
         if (int rc = issue(s, y, x_out)) return rc;
     }
+    if (st_h) HIP_TRY(hipEventRecord(b->ev_call[1], s));
     // the slots, counters and flags lead the device state
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[N & 1];
     profile_collect(N, fin.iterations, m > rl0::kPreRows);
-    if (st_h) {
-        st_h->iterations = fin.iterations;
-        st_h->accepted = fin.accepted;
-        st_h->l1_final_fx = fin.L_hat;
-        st_h->l1_final = static_cast<double>(fin.L_hat) / 1073741824.0;
-        st_h->l1_tol = dc->hc.tol;
-        st_h->converged = (static_cast<double>(fin.L_hat) <= dc->hc.tol * 1073741824.0) ? 1 : 0;
-        st_h->updates_total = ds.updates_total;
-        st_h->t_final = fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f;
-        st_h->error_flags = ds.err;
-    }
+    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b);
     return err_code_of(ds.err);
 }
 
@@ -1130,7 +1169,9 @@ int rl0_decode_batched(const rl0_problem* probs_h, int32_t count, rl0_stats* st_
     if (count == 0) return RL0_OK;
     const rl0_batch_schedule sc = schedule_of(plan.device);
     if (int rc = upload_batch(probs_h, plan, sc, s)) return rc;
+    HIP_TRY(hipEventRecord(plan.b->ev_call[0], s));
     if (int rc = run_batch(plan, sc, probs_h, s, false)) return rc;
+    HIP_TRY(hipEventRecord(plan.b->ev_call[1], s));
     return collect_batch(probs_h, plan, st_h, s);
 }
 
@@ -1351,6 +1392,25 @@ int rl0_mlp_train(const float* feats, const float* labels, int64_t N, int32_t d,
         for (int i = cfg->steps - tail; i < cfg->steps; ++i) acc += mb->host_losses[i];
         *loss_h = tail > 0 ? static_cast<float>(acc / tail) : 0.0f;
     }
+    return RL0_OK;
+}
+
+int rl0_mlp_adam(float* w, const float* grad, float* adam_m, float* adam_v, int32_t d, int32_t t,
+                 const rl0_train_cfg* cfg, void* stream) {
+    if (!cfg) return fail(RL0_EINVAL, "cfg is NULL");
+    if (d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "d must be in [1, 16]");
+    if (t < 1) return fail(RL0_EINVAL, "t must be >= 1");
+    if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+        !(cfg->eps > 0.0f))
+        return fail(RL0_EINVAL, "Adam settings out of range");
+    if (!w || !grad || !adam_m || !adam_v) return fail(RL0_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), static_cast<double>(t)));
+    const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), static_cast<double>(t)));
+    HIP_TRY(rl0::launch_mlp_adam(w, grad, adam_m, adam_v, rl0::mlp_params(d), cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
+                                 c1, c2, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return RL0_OK;
 }
 

@@ -41,6 +41,8 @@ class Params(ctypes.Structure):
         ("posterior", ctypes.c_int32),
         ("mlp", ctypes.c_void_p),
         ("validate", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("adaptive_k", ctypes.c_int32),
     ]
 
 
@@ -55,10 +57,23 @@ class Stats(ctypes.Structure):
         ("l1_tol", ctypes.c_double),
         ("t_final", ctypes.c_float),
         ("error_flags", ctypes.c_int32),
+        ("ms_total", ctypes.c_float),
+        ("fx_inexact_y", ctypes.c_int32),
+        ("fx_inexact_x", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# stats fields that depend only on the inputs (ms_total is a timing), and of those the
+# ones a batched decode reports too (it does not count fixed-point roundings)
+DETERMINISTIC_STATS = tuple(f for f, _ in Stats._fields_ if f != "ms_total")
+LOOP_STATS = tuple(f for f in DETERMINISTIC_STATS if not f.startswith("fx_inexact"))
+
+
+def stats_subset(st: dict, fields=DETERMINISTIC_STATS) -> dict:
+    return {f: st[f] for f in fields}
 
 
 class Constants(ctypes.Structure):
@@ -170,12 +185,13 @@ def lib() -> ctypes.CDLL:
         L.rl0_mlp_train.argtypes = [P, P, I64, I32, P, P, P, ctypes.POINTER(TrainCfg),
                                     ctypes.POINTER(ctypes.c_float), V]
         L.rl0_mlp_forward.argtypes = [P, I32, I32, P, P, I32, V]
+        L.rl0_mlp_adam.argtypes = [P, P, P, P, I32, I32, ctypes.POINTER(TrainCfg), V]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
                      "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get",
                      "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_mlp_init", "rl0_mlp_features",
-                     "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward"):
+                     "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -499,6 +515,17 @@ def mlp_train(feats, labels, w, m, v, steps: int, t0: int = 0, lr: float = 1e-3,
                                _dev_ptr(v, torch.float32, None, "v"), ctypes.byref(cfg), ctypes.byref(loss),
                                _stream()))
     return loss.value
+
+
+def mlp_adam(w, grad, m, v, d: int, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8) -> None:
+    """rl0_mlp_adam: one Adam update of (w, m, v) in place with the gradient grad at step t."""
+    torch = _torch()
+    P = mlp_num_params(d)
+    cfg = TrainCfg(lr, beta1, beta2, eps, 1.0, 1, 1, 0)
+    _check(lib().rl0_mlp_adam(_dev_ptr(w, torch.float32, (P,), "w"), _dev_ptr(grad, torch.float32, (P,), "grad"),
+                              _dev_ptr(m, torch.float32, (P,), "m"), _dev_ptr(v, torch.float32, (P,), "v"), d, t,
+                              ctypes.byref(cfg), _stream()))
 
 
 def mlp_forward(feats, w, bf16: bool = True):

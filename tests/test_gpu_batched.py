@@ -128,7 +128,7 @@ def test_batched_uneven_against_single_decode(seed):
     for inst, pr, st in zip(insts, probs, stats):
         x1, st1 = R.decode(pr["A"], pr["y"], sigma=inst.sigma, k=inst.k)
         assert np.array_equal(host(pr["out"]), host(x1))
-        assert st == st1
+        assert R.stats_subset(st, R.LOOP_STATS) == R.stats_subset(st1, R.LOOP_STATS)
 
 
 def test_batched_schedules_do_not_change_results():
@@ -145,7 +145,7 @@ def test_batched_schedules_do_not_change_results():
             if ref is None:
                 ref = (outs, stats)
             else:
-                assert stats == ref[1]
+                assert [R.stats_subset(a) for a in stats] == [R.stats_subset(b) for b in ref[1]]
                 for a, b in zip(outs, ref[0]):
                     assert np.array_equal(a, b)
     finally:

@@ -75,7 +75,7 @@ def test_large_decode_properties(large):
     x2, st2 = R.decode(A_t, y_t, params=params)
     a, b = host(x1), host(x2)
     print("decode stats", st1, flush=True)
-    assert np.array_equal(a, b) and st1 == st2
+    assert np.array_equal(a, b) and R.stats_subset(st1) == R.stats_subset(st2)
     assert np.count_nonzero(a) <= k
     r = D.residual(inst.A_cols, y, a, m)
     assert D.l1_fixed(r) == st1["l1_final_fx"]

@@ -237,3 +237,114 @@ def test_device_learned_decode_matches_the_stepwise_loop(n, m, k, snr, seed):
         xg, st = R.decode(A, yt, sigma=sig, k=k, mlp=wt)
         assert np.array_equal(host(xg), xe)
         assert st["l1_final_fx"] == Le and st["iterations"] == ie and st["accepted"] == ae
+
+
+def test_adam_update_matches_the_oracle():
+    """rl0_mlp_adam (the update rl0_mlp_train applies) against oracle.mlp.adam_step over
+    three steps with given gradients.  The device computes in float32, the oracle in fp64;
+    the bar on m and v is a few float32 roundings of the terms of each update (b1 m and
+    (1 - b1) g can cancel), carried over the steps, and on w its float32 rounding plus
+    the step's share of the error in m."""
+    d = 7
+    P = M.n_params(d)
+    rng = np.random.default_rng(61)
+    w = net(d, 61)
+    m = np.zeros(P, np.float32)
+    v = np.zeros(P, np.float32)
+    wt, mt, vt = dev(w), dev(m), dev(v)
+    wo, mo, vo = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    # the settings cross the C-ABI as float32: the oracle takes the same values
+    hp = {k: float(np.float32(x)) for k, x in dict(lr=1e-3, b1=0.9, b2=0.999, eps=1e-8).items()}
+    b1, b2, lr = hp["b1"], hp["b2"], hp["lr"]
+    u = 2.0 ** -24
+    em = np.zeros(P)
+    ev = np.zeros(P)
+    ew = np.zeros(P)
+    for t in (1, 2, 3):
+        g = (rng.normal(0, 1, P) * 10.0 ** rng.uniform(-4, 0, P)).astype(np.float32).astype(np.float64)
+        em = b1 * em + 4 * u * (b1 * np.abs(mo) + (1 - b1) * np.abs(g))
+        ev = b2 * ev + 4 * u * (b2 * vo + (1 - b2) * g * g)
+        R.mlp_adam(wt, dev(g.astype(np.float32)), mt, vt, d, t, lr=1e-3)
+        wo, mo, vo = M.adam_step(wo, g, mo, vo, t, **hp)
+        c1, c2 = 1 - b1 ** t, 1 - b2 ** t
+        den = np.sqrt(vo / c2) + hp["eps"]
+        step = lr * np.abs(mo) / c1 / den
+        ew = ew + 2 * u * np.abs(wo) + lr * (em / c1) / den + step * (8 * u + 0.5 * ev / np.maximum(vo, 1e-300))
+        gw, gm, gv = host(wt), host(mt), host(vt)
+        assert np.all(np.abs(gm - mo) <= em), t
+        assert np.all(np.abs(gv - vo) <= ev), t
+        assert np.all(np.abs(gw - wo) <= ew), t
+
+
+def test_training_steps_match_the_oracle():
+    """Three rl0_mlp_train steps (fp32 gradient, then Adam) against the fp64 oracle's
+    gradient and adam_step.  Where the oracle's gradient component is not small against
+    the largest one (the fp32 gradient is within 1e-4 of that largest component), the
+    steps are settled and the weights agree to 2e-2 of the learning rate; elsewhere (a
+    sign that fp32 rounding can flip) within the 2 lr a step can move."""
+    d, N, lr = 7, 4096, 1e-3
+    rng = np.random.default_rng(62)
+    w = net(d, 62)
+    F = rng.normal(0, 0.3, (3 * N, d + 1)).astype(np.float32)
+    Y = np.stack([(rng.random(3 * N) < 0.3).astype(np.float32), rng.normal(0, 1, 3 * N).astype(np.float32)], 1)
+    P = M.n_params(d)
+    wt, mt, vt = dev(w), torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda")
+    R.mlp_train(dev(F), dev(Y), wt, mt, vt, steps=3, lr=lr, batch=N)
+    wo, mo, vo = w.astype(np.float64), np.zeros(P), np.zeros(P)
+    hp = {k: float(np.float32(x)) for k, x in dict(lr=lr, b1=0.9, b2=0.999, eps=1e-8).items()}
+    settled = np.ones(P, bool)
+    for t in (1, 2, 3):
+        _, g = M.loss_and_grad(wo, F[(t - 1) * N:t * N], Y[(t - 1) * N:t * N], d, lam=1.0)
+        settled &= np.abs(g) > 0.05 * np.max(np.abs(g))
+        wo, mo, vo = M.adam_step(wo, g, mo, vo, t, **hp)
+    gw = host(wt)
+    print("settled components", int(settled.sum()), "of", P, flush=True)
+    assert settled.sum() >= 20
+    assert np.max(np.abs(gw - wo)[settled]) <= 2e-2 * lr
+    assert np.max(np.abs(gw - wo)) <= 2 * lr * 3
+
+
+def exact_net(d, sigma):
+    """A hand-set network whose every output that a decision lets through is the same,
+    bit for bit, in the oracle's bf16 emulation and on the matrix cores, whatever their
+    accumulation order.  s = 1/sigma is a power of two and f = bf16 of the column's median
+    residual (feature d // 2):
+      layer 1: u0 = s f - 8, u1 = -s f - 8, u2 = s f, u3 = -s f
+      layer 2: v_i = gelu(u_i) + 16, i < 4
+      layer 3: logit = v0 + v1 - 48, value = (v2 - v3) / s
+    A column updates when logit >= log(t / (1 - t)) >= -3.67, which needs s|f| >= 20.3.
+    Every GELU input is then >= 12 in magnitude, where both GELUs give u or 0 to float32
+    precision, so the outputs are sums of bf16 numbers times dyadic weights, exact in fp32.
+    Where s|f| < 16 the logit is below -7.9, far from every threshold."""
+    w = np.zeros(M.n_params(d), np.float32)
+    W1, b1, W2, b2, W3, b3 = M.unpack(w, d)
+    s = np.float32(1.0 / sigma)
+    mid = d // 2
+    W1[0, mid], b1[0] = s, -8.0
+    W1[1, mid], b1[1] = -s, -8.0
+    W1[2, mid] = s
+    W1[3, mid] = -s
+    for i in range(4):
+        W2[i, i], b2[i] = 1.0, 16.0
+    W3[0, 0], W3[0, 1], b3[0] = 1.0, 1.0, -48.0
+    W3[1, 2], W3[1, 3] = 1.0 / s, -1.0 / s
+    return w
+
+
+@pytest.mark.parametrize("n,m,k,seed", [(4096, 1024, 80, 71), (8192, 2048, 160, 72)])
+def test_device_learned_decode_matches_the_oracle(n, m, k, seed):
+    """The whole learned decode (Alg. 1 with the learned decision, the analytic retry at
+    the same t when a learned iteration is not accepted) on the device against
+    oracle.mlp.learned_decode, bitwise, with the exactly evaluated network above."""
+    d = 7
+    sig = 2.0 ** -7
+    inst = I.draw_instance(n, m, k, d, sig, seed)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    w = exact_net(d, sig)
+    C = D.make_constants(n, m, d, k, sig)
+    xo, io, ao, Lo = M.learned_decode(inst.A_cols, y, C, w)
+    xg, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=dev(w))
+    print(f"n={n}: oracle iterations {io}, accepted {ao}; gpu {st['iterations']}, {st['accepted']}", flush=True)
+    assert ao > 0
+    assert np.array_equal(host(xg), xo)
+    assert st["iterations"] == io and st["accepted"] == ao and st["l1_final_fx"] == Lo

@@ -60,6 +60,8 @@ def assert_same_decode(xg, stg, res):
     assert stg["l1_final_fx"] == res.L_hat
     assert stg["converged"] == int(res.converged)
     assert stg["updates_total"] == res.updates_total
+    assert stg["fx_inexact_y"] == res.fx_inexact_y
+    assert stg["fx_inexact_x"] == res.fx_inexact_x
 
 
 # ------------------------------------------------------------------ sketch
@@ -283,7 +285,7 @@ def test_decode_zero_signal_and_determinism():
     inst, x, y, sig = problem(2 ** 17, 13107, 1310, 7, 40, 9)
     a, sa = gpu_decode(inst, y, sig)
     b, sb = gpu_decode(inst, y, sig)
-    assert np.array_equal(a, b) and sa == sb
+    assert np.array_equal(a, b) and R.stats_subset(sa) == R.stats_subset(sb)
 
 
 def test_decode_replay_into_the_same_buffers():
@@ -345,8 +347,9 @@ def _golden_cases():
 
 @pytest.mark.parametrize("fname", _golden_cases())
 def test_decode_full_size_against_stored_oracle(fname):
-    """n = 2^20, m = n/10, k = m/10, d = 7 at 20/40/60 dB, and the large-m cases (m above
-    393216, d = 8; one decoded with k below the signal's sparsity so that H_k selects):
+    """n = 2^20, m = n/10, k = m/10, d = 7 at 20/40/60 dB (five seeds each), the large-m
+    cases (m above 393216, d = 8; one decoded with k below the signal's sparsity so that
+    H_k selects) and the large workload n = 2^24, m = 2^21, d = 8, k = 2^18 at 40 dB:
     identical support and rel-l2 <= 1e-5 against the oracle's decode (stored by
     tests/golden/make_golden.py); the contract makes it bitwise."""
     g = np.load(os.path.join(GOLDEN, fname))
@@ -356,7 +359,7 @@ def test_decode_full_size_against_stored_oracle(fname):
     print(f"golden {fname}", flush=True)
     inst = I.draw_instance(n, m, k, d, sig, int(g["seed"]))
     x = inst.x_dense()
-    y = D.measure(inst.A_cols, x, inst.eta, m)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)   # only supp(x) adds to A x
     x_hat, stg = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k_dec)
     xg = host(x_hat)
     supp = np.nonzero(xg)[0]
