@@ -124,6 +124,18 @@ int rl0_compute_constants(const rl0_params* p_h, int32_t n, int32_t m, int32_t d
 int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* x,
                float* y, void* stream);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc): rl0_sketch with the same arguments, results and errors, whose
+ * scratch memory (the 64-bit sums, 8 bytes per row, and the error flags) is a fixed array
+ * of the library's, one per GPU, held until the process ends.  It calls no allocating
+ * routine.  m must be <= RL0_SKETCH_STATIC_MAX_M (else RL0_EINVAL).  Calls on one GPU share
+ * that array: the library serialises its own calls (each synchronises its stream before
+ * returning), but two processes' arrays are their own, and calls that overlap on one GPU
+ * from outside that order race.  Synchronises the stream. */
+#define RL0_SKETCH_STATIC_MAX_M 2097152
+int rl0_sketch_static(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* x,
+                      float* y, void* stream);
+
 /* Device-side check of A_cols: RL0_EINDEX if any index is outside [0, m) or a column
  * is not strictly ascending.  Synchronises the stream. */
 int rl0_validate(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, void* stream);

@@ -23,6 +23,7 @@
 #include "kernels.h"
 #include "batched.h"
 #include "mlp.h"
+#include "noalloc.h"
 
 namespace {
 
@@ -1074,6 +1075,25 @@ int rl0_sketch(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     HIP_TRY(hipMemcpyAsync(b->st_host, b->w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return err_code_of(b->st_host->err);
+}
+
+int rl0_sketch_static(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* x, float* y,
+                      void* stream) {
+    static_assert(RL0_SKETCH_STATIC_MAX_M == rl0::kStaticSketchRows, "scratch rows");
+    if (int rc = check_dims(n, m, d)) return rc;
+    if (!A_cols || !x || !y) return fail(RL0_EINVAL, "NULL pointer");
+    if (m > RL0_SKETCH_STATIC_MAX_M) return fail(RL0_EINVAL, "m exceeds RL0_SKETCH_STATIC_MAX_M");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    long long* scr = nullptr;
+    HIP_TRY(rl0::static_scratch(&scr));
+    int* err = reinterpret_cast<int*>(scr + rl0::kStaticSketchRows);
+    HIP_TRY(rl0::launch_zero_i32(err, 1, s));   // the flags keep the last call's value
+    HIP_TRY(rl0::launch_sketch(A_cols, n, m, d, x, y, scr, err, s));
+    int flags = 0;
+    HIP_TRY(hipMemcpyAsync(&flags, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return err_code_of(flags);
 }
 
 int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float* y,

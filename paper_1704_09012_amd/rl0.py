@@ -160,6 +160,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_params_default.argtypes = [ctypes.POINTER(Params), I32, I32, I32, I32, ctypes.c_float]
         L.rl0_compute_constants.argtypes = [ctypes.POINTER(Params), I32, I32, I32, ctypes.POINTER(Constants), P, P]
         L.rl0_sketch.argtypes = [P, I32, I32, I32, P, P, V]
+        L.rl0_sketch_static.argtypes = [P, I32, I32, I32, P, P, V]
         L.rl0_validate.argtypes = [P, I32, I32, I32, V]
         L.rl0_decode.argtypes = [P, I32, I32, I32, P, ctypes.POINTER(Params), P, ctypes.POINTER(Stats), V]
         L.rl0_step.argtypes = [P, I32, I32, I32, P, ctypes.POINTER(Params), I32, P, P,
@@ -188,7 +189,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_mlp_adam.argtypes = [P, P, P, P, I32, I32, ctypes.POINTER(TrainCfg), V]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
-        for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_validate",
+        for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_sketch_static", "rl0_validate",
                      "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get",
                      "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_mlp_init", "rl0_mlp_features",
                      "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam"):
@@ -283,6 +284,20 @@ def sketch(A_cols, x, m: int, out=None):
     _check(lib().rl0_sketch(_dev_ptr(A_cols, torch.int32, (n, d), "A_cols"), n, m, d,
                             _dev_ptr(x, torch.float32, (n,), "x"), _dev_ptr(y, torch.float32, (m,), "y"),
                             _stream()))
+    return y
+
+
+RL0_SKETCH_STATIC_MAX_M = 2097152
+
+
+def sketch_static(A_cols, x, m: int, out=None):
+    """y = A x through rl0_sketch_static (no allocation; m <= RL0_SKETCH_STATIC_MAX_M)."""
+    torch = _torch()
+    n, d = A_cols.shape
+    y = out if out is not None else torch.empty(m, dtype=torch.float32, device=x.device)
+    _check(lib().rl0_sketch_static(_dev_ptr(A_cols, torch.int32, (n, d), "A_cols"), n, m, d,
+                                   _dev_ptr(x, torch.float32, (n,), "x"), _dev_ptr(y, torch.float32, (m,), "y"),
+                                   _stream()))
     return y
 
 
