@@ -199,7 +199,7 @@ struct GraphEntry {
     unsigned long long last_use = 0;
 };
 
-constexpr size_t kMaxGraphs = 16;   // per workspace; least recently used is dropped
+constexpr size_t kMaxGraphs = 64;   // per workspace; least recently used is dropped
 
 struct Buffers {
     int cap_n = 0, cap_m = 0;
