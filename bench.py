@@ -75,11 +75,11 @@ def iteration_bytes(n: int, m: int, d: int, k: int, u: float) -> float:
 def _oracle_sample(args) -> tuple[int, float]:
     """One process of the CPU baseline: the oracle's first loop iterations of the seeded
     instance, as many as fit in budget_s seconds; returns (iterations, seconds)."""
-    n, m, k, d, sigma, seed, budget_s = args
+    n, m, k, d, sigma, seed, budget_s, variant = args
     from oracle import decoder as D
     inst = I.draw_instance(n, m, k, d, sigma, seed)
     y_hat = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-    C = D.make_constants(n, m, d, k, sigma)
+    C = D.make_constants(n, m, d, k, sigma, variant=variant)
     st = D.init_state(y_hat, n)
     t0 = time.perf_counter()
     done = 0
@@ -91,14 +91,14 @@ def _oracle_sample(args) -> tuple[int, float]:
     return done, time.perf_counter() - t0
 
 
-def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 8) -> dict:
+def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 8, variant: int = 0) -> dict:
     """The oracle (test infrastructure) timed on the host: single-threaded numpy, first on
     one core, then `procs` processes at once on different seeds (the aggregate rate)."""
     import multiprocessing as mp
 
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    done1, dt1 = _oracle_sample((n, m, k, d, sigma, seeds[0], budget_s))
+    done1, dt1 = _oracle_sample((n, m, k, d, sigma, seeds[0], budget_s, variant))
     rate1 = d * n * done1 / dt1
     try:
         avail = len(os.sched_getaffinity(0))
@@ -107,7 +107,8 @@ def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 
     procs = max(1, min(procs, avail))
     ctx = mp.get_context("spawn")
     with ctx.Pool(procs) as pool:
-        res = pool.map(_oracle_sample, [(n, m, k, d, sigma, seeds[i % len(seeds)], budget_s) for i in range(procs)])
+        res = pool.map(_oracle_sample,
+                       [(n, m, k, d, sigma, seeds[i % len(seeds)], budget_s, variant) for i in range(procs)])
     agg = sum(d * n * it / t for it, t in res)
     its = [it for it, _ in res]
     return {"value": agg, "unit": "nnz(A)-updates/s", "cores": procs, "kind": "oracle",
@@ -256,7 +257,7 @@ def bench_batched(args) -> int:
 
 
 def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int, workload: str,
-                 cpu: bool) -> int:
+                 cpu: bool, variant: int = 0) -> int:
     """Single decodes of `seeds` seeded instances of GM(N, M, K, DD) at SNR 40 dB, step i on
     seed i mod seeds (sketch + decode, graph replay), then the same steps again with HIP
     events on every loop kernel for the roofline."""
@@ -276,7 +277,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
             "eta": torch.from_numpy(inst.eta).to(dev),
         })
         del inst
-    params = R.params_default(N, M, DD, K, sigma)
+    params = R.params_default(N, M, DD, K, sigma, variant=variant)
     y = torch.empty(M, dtype=torch.float32, device=dev)
     y_hat = torch.empty(M, dtype=torch.float32, device=dev)
     x_hat = torch.empty(N, dtype=torch.float32, device=dev)
@@ -339,8 +340,11 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     achieved = B_it / sweep_avg_s / 1e9
     large = (M + 31) // 32 > 12288
     packed = DD <= 4 or M <= 2 ** (128 // DD)
+    metric = METRIC if (N, DD) == (2 ** 20, 7) else f"Robust-l0 nnz(A)-updates/s and time-to-solution, n={N} d={DD}"
+    if variant == 1:
+        metric = metric.replace("Robust-l0", "Robust-l0-quantised", 1)
     out = {
-        "metric": METRIC if (N, DD) == (2 ** 20, 7) else f"Robust-l0 nnz(A)-updates/s and time-to-solution, n={N} d={DD}",
+        "metric": metric,
         "value": value,
         "unit": "nnz(A)-updates/s",
         "n_gpus": 1,
@@ -358,6 +362,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "n": N, "m": M, "d": DD, "k": K, "snr_db": SNR, "seeds": seeds,
+                   "scores": "quantised" if variant == 1 else "continuous",
                    "setup": "one untimed decode per instance captures its graph before the warm-up; "
                             "y_hat and x_hat are fixed device buffers; the host constants of the "
                             "parameter set (score tables, thresholds) are computed once and cached"},
@@ -381,7 +386,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     }
     if cpu:
         del insts
-        out["cpu_baseline"] = cpu_baseline(N, M, K, DD, sigma, seed_ids[:8])
+        out["cpu_baseline"] = cpu_baseline(N, M, K, DD, sigma, seed_ids[:8], variant=variant)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -393,7 +398,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seeds", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "batched", "learned", "large"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batched", "learned", "large", "quantised"],
+                    default="headline",
                     help="batched: 512 uneven instances in one persistent launch, against "
                          "sequential single decodes of the same instances")
     ap.add_argument("--batch", type=int, default=512)
@@ -417,6 +423,11 @@ def main() -> int:
         return bench_decode(args, 2 ** 24, 2 ** 21, 2 ** 18, 8, 3, min(args.seeds, 3),
                             "Robust-l0 decode of y_hat = A x + eta, n=2^24, m=2^21, d=8, k=2^18 N(0,1) "
                             "nonzeros, SNR 40 dB; step = sketch + decode", cpu=False)
+    if args.workload == "quantised":
+        return bench_decode(args, N, M, K, DD, 6, args.seeds,
+                            "Robust-l0-quantised decode of y_hat = A x + eta, n=2^20, m=104857, d=7, "
+                            "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode",
+                            cpu=not args.no_cpu_baseline, variant=1)
     return bench_decode(args, N, M, K, DD, 2, args.seeds,
                         "Robust-l0 decode of y_hat = A x + eta, n=2^20, m=104857, d=7, "
                         "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode",

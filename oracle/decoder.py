@@ -51,6 +51,13 @@ Float32 contract (both this oracle and the GPU follow it, so their bits agree):
   * ||r||_1 is the integer L(r) = sum_i rint(2^30 |r_i|) (unit 2^-30), accepted on a
     strict decrease.
 
+Quantised scores (Table "scores", middle column; Alg. 1's quantised flag): the weights
+become indicators of the same tabulated scores, taken in float32,
+      q_z(v) = 1{Tz(|v|) >= fl32(1 - t)},   q_e(a) = 1{Te(|a|) >= t}   (w_pp = 1 as before),
+so n_e and n_z count rows and omega is the mean of the rows agreeing with row p; the
+outer test is unchanged, and c = 0 selects eq:finetune_c_quant.  At t = 1 every row
+counts as a zero (q_z = 1), so iteration 0 updates nothing.
+
 With sigma = 0 the scores are Parallel-l0's indicators and the same loop is Alg. 2
 with its one-update-per-column rule (exact recovery check, Thm. "Convergence of
 Algorithm 2").
@@ -105,17 +112,20 @@ class Constants:
     Tz: _scores.Table
     Te: _scores.Table
     l1_test: int = 0
+    variant: int = 0          # 0 continuous scores, 1 quantised (indicator) scores
 
 
 def make_constants(n, m, d, k, sigma, sigma_s=1.0, alpha=2.0, c=0.0, ell=4,
-                   max_iters=0, l1_test=0) -> Constants:
+                   max_iters=0, l1_test=0, variant=0) -> Constants:
     """Alg. 1 prologue: p_breve_z, p_breve_e for GM(n, m, k, d, N(0,ss^2), N(0,sn^2))."""
     # Alg. 1 takes the consensus level alpha from (1, d]
     if not (1.0 < alpha <= d):
         raise ValueError("alpha must be in (1, d]")
+    if variant not in (0, 1):
+        raise ValueError("variant must be 0 (continuous) or 1 (quantised)")
     rho = k / m
     if c == 0.0:
-        c = _scores.c_rule(m / n)
+        c = _scores.c_rule(m / n, rho, quantised=variant == 1)
     n_it = _scores.n_iters(c)
     if max_iters > 0:
         n_it = min(n_it, max_iters)
@@ -123,7 +133,7 @@ def make_constants(n, m, d, k, sigma, sigma_s=1.0, alpha=2.0, c=0.0, ell=4,
     Te = _scores.build_table("e", d, rho, sigma, sigma_s, ell)
     return Constants(n=n, m=m, d=d, k=k, sigma=float(sigma), sigma_s=float(sigma_s),
                      alpha=np.float32(alpha), c=float(c), n_iters=n_it,
-                     tol=_scores.tolerance(m, sigma), Tz=Tz, Te=Te, l1_test=l1_test)
+                     tol=_scores.tolerance(m, sigma), Tz=Tz, Te=Te, l1_test=l1_test, variant=variant)
 
 
 # ----------------------------------------------------------------------------- fixed point
@@ -192,13 +202,16 @@ def sweep(A_cols, r_hat, x_hat, t, C: Constants) -> SweepOut:
     f32 = np.float32
     V = np.asarray(r_hat, dtype=np.float32)[A_cols]          # v_p = r_hat[row_p]
     absV = np.abs(V)
+    t = f32(t)
     Z = np.stack([_scores.lookup(C.Tz, absV[:, p]) for p in range(d)], axis=1)
-    n_z = Z[:, 0].copy()
+    quant = C.variant == 1 and not C.Tz.exact
+    # the z-weights: the score itself, or its indicator at level 1 - t (quantised)
+    Zw = (Z >= (f32(1.0) - t).astype(f32)).astype(f32) if quant else Z
+    n_z = Zw[:, 0].copy()
     S1 = absV[:, 0].copy()
     for p in range(1, d):
-        n_z = (n_z + Z[:, p]).astype(f32)
+        n_z = (n_z + Zw[:, p]).astype(f32)
         S1 = (S1 + absV[:, p]).astype(f32)
-    t = f32(t)
     has = np.zeros(n, dtype=bool)
     best_ne = np.zeros(n, dtype=f32)
     best_om = np.zeros(n, dtype=f32)
@@ -212,6 +225,8 @@ def sweep(A_cols, r_hat, x_hat, t, C: Constants) -> SweepOut:
                 w = np.ones(n, dtype=f32)
             else:
                 w = _scores.lookup(C.Te, np.abs((V[:, p] - V[:, l]).astype(f32)))
+                if quant:
+                    w = (w >= t).astype(f32)
             n_e = (n_e + w).astype(f32)
             s = (s + (V[:, l] * w).astype(f32)).astype(f32)
         omega = (s / n_e).astype(f32)

@@ -24,10 +24,13 @@ struct BatchProblem {
     const float* Tz;         // score tables, kTableN + 1 entries each
     const float* Te;
     const uint32_t* tau;     // [n_iters] outer-test threshold bits per iteration
+    const uint32_t* qe;      // [n_iters] quantised-score thresholds per iteration (quant = 1)
+    const uint32_t* qz;
     double tol_fx;           // stopping tolerance in units of 2^-30
     int n, m, d, k;
     float alpha, inv_h_z, inv_h_e;
     int exact, l1_test, validate, n_iters;
+    int quant;               // quantised scores (Table "scores", middle column)
     int cols;                // columns per thread per tile: 1, 2 or 4 (the schedule)
     uint32_t e_zero_bits;    // |a| >= this (float bits)  =>  e-score 0
 };

@@ -370,13 +370,19 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             sh.nzd = 0;
         }
         __syncthreads();
-        // ---- 2. sweep
+        // ---- 2. sweep (with this iteration's quantised-score thresholds)
+        ScoreTables tbi = tb;
+        if (P.quant) {
+            tbi.quant = 1;
+            tbi.qe_bits = P.qe[it];
+            tbi.qz_bits = P.qz[it];
+        }
         if (P.cols == 1)
-            wg_sweep<D, BLOCK, 1>(P, tb, bm, it, sh);
+            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh);
         else if (P.cols == 2)
-            wg_sweep<D, BLOCK, 2>(P, tb, bm, it, sh);
+            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh);
         else
-            wg_sweep<D, BLOCK, 4>(P, tb, bm, it, sh);
+            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh);
         __syncthreads();
         updates += sh.nupd;
         // ---- 3. H_k

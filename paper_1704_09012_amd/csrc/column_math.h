@@ -78,7 +78,10 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
     float S1 = 0.0f;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
-        n_z = n_z + score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v[p]));
+        // quantised: the indicator 1{p_breve_z(v) >= 1 - t}, a threshold on |v|
+        const float z = tb.quant ? (abs_bits(v[p]) <= tb.qz_bits ? 1.0f : 0.0f)
+                                 : score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v[p]));
+        n_z = n_z + z;
         S1 = S1 + fabsf(v[p]);
     }
     bool has = false;
@@ -94,14 +97,22 @@ __device__ __forceinline__ bool column_update(const float (&v)[D], unsigned int 
         // every e-score is at most 1 and is 0 once |v_p - v_l| reaches the end of the
         // table, so n_e <= 1 + (rows closer than that); when even that bound fails the
         // test, the candidate fails it (fp32 sums and differences are monotone)
+        // (quantised: near counts the rows with q_e = 1, so 1 + near is n_e itself)
         int near = 0;
+        const uint32_t e_bound = tb.quant ? tb.qe_bits + 1u : tb.e_zero_bits;
 #pragma unroll
-        for (int l = 0; l < D; ++l) near += (l != p && abs_bits(vp - v[l]) < tb.e_zero_bits) ? 1 : 0;
+        for (int l = 0; l < D; ++l) near += (l != p && abs_bits(vp - v[l]) < e_bound) ? 1 : 0;
         if (!((1.0f + static_cast<float>(near)) - n_z >= alpha)) continue;
         float n_e = 0.0f, s = 0.0f;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-            const float w = (l == p) ? 1.0f : score(tb.Te, tb.inv_h_e, tb.exact, fabsf(vp - v[l]));
+            float w;
+            if (l == p)
+                w = 1.0f;
+            else if (tb.quant)
+                w = abs_bits(vp - v[l]) <= tb.qe_bits ? 1.0f : 0.0f;   // 1{p_breve_e(a) >= t}
+            else
+                w = score(tb.Te, tb.inv_h_e, tb.exact, fabsf(vp - v[l]));
             n_e = n_e + w;
             s = s + v[l] * w;
         }

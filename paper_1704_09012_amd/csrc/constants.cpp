@@ -8,7 +8,9 @@
 //                                    the remainder, variance from Lemma "Sums of centred
 //                                    density functions"
 //   eq:breve                         normalisation by the maximum, attained at w = 0
-//   eq:finetune_c_cont               default decrement c of the t-sweep
+//   eq:finetune_c_cont / _quant      default decrement c of the t-sweep (continuous and
+//                                    quantised scores)
+//   Table "scores"                   quantised scores: indicators of the same posteriors
 //   Sec. 4 "Stopping conditions"     tolerance m sigma sqrt(2/pi)
 #include "constants.h"
 
@@ -130,13 +132,34 @@ static uint32_t outer_threshold_bits(const HostConstants& hc, float t) {
     return hi;
 }
 
-double c_rule(double delta) { return delta <= 0.05 ? 0.01 : 0.025; }
+// Largest non-negative float a with T(a) >= level, as its bit pattern: the tabulated score
+// is non-increasing in a, so the indicator 1{T(|a|) >= level} of the quantised scores is
+// the threshold bits(|a|) <= this.  T(0) = 1 >= level for every level <= 1.
+static uint32_t indicator_threshold_bits(const float* T, float inv_h, float level) {
+    uint32_t lo = 0, hi = 0x7F800000u;   // T(lo) >= level; T(+inf) = 0
+    if (table_score(T, inv_h, u2f(hi)) >= level) return hi;
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (table_score(T, inv_h, u2f(mid)) >= level) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+double c_rule(double delta, double rho, bool quantised) {
+    if (delta <= 0.05) return 0.01;
+    if (!quantised) return 0.025;
+    if (rho <= 0.1) return 0.05;
+    if (rho <= 0.2) return 0.075;
+    return 0.1;
+}
 
 int iterations_for(double c) { return static_cast<int>(std::ceil(1.0 / c - 1e-9)); }
 
 bool compute_constants(const Problem& pr, HostConstants* hc) {
     hc->exact = (pr.sigma == 0.0);
-    hc->c = pr.c > 0.0 ? pr.c : c_rule(static_cast<double>(pr.m) / pr.n);
+    hc->quant = pr.variant == 1 && !hc->exact;   // sigma = 0: Parallel-l0's indicators either way
+    hc->c = pr.c > 0.0 ? pr.c
+                       : c_rule(static_cast<double>(pr.m) / pr.n, static_cast<double>(pr.k) / pr.m, pr.variant == 1);
     hc->n_iters = iterations_for(hc->c);
     if (pr.max_iters > 0 && pr.max_iters < hc->n_iters) hc->n_iters = pr.max_iters;
     hc->tol = pr.m * pr.sigma * std::sqrt(2.0 / M_PI);
@@ -154,9 +177,15 @@ bool compute_constants(const Problem& pr, HostConstants* hc) {
     }
     hc->t.resize(hc->n_iters);
     hc->tau_bits.resize(hc->n_iters);
+    hc->qe_bits.assign(hc->n_iters, 0u);
+    hc->qz_bits.assign(hc->n_iters, 0u);
     for (int it = 0; it < hc->n_iters; ++it) {
         hc->t[it] = static_cast<float>(1.0 - it * hc->c);
         hc->tau_bits[it] = outer_threshold_bits(*hc, hc->t[it]);
+        if (hc->quant) {
+            hc->qe_bits[it] = indicator_threshold_bits(hc->table_e, hc->inv_h_e, hc->t[it]);
+            hc->qz_bits[it] = indicator_threshold_bits(hc->table_z, hc->inv_h_z, 1.0f - hc->t[it]);
+        }
     }
     // smallest |difference| whose e-score is 0 (the table ends): bits of that float
     if (hc->exact) {

@@ -14,6 +14,7 @@ struct Problem {
     double c = 0.0;
     int ell = 4;
     int max_iters = 0;
+    int variant = 0;   // 0 continuous scores, 1 quantised
 };
 
 struct HostConstants {
@@ -27,9 +28,12 @@ struct HostConstants {
     std::vector<float> t;            // t_it = fl32(1 - it c)
     std::vector<uint32_t> tau_bits;  // outer test threshold per iteration (float bits)
     uint32_t e_zero_bits = 0;        // |v_p - v_l| >= this  =>  e-score 0
+    bool quant = false;              // quantised scores (never with exact = true)
+    std::vector<uint32_t> qe_bits;   // per iteration: Te(a) >= t      iff bits(a) <= qe_bits
+    std::vector<uint32_t> qz_bits;   // per iteration: Tz(a) >= 1 - t  iff bits(a) <= qz_bits
 };
 
-double c_rule(double delta);
+double c_rule(double delta, double rho = 0.0, bool quantised = false);
 int iterations_for(double c);
 bool compute_constants(const Problem& pr, HostConstants* hc);
 float table_score(const float* T, float inv_h, float a);

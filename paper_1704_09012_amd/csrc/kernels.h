@@ -70,6 +70,10 @@ struct ScoreTables {
     float inv_h_z, inv_h_e;
     int exact;         // indicator scores (sigma = 0)
     uint32_t e_zero_bits;   // |a| >= this (float bits)  =>  e-score 0
+    // quantised scores of one iteration (Table "scores", middle column): q_e = 1 iff
+    // |a| <= qe_bits (float bits), q_z = 1 iff |v| <= qz_bits
+    int quant = 0;
+    uint32_t qe_bits = 0, qz_bits = 0;
 };
 
 struct IterParams {
@@ -83,6 +87,9 @@ struct IterParams {
     double tol_fx;        // tolerance in units of 2^-30 (negative: never converged)
     int step = 0;         // index of t in the schedule (= it, except in the learned decode)
     int retry = 0;        // 1: an analytic retry, skipped when the iteration before was accepted
+    int quant = 0;        // quantised scores, with this iteration's thresholds:
+    uint32_t qe_bits = 0; //   q_e(a) = 1 iff bits(|a|) <= qe_bits
+    uint32_t qz_bits = 0; //   q_z(v) = 1 iff bits(|v|) <= qz_bits
 };
 
 // Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.  x_hat

@@ -646,6 +646,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     ScoreTables lt = a.tb;
     lt.Tz = Tz;
     lt.Te = Te;
+    lt.quant = a.ip.quant;
+    lt.qe_bits = a.ip.qe_bits;
+    lt.qz_bits = a.ip.qz_bits;
 
     // ---- the decision picks: outer-test bitmask into LDS, S_trial = S_hat
     if (a.bm_lds) {

@@ -93,9 +93,11 @@ struct DeviceConstants {
     rl0::HostConstants hc;
     float* d_tables = nullptr;        // table_z, table_e (kTableStrideFloats apart), then tau
     const uint32_t* d_tau = nullptr;  // outer-test threshold bits per iteration
+    const uint32_t* d_qe = nullptr;   // quantised-score thresholds per iteration (after tau)
+    const uint32_t* d_qz = nullptr;
 };
 
-using ConstKey = std::tuple<int, int, int, int, int, uint32_t, uint32_t, double, int, int>;
+using ConstKey = std::tuple<int, int, int, int, int, uint32_t, uint32_t, double, int, int, int>;
 std::map<ConstKey, std::unique_ptr<DeviceConstants>> g_consts;
 
 uint32_t fbits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
@@ -104,22 +106,31 @@ uint32_t fbits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 // written with a blocking copy, so it is ready before any later launch.
 ConstKey key_of(const rl0::Problem& pr, int device) {
     return ConstKey{device, pr.n, pr.m, pr.d, pr.k, fbits(static_cast<float>(pr.sigma)),
-                    fbits(static_cast<float>(pr.sigma_s)), pr.c, pr.ell, pr.max_iters};
+                    fbits(static_cast<float>(pr.sigma_s)), pr.c, pr.ell, pr.max_iters, pr.variant};
 }
 
-// Device copy of computed constants: both tables and the thresholds in one allocation,
-// written with a blocking copy, so they are ready before any later launch.
+// Device copy of computed constants: both tables and the per-iteration thresholds (tau,
+// then the quantised-score thresholds qe and qz) in one allocation, written with a
+// blocking copy, so they are ready before any later launch.
 int upload_constants(DeviceConstants* dc) {
     const size_t tab = 2 * rl0::kTableStrideFloats * sizeof(float);
     const size_t ntau = dc->hc.tau_bits.size();
-    std::vector<char> staging(tab + sizeof(uint32_t) * (ntau ? ntau : 1), 0);
+    const size_t per = sizeof(uint32_t) * (ntau ? ntau : 1);
+    std::vector<char> staging(tab + 3 * per, 0);
     std::memcpy(staging.data(), dc->hc.table_z, (rl0::kTableN + 1) * sizeof(float));
     std::memcpy(staging.data() + rl0::kTableStrideFloats * sizeof(float), dc->hc.table_e,
                 (rl0::kTableN + 1) * sizeof(float));
-    if (ntau) std::memcpy(staging.data() + tab, dc->hc.tau_bits.data(), ntau * sizeof(uint32_t));
+    if (ntau) {
+        std::memcpy(staging.data() + tab, dc->hc.tau_bits.data(), ntau * sizeof(uint32_t));
+        std::memcpy(staging.data() + tab + per, dc->hc.qe_bits.data(), ntau * sizeof(uint32_t));
+        std::memcpy(staging.data() + tab + 2 * per, dc->hc.qz_bits.data(), ntau * sizeof(uint32_t));
+    }
     if (hipMalloc(&dc->d_tables, staging.size()) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(tables)");
     HIP_TRY(hipMemcpy(dc->d_tables, staging.data(), staging.size(), hipMemcpyHostToDevice));
-    dc->d_tau = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(dc->d_tables) + tab);
+    const char* base = reinterpret_cast<const char*>(dc->d_tables);
+    dc->d_tau = reinterpret_cast<const uint32_t*>(base + tab);
+    dc->d_qe = reinterpret_cast<const uint32_t*>(base + tab + per);
+    dc->d_qz = reinterpret_cast<const uint32_t*>(base + tab + 2 * per);
     return RL0_OK;
 }
 
@@ -303,7 +314,8 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     if (p->posterior == 1 && !p->mlp) return fail(RL0_ENOWEIGHTS, "learned posterior requested without weights");
     if (p->posterior == 1 && d + 1 > rl0::kMlpMaxFeatures)
         return fail(RL0_EINVAL, "the learned posterior supports d <= 15");
-    if (p->variant != 0) return fail(RL0_EINVAL, "variant must be 0 (continuous scores)");
+    if (p->variant != 0 && p->variant != 1)
+        return fail(RL0_EINVAL, "variant must be 0 (continuous scores) or 1 (quantised)");
     if (p->adaptive_k != 0) return fail(RL0_EINVAL, "adaptive_k is not supported (must be 0)");
     return RL0_OK;
 }
@@ -337,6 +349,7 @@ rl0::Problem problem_of(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     pr.c = static_cast<double>(p->c);
     pr.ell = p->series_terms;
     pr.max_iters = p->max_iters;
+    pr.variant = p->variant;
     return pr;
 }
 
@@ -443,6 +456,11 @@ rl0::IterParams iter_params(const DeviceConstants* dc, const rl0_params* p, int 
     ip.l1_test = p->l1_test;
     ip.n_iters = N;
     ip.tol_fx = dc->hc.tol * 1073741824.0;
+    ip.quant = dc->hc.quant ? 1 : 0;
+    if (ip.quant && it < N) {
+        ip.qe_bits = dc->hc.qe_bits[it];
+        ip.qz_bits = dc->hc.qz_bits[it];
+    }
     return ip;
 }
 
@@ -650,6 +668,9 @@ int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_s
         B.Tz = dc->d_tables;
         B.Te = dc->d_tables + rl0::kTableStrideFloats;
         B.tau = dc->d_tau;
+        B.qe = dc->d_qe;
+        B.qz = dc->d_qz;
+        B.quant = dc->hc.quant ? 1 : 0;
         B.tol_fx = dc->hc.tol * 1073741824.0;
         B.n = q.n;
         B.m = q.m;

@@ -6,12 +6,16 @@ Only the CPU oracle (oracle/) and the seeded instance generator are called.  Eac
 holds, for one seeded instance (Gaussian N(0,1) signal, Gaussian noise at the stated
 SNR), the oracle's recovered x_hat (support and values) and its loop statistics.  The
 workloads:
-  * n = 2^20, m = n/10, k = m/10, d = 7 at 20, 40 and 60 dB, two seeds each;
+  * n = 2^20, m = n/10, k = m/10, d = 7 at 20, 40 and 60 dB, five seeds each;
   * n = 2^20, m = n/2, k = m/8, d = 8 at 40 dB: the large workload's d and k/m at 1/16 of
     its n, with m above 393216 rows (the decoder's large-m paths);
   * n = 2^21, m = n/2, a signal of m/8 nonzeros decoded with k = m/16, d = 8 at 40 dB:
     every iteration then has more candidates than k, so H_k selects on the large-m
-    path, with boundary buckets of about 2 100 and 5 000 entries.
+    path, with boundary buckets of about 2 100 and 5 000 entries;
+  * the large workload itself: n = 2^24, m = 2^21, k = 2^18, d = 8 at 40 dB (sigma_n =
+    0.01), seed 30100.  Its oracle decode takes about half an hour on one core;
+  * the quantised variant (files decodeq_*) at n = 2^20, m = n/10, k = m/10, d = 7 at 20,
+    40 and 60 dB, one seed each (c from eq:finetune_c_quant: 0.05, 20 iterations).
 """
 from __future__ import annotations
 
@@ -34,32 +38,39 @@ M = N // 10
 K = M // 10
 DD = 7
 SNRS = (20, 40, 60)
-SEEDS_PER_SNR = 2
+SEEDS_PER_SNR = 5
 
 
 def case_name(snr: int, i: int) -> str:
     return f"decode_n1048576_d7_snr{snr}_i{i}.npz"
 
 
-# (file name, n, m, k of the signal, d, snr, seed, k of the decoder)
+# (file name, n, m, k of the signal, d, snr, seed, k of the decoder[, variant])
 CASES = [(case_name(snr, i), N, M, K, DD, snr, I.seed_for(2, si, i), K)
          for si, snr in enumerate(SNRS) for i in range(SEEDS_PER_SNR)]
+CASES += [(f"decodeq_n1048576_d7_snr{snr}_i0.npz", N, M, K, DD, snr, I.seed_for(6, si, 0), K, 1)
+          for si, snr in enumerate(SNRS)]
 CASES.append(("decode_n1048576_m524288_d8_snr40_i0.npz", N, N // 2, N // 16, 8, 40, I.seed_for(3, 1, 10), N // 16))
 CASES.append(("decode_n2097152_m1048576_d8_snr40_kdec65536_i0.npz", 2 * N, N, N // 8, 8, 40, I.seed_for(3, 1, 10),
               N // 16))
+CASES.append(("decode_n16777216_m2097152_d8_snr40_i0.npz", 2 ** 24, 2 ** 21, 2 ** 18, 8, 40, I.seed_for(3, 1, 0),
+              2 ** 18))
 
 
 def one(case):
-    name, n, m, k, d, snr, seed, k_dec = case
+    name, n, m, k, d, snr, seed, k_dec = case[:8]
+    variant = case[8] if len(case) > 8 else 0
     sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
     inst = I.draw_instance(n, m, k, d, sig, seed)
     x = inst.x_dense()
-    y = D.measure(inst.A_cols, x, inst.eta, m)
-    C = D.make_constants(n, m, d, k_dec, sig)
+    # only the support's columns contribute to A x
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+    C = D.make_constants(n, m, d, k_dec, sig, variant=variant)
     res = D.decode(inst.A_cols, y, C)
     supp = np.nonzero(res.x_hat)[0].astype(np.int32)
     path = os.path.join(HERE, name)
     np.savez_compressed(path, n=n, m=m, k=k, k_decode=k_dec, d=d, snr=snr, seed=seed, sigma=np.float32(sig),
+                        variant=variant, fx_inexact_y=res.fx_inexact_y, fx_inexact_x=res.fx_inexact_x,
                         support=supp, values=res.x_hat[supp].astype(np.float32),
                         iterations=res.iterations, accepted=res.accepted, L_hat=np.int64(res.L_hat),
                         converged=int(res.converged), updates_total=res.updates_total)
@@ -71,8 +82,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)
     ap.add_argument("--only", default="", help="write only the files whose name starts with this")
+    ap.add_argument("--missing", action="store_true", help="write only the files that do not exist yet")
     a = ap.parse_args()
     work = [c for c in CASES if c[0].startswith(a.only)]
+    if a.missing:
+        work = [c for c in work if not os.path.exists(os.path.join(HERE, c[0]))]
+    # the largest first, so that it does not start last
+    work.sort(key=lambda c: -c[1] * c[4])
     with ProcessPoolExecutor(a.jobs) as ex:
         for path, it, acc, err in ex.map(one, work):
             print(os.path.basename(path), "iterations", it, "accepted", acc, "rel_l2_vs_truth", f"{err:.3e}", flush=True)

@@ -44,7 +44,7 @@ def test_params_default_follow_the_paper():
 @pytest.mark.parametrize("field,value", [
     ("k", 0), ("k", 256), ("alpha", 1.0), ("alpha", 7.5), ("c", 1.0), ("c", -0.1),
     ("sigma", -1.0), ("sigma", float("nan")), ("sigma_signal", 0.0), ("series_terms", 0),
-    ("max_iters", -1), ("l1_test", 2), ("posterior", 3),
+    ("max_iters", -1), ("l1_test", 2), ("posterior", 3), ("variant", 2), ("variant", -1), ("adaptive_k", 1),
 ])
 def test_bad_params_are_rejected_on_the_host(field, value):
     p = R.params_default(1024, 256, 7, 25, 0.01)
@@ -111,6 +111,18 @@ def test_host_constants_equal_the_oracle(n, m, d, k, snr):
     assert hc.tol == pytest.approx(C.tol, rel=1e-15)
     ts = np.array([S.t_of(i, C.c) for i in range(C.n_iters)], np.float32)
     assert np.array_equal(hc.t, ts)
+
+
+@pytest.mark.parametrize("n,m,k,want", [(1024, 256, 25, 0.05), (1024, 256, 40, 0.075), (1024, 256, 60, 0.1),
+                                        (10000, 400, 60, 0.01)])
+def test_quantised_c_rule_on_the_host(n, m, k, want):
+    """eq:finetune_c_quant through rl0_compute_constants, as the oracle takes it."""
+    sig = float(np.float32(0.01))     # sigma crosses the C-ABI as float32
+    p = R.params_default(n, m, 7, k, sig, variant=1)
+    hc = R.compute_constants(p, n, m, 7)
+    C = D.make_constants(n, m, 7, k, sig, variant=1)
+    assert hc.c == want == C.c and hc.n_iters == C.n_iters
+    assert np.array_equal(hc.table_z, C.Tz.T) and np.array_equal(hc.table_e, C.Te.T)
 
 
 @pytest.mark.parametrize("n,m,d,k,snr", CONFIGS[:4])
