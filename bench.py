@@ -186,6 +186,45 @@ def bench_learned(args) -> int:
     return 0
 
 
+def bench_phase(args) -> int:
+    """Phase transitions for extreme subsampling (Sec. 4): the ladder of
+    paper_1704_09012_amd.phase for (delta, sigma) in {0.001, 0.01} x {0.001, 0.01} at n =
+    --phase-n, Robust-l0 and Robust-l0-quantised, 10 instances per rho drawn on the device;
+    reports the 50% point of the logistic fit and the largest rho with half recovered.
+    The paper states, for Robust-l0 at n = 2^22 -> 2^24: rho* ~ 0.08 -> 0.1 at delta =
+    sigma = 0.001, ~0.17 at delta = 0.01, sigma = 0.001 and ~0.12 at delta = sigma = 0.01."""
+    from paper_1704_09012_amd import phase as PH
+
+    t0 = time.perf_counter()
+    rows = []
+    for variant in (0, 1):
+        for delta in (0.001, 0.01):
+            for sigma in (0.001, 0.01):
+                res = PH.ladder(PH.gpu_trials, n=args.phase_n, delta=delta, sigma=sigma, variant=variant,
+                                trials=10, seed=int(1e6 * delta + 1e3 * sigma))
+                rows.append(res.as_dict())
+                print(json.dumps({"ladder": rows[-1]}), flush=True)
+    paper = {"(0.001, 0.001)": "0.08 (n=2^22) -> 0.1 (n=2^24)", "(0.01, 0.001)": "0.17",
+             "(0.01, 0.01)": "0.12"}
+    out = {
+        "metric": "Robust-l0 phase transition rho* (50% point of the logistic fit), extreme subsampling",
+        "value": next(r["rho50"] for r in rows if r["variant"] == 0 and r["delta"] == 0.01 and r["sigma"] == 0.001),
+        "unit": "rho* at delta=0.01, sigma=0.001",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ladders rho = 0.01, 0.02, ... with 10 GM instances each (N(0,1) signal, "
+                               f"N(0, sigma^2) noise, d=7), n={args.phase_n}; success = eq:success_condition_clip, "
+                               "C1 = 1", "n": args.phase_n},
+        "paper_rho_star_robust_l0": paper,
+        "ladders": rows,
+        "seconds": time.perf_counter() - t0,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_batched(args) -> int:
     """Batched decoding: `--batch` instances with n log-uniform in [2^12, 2^18], m/n in
     [0.05, 0.5], k/m in [0.05, 0.3], d = 7, SNR in [20, 60] dB.  The schedule is tuned
@@ -398,7 +437,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seeds", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "batched", "learned", "large", "quantised"],
+    ap.add_argument("--phase-n", type=int, default=2 ** 22, help="n of the phase-transition ladders")
+    ap.add_argument("--workload", choices=["headline", "batched", "learned", "large", "quantised", "phase"],
                     default="headline",
                     help="batched: 512 uneven instances in one persistent launch, against "
                          "sequential single decodes of the same instances")
@@ -416,6 +456,8 @@ def main() -> int:
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "phase":
+        return bench_phase(args)
     if args.workload == "learned":
         return bench_learned(args)
 

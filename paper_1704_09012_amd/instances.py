@@ -32,6 +32,7 @@ __all__ = [
     "draw_signal",
     "draw_noise",
     "draw_instance",
+    "draw_instance_device",
     "seed_for",
 ]
 
@@ -151,3 +152,33 @@ def draw_batch(count: int, seed: int, d: int = 7, **shape_kw) -> list[Instance]:
         sig = float(np.float32(sigma_for_snr(snr, n, m, k, d)))
         out.append(draw_instance(n, m, k, d, sig, seed * 100000 + i))
     return out
+
+
+def draw_instance_device(n: int, m: int, k: int, d: int, sigma: float, seed: int, device="cuda",
+                         sigma_s: float = 1.0):
+    """One instance of GM(n, m, k, d, N(0, sigma_s^2), N(0, sigma^2)) drawn on the device
+    with torch's generator seeded by `seed` (for experiments of many large instances,
+    where the host generator is the bottleneck; not the stream draw_instance gives).
+    Returns (A_cols int32 [n][d], x float32 [n], eta float32 [m]) device tensors; the
+    columns follow draw_columns' recipe: d iid rows, a column with a repeated row is
+    redrawn whole, rows sorted ascending."""
+    import torch
+
+    if not (0 < k < m) or not (0 < d <= m):
+        raise ValueError("need 0 < k < m and 0 < d <= m")
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    cols = torch.randint(0, m, (n, d), generator=g, device=device, dtype=torch.int64)
+    cols, _ = torch.sort(cols, dim=1)
+    while d > 1:
+        bad = torch.nonzero((cols[:, 1:] == cols[:, :-1]).any(dim=1)).flatten()
+        if bad.numel() == 0:
+            break
+        redraw = torch.randint(0, m, (bad.numel(), d), generator=g, device=device, dtype=torch.int64)
+        cols[bad] = torch.sort(redraw, dim=1)[0]
+    A = cols.to(torch.int32).contiguous()
+    support = torch.randperm(n, generator=g, device=device)[:k]
+    x = torch.zeros(n, dtype=torch.float32, device=device)
+    x[support] = torch.randn(k, generator=g, device=device, dtype=torch.float32) * float(sigma_s)
+    eta = torch.randn(m, generator=g, device=device, dtype=torch.float32) * float(sigma)
+    return A, x, eta
