@@ -241,7 +241,7 @@ def bench_batched(args) -> int:
         y = R.sketch(A, x, inst.m) + torch.from_numpy(inst.eta).cuda()
         probs.append({"A": A, "y": y, "sigma": inst.sigma, "k": inst.k, "x": x})
     batch = [{k: v for k, v in p.items() if k != "x"} for p in probs]
-    best, tuned_ms = R.autotune_batched(batch, reps=1)
+    best, tuned_ms = R.autotune_batched(batch, reps=2)
     for _ in range(args.warmup):
         stats = R.decode_batched(batch)
     torch.cuda.synchronize()
@@ -250,6 +250,9 @@ def bench_batched(args) -> int:
         stats = R.decode_batched(batch)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
+    t_start, t_end, groups = R.batch_timeline(len(batch))
+    busy = float(np.sum((t_end - t_start) * groups))          # workgroup-milliseconds
+    W = 256 * best["per_cu"]
     upd = sum(DD * inst.n * st["iterations"] for inst, st in zip(insts, stats))
     # algorithmic HBM bytes of every executed iteration: indices and one residual read
     algo = sum((4.0 * DD * inst.n + 8.0 * inst.m) * st["iterations"] for inst, st in zip(insts, stats))
@@ -282,6 +285,11 @@ def bench_batched(args) -> int:
                                "k/m U[0.05, 0.3], d=7, SNR U[20, 60] dB; step = one batched decode",
                    "instances": args.batch, "sum_n": int(sum(i.n for i in insts)), "d": DD},
         "schedule": best,
+        "timeline": {"span_ms": float(t_end.max() - t_start.min()), "mean_workgroup_busy_ms": busy / W,
+                     "span_over_mean_busy": float(t_end.max() - t_start.min()) / (busy / W),
+                     "instances_split": int(np.sum(groups > 1)), "largest_group": int(groups.max()),
+                     "note": "device clock of the last timed call; busy = sum of decode durations times "
+                             "group size over the resident workgroups"},
         "sequential_single_decodes_ms": 1e3 * t_seq,
         "speedup_vs_sequential": t_seq / t_batch,
         "identical_to_single_decodes": same,

@@ -194,12 +194,16 @@ typedef struct rl0_problem {
 } rl0_problem;
 
 /* How a batch runs: the launch shape, and per size class the columns each thread takes
- * per tile of the column sweep.  Results do not depend on it. */
+ * per tile of the column sweep and the number of workgroups that decode one instance
+ * together.  Results do not depend on it. */
 typedef struct rl0_batch_schedule {
     int32_t block;                      /* threads per workgroup: 256, 512 or 1024 */
     int32_t per_cu;                     /* resident workgroups per compute unit the
                                            persistent grid is sized for, 1..8 */
     int32_t cols[RL0_SIZE_CLASSES];     /* 1, 2 or 4 */
+    int32_t group[RL0_SIZE_CLASSES];    /* 1, 2, 4, 8 or 16 workgroups per instance (a group
+                                           splits each step's columns, rows and lists and
+                                           meets at bounded barriers; capped by the grid) */
 } rl0_batch_schedule;
 
 /* Decode count instances (probs_h: host array).  Every instance is checked as in
@@ -211,6 +215,13 @@ typedef struct rl0_batch_schedule {
  * are unaffected, and the call returns the first such error's code.  Uses the
  * calling device's current schedule. */
 int rl0_decode_batched(const rl0_problem* probs_h, int32_t count, rl0_stats* st_h, void* stream);
+
+/* Timeline of the last rl0_decode_batched (or autotuning run) on this device and stream,
+ * for its first `count` instances (host arrays, count entries each, any may be NULL):
+ * when each instance's decode began and ended on the device, in milliseconds after the
+ * earliest start, and how many workgroups decoded it.  RL0_EINVAL if there was no such
+ * call or count exceeds its instances. */
+int rl0_batch_timeline(int32_t count, double* start_ms_h, double* end_ms_h, int32_t* group_h, void* stream);
 
 /* The calling device's batch schedule (a default until set or tuned). */
 int rl0_batch_schedule_get(rl0_batch_schedule* out_h);

@@ -11,6 +11,8 @@ namespace rl0 {
 
 constexpr int kBatchMaxRows = 1 << 19;   // m of one instance: its outer-test bitmask sits in LDS
 
+struct BatchCtl;
+
 // One instance, as the persistent kernel reads it (device memory).
 struct BatchProblem {
     const int32_t* A;        // [n][d] row indices, ascending per column, 16-byte aligned
@@ -20,6 +22,7 @@ struct BatchProblem {
     float* xp;               // [n] workspace: x' (equals x_hat between iterations)
     int* stamp;              // [n] workspace: last iteration that put the column on the change list
     int* chg;                // [n] workspace: change list of the current iteration
+    int* chg2;               // [n] workspace: the second change list of a group (odd iterations)
     unsigned long long* keys;  // [n] workspace: H_k keys of the nonzero entries of x' 
     const float* Tz;         // score tables, kTableN + 1 entries each
     const float* Te;
@@ -31,14 +34,36 @@ struct BatchProblem {
     float alpha, inv_h_z, inv_h_e;
     int exact, l1_test, validate, n_iters;
     int quant;               // quantised scores (Table "scores", middle column)
+    int group;               // workgroups that decode the instance together (1 = alone)
+    BatchCtl* ctl;           // their shared state (group > 1)
     int cols;                // columns per thread per tile: 1, 2 or 4 (the schedule)
     uint32_t e_zero_bits;    // |a| >= this (float bits)  =>  e-score 0
 };
+
+// Shared state of the G workgroups that decode one instance together (device memory,
+// zeroed before every launch).  Counters that live for one iteration come in two copies,
+// by iteration parity: the copy of iteration it + 1 is cleared during iteration it.
+struct BatchCtl {
+    unsigned bar;            // barrier arrivals so far (all members)
+    int abort;               // a member's bounded wait timed out: every member leaves
+    int err;                 // ErrFlag bits of the instance
+    int nchg[2], nupd[2], nzd[2], nkeys[2];
+    long long L0;            // ||r||_1 of r = y, summed over the members
+    long long dl[2];         // change of ||r||_1 by the iteration's residual change
+    long long dsupp[2];      // change of |supp x'|
+    int pad[10];
+};
+static_assert(sizeof(BatchCtl) % 16 == 0, "BatchCtl keeps 16-byte alignment");
+
+// A ticket of the queue: instance index and member (part) of its group.
+constexpr int kTicketParts = 32;   // tickets are instance * kTicketParts + part
+constexpr int kMaxGroup = 16;      // largest group of workgroups on one instance
 
 // What a decode did (device memory, one per instance).
 struct BatchResult {
     long long L_hat;
     int iterations, accepted, updates_total, err;
+    unsigned long long t_start, t_end;   // wall clock (100 MHz) when the decode began and ended
 };
 
 // The launch-wide part of a schedule.
@@ -57,10 +82,13 @@ int batched_max_resident(int d, int block, size_t lds_bytes);
 // Raise every batched kernel's dynamic LDS limit to what kBatchMaxRows needs (once per
 // device, before the first launch or capture).
 hipError_t batched_set_lds_limits();
-// Zero the queue counter, then the persistent decode of `count` instances taken in
-// `order` (indices into probs).  All instances have the same d.
+// Zero the queue counter, then the persistent decode of the `count` tickets in `order`
+// (instance * kTicketParts + part; a group's tickets are consecutive).  All instances
+// have the same d.  The caller zeroes the groups' BatchCtl blocks first (launch_zero_words).
 hipError_t launch_batched(int d, const BatchLaunch& L, int grid, size_t lds_bytes, const BatchProblem* probs,
                           const int* order, int count, BatchResult* res, int* counter, hipStream_t s,
                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// words [count] <- 0 with a fill kernel (capturable).
+hipError_t launch_zero_words(int* words, long long count, hipStream_t s);
 
 }  // namespace rl0

@@ -192,14 +192,14 @@ __device__ __forceinline__ void load_tile(const int32_t* __restrict__ A, int n, 
 // queued columns rather than once per tile.
 template <int D, int BLOCK, int C>
 __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uint32_t* bm, int it,
-                         BatchShared<BLOCK>& sh) {
+                         BatchShared<BLOCK>& sh, int j_begin, int j_end, int* nchg, int* chg) {
     const int tid = threadIdx.x;
-    const int n = P.n;
+    const int n = j_end;   // the columns [j_begin, j_end); j_begin is a multiple of 4
     constexpr int kTile = BLOCK * C;
     int cur[C][D];
-    load_tile<D, C>(P.A, n, tid * C, cur);
+    load_tile<D, C>(P.A, n, j_begin + tid * C, cur);
     int nupd = 0, nzd = 0;
-    for (int base = 0; base < n; base += kTile) {
+    for (int base = j_begin; base < n; base += kTile) {
         const int j0 = base + tid * C;
 #pragma unroll
         for (int q = 0; q < C; ++q) {
@@ -247,8 +247,8 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                     nzd += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
                 }
             }
-            const int slot = wave_append(&sh.nchg, upd);
-            if (upd) P.chg[slot] = j;
+            const int slot = wave_append(nchg, upd);
+            if (upd) chg[slot] = j;
         }
         if (tid == 0) sh.nq = 0;
         __syncthreads();
@@ -280,6 +280,7 @@ __device__ __forceinline__ long long apply_change(const BatchProblem& P, int j, 
 
 template <int D, int BLOCK>
 __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn, BatchShared<BLOCK>& sh) {
+    const unsigned long long t_start = wall_clock64();
     const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
     float* Tz = dyn;
@@ -378,11 +379,11 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             tbi.qz_bits = P.qz[it];
         }
         if (P.cols == 1)
-            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh);
+            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg);
         else if (P.cols == 2)
-            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh);
+            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg);
         else
-            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh);
+            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg);
         __syncthreads();
         updates += sh.nupd;
         // ---- 3. H_k
@@ -461,6 +462,342 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         R->accepted = accepted;
         R->updates_total = updates;
         R->err = sh.err;
+        R->t_start = t_start;
+        R->t_end = wall_clock64();
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- groups of workgroups
+//
+// A large instance is decoded by G workgroups together.  Member p of the group sweeps the
+// p-th slice of the columns and takes the p-th slice of each list (dropped keys, changed
+// columns); everything the members need from each other goes through global memory (x',
+// the change and key lists, S) and the group's BatchCtl, separated by group barriers.
+// Every member builds the whole outer-test bitmask in its own LDS and runs H_k's radix
+// passes over the whole key list itself, so those need no barrier and every member
+// reaches the same threshold.  Sums are exact integers, so the result is the same bits as
+// a decode by one workgroup whatever the members' order.
+
+// Wall-clock ticks (100 MHz) a member waits at a group barrier before it gives up.  The
+// other members of a group take their tickets as soon as a workgroup is free, and the
+// host queues groups first, so a healthy barrier completes in microseconds.
+constexpr unsigned long long kGroupWaitTicks = 500000000ull;   // 5 s
+
+// Barrier of the group's G members (the `count`-th one of this decode).  Returns false when
+// a member's wait timed out; then every member returns from the instance.
+template <int BLOCK>
+__device__ bool group_barrier(BatchCtl* c, int G, unsigned count, BatchShared<BLOCK>& sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // this workgroup's writes, before its arrival
+        atomicAdd(&c->bar, 1u);
+        const unsigned target = count * static_cast<unsigned>(G);
+        const unsigned long long deadline = wall_clock64() + kGroupWaitTicks;
+        int ok = 1;
+        for (;;) {
+            if (__hip_atomic_load(&c->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() > deadline) {
+                __hip_atomic_store(&c->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicOr(&c->err, kErrTimeout);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();   // the other members' writes, after the wait
+        sh.digit = ok;
+    }
+    __syncthreads();
+    const bool ok = sh.digit != 0;
+    __syncthreads();
+    return ok;
+}
+
+// A member left the instance after a timed-out wait: its result says so (every member
+// that leaves writes the same).
+__device__ __forceinline__ void group_failed(BatchResult* R) {
+    if (threadIdx.x == 0) {
+        R->L_hat = 0;
+        R->iterations = 0;
+        R->accepted = 0;
+        R->updates_total = 0;
+        R->err = kErrTimeout;
+    }
+}
+
+// [lo, hi) of member p of G over count items, in multiples of `align`.
+__device__ __forceinline__ void member_slice(int count, int p, int G, int align, int* lo, int* hi) {
+    const int units = (count + align - 1) / align;
+    const int per = (units + G - 1) / G;
+    *lo = min(count, p * per * align);
+    *hi = min(count, (p + 1) * per * align);
+}
+
+template <int D, int BLOCK>
+__device__ __noinline__ void decode_instance_group(const BatchProblem P, int part, BatchResult* R, float* dyn,
+                                      BatchShared<BLOCK>& sh) {
+    const unsigned long long t_start = wall_clock64();
+    const int tid = threadIdx.x;
+    const int n = P.n, m = P.m, G = P.group;
+    BatchCtl* ctl = P.ctl;
+    float* Tz = dyn;
+    float* Te = dyn + kTabStride;
+    uint32_t* bm = reinterpret_cast<uint32_t*>(dyn + 2 * kTabStride);
+    if (!P.exact)
+        for (int i = tid; i <= kTableN; i += BLOCK) {
+            Tz[i] = P.Tz[i];
+            Te[i] = P.Te[i];
+        }
+    if (tid == 0) sh.err = 0;
+    __syncthreads();
+    const ScoreTables tb{Tz, Te, P.inv_h_z, P.inv_h_e, P.exact, P.e_zero_bits};
+    unsigned nbar = 0;
+    int c_lo, c_hi;                                  // this member's columns
+    member_slice(n, part, G, 64, &c_lo, &c_hi);
+    int r_lo, r_hi;                                  // and rows
+    member_slice(m, part, G, 64, &r_lo, &r_hi);
+
+    // ---- ingest, each member on its slices
+    if (P.validate) {
+        for (int j = c_lo + tid; j < c_hi; j += BLOCK) {
+            const int32_t* __restrict__ col = P.A + static_cast<size_t>(j) * D;
+            int prev = -1;
+            bool bad = false;
+#pragma unroll
+            for (int p = 0; p < D; ++p) {
+                const int r = col[p];
+                bad = bad || r <= prev || r >= m;
+                prev = r;
+            }
+            if (bad) atomicOr(&sh.err, kErrIndex);
+        }
+    }
+    for (int j = c_lo + tid; j < c_hi; j += BLOCK) {
+        P.x[j] = 0.0f;
+        P.xp[j] = 0.0f;
+        P.stamp[j] = -1;
+    }
+    long long l = 0;
+    for (int i = r_lo + tid; i < r_hi; i += BLOCK) {
+        const float yv = P.y[i];
+        long long sfx = 0;
+        if (!isfinite(yv))
+            atomicOr(&sh.err, kErrNonFinite);
+        else
+            sfx = to_fx(yv, &sh.err);
+        P.S[i] = sfx;
+        l += l1_term(from_fx(sfx));
+    }
+    l = wg_sum<BLOCK>(l, sh.red);
+    if (tid == 0) {
+        if (l) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->L0), static_cast<unsigned long long>(l));
+        if (sh.err) atomicOr(&ctl->err, sh.err);
+    }
+    if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
+    long long L_hat = __hip_atomic_load(&ctl->L0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    int iters = 0, accepted = 0, updates = 0, supp = 0;
+    const int words = (m + 31) >> 5;
+    for (int it = 0;; ++it) {
+        const int par = it & 1, nxt = par ^ 1;
+        const int err = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (err != 0 || static_cast<double>(L_hat) <= P.tol_fx || it >= P.n_iters) break;
+        // ---- 1. the whole outer-test bitmask, in this member's LDS
+        const uint32_t tau = P.tau[it];
+        for (int base = 0; base < words * 32; base += BLOCK * kU) {
+            long long sv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = base + u * BLOCK + tid;
+                sv[u] = i < m ? P.S[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = base + u * BLOCK + tid;
+                const bool pred = i < m && abs_bits(from_fx(sv[u])) >= tau;
+                const unsigned long long b = __ballot(pred);
+                if ((tid & 63) == 0) {
+                    const int w = i >> 5;
+                    if (w < words) bm[w] = static_cast<uint32_t>(b);
+                    if (w + 1 < words) bm[w + 1] = static_cast<uint32_t>(b >> 32);
+                }
+            }
+        }
+        if (tid == 0) {
+            sh.nq = 0;
+            sh.nupd = 0;
+            sh.nzd = 0;
+        }
+        __syncthreads();
+        // the change list of this iteration: one of two, by parity, since a member may start
+        // the next iteration while another still reads this one's list (after an accept)
+        int* __restrict__ chg = par ? P.chg2 : P.chg;
+        // ---- 2. sweep of this member's columns
+        ScoreTables tbi = tb;
+        if (P.quant) {
+            tbi.quant = 1;
+            tbi.qe_bits = P.qe[it];
+            tbi.qz_bits = P.qz[it];
+        }
+        if (P.cols == 1)
+            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg);
+        else if (P.cols == 2)
+            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg);
+        else
+            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg);
+        __syncthreads();
+        if (tid == 0) {
+            if (sh.nupd) atomicAdd(&ctl->nupd[par], sh.nupd);
+            if (sh.nzd) atomicAdd(&ctl->nzd[par], sh.nzd);
+        }
+        if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
+        // the next iteration's counters: every member has passed the previous iteration's
+        // last reads of them (they arrived here after it); the next barrier publishes
+        if (part == 0 && tid == 0) {
+            ctl->nchg[nxt] = 0;
+            ctl->nupd[nxt] = 0;
+            ctl->nzd[nxt] = 0;
+            ctl->nkeys[nxt] = 0;
+            ctl->dl[nxt] = 0;
+            ctl->dsupp[nxt] = 0;
+        }
+        updates += __hip_atomic_load(&ctl->nupd[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int nzd = __hip_atomic_load(&ctl->nzd[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // ---- 3. H_k
+        if (supp + nzd > P.k) {
+            // the nonzero keys of this member's columns join the key list
+            for (int base = c_lo; base < c_hi; base += BLOCK * kU) {
+                float v[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int j = base + u * BLOCK + tid;
+                    v[u] = j < c_hi ? P.xp[j] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const bool nz = v[u] != 0.0f;
+                    const int slot = wave_append(&ctl->nkeys[par], nz);
+                    if (nz) P.keys[slot] = hk_key(base + u * BLOCK + tid, v[u]);
+                }
+            }
+            if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
+            const int nk = __hip_atomic_load(&ctl->nkeys[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // every member selects the k-th key over the whole list (radix passes in LDS)
+            unsigned long long prefix = 0ull, pmask = 0ull;
+            unsigned rem = static_cast<unsigned>(P.k);
+            for (int pass = 0; pass < 6; ++pass) {
+                const int sft = pass < 5 ? 52 - 11 * pass : 0;
+                const unsigned dmask = pass < 5 ? 0x7FFu : 0xFFu;
+                for (int b = tid; b < kBins; b += BLOCK) sh.hist[b] = 0u;
+                __syncthreads();
+                for (int base = 0; base < nk; base += BLOCK * kU) {
+                    unsigned long long kv[kU];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const int e = base + u * BLOCK + tid;
+                        kv[u] = e < nk ? P.keys[e] : 0ull;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kU; ++u)
+                        hist_add(sh.hist, static_cast<unsigned>((kv[u] >> sft) & dmask),
+                                 kv[u] != 0ull && (kv[u] & pmask) == prefix);
+                }
+                __syncthreads();
+                wg_find_digit<BLOCK>(sh.hist, rem, sh);
+                prefix |= static_cast<unsigned long long>(sh.digit) << sft;
+                pmask |= static_cast<unsigned long long>(dmask) << sft;
+                rem -= sh.above;
+                const bool exact = (rem == sh.bucket);
+                __syncthreads();
+                if (exact) break;
+            }
+            const unsigned long long kth = prefix;
+            // the dropped columns of this member's slice of the key list
+            int k_lo, k_hi;
+            member_slice(nk, part, G, 1, &k_lo, &k_hi);
+            for (int e0 = k_lo; e0 < k_hi; e0 += BLOCK) {
+                const int e = e0 + tid;
+                bool add = false;
+                int j = 0;
+                if (e < k_hi) {
+                    const unsigned long long key = P.keys[e];
+                    if (key < kth) {
+                        j = static_cast<int>(0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull));
+                        P.xp[j] = 0.0f;
+                        add = P.stamp[j] != it;
+                        if (add) P.stamp[j] = it;
+                    }
+                }
+                const int slot = wave_append(&ctl->nchg[par], add);
+                if (add) chg[slot] = j;
+            }
+            if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
+        }
+        // ---- 4. residual change of this member's slice of the change list
+        const int nchg = __hip_atomic_load(&ctl->nchg[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int h_lo, h_hi;
+        member_slice(nchg, part, G, 1, &h_lo, &h_hi);
+        long long dl = 0, dsupp = 0;
+        for (int c = h_lo + tid; c < h_hi; c += BLOCK) {
+            const int j = chg[c];
+            const float xh = P.x[j], xn = P.xp[j];
+            if (xh == xn) continue;
+            dsupp += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
+            dl += apply_change<D>(P, j, xh, xn, true, &sh.err);
+        }
+        dl = wg_sum<BLOCK>(dl, sh.red);
+        dsupp = wg_sum<BLOCK>(dsupp, sh.red);
+        if (tid == 0) {
+            if (dl) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->dl[par]), static_cast<unsigned long long>(dl));
+            if (dsupp)
+                atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->dsupp[par]), static_cast<unsigned long long>(dsupp));
+            if (sh.err) atomicOr(&ctl->err, sh.err);
+        }
+        if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
+        // ---- 5. accept or undo, each member on its slice of the change list
+        const long long Lt = L_hat + __hip_atomic_load(&ctl->dl[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long ds = __hip_atomic_load(&ctl->dsupp[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int err2 = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool acc = (Lt < L_hat) && (err2 == 0);
+        ++iters;
+        if (acc) {
+            // each member takes over x' on its own columns: the next iteration reads x
+            // and x' there before any barrier, so no barrier is needed here (S is final
+            // since the barrier above; the owners' writes are published by the next one)
+            for (int c = tid; c < nchg; c += BLOCK) {
+                const int j = chg[c];
+                if (j >= c_lo && j < c_hi) P.x[j] = P.xp[j];
+            }
+            L_hat = Lt;
+            supp += static_cast<int>(ds);
+            ++accepted;
+        } else {
+            for (int c = h_lo + tid; c < h_hi; c += BLOCK) {
+                const int j = chg[c];
+                const float xh = P.x[j], xn = P.xp[j];
+                if (xh == xn) continue;
+                P.xp[j] = xh;
+                apply_change<D>(P, j, xn, xh, false, &sh.err);
+            }
+            if (tid == 0 && sh.err) atomicOr(&ctl->err, sh.err);
+            // the undo changed S, which every member's next bitmask reads
+            if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
+        }
+        __syncthreads();
+    }
+    if (part == 0 && tid == 0) {
+        R->L_hat = L_hat;
+        R->iterations = iters;
+        R->accepted = accepted;
+        R->updates_total = updates;
+        R->err = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R->t_start = t_start;
+        R->t_end = wall_clock64();
     }
     __syncthreads();
 }
@@ -479,12 +816,22 @@ __global__ __launch_bounds__(BLOCK) void k_decode_batched(const BatchProblem* __
         const int q = __builtin_amdgcn_readfirstlane(sh.idx);
         __syncthreads();
         if (q >= count) return;
-        const int pi = __builtin_amdgcn_readfirstlane(order[q]);
-        decode_instance<D, BLOCK>(probs[pi], res + pi, dyn, sh);
+        const int ticket = __builtin_amdgcn_readfirstlane(order[q]);
+        const int pi = ticket / kTicketParts, part = ticket % kTicketParts;
+        const BatchProblem P = probs[pi];
+        if (P.group > 1)
+            decode_instance_group<D, BLOCK>(P, part, res + pi, dyn, sh);
+        else
+            decode_instance<D, BLOCK>(P, res + pi, dyn, sh);
     }
 }
 
 __global__ void k_zero_counter(int* counter) { *counter = 0; }
+
+__global__ void k_zero_words(int* __restrict__ w, long long count) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) w[i] = 0;
+}
 
 template <int D, int BLOCK>
 hipError_t launch_db(int grid, size_t lds, const BatchProblem* probs, const int* order, int count,
@@ -569,6 +916,11 @@ int batched_max_resident(int d, int block, size_t lds_bytes) {
 size_t batched_lds_bytes(int max_m) {
     const size_t words = (static_cast<size_t>(max_m) + 31) / 32;
     return (2 * static_cast<size_t>(kTabStride)) * sizeof(float) + 4 * words;
+}
+
+hipError_t launch_zero_words(int* words, long long count, hipStream_t s) {
+    if (count > 0) k_zero_words<<<static_cast<int>((count + 255) / 256), 256, 0, s>>>(words, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_batched(int d, const BatchLaunch& L, int grid, size_t lds, const BatchProblem* probs,

@@ -20,6 +20,7 @@ enum ErrFlag : int {
     kErrRange = 1,      // a value left the fixed-point range
     kErrIndex = 2,      // A_cols malformed
     kErrNonFinite = 4,  // y holds NaN or Inf
+    kErrTimeout = 8,    // a bounded wait between workgroups timed out (batched groups)
 };
 
 // Loop state after the decision of one iteration.  Iteration it decides iteration it-1

@@ -357,6 +357,7 @@ int err_code_of(int flags) {
     if (flags & rl0::kErrIndex) return fail(RL0_EINDEX, "A_cols: index out of range or column not strictly ascending");
     if (flags & rl0::kErrNonFinite) return fail(RL0_EINVAL, "y holds a non-finite value");
     if (flags & rl0::kErrRange) return fail(RL0_ERANGE, "a value left the fixed-point range (|v| >= 2^22)");
+    if (flags & rl0::kErrTimeout) return fail(RL0_EHIP, "a bounded wait of a workgroup group timed out");
     return RL0_OK;
 }
 
@@ -471,6 +472,7 @@ struct BatchKey {
     int32_t count, d, block, per_cu, grid;
     size_t lds;
     const void* meta;
+    uint64_t queue;   // hash of the launches' ticket ranges and grids
 };
 
 struct BatchGraph {
@@ -491,6 +493,8 @@ struct BatchBuffers {
     hipEvent_t ev_call[2] = {nullptr, nullptr};   // around a whole batched call (ms_total)
     std::vector<BatchGraph> graphs;
     unsigned long long uses = 0;
+    std::vector<rl0::BatchResult> last_res;   // the last call's results (rl0_batch_timeline)
+    std::vector<int> last_group;
     rl0::BatchProblem* desc_d() const { return static_cast<rl0::BatchProblem*>(meta); }
 };
 
@@ -499,14 +503,15 @@ std::map<int, rl0_batch_schedule> g_sched;
 std::map<int, bool> g_lds_ready;
 
 size_t meta_bytes(size_t count) {
-    return rl0::al_host(count * sizeof(rl0::BatchProblem)) + rl0::al_host(count * sizeof(int)) +
-           rl0::al_host(count * sizeof(rl0::BatchResult)) + 256;
+    return rl0::al_host(count * sizeof(rl0::BatchProblem)) + rl0::al_host(count * rl0::kMaxGroup * sizeof(int)) +
+           rl0::al_host(count * sizeof(rl0::BatchResult)) + rl0::al_host(count * sizeof(rl0::BatchCtl)) + 256;
 }
 
 struct MetaView {
     rl0::BatchProblem* desc;
-    int* order;
+    int* order;                 // tickets: instance * kTicketParts + part
     rl0::BatchResult* res;
+    rl0::BatchCtl* ctl;         // one per instance (used by groups)
     int* counter;
 };
 
@@ -516,9 +521,11 @@ MetaView meta_view(void* base, size_t count) {
     v.desc = reinterpret_cast<rl0::BatchProblem*>(p);
     p += rl0::al_host(count * sizeof(rl0::BatchProblem));
     v.order = reinterpret_cast<int*>(p);
-    p += rl0::al_host(count * sizeof(int));
+    p += rl0::al_host(count * rl0::kMaxGroup * sizeof(int));
     v.res = reinterpret_cast<rl0::BatchResult*>(p);
     p += rl0::al_host(count * sizeof(rl0::BatchResult));
+    v.ctl = reinterpret_cast<rl0::BatchCtl*>(p);
+    p += rl0::al_host(count * sizeof(rl0::BatchCtl));
     v.counter = reinterpret_cast<int*>(p);
     return v;
 }
@@ -573,15 +580,22 @@ rl0_batch_schedule default_schedule() {
     rl0_batch_schedule s;
     s.block = 256;
     s.per_cu = 3;
-    for (int c = 0; c < RL0_SIZE_CLASSES; ++c) s.cols[c] = 4;
+    for (int c = 0; c < RL0_SIZE_CLASSES; ++c) {
+        s.cols[c] = 4;
+        s.group[c] = 4;   // the work estimate decides which instances are split (most are not)
+    }
     return s;
 }
 
 int check_schedule(const rl0_batch_schedule& s) {
     if (s.block != 256 && s.block != 512 && s.block != 1024) return fail(RL0_EINVAL, "schedule: block must be 256, 512 or 1024");
     if (s.per_cu < 1 || s.per_cu > 8) return fail(RL0_EINVAL, "schedule: per_cu must be in [1, 8]");
-    for (int c = 0; c < RL0_SIZE_CLASSES; ++c)
+    for (int c = 0; c < RL0_SIZE_CLASSES; ++c) {
         if (s.cols[c] != 1 && s.cols[c] != 2 && s.cols[c] != 4) return fail(RL0_EINVAL, "schedule: cols must be 1, 2 or 4");
+        const int g = s.group[c];
+        if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16)
+            return fail(RL0_EINVAL, "schedule: group must be 1, 2, 4, 8 or 16");
+    }
     return RL0_OK;
 }
 
@@ -625,7 +639,7 @@ int plan_batch(const rl0_problem* probs, int count, hipStream_t s, BatchPlan* pl
     plan->d = probs[0].d;
     for (int i = 0; i < count; ++i) {
         plan->offs[i] = total;
-        total += rl0::al_host(8ull * probs[i].m) + 3 * rl0::al_host(4ull * probs[i].n) + rl0::al_host(8ull * probs[i].n);
+        total += rl0::al_host(8ull * probs[i].m) + 4 * rl0::al_host(4ull * probs[i].n) + rl0::al_host(8ull * probs[i].n);
         plan->max_m = std::max(plan->max_m, probs[i].m);
         plan->uniform_d = plan->uniform_d && probs[i].d == plan->d;
     }
@@ -643,9 +657,85 @@ int plan_batch(const rl0_problem* probs, int count, hipStream_t s, BatchPlan* pl
     return get_batch_buffers(plan->device, s, total, count, &plan->b);
 }
 
-// Descriptors (with the schedule's columns per tile) and order to the device.
+size_t batch_lds(const BatchPlan& P);
+
+// Workgroups of a persistent launch of column weight d that are resident at once under
+// the schedule (its per_cu, capped by what the occupancy query says fits).
+int batch_capacity(const BatchPlan& P, const rl0_batch_schedule& sc, int d) {
+    hipDeviceProp_t prop;
+    const int cus = hipGetDeviceProperties(&prop, P.device) == hipSuccess ? prop.multiProcessorCount : 256;
+    const int fit = rl0::batched_max_resident(d, sc.block, batch_lds(P));
+    const int per = fit > 0 ? std::min(sc.per_cu, fit) : sc.per_cu;
+    return std::max(1, cus * per);
+}
+
+// The queue of one batched call: per instance its group size, the tickets (a group's
+// consecutive), and per distinct d the range of tickets its launch takes and its grid.
+struct BatchTickets {
+    std::vector<int> group;       // per instance
+    std::vector<int> tickets;
+    struct Launch { int d, start, count, grid; };
+    std::vector<Launch> launches;
+};
+
+// An instance's work, in arbitrary units, for the batch schedule.  A sweep's cost grows
+// with the columns its consensus test queues, about n d / m columns per flagged row and
+// flagged rows in proportion to the support, so n k / m per iteration (measured on one
+// workgroup, the instance times follow n k / m more closely than n).
+double instance_work(const rl0_problem& q, const DeviceConstants* dc) {
+    const double per_it = static_cast<double>(q.n) * std::max(static_cast<double>(q.params.k) / q.m, 0.01);
+    return per_it * dc->hc.n_iters;
+}
+
+// Group sizes and queue order of one launch (instances of one d).  An instance gets the
+// smallest power-of-two group that brings its share of the work per member to half the
+// average load of a resident workgroup (total work / resident workgroups), capped by the
+// schedule's group for its size class, the resident grid and one member per 4096
+// columns; so only the instances that would outlast the rest are split.  The queue then
+// takes the instances by share per member, largest first (a group's tickets
+// consecutive), so the long ones start at once.
+BatchTickets make_tickets(const BatchPlan& P, const rl0_problem* probs, const rl0_batch_schedule& sc) {
+    BatchTickets T;
+    T.group.assign(P.count, 1);
+    int start = 0;
+    while (start < P.count) {
+        const int d = probs[P.order[start]].d;
+        const int cap = batch_capacity(P, sc, d);
+        int end = start;
+        double total = 0.0;
+        for (; end < P.count && probs[P.order[end]].d == d; ++end) {
+            const int i = P.order[end];
+            total += instance_work(probs[i], P.dc[i]);
+        }
+        const double load = 0.5 * total / cap;
+        std::vector<std::pair<double, int>> share;
+        for (int e = start; e < end; ++e) {
+            const int i = P.order[e];
+            const double work = instance_work(probs[i], P.dc[i]);
+            const int gmax = sc.group[size_class(probs[i].n)];
+            int g = 1;
+            while (g < gmax && 2 * g <= cap && static_cast<long long>(2 * g) * 4096 <= probs[i].n && work / g > load)
+                g *= 2;
+            T.group[i] = g;
+            share.push_back({work / g, i});
+        }
+        std::stable_sort(share.begin(), share.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        const int t0 = static_cast<int>(T.tickets.size());
+        for (const auto& sh : share)
+            for (int p = 0; p < T.group[sh.second]; ++p) T.tickets.push_back(sh.second * rl0::kTicketParts + p);
+        const int cnt = static_cast<int>(T.tickets.size()) - t0;
+        T.launches.push_back({d, t0, cnt, std::max(1, std::min(cnt, cap))});
+        start = end;
+    }
+    return T;
+}
+
+// Descriptors (with the schedule's columns per tile and group sizes) and the ticket queue
+// to the device.
 int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_schedule& sc, hipStream_t s) {
     const MetaView h = meta_view(P.b->host, P.count);
+    const MetaView dv = meta_view(P.b->meta, P.count);
+    const BatchTickets T = make_tickets(P, probs, sc);
     char* ws = static_cast<char*>(P.b->block);
     for (int i = 0; i < P.count; ++i) {
         const rl0_problem& q = probs[i];
@@ -663,6 +753,8 @@ int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_s
         B.stamp = reinterpret_cast<int*>(w);
         w += rl0::al_host(4ull * q.n);
         B.chg = reinterpret_cast<int*>(w);
+        w += rl0::al_host(4ull * q.n);
+        B.chg2 = reinterpret_cast<int*>(w);
         w += rl0::al_host(4ull * q.n);
         B.keys = reinterpret_cast<unsigned long long*>(w);
         B.Tz = dc->d_tables;
@@ -685,18 +777,13 @@ int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_s
         B.validate = q.params.validate;
         B.n_iters = dc->hc.n_iters;
         B.cols = sc.cols[size_class(q.n)];
+        B.group = T.group[i];
+        B.ctl = dv.ctl + i;
     }
-    std::memcpy(h.order, P.order.data(), sizeof(int) * P.count);
-    const MetaView dv = meta_view(P.b->meta, P.count);
+    std::memcpy(h.order, T.tickets.data(), sizeof(int) * T.tickets.size());
     HIP_TRY(hipMemcpyAsync(dv.desc, h.desc, sizeof(rl0::BatchProblem) * P.count, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dv.order, h.order, sizeof(int) * P.count, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dv.order, h.order, sizeof(int) * T.tickets.size(), hipMemcpyHostToDevice, s));
     return RL0_OK;
-}
-
-int batch_grid(const BatchPlan& P, const rl0_batch_schedule& sc, int count) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, P.device) != hipSuccess) return std::min(count, 256 * sc.per_cu);
-    return std::max(1, std::min(count, prop.multiProcessorCount * sc.per_cu));
 }
 
 size_t batch_lds(const BatchPlan& P) {
@@ -705,25 +792,21 @@ size_t batch_lds(const BatchPlan& P) {
     return rl0::batched_lds_bytes(std::min(m, rl0::kBatchMaxRows));
 }
 
-// Every launch of the plan (one per distinct d, in order), optionally timed.
+// Every launch of the plan (one per distinct d, in order), optionally timed; the groups'
+// shared blocks are cleared first by a fill kernel.
 int issue_batch(const BatchPlan& P, const rl0_batch_schedule& sc, const rl0_problem* probs, hipStream_t q,
                 bool timed) {
     const MetaView dv = meta_view(P.b->meta, P.count);
     const rl0::BatchLaunch L{sc.block, sc.per_cu};
     const size_t lds = batch_lds(P);
-    int start = 0;
-    bool first = true;
-    while (start < P.count) {
-        const int d = probs[P.order[start]].d;
-        int end = start;
-        while (end < P.count && probs[P.order[end]].d == d) ++end;
-        const int cnt = end - start;
-        const bool last = end == P.count;
-        HIP_TRY(rl0::launch_batched(d, L, batch_grid(P, sc, cnt), lds, dv.desc, dv.order + start, cnt, dv.res,
-                                    dv.counter, q, timed && first ? P.b->ev[0] : nullptr,
-                                    timed && last ? P.b->ev[1] : nullptr));
-        first = false;
-        start = end;
+    const BatchTickets T = make_tickets(P, probs, sc);
+    HIP_TRY(rl0::launch_zero_words(reinterpret_cast<int*>(dv.ctl),
+                                   static_cast<long long>(P.count) * (sizeof(rl0::BatchCtl) / sizeof(int)), q));
+    for (size_t li = 0; li < T.launches.size(); ++li) {
+        const BatchTickets::Launch& G = T.launches[li];
+        HIP_TRY(rl0::launch_batched(G.d, L, G.grid, lds, dv.desc, dv.order + G.start, G.count, dv.res, dv.counter, q,
+                                    timed && li == 0 ? P.b->ev[0] : nullptr,
+                                    timed && li + 1 == T.launches.size() ? P.b->ev[1] : nullptr));
     }
     return RL0_OK;
 }
@@ -737,9 +820,19 @@ int run_batch(const BatchPlan& P, const rl0_batch_schedule& sc, const rl0_proble
     key.d = P.d;
     key.block = sc.block;
     key.per_cu = sc.per_cu;
-    key.grid = batch_grid(P, sc, P.count);
     key.lds = batch_lds(P);
     key.meta = P.b->meta;
+    {
+        const BatchTickets T = make_tickets(P, probs, sc);
+        uint64_t h = 1469598103934665603ull;   // FNV-1a over the launches
+        for (const auto& G : T.launches)
+            for (int v : {G.d, G.start, G.count, G.grid}) {
+                h ^= static_cast<uint32_t>(v);
+                h *= 1099511628211ull;
+            }
+        key.queue = h;
+        key.grid = T.launches.empty() ? 0 : T.launches[0].grid;
+    }
     BatchBuffers* b = P.b;
     BatchGraph* hit = nullptr;
     for (BatchGraph& g : b->graphs)
@@ -784,8 +877,14 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
     const MetaView dv = meta_view(P.b->meta, P.count);
     HIP_TRY(hipMemcpyAsync(h.res, dv.res, sizeof(rl0::BatchResult) * P.count, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    P.b->last_res.assign(h.res, h.res + P.count);
+    P.b->last_group.resize(P.count);
+    for (int i = 0; i < P.count; ++i) P.b->last_group[i] = h.desc[i].group;
     float call_ms = -1.0f;
-    if (hipEventElapsedTime(&call_ms, P.b->ev_call[0], P.b->ev_call[1]) != hipSuccess) call_ms = -1.0f;
+    if (st && hipEventElapsedTime(&call_ms, P.b->ev_call[0], P.b->ev_call[1]) != hipSuccess) {
+        call_ms = -1.0f;
+        (void)hipGetLastError();   // leave no error behind for the caller's next HIP call
+    }
     int first_rc = RL0_OK;
     std::string first_msg;
     for (int i = 0; i < P.count; ++i) {
@@ -832,7 +931,12 @@ void fill_stats(rl0_stats* st_h, const rl0::DevState& ds, const rl0::Slot& fin, 
     st_h->fx_inexact_y = ds.inexact_y;
     st_h->fx_inexact_x = ds.inexact_x;
     float ms = 0.0f;
-    st_h->ms_total = hipEventElapsedTime(&ms, b->ev_call[0], b->ev_call[1]) == hipSuccess ? ms : -1.0f;
+    if (hipEventElapsedTime(&ms, b->ev_call[0], b->ev_call[1]) == hipSuccess) {
+        st_h->ms_total = ms;
+    } else {
+        st_h->ms_total = -1.0f;
+        (void)hipGetLastError();
+    }
 }
 
 // ---------------------------------------------------------------- one iteration from x_hat
@@ -1216,6 +1320,29 @@ int rl0_decode_batched(const rl0_problem* probs_h, int32_t count, rl0_stats* st_
     return collect_batch(probs_h, plan, st_h, s);
 }
 
+int rl0_batch_timeline(int32_t count, double* start_ms_h, double* end_ms_h, int32_t* group_h, void* stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto it = g_bws.find({dev, static_cast<hipStream_t>(stream)});
+    if (it == g_bws.end() || !it->second) return fail(RL0_EINVAL, "no batched decode on this device and stream");
+    const BatchBuffers& b = *it->second;
+    if (count < 0 || static_cast<size_t>(count) > b.last_res.size())
+        return fail(RL0_EINVAL, "count exceeds the last batch's instances");
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const double ms_per_tick = khz > 0 ? 1.0 / khz : 1e-5;
+    unsigned long long t0 = ~0ull;
+    for (const auto& r : b.last_res) t0 = std::min(t0, r.t_start);
+    for (int i = 0; i < count; ++i) {
+        const rl0::BatchResult& r = b.last_res[i];
+        if (start_ms_h) start_ms_h[i] = static_cast<double>(r.t_start - t0) * ms_per_tick;
+        if (end_ms_h) end_ms_h[i] = static_cast<double>(r.t_end - t0) * ms_per_tick;
+        if (group_h) group_h[i] = b.last_group[i];
+    }
+    return RL0_OK;
+}
+
 int rl0_batch_schedule_get(rl0_batch_schedule* out_h) {
     if (!out_h) return fail(RL0_EINVAL, "out_h is NULL");
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1279,12 +1406,38 @@ int rl0_autotune_batched(const rl0_problem* probs_h, int32_t count, int32_t reps
             }
         }
     }
-    // 2. columns per tile, size class by size class, the classes with most columns first
     std::vector<long long> cls_cols(RL0_SIZE_CLASSES, 0);
     for (int i = 0; i < count; ++i) cls_cols[size_class(probs_h[i].n)] += probs_h[i].n;
     std::vector<int> cls;
     for (int c = 0; c < RL0_SIZE_CLASSES; ++c)
         if (cls_cols[c] > 0) cls.push_back(c);
+    // 2. the cap on workgroups per instance (which instances are split, and how far, follows
+    // from their work against the average load), first for every class at once, then
+    // lowered class by class, the largest first
+    for (int g : {2, 4, 8, 16}) {
+        rl0_batch_schedule cand = best;
+        for (int c = 0; c < RL0_SIZE_CLASSES; ++c) cand.group[c] = g;
+        double ms = 0.0;
+        if (int rc = time_of(cand, &ms)) return rc;
+        if (ms < best_ms) {
+            best = cand;
+            best_ms = ms;
+        }
+    }
+    for (int c = RL0_SIZE_CLASSES - 1; c >= 0; --c) {
+        if (cls_cols[c] == 0 || best.group[c] == 1) continue;
+        for (int g = best.group[c] / 2; g >= 1; g /= 2) {
+            rl0_batch_schedule cand = best;
+            cand.group[c] = g;
+            double ms = 0.0;
+            if (int rc = time_of(cand, &ms)) return rc;
+            if (ms < best_ms) {
+                best = cand;
+                best_ms = ms;
+            }
+        }
+    }
+    // 3. columns per tile, size class by size class, the classes with most columns first
     std::stable_sort(cls.begin(), cls.end(), [&](int a, int b) { return cls_cols[a] > cls_cols[b]; });
     for (int c : cls) {
         for (int cols : {1, 2, 4}) {

@@ -112,10 +112,11 @@ class BatchSchedule(ctypes.Structure):
         ("block", ctypes.c_int32),
         ("per_cu", ctypes.c_int32),
         ("cols", ctypes.c_int32 * RL0_SIZE_CLASSES),
+        ("group", ctypes.c_int32 * RL0_SIZE_CLASSES),
     ]
 
     def as_dict(self) -> dict:
-        return {"block": self.block, "per_cu": self.per_cu, "cols": list(self.cols)}
+        return {"block": self.block, "per_cu": self.per_cu, "cols": list(self.cols), "group": list(self.group)}
 
     @classmethod
     def from_dict(cls, d: dict) -> "BatchSchedule":
@@ -124,6 +125,8 @@ class BatchSchedule(ctypes.Structure):
         s.per_cu = d["per_cu"]
         for i, c in enumerate(d["cols"]):
             s.cols[i] = c
+        for i, g in enumerate(d.get("group", [1] * RL0_SIZE_CLASSES)):
+            s.group[i] = g
         return s
 
 
@@ -170,6 +173,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_decode_batched.argtypes = [ctypes.POINTER(Problem), I32, ctypes.POINTER(Stats), V]
         L.rl0_batch_schedule_get.argtypes = [ctypes.POINTER(BatchSchedule)]
+        L.rl0_batch_timeline.argtypes = [I32, P, P, P, V]
         L.rl0_batch_schedule_set.argtypes = [ctypes.POINTER(BatchSchedule)]
         L.rl0_autotune_batched.argtypes = [ctypes.POINTER(Problem), I32, I32, ctypes.POINTER(BatchSchedule),
                                            ctypes.POINTER(ctypes.c_double), V]
@@ -191,7 +195,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_sketch_static", "rl0_validate",
                      "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get",
-                     "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_mlp_init", "rl0_mlp_features",
+                     "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_batch_timeline", "rl0_mlp_init", "rl0_mlp_features",
                      "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -444,6 +448,17 @@ def decode_batched(problems) -> list:
     st = (Stats * max(len(problems), 1))()
     _check(lib().rl0_decode_batched(arr, len(problems), st, _stream()))
     return [st[i].as_dict() for i in range(len(problems))]
+
+
+def batch_timeline(count: int):
+    """(start_ms, end_ms, group) arrays of the last batched call's first `count` instances."""
+    import numpy as np
+    a = np.zeros(count, np.float64)
+    b = np.zeros(count, np.float64)
+    g = np.zeros(count, np.int32)
+    _check(lib().rl0_batch_timeline(count, a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                                    g.ctypes.data_as(ctypes.c_void_p), _stream()))
+    return a, b, g
 
 
 def batch_schedule_get() -> dict:

@@ -186,7 +186,10 @@ def test_batched_rejects_bad_instances_before_device_work():
 def test_batch_schedule_rejects_bad_fields():
     L = R.lib()
     for bad in ({"block": 128, "per_cu": 1, "cols": [4] * 12}, {"block": 256, "per_cu": 0, "cols": [4] * 12},
-                {"block": 256, "per_cu": 9, "cols": [4] * 12}, {"block": 256, "per_cu": 1, "cols": [3] * 12}):
+                {"block": 256, "per_cu": 9, "cols": [4] * 12}, {"block": 256, "per_cu": 1, "cols": [3] * 12},
+                {"block": 256, "per_cu": 1, "cols": [4] * 12, "group": [3] * 12},
+                {"block": 256, "per_cu": 1, "cols": [4] * 12, "group": [32] * 12},
+                {"block": 256, "per_cu": 1, "cols": [4] * 12, "group": [0] * 12}):
         s = R.BatchSchedule.from_dict(bad)
         assert L.rl0_batch_schedule_set(ctypes.byref(s)) == -1
 

@@ -137,8 +137,10 @@ def test_batched_schedules_do_not_change_results():
     saved = R.batch_schedule_get()
     try:
         ref = None
-        for block, per_cu, cols in ((256, 1, 1), (512, 1, 2), (1024, 1, 4), (256, 2, 4)):
-            R.batch_schedule_set({"block": block, "per_cu": per_cu, "cols": [cols] * R.RL0_SIZE_CLASSES})
+        for block, per_cu, cols, grp in ((256, 1, 1, 1), (512, 1, 2, 1), (1024, 1, 4, 1), (256, 2, 4, 1),
+                                         (1024, 1, 4, 4), (256, 2, 2, 16)):
+            R.batch_schedule_set({"block": block, "per_cu": per_cu, "cols": [cols] * R.RL0_SIZE_CLASSES,
+                                  "group": [grp] * R.RL0_SIZE_CLASSES})
             print("schedule", block, per_cu, cols, flush=True)
             stats = R.decode_batched(probs)
             outs = [host(p["out"]).copy() for p in probs]
@@ -196,10 +198,86 @@ def test_autotune_installs_a_valid_schedule():
         print("tuned", best, ms, flush=True)
         assert best["block"] in (256, 512, 1024) and 1 <= best["per_cu"] <= 8
         assert all(c in (1, 2, 4) for c in best["cols"])
+        assert all(g in (1, 2, 4, 8, 16) for g in best["group"])
         assert ms > 0
         assert R.batch_schedule_get() == best
+        # the tuner leaves no HIP error behind for the next kernel launch of the caller
+        assert float(torch.linalg.norm(probs[0]["out"])) >= 0.0
         for inst, pr in zip(insts, probs):
             x1, _ = R.decode(pr["A"], pr["y"], sigma=inst.sigma, k=inst.k)
             assert np.array_equal(host(pr["out"]), host(x1))
+    finally:
+        R.batch_schedule_set(saved)
+
+
+def group_schedule(groups):
+    s = R.batch_schedule_get()
+    s["group"] = list(groups) + [groups[-1]] * (R.RL0_SIZE_CLASSES - len(groups))
+    return s
+
+
+@pytest.mark.parametrize("groups", [[1, 1, 2, 4, 8, 16], [16] * 12, [1, 1, 1, 2, 2, 2]])
+def test_batched_groups_match_oracle(groups):
+    """Instances decoded by groups of workgroups (capped at one member per 4096 columns):
+    every result bitwise the oracle's, with and without other instances in the queue."""
+    insts = mixed_batch()
+    sig = float(np.float32(I.sigma_for_snr(30, 70000, 7000, 900, 7)))
+    insts.append(I.draw_instance(70000, 7000, 900, 7, sig, 1201))     # up to 16 members
+    probs = problems_of(insts)
+    saved = R.batch_schedule_get()
+    try:
+        R.batch_schedule_set(group_schedule(groups))
+        print("batched groups", groups, flush=True)
+        stats = R.decode_batched(probs)
+        for inst, pr, st in zip(insts, probs, stats):
+            same(host(pr["out"]), st, oracle_of(inst))
+        # quantised scores through the groups too
+        probs_q = problems_of(insts[-3:], variant=1)
+        stats = R.decode_batched(probs_q)
+        for inst, pr, st in zip(insts[-3:], probs_q, stats):
+            same(host(pr["out"]), st, oracle_of(inst, variant=1))
+    finally:
+        R.batch_schedule_set(saved)
+
+
+@pytest.mark.parametrize("seed", [3])
+def test_batched_groups_uneven_against_single_decode(seed):
+    insts = I.draw_batch(64, seed)
+    probs = problems_of(insts)
+    saved = R.batch_schedule_get()
+    try:
+        R.batch_schedule_set(group_schedule([1, 1, 1, 2, 4, 8, 16]))
+        print("batched groups uneven", seed, max(i.n for i in insts), flush=True)
+        stats = R.decode_batched(probs)
+        for rep in range(2):              # the second call replays the captured graph
+            for inst, pr, st in zip(insts, probs, stats):
+                x1, st1 = R.decode(pr["A"], pr["y"], sigma=inst.sigma, k=inst.k)
+                assert np.array_equal(host(pr["out"]), host(x1))
+                assert R.stats_subset(st, R.LOOP_STATS) == R.stats_subset(st1, R.LOOP_STATS)
+            stats = R.decode_batched(probs)
+    finally:
+        R.batch_schedule_set(saved)
+
+
+def test_batched_group_with_a_failing_instance():
+    """A malformed instance decoded by a group fails alone; the others are unaffected."""
+    insts = mixed_batch()[:4]
+    sig = float(np.float32(I.sigma_for_snr(40, 40000, 5000, 400, 7)))
+    big = I.draw_instance(40000, 5000, 400, 7, sig, 1301)
+    probs = problems_of(insts + [big])
+    bad = probs[-1]["A"].clone()
+    bad[123, 3] = bad[123, 2]
+    probs[-1]["A"] = bad
+    saved = R.batch_schedule_get()
+    try:
+        R.batch_schedule_set(group_schedule([1, 1, 1, 2, 4, 8, 8, 8]))
+        with pytest.raises(R.Rl0Error):
+            R.decode_batched(probs)
+        st = (R.Stats * len(probs))()
+        arr, _keep = R._problems(probs)
+        rc = R.lib().rl0_decode_batched(arr, len(probs), st, R._stream())
+        assert rc == -2 and st[len(probs) - 1].error_flags & 2
+        for i, inst in enumerate(insts):
+            same(host(probs[i]["out"]), st[i].as_dict(), oracle_of(inst))
     finally:
         R.batch_schedule_set(saved)
