@@ -58,6 +58,14 @@ so n_e and n_z count rows and omega is the mean of the rows agreeing with row p;
 outer test is unchanged, and c = 0 selects eq:finetune_c_quant.  At t = 1 every row
 counts as a zero (q_z = 1), so iteration 0 updates nothing.
 
+adaptive_k (Alg. 1's adaptive_k branch; reading R17): after an accepted iteration the
+posteriors are rebuilt for the sparsity still to be found,
+      k_0 = max(k - sum_j (1 - p_breve_z(x_hat_j)), floor(m/100), 1),
+each term taken on the current z-table in float32, fl32(1 - Tz(|x_hat_j|)), and summed
+exactly as the integer sum_j rint(2^30 term) (x_hat_j = 0 adds 0), so k_0 is an exact
+fp64 number; the tables are rebuilt with rho = k_0 / m.  H_k keeps the decoder's k, and the
+schedule (c, the iterations) and the tolerance stay those of the start.
+
 With sigma = 0 the scores are Parallel-l0's indicators and the same loop is Alg. 2
 with its one-update-per-column rule (exact recovery check, Thm. "Convergence of
 Algorithm 2").
@@ -65,7 +73,7 @@ Algorithm 2").
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -76,6 +84,8 @@ __all__ = [
     "L1_SHIFT",
     "Constants",
     "make_constants",
+    "adapted_sparsity",
+    "adapt",
     "to_fixed",
     "from_fixed",
     "l1_fixed",
@@ -113,10 +123,13 @@ class Constants:
     Te: _scores.Table
     l1_test: int = 0
     variant: int = 0          # 0 continuous scores, 1 quantised (indicator) scores
+    adaptive_k: int = 0       # rebuild the posteriors after each accepted iteration
+    ell: int = 4
+    k_post: float = 0.0       # the sparsity the current posteriors assume (k at the start)
 
 
 def make_constants(n, m, d, k, sigma, sigma_s=1.0, alpha=2.0, c=0.0, ell=4,
-                   max_iters=0, l1_test=0, variant=0) -> Constants:
+                   max_iters=0, l1_test=0, variant=0, adaptive_k=0) -> Constants:
     """Alg. 1 prologue: p_breve_z, p_breve_e for GM(n, m, k, d, N(0,ss^2), N(0,sn^2))."""
     # Alg. 1 takes the consensus level alpha from (1, d]
     if not (1.0 < alpha <= d):
@@ -133,7 +146,29 @@ def make_constants(n, m, d, k, sigma, sigma_s=1.0, alpha=2.0, c=0.0, ell=4,
     Te = _scores.build_table("e", d, rho, sigma, sigma_s, ell)
     return Constants(n=n, m=m, d=d, k=k, sigma=float(sigma), sigma_s=float(sigma_s),
                      alpha=np.float32(alpha), c=float(c), n_iters=n_it,
-                     tol=_scores.tolerance(m, sigma), Tz=Tz, Te=Te, l1_test=l1_test, variant=variant)
+                     tol=_scores.tolerance(m, sigma), Tz=Tz, Te=Te, l1_test=l1_test, variant=variant,
+                     adaptive_k=adaptive_k, ell=ell, k_post=float(k))
+
+
+def adapted_sparsity(C: Constants, x_hat: np.ndarray) -> float:
+    """k_0 of the adaptive_k branch (module docstring, reading R17)."""
+    x = np.asarray(x_hat, dtype=np.float32)
+    nz = x[x != 0]
+    z = _scores.lookup(C.Tz, np.abs(nz))
+    term = (np.float32(1.0) - z).astype(np.float32)
+    S = int(np.rint(term.astype(np.float64) * (2.0 ** L1_SHIFT)).astype(np.int64).sum(dtype=np.int64))
+    k0 = float(C.k) - float(S) * (2.0 ** -L1_SHIFT)
+    return max(k0, float(C.m // 100), 1.0)
+
+
+def adapt(C: Constants, x_hat: np.ndarray) -> Constants:
+    """The constants after an accepted iteration of the adaptive_k branch: the tables of
+    p_breve_z and p_breve_e rebuilt with rho = k_0 / m; everything else kept."""
+    k0 = adapted_sparsity(C, x_hat)
+    rho = k0 / C.m
+    Tz = _scores.build_table("z", C.d, rho, C.sigma, C.sigma_s, C.ell)
+    Te = _scores.build_table("e", C.d, rho, C.sigma, C.sigma_s, C.ell)
+    return replace(C, Tz=Tz, Te=Te, k_post=k0)
 
 
 # ----------------------------------------------------------------------------- fixed point
@@ -361,6 +396,8 @@ def decode(A_cols, y_hat, C: Constants, keep_trace: bool = False) -> DecodeResul
         updates += int(out.sweep.updated.sum())
         xp = out.sweep.x_prime[out.sweep.updated]
         inexact_x += fx_inexact(xp[xp != 0])
+        if C.adaptive_k and out.accepted and not C.Tz.exact:
+            C = adapt(C, out.state.x_hat)
         if keep_trace:
             trace.append((st.L_hat, out.L_trial, out.accepted))
         st = out.state
