@@ -75,30 +75,34 @@ def iteration_bytes(n: int, m: int, d: int, k: int, u: float) -> float:
 def _oracle_sample(args) -> tuple[int, float]:
     """One process of the CPU baseline: the oracle's first loop iterations of the seeded
     instance, as many as fit in budget_s seconds; returns (iterations, seconds)."""
-    n, m, k, d, sigma, seed, budget_s, variant = args
+    n, m, k, d, sigma, seed, budget_s, variant, adaptive = args
     from oracle import decoder as D
     inst = I.draw_instance(n, m, k, d, sigma, seed)
     y_hat = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-    C = D.make_constants(n, m, d, k, sigma, variant=variant)
+    C = D.make_constants(n, m, d, k, sigma, variant=variant, adaptive_k=adaptive)
     st = D.init_state(y_hat, n)
     t0 = time.perf_counter()
     done = 0
     while time.perf_counter() - t0 < budget_s:
         if st.it >= C.n_iters or D.converged(st, C):
             break
-        st = D.step(inst.A_cols, y_hat, st, C).state
+        out = D.step(inst.A_cols, y_hat, st, C)
+        if adaptive and out.accepted and not C.Tz.exact:
+            C = D.adapt(C, out.state.x_hat)
+        st = out.state
         done += 1
     return done, time.perf_counter() - t0
 
 
-def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 8, variant: int = 0) -> dict:
+def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 8, variant: int = 0,
+                 adaptive: int = 0) -> dict:
     """The oracle (test infrastructure) timed on the host: single-threaded numpy, first on
     one core, then `procs` processes at once on different seeds (the aggregate rate)."""
     import multiprocessing as mp
 
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    done1, dt1 = _oracle_sample((n, m, k, d, sigma, seeds[0], budget_s, variant))
+    done1, dt1 = _oracle_sample((n, m, k, d, sigma, seeds[0], budget_s, variant, adaptive))
     rate1 = d * n * done1 / dt1
     try:
         avail = len(os.sched_getaffinity(0))
@@ -108,7 +112,8 @@ def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 
     ctx = mp.get_context("spawn")
     with ctx.Pool(procs) as pool:
         res = pool.map(_oracle_sample,
-                       [(n, m, k, d, sigma, seeds[i % len(seeds)], budget_s, variant) for i in range(procs)])
+                       [(n, m, k, d, sigma, seeds[i % len(seeds)], budget_s, variant, adaptive)
+                        for i in range(procs)])
     agg = sum(d * n * it / t for it, t in res)
     its = [it for it, _ in res]
     return {"value": agg, "unit": "nnz(A)-updates/s", "cores": procs, "kind": "oracle",
@@ -304,7 +309,7 @@ def bench_batched(args) -> int:
 
 
 def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int, workload: str,
-                 cpu: bool, variant: int = 0) -> int:
+                 cpu: bool, variant: int = 0, adaptive: int = 0) -> int:
     """Single decodes of `seeds` seeded instances of GM(N, M, K, DD) at SNR 40 dB, step i on
     seed i mod seeds (sketch + decode, graph replay), then the same steps again with HIP
     events on every loop kernel for the roofline."""
@@ -324,7 +329,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
             "eta": torch.from_numpy(inst.eta).to(dev),
         })
         del inst
-    params = R.params_default(N, M, DD, K, sigma, variant=variant)
+    params = R.params_default(N, M, DD, K, sigma, variant=variant, adaptive_k=adaptive)
     y = torch.empty(M, dtype=torch.float32, device=dev)
     y_hat = torch.empty(M, dtype=torch.float32, device=dev)
     x_hat = torch.empty(N, dtype=torch.float32, device=dev)
@@ -390,6 +395,8 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     metric = METRIC if (N, DD) == (2 ** 20, 7) else f"Robust-l0 nnz(A)-updates/s and time-to-solution, n={N} d={DD}"
     if variant == 1:
         metric = metric.replace("Robust-l0", "Robust-l0-quantised", 1)
+    if adaptive:
+        metric = metric.replace("Robust-l0", "Robust-l0 (adaptive_k)", 1)
     out = {
         "metric": metric,
         "value": value,
@@ -409,10 +416,14 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "n": N, "m": M, "d": DD, "k": K, "snr_db": SNR, "seeds": seeds,
-                   "scores": "quantised" if variant == 1 else "continuous",
-                   "setup": "one untimed decode per instance captures its graph before the warm-up; "
-                            "y_hat and x_hat are fixed device buffers; the host constants of the "
-                            "parameter set (score tables, thresholds) are computed once and cached"},
+                   "scores": "quantised" if variant == 1 else "continuous", "adaptive_k": adaptive,
+                   "setup": ("one untimed decode per instance captures its graph before the warm-up; "
+                             "y_hat and x_hat are fixed device buffers; the host constants of the "
+                             "parameter set (score tables, thresholds) are computed once and cached")
+                            if not adaptive else
+                            ("eager launches; after every iteration the host reads back the decision and "
+                             "k_0 and, after an accepted one, recomputes the score tables and thresholds "
+                             "(inside the timed region)")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": sweep_traffic() if (N, M, DD) == (2 ** 20, 104857, 7) else None,
@@ -433,7 +444,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     }
     if cpu:
         del insts
-        out["cpu_baseline"] = cpu_baseline(N, M, K, DD, sigma, seed_ids[:8], variant=variant)
+        out["cpu_baseline"] = cpu_baseline(N, M, K, DD, sigma, seed_ids[:8], variant=variant, adaptive=adaptive)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -446,7 +457,8 @@ def main() -> int:
     ap.add_argument("--seeds", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-n", type=int, default=2 ** 22, help="n of the phase-transition ladders")
-    ap.add_argument("--workload", choices=["headline", "batched", "learned", "large", "quantised", "phase"],
+    ap.add_argument("--workload", choices=["headline", "batched", "learned", "large", "quantised", "phase",
+                                           "adaptive"],
                     default="headline",
                     help="batched: 512 uneven instances in one persistent launch, against "
                          "sequential single decodes of the same instances")
@@ -478,6 +490,12 @@ def main() -> int:
                             "Robust-l0-quantised decode of y_hat = A x + eta, n=2^20, m=104857, d=7, "
                             "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode",
                             cpu=not args.no_cpu_baseline, variant=1)
+    if args.workload == "adaptive":
+        return bench_decode(args, N, M, K, DD, 2, args.seeds,
+                            "Robust-l0 decode with adaptive_k of y_hat = A x + eta, n=2^20, m=104857, d=7, "
+                            "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode (eager launches, "
+                            "one host round trip per iteration)",
+                            cpu=not args.no_cpu_baseline, adaptive=1)
     return bench_decode(args, N, M, K, DD, 2, args.seeds,
                         "Robust-l0 decode of y_hat = A x + eta, n=2^20, m=104857, d=7, "
                         "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode",

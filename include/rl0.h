@@ -65,7 +65,16 @@ typedef struct rl0_params {
     int32_t variant;        /* scores of Table "scores": 0 = continuous, 1 = quantised
                                (indicators q_e = 1{p_breve_e >= t}, q_z = 1{p_breve_z >= 1 - t};
                                c = 0 then selects eq:finetune_c_quant) */
-    int32_t adaptive_k;     /* 0 (Alg. 1's adaptive_k branch is not supported: RL0_EINVAL) */
+    int32_t adaptive_k;     /* 1 = Alg. 1's adaptive_k branch (rl0_decode, analytic scores,
+                               sigma > 0): after every accepted iteration the posteriors'
+                               sparsity becomes k_0 = max(k - sum_j (1 - p_breve_z(|x_hat_j|)),
+                               floor(m/100), 1) and the score tables and outer-test thresholds
+                               are rebuilt with rho = k_0/m (c, the t-sweep, H_k's k and the
+                               stopping tolerance stay); the sum is taken in units of 2^-30,
+                               sum_j rint(2^30 fl32(1 - Tz(|x_hat_j|))).  The host reads k_0
+                               back after every iteration, so such a decode is launched
+                               eagerly rather than replayed from a graph.  Ignored for
+                               sigma = 0.  rl0_step, learned and batched decodes: RL0_EINVAL */
 } rl0_params;
 
 /* What a decode did.  l1 values are ||r_hat||_1; the fixed-point one is exact. */
@@ -86,6 +95,8 @@ typedef struct rl0_stats {
                                exact on those rows */
     int32_t fx_inexact_x;   /* updated entries x'_j != 0 whose conversion rounds, summed over
                                the executed iterations (0 for batched and learned decodes) */
+    double k_post;          /* the sparsity the posteriors assumed last: k, or with adaptive_k
+                               the last k_0 */
 } rl0_stats;
 
 /* Host copy of the decoder's constants, for inspection and tests. */

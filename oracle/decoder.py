@@ -381,6 +381,8 @@ class DecodeResult:
     fx_inexact_y: int = 0     # entries of y_hat whose fixed-point conversion rounds
     fx_inexact_x: int = 0     # nonzero x'_j of updated columns whose conversion rounds,
                               # summed over the executed iterations
+    k_post: float = 0.0       # the sparsity the posteriors of the last executed iteration
+                              # assumed (k unless adaptive_k)
     trace: list = field(default_factory=list)
 
 
@@ -391,7 +393,9 @@ def decode(A_cols, y_hat, C: Constants, keep_trace: bool = False) -> DecodeResul
     trace = []
     updates = 0
     inexact_x = 0
+    k_last = C.k_post
     while st.it < C.n_iters and not converged(st, C):
+        k_last = C.k_post
         out = step(A_cols, y_hat, st, C)
         updates += int(out.sweep.updated.sum())
         xp = out.sweep.x_prime[out.sweep.updated]
@@ -404,4 +408,4 @@ def decode(A_cols, y_hat, C: Constants, keep_trace: bool = False) -> DecodeResul
     return DecodeResult(x_hat=st.x_hat, r_hat=st.r_hat, L_hat=st.L_hat, iterations=st.it,
                         accepted=st.accepted, converged=converged(st, C),
                         updates_total=updates, fx_inexact_y=fx_inexact(y_hat), fx_inexact_x=inexact_x,
-                        trace=trace)
+                        k_post=k_last, trace=trace)

@@ -163,7 +163,7 @@ bool compute_constants(const Problem& pr, HostConstants* hc) {
     hc->n_iters = iterations_for(hc->c);
     if (pr.max_iters > 0 && pr.max_iters < hc->n_iters) hc->n_iters = pr.max_iters;
     hc->tol = pr.m * pr.sigma * std::sqrt(2.0 / M_PI);
-    const double rho = static_cast<double>(pr.k) / pr.m;
+    const double rho = (pr.k_post > 0.0 ? pr.k_post : static_cast<double>(pr.k)) / pr.m;
     if (hc->exact) {
         std::memset(hc->table_z, 0, sizeof(hc->table_z));
         std::memset(hc->table_e, 0, sizeof(hc->table_e));

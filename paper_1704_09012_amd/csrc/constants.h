@@ -15,6 +15,7 @@ struct Problem {
     int ell = 4;
     int max_iters = 0;
     int variant = 0;   // 0 continuous scores, 1 quantised
+    double k_post = 0.0;   // the sparsity the posteriors assume (adaptive_k); 0 = k
 };
 
 struct HostConstants {

@@ -47,7 +47,9 @@ struct DevState {
     int err;                              // ErrFlag bits
     int inexact_y;                        // entries of y whose fixed-point conversion rounds
     int inexact_x;                        // updated x'_j != 0 whose conversion rounds (all sweeps)
-    int peek_cur, peek_done;              // the coming decision, evaluated ahead (learned decode)
+    int peek_cur, peek_done;              // the coming decision, evaluated ahead (learned decode,
+    int peek_acc;                         //   adaptive_k): buffer, stop, accepted
+    long long adapt_sum;                  // sum_j rint(2^30 fl32(1 - Tz(|x_hat_j|))) (adaptive_k)
     int bucket_n[2];                      // entries of H_k's boundary bucket listed by k_hk_classify
     int seg_count[2][kSweepGridMax];      // candidates written by each sweep workgroup
     int seg_front[2][kSweepGridMax];      //   of which at the segment's front (tested columns)
@@ -149,9 +151,18 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
 hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Workspace& w,
                             const ScoreTables& tb, const IterParams& ip, const DebugOut& dbg,
                             hipStream_t s, const hipEvent_t* ev = nullptr, const float* learned = nullptr);
-// The decision the next sweep will take, written ahead to DevState::peek_cur/peek_done
-// (ip.it = that sweep's iteration).
+// The decision the next sweep will take, written ahead to DevState::peek_cur/peek_done/
+// peek_acc (ip.it = that sweep's iteration).
 hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s);
+// adaptive_k, after iteration it (ip.it = it + 1, whose decision launch_peek evaluated):
+// DevState::adapt_sum <- sum over x_hat = H_k(x') of iteration it (were it accepted) of
+// rint(2^30 fl32(1 - Tz(|x_hat_j|))), on the tables of tb.
+hipError_t launch_adapt_sum(const Workspace& w, const ScoreTables& tb, int it, hipStream_t s);
+// The outer-test bitmask (and, for large m, its summary and flagged-row counts) of the
+// residual buffer `buf` redone for the threshold tau, after the posteriors changed
+// (adaptive_k); it = the iteration that produced that residual.
+hipError_t launch_rebuild_outer(const DecodeDims& dm, const Workspace& w, int buf, uint32_t tau, int it,
+                                hipStream_t s);
 // Decide the last iteration (ip_last.it = n_iters) and write x_out = x_hat (x_zeroed: x_out
 // already holds zeros).
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,

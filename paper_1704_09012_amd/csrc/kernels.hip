@@ -1398,6 +1398,64 @@ __global__ __launch_bounds__(256) void k_peek(DevState* st, int it, int n_iters,
         const Slot s = decide(st, it, n_iters, tol_fx, Lt);
         st->peek_cur = s.cur;
         st->peek_done = s.done;
+        st->peek_acc = s.accepted_last;
+        st->adapt_sum = 0;
+    }
+}
+
+// adaptive_k: the sum over x_hat = H_k(x') of iteration it (segments of parity it & 1) of
+// rint(2^30 fl32(1 - Tz(|x_hat_j|))).  One workgroup per segment; runs after k_peek.
+__global__ __launch_bounds__(256) void k_adapt_sum(const Workspace w, ScoreTables tb, int it) {
+    __shared__ long long red[4];
+    const int par = it & 1;
+    const int seg = blockIdx.x;
+    const int cnt = w.st->seg_count[par][seg];
+    const int front = w.st->seg_front[par][seg];
+    const unsigned long long kth = w.st->kth_key[par];
+    long long acc = 0;
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const size_t ix = static_cast<size_t>(seg) * w.seg_cap + (e < front ? e : w.seg_cap - 1 - (e - front));
+        const int j = w.cand_j[par][ix];
+        const float v = current_value(1, j, w.cand_x[par][ix], w.cand_h[par][ix], kth);
+        if (v == 0.0f) continue;
+        const float z = score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v));
+        acc += __double2ll_rn(static_cast<double>(1.0f - z) * kTwo30);
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(reinterpret_cast<unsigned long long*>(&w.st->adapt_sum), static_cast<unsigned long long>(t));
+    }
+}
+
+// The outer-test bitmask of residual buffer b redone for threshold tau; for m past the LDS
+// bitmask also its 8-row summary and the flagged-row counts the next sweep's dense mode
+// reads (flag_part of parity it & 1, buffer b).
+__global__ __launch_bounds__(kRowBlock) void k_rebuild_outer(const float* __restrict__ r, uint32_t* __restrict__ bm,
+                                                             uint8_t* __restrict__ bs, int m, uint32_t tau,
+                                                             unsigned* __restrict__ flags) {
+    __shared__ unsigned flw[kRowBlock / 64];
+    const int words = (m + 31) >> 5;
+    unsigned fl = 0u;
+    for (int base = blockIdx.x * kRowBlock; base < m; base += gridDim.x * kRowBlock) {
+        const int i = base + threadIdx.x;
+        const bool bit = i < m && abs_bits(r[i]) >= tau;
+        const unsigned long long b = __ballot(bit);
+        fl += static_cast<unsigned>(__popcll(b));
+        if ((threadIdx.x & 63) == 0) {
+            const int wb = base + (threadIdx.x & ~63);
+            store_bits(bm, words, wb, b);
+            if (bs && wb < m) bs[wb >> 6] = summary8(b);
+        }
+    }
+    if ((threadIdx.x & 63) == 0) flw[threadIdx.x >> 6] = fl;
+    __syncthreads();
+    if (threadIdx.x == 0 && flags) {
+        unsigned f = 0u;
+        for (int w = 0; w < kRowBlock / 64; ++w) f += flw[w];
+        flags[blockIdx.x] = f;
     }
 }
 
@@ -1678,6 +1736,21 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
 
 hipError_t launch_peek(const Workspace& w, const IterParams& ip, hipStream_t s) {
     k_peek<<<1, 256, 0, s>>>(w.st, ip.it, ip.n_iters, ip.tol_fx);
+    return hipGetLastError();
+}
+
+hipError_t launch_adapt_sum(const Workspace& w, const ScoreTables& tb, int it, hipStream_t s) {
+    k_adapt_sum<<<w.sweep_grid, 256, 0, s>>>(w, tb, it);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebuild_outer(const DecodeDims& dm, const Workspace& w, int buf, uint32_t tau, int it,
+                                hipStream_t s) {
+    const bool summary = ((dm.m + 31) / 32) > kBmLdsWords && ((dm.m + 255) / 256) <= kBmLdsWords;
+    const bool counts = ((dm.m + 31) / 32) > kBmLdsWords;
+    k_rebuild_outer<<<kRowGrid, kRowBlock, 0, s>>>(w.r[buf], w.bm[buf],
+                                                  summary ? reinterpret_cast<uint8_t*>(w.bs[buf]) : nullptr, dm.m, tau,
+                                                  counts ? w.st->flag_part[it & 1][buf] : nullptr);
     return hipGetLastError();
 }
 

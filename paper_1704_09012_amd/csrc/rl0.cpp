@@ -95,6 +95,7 @@ struct DeviceConstants {
     const uint32_t* d_tau = nullptr;  // outer-test threshold bits per iteration
     const uint32_t* d_qe = nullptr;   // quantised-score thresholds per iteration (after tau)
     const uint32_t* d_qz = nullptr;
+    size_t bytes = 0;                 // size of the d_tables allocation
 };
 
 using ConstKey = std::tuple<int, int, int, int, int, uint32_t, uint32_t, double, int, int, int>;
@@ -125,7 +126,13 @@ int upload_constants(DeviceConstants* dc) {
         std::memcpy(staging.data() + tab + per, dc->hc.qe_bits.data(), ntau * sizeof(uint32_t));
         std::memcpy(staging.data() + tab + 2 * per, dc->hc.qz_bits.data(), ntau * sizeof(uint32_t));
     }
-    if (hipMalloc(&dc->d_tables, staging.size()) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(tables)");
+    if (dc->bytes < staging.size()) {   // a constant set rewritten in place keeps a large enough block
+        if (dc->d_tables) HIP_TRY(hipFree(dc->d_tables));
+        dc->d_tables = nullptr;
+        dc->bytes = 0;
+        if (hipMalloc(&dc->d_tables, staging.size()) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(tables)");
+        dc->bytes = staging.size();
+    }
     HIP_TRY(hipMemcpy(dc->d_tables, staging.data(), staging.size(), hipMemcpyHostToDevice));
     const char* base = reinterpret_cast<const char*>(dc->d_tables);
     dc->d_tau = reinterpret_cast<const uint32_t*>(base + tab);
@@ -221,6 +228,7 @@ struct Buffers {
     hipEvent_t ev_call[2] = {nullptr, nullptr};   // start and end of a decode (rl0_stats.ms_total)
     std::vector<GraphEntry> graphs;    // replayable decodes on this workspace
     unsigned long long uses = 0;
+    std::unique_ptr<DeviceConstants> adapted;   // adaptive_k: the decode's current constants
 };
 
 bool graphs_enabled() {
@@ -316,7 +324,9 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
         return fail(RL0_EINVAL, "the learned posterior supports d <= 15");
     if (p->variant != 0 && p->variant != 1)
         return fail(RL0_EINVAL, "variant must be 0 (continuous scores) or 1 (quantised)");
-    if (p->adaptive_k != 0) return fail(RL0_EINVAL, "adaptive_k is not supported (must be 0)");
+    if (p->adaptive_k != 0 && p->adaptive_k != 1) return fail(RL0_EINVAL, "adaptive_k must be 0 or 1");
+    if (p->adaptive_k == 1 && p->posterior == 1)
+        return fail(RL0_EINVAL, "adaptive_k applies to the analytic posteriors only");
     return RL0_OK;
 }
 
@@ -623,6 +633,7 @@ int plan_batch(const rl0_problem* probs, int count, hipStream_t s, BatchPlan* pl
         const rl0_problem& q = probs[i];
         auto bad = [&](int rc) { return fail(rc, "instance " + std::to_string(i) + ": " + g_last_error); };
         if (int rc = check_params(&q.params, q.n, q.m, q.d)) return bad(rc);
+        if (q.params.adaptive_k) return bad(fail(RL0_EINVAL, "adaptive_k is not supported by batched decodes"));
         if (!q.A_cols || !q.y || !q.x_out) return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": NULL pointer");
         if (reinterpret_cast<uintptr_t>(q.A_cols) % 16)
             return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": A_cols must be 16-byte aligned");
@@ -918,7 +929,7 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
 // Fills *st_h from a finished decode's device state (copied to the host) and the
 // workspace's call events (both recorded on the decode's stream, now synchronised).
 void fill_stats(rl0_stats* st_h, const rl0::DevState& ds, const rl0::Slot& fin, const DeviceConstants* dc,
-                float t_final, Buffers* b) {
+                float t_final, Buffers* b, double k_post) {
     st_h->iterations = fin.iterations;
     st_h->accepted = fin.accepted;
     st_h->l1_final_fx = fin.L_hat;
@@ -930,6 +941,7 @@ void fill_stats(rl0_stats* st_h, const rl0::DevState& ds, const rl0::Slot& fin, 
     st_h->error_flags = ds.err;
     st_h->fx_inexact_y = ds.inexact_y;
     st_h->fx_inexact_x = ds.inexact_x;
+    st_h->k_post = k_post;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, b->ev_call[0], b->ev_call[1]) == hipSuccess) {
         st_h->ms_total = ms;
@@ -1069,11 +1081,71 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[0];   // sub-iteration 2N decides last
-    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f, b);
+    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f, b, p->k);
     return err_code_of(ds.err);
 }
 
 // ---------------------------------------------------------------- network training memory
+
+// Alg. 1 with the adaptive_k branch.  After iteration it the decision on it (evaluated
+// ahead by launch_peek) and sum_j rint(2^30 fl32(1 - Tz(|x_hat_j|))) over the x_hat that
+// acceptance would give are read back; when accepted, the posteriors' sparsity becomes
+// k_0 = max(k - 2^-30 sum, floor(m/100), 1) and the constants of every later iteration are
+// recomputed with rho = k_0/m (the t-sweep and c stay, being functions of k).  The
+// outer-test bitmask of the residual the next sweep starts from was built with the old
+// threshold tau_{it+1}; it is redone with the new one.  The launches of it + 1 depend on a
+// value read back after it, so the decode is launched eagerly, one host round trip per
+// iteration.
+int decode_adaptive(Buffers* b, const DeviceConstants* dc0, const rl0::Problem& pr0, const rl0::DecodeDims& dm,
+                    const int32_t* A, const float* y, const rl0_params* p, float* x_out, rl0_stats* st_h,
+                    hipStream_t s) {
+    const rl0::Workspace& w = b->w;
+    const int N = dc0->hc.n_iters;
+    const rl0::DebugOut dbg{nullptr, nullptr};
+    const DeviceConstants* dc = dc0;
+    rl0::Problem pr = pr0;
+    double k_post = static_cast<double>(p->k);
+    const double k_floor = std::max(static_cast<double>(dm.m / 100), 1.0);
+    if (st_h) HIP_TRY(hipEventRecord(b->ev_call[0], s));
+    HIP_TRY(rl0::launch_prepare(dm, A, p->validate != 0, y, nullptr, w, iter_params(dc, p, 0), s, x_out));
+    int it_end = N;
+    for (int it = 0; it < N; ++it) {
+        HIP_TRY(rl0::launch_iteration(dm, A, w, tables_of(dc), iter_params(dc, p, it), dbg, s, profile_events(it)));
+        if (it + 1 == N) break;
+        HIP_TRY(rl0::launch_peek(w, iter_params(dc, p, it + 1), s));
+        HIP_TRY(rl0::launch_adapt_sum(w, tables_of(dc), it, s));
+        HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const rl0::DevState& ds = *b->st_host;
+        if (ds.peek_done) {   // stopped (converged, or an error flag): the decision is final
+            it_end = it + 1;
+            break;
+        }
+        if (!ds.peek_acc) continue;
+        const double k0 = std::max(static_cast<double>(p->k) - static_cast<double>(ds.adapt_sum) * 0x1p-30, k_floor);
+        if (k0 == k_post) continue;
+        k_post = k0;
+        pr.k_post = k0;
+        const uint32_t tau_old = dc->hc.tau_bits[it + 1];
+        if (!b->adapted) b->adapted = std::make_unique<DeviceConstants>();
+        // every launch that read the previous constants has completed (the stream is
+        // synchronised), so the one set is rewritten in place
+        rl0::compute_constants(pr, &b->adapted->hc);
+        if (int rc = upload_constants(b->adapted.get())) return rc;
+        dc = b->adapted.get();
+        if (dc->hc.tau_bits[it + 1] != tau_old)
+            HIP_TRY(rl0::launch_rebuild_outer(dm, w, ds.peek_cur, dc->hc.tau_bits[it + 1], it, s));
+    }
+    HIP_TRY(rl0::launch_finish(dm, w, iter_params(dc, p, it_end), x_out, s, true));
+    if (st_h) HIP_TRY(hipEventRecord(b->ev_call[1], s));
+    HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const rl0::DevState& ds = *b->st_host;
+    const rl0::Slot& fin = ds.slot[it_end & 1];
+    profile_collect(it_end, fin.iterations, dm.m > rl0::kPreRows);
+    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b, k_post);
+    return err_code_of(ds.err);
+}
 
 struct MlpBuffers {
     float* grad = nullptr;
@@ -1236,6 +1308,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     if (int rc = get_workspace(dev, s, n, m, &b)) return rc;
     const rl0::DecodeDims dm{n, m, d, p->k};
     if (p->posterior == 1) return decode_learned(b, dc, dm, A_cols, y, p, x_out, st_h, s);
+    if (p->adaptive_k == 1 && !dc->hc.exact) return decode_adaptive(b, dc, problem_of(p, n, m, d), dm, A_cols, y, p, x_out, st_h, s);
     const rl0::ScoreTables tb = tables_of(dc);
     const int N = dc->hc.n_iters;
     auto issue = [&](hipStream_t q, const float* yq, float* xq) -> int {
@@ -1269,7 +1342,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[N & 1];
     profile_collect(N, fin.iterations, m > rl0::kPreRows);
-    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b);
+    if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b, p->k);
     return err_code_of(ds.err);
 }
 
@@ -1281,6 +1354,7 @@ int rl0_step(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const float
     if (!A_cols || !y || !x_hat || !r_hat || !L_hat_h) return fail(RL0_EINVAL, "NULL pointer");
     if (reinterpret_cast<uintptr_t>(A_cols) % 16) return fail(RL0_EINVAL, "A_cols must be 16-byte aligned");
     if (it < 0) return fail(RL0_EINVAL, "it must be >= 0");
+    if (p->adaptive_k) return fail(RL0_EINVAL, "adaptive_k applies to whole decodes (rl0_decode)");
     std::lock_guard<std::mutex> lk(g_mu);
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;

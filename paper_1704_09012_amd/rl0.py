@@ -60,6 +60,7 @@ class Stats(ctypes.Structure):
         ("ms_total", ctypes.c_float),
         ("fx_inexact_y", ctypes.c_int32),
         ("fx_inexact_x", ctypes.c_int32),
+        ("k_post", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

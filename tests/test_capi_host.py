@@ -44,7 +44,8 @@ def test_params_default_follow_the_paper():
 @pytest.mark.parametrize("field,value", [
     ("k", 0), ("k", 256), ("alpha", 1.0), ("alpha", 7.5), ("c", 1.0), ("c", -0.1),
     ("sigma", -1.0), ("sigma", float("nan")), ("sigma_signal", 0.0), ("series_terms", 0),
-    ("max_iters", -1), ("l1_test", 2), ("posterior", 3), ("variant", 2), ("variant", -1), ("adaptive_k", 1),
+    ("max_iters", -1), ("l1_test", 2), ("posterior", 3), ("variant", 2), ("variant", -1), ("adaptive_k", 2),
+    ("adaptive_k", -1),
 ])
 def test_bad_params_are_rejected_on_the_host(field, value):
     p = R.params_default(1024, 256, 7, 25, 0.01)
@@ -181,6 +182,29 @@ def test_batched_rejects_bad_instances_before_device_work():
     arr[1] = _fake_problem()
     assert L.rl0_decode_batched(arr, 3, None, None) == -1
     assert b"instance 2" in L.rl0_last_error()
+
+
+def test_adaptive_k_is_refused_where_it_does_not_apply():
+    # the branch needs the analytic posteriors and a whole decode: a learned decode, one
+    # step from a caller's state and the batched kernel refuse it before any device work
+    L = R.lib()
+    p = R.params_default(1024, 256, 7, 25, 0.01)
+    p.adaptive_k = 1
+    R.compute_constants(p, 1024, 256, 7)          # accepted on its own
+    p.posterior, p.mlp = 1, 4096
+    with pytest.raises(R.Rl0Error) as e:
+        R.compute_constants(p, 1024, 256, 7)
+    assert e.value.code == -1 and "analytic" in str(e.value)
+    p.posterior, p.mlp = 0, None
+    Lh = ctypes.c_int64(0)
+    rc = L.rl0_step(ctypes.c_void_p(4096), 1024, 256, 7, ctypes.c_void_p(8192), ctypes.byref(p), 0,
+                    ctypes.c_void_p(16384), ctypes.c_void_p(32768), ctypes.byref(Lh), None, None, None,
+                    None, None, None)
+    assert rc == -1 and b"whole decodes" in L.rl0_last_error()
+    arr = (R.Problem * 2)(_fake_problem(), _fake_problem())
+    arr[1].params.adaptive_k = 1
+    assert L.rl0_decode_batched(arr, 2, None, None) == -1
+    assert b"instance 1" in L.rl0_last_error() and b"adaptive_k" in L.rl0_last_error()
 
 
 def test_batch_schedule_rejects_bad_fields():
