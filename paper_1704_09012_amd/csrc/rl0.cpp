@@ -1721,32 +1721,39 @@ int rl0_profile_read_kernels(double* ms_total_h, int64_t* counts_h) {
 
 void rl0_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
-    hipDeviceSynchronize();
+    // teardown: errors are not reported (the handles are dropped either way)
+    (void)hipDeviceSynchronize();
     for (auto& kv : g_ws) {
-        drop_graphs(kv.second.get());
-        if (kv.second->capture) hipStreamDestroy(kv.second->capture);
-        if (kv.second->block) hipFree(kv.second->block);
-        if (kv.second->st_host) hipHostFree(kv.second->st_host);
+        Buffers* b = kv.second.get();
+        drop_graphs(b);
+        if (b->capture) (void)hipStreamDestroy(b->capture);
+        for (hipEvent_t e : b->ev_call)
+            if (e) (void)hipEventDestroy(e);
+        if (b->block) (void)hipFree(b->block);
+        if (b->st_host) (void)hipHostFree(b->st_host);
+        if (b->adapted && b->adapted->d_tables) (void)hipFree(b->adapted->d_tables);
     }
     g_ws.clear();
     for (auto& kv : g_bws) {
         BatchBuffers* b = kv.second.get();
         drop_batch_graphs(b);
-        if (b->capture) hipStreamDestroy(b->capture);
+        if (b->capture) (void)hipStreamDestroy(b->capture);
         for (hipEvent_t e : b->ev)
-            if (e) hipEventDestroy(e);
-        if (b->block) hipFree(b->block);
-        if (b->meta) hipFree(b->meta);
-        if (b->host) hipHostFree(b->host);
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : b->ev_call)
+            if (e) (void)hipEventDestroy(e);
+        if (b->block) (void)hipFree(b->block);
+        if (b->meta) (void)hipFree(b->meta);
+        if (b->host) (void)hipHostFree(b->host);
     }
     g_bws.clear();
     for (auto& kv : g_mlp)
-        if (kv.second.grad) hipFree(kv.second.grad);
+        if (kv.second.grad) (void)hipFree(kv.second.grad);
     g_mlp.clear();
     for (auto& kv : g_consts)
-        if (kv.second->d_tables) hipFree(kv.second->d_tables);
+        if (kv.second->d_tables) (void)hipFree(kv.second->d_tables);
     g_consts.clear();
-    for (hipEvent_t e : g_prof.pool) hipEventDestroy(e);
+    for (hipEvent_t e : g_prof.pool) (void)hipEventDestroy(e);
     g_prof.pool.clear();
 }
 

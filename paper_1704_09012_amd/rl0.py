@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librl0.so")
+# RL0_LIBRARY names another build of the same library (e.g. one with host sanitizers)
+LIB_PATH = os.environ.get("RL0_LIBRARY") or os.path.join(_HERE, "librl0.so")
 
 RL0_TABLE_N = 4096
 RL0_MAX_D = 16
