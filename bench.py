@@ -154,12 +154,15 @@ def bench_learned(args) -> int:
     F, Y = Lrn.trajectories(2000, 1)
     torch.cuda.synchronize()
     t_traj = time.perf_counter() - t0
+    print(f"trajectories: {F.shape[0]} samples in {t_traj:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     w, loss = Lrn.train(F, Y, epochs=30)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    print(f"trained in {t_train:.1f} s, loss {loss:.4f}", file=sys.stderr, flush=True)
     per_snr = {}
     for snr in (20, 40, 60):
+        print(f"comparing at {snr} dB", file=sys.stderr, flush=True)
         rows = Lrn.compare(w, N, M, K, snr, [I.seed_for(5, i, j) for i, j in [(snr // 20, j) for j in range(args.seeds)]])
         agg = {}
         for tag in ("analytic", "learned"):
@@ -172,6 +175,7 @@ def bench_learned(args) -> int:
                 "ms_each": [round(r[tag]["ms"], 3) for r in rows],
             }
         per_snr[str(snr)] = agg
+    kernels = _learned_kernel_costs(w)
     out = {
         "metric": "learned vs analytic column decision, n=2^20 d=7",
         "value": per_snr["40"]["learned"]["ms_median"],
@@ -186,9 +190,90 @@ def bench_learned(args) -> int:
         "training": {"samples": int(F.shape[0]), "positives": int(Y[:, 0].sum()), "loss": loss,
                      "trajectory_s": t_traj, "train_s": t_train},
         "per_snr": per_snr,
+        "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+# VALU model of the learned column decision (bf16 network on the matrix cores): per column
+# 128 GELUs (two hidden layers of 64), each 12 full-rate VALU instructions and 2
+# transcendental ones (reciprocal, base-2 exponential), which issue at a quarter of the
+# rate, so 12 + 2 * 4 = 20 issue slots per GELU.  Packed fp32 instructions are not used, so
+# the peak is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-slots/s.
+LEARNED_SLOTS_PER_COLUMN = 128 * (12 + 2 * 4)
+VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# fp32 training arithmetic per sample: forward 2 (64 F + 64 * 64 + 2 * 64) flops, backward
+# twice that (input gradients and weight gradients), F = d + 1 = 8
+TRAIN_FLOPS_PER_SAMPLE = 3 * 2 * (64 * 8 + 64 * 64 + 2 * 64)
+
+
+def _learned_kernel_costs(w, reps: int = 10, train_steps: int = 200, batch: int = 4096) -> dict:
+    """Live costs of the learned path's kernels with HIP events on the stream they run on:
+    one learned iteration (rl0_step with the network's decisions, which evaluates the
+    network on every column: n = 2^20, d = 7, 40 dB, from x_hat = 0 at t-step 10) against
+    the same analytic iteration, and training steps of `batch` samples (gradient + Adam)."""
+    import torch
+    from paper_1704_09012_amd import rl0 as R
+
+    sigma = float(np.float32(I.sigma_for_snr(SNR, N, M, K, DD)))
+    A, x, eta = I.draw_instance_device(N, M, K, DD, sigma, 777)
+    y = R.sketch(A, x, M) + eta
+    x0 = torch.zeros(N, dtype=torch.float32, device="cuda")
+    L0 = int(torch.round(torch.abs(y).double() * 2.0 ** 30).sum().item())
+
+    def time_steps(params) -> float:
+        xs, rs = x0.clone(), y.clone()
+        R.step(A, y, params, 10, xs, rs, L0, debug=False)            # warm
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            xs.copy_(x0)
+            rs.copy_(y)
+            ev0.record()
+            R.step(A, y, params, 10, xs, rs, L0, debug=False)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms.append(ev0.elapsed_time(ev1))
+        return float(np.median(ms))
+
+    step_learned = time_steps(R.params_default(N, M, DD, K, sigma, mlp=w))
+    step_analytic = time_steps(R.params_default(N, M, DD, K, sigma))
+    # the learned decision's own kernel, timed by the library with HIP events around it
+    R.profile_enable(True)
+    time_steps(R.params_default(N, M, DD, K, sigma, mlp=w))
+    lc_ms, lc_launches = R.profile_read_learned()
+    R.profile_enable(False)
+    lc_us = 1e3 * lc_ms / max(lc_launches, 1)
+    bound_us = 1e6 * N * LEARNED_SLOTS_PER_COLUMN / VALU_LANE_SLOTS_PER_S
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    F = torch.randn(batch * 8, DD + 1, device="cuda", generator=g)
+    Y = torch.stack([(torch.rand(batch * 8, device="cuda", generator=g) < 0.1).float(),
+                     torch.randn(batch * 8, device="cuda", generator=g)], dim=1).contiguous()
+    wt = w.clone()
+    mm, vv = torch.zeros_like(wt), torch.zeros_like(wt)
+    R.mlp_train(F, Y, wt, mm, vv, 8, batch=batch)                     # warm
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    R.mlp_train(F, Y, wt, mm, vv, train_steps, t0=8, batch=batch)
+    ev1.record()
+    torch.cuda.synchronize()
+    train_us = 1e3 * ev0.elapsed_time(ev1) / train_steps
+    return {
+        "learned_step_ms": step_learned,
+        "analytic_step_ms": step_analytic,
+        "learned_cols_full_us": lc_us,
+        "learned_cols_launches": lc_launches,
+        "learned_cols_valu_bound_us": bound_us,
+        "learned_cols_frac_of_bound": bound_us / lc_us,
+        "learned_cols_model": "every column of n = 2^20 through the network; bound = 128 GELUs per column x "
+                              "(12 + 2 x 4) issue slots / (256 CU x 64 lanes x 2.4 GHz)",
+        "train_step_us": train_us,
+        "train_batch": batch,
+        "train_tflops": TRAIN_FLOPS_PER_SAMPLE * batch / (train_us * 1e-6) / 1e12,
+    }
 
 
 def bench_phase(args) -> int:

@@ -283,7 +283,9 @@ int rl0_mlp_labels(const float* x_true, const float* x_hat, int32_t n, int32_t d
 
 /* Loss over N samples (feats [N][d+1], labels [N][2]): the mean of
  * BCE(logit, y_acc) + lam * (value - y_val)^2.  grad [P] (device) <- its
- * gradient at w (fp32 backpropagation); *loss_h <- the loss.  Synchronises. */
+ * gradient at w (fp32 backpropagation; the shares of the workgroups, which take tiles
+ * of 16 samples, are added in a fixed order, so the result does not vary from run to
+ * run); *loss_h <- the loss.  Synchronises. */
 int rl0_mlp_grad(const float* feats, const float* labels, int32_t N, int32_t d, const float* w, float lam,
                  float* grad, float* loss_h, void* stream);
 
@@ -341,6 +343,11 @@ int rl0_profile_read(double* sweep_ms_total_h, int64_t* sweep_launches_h);
  * before the stopping condition.  counts_h (2 int64, may be NULL): the two iteration
  * counts. */
 int rl0_profile_read_kernels(double* ms_total_h, int64_t* counts_h);
+
+/* The learned column decision (the network on every column of the residual) as
+ * rl0_step with posterior = 1 launches it: total milliseconds and launches since the last
+ * rl0_profile_enable, each launch timed with a pair of HIP events on the step's stream. */
+int rl0_profile_read_learned(double* ms_total_h, int64_t* launches_h);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* rl0_last_error(void);

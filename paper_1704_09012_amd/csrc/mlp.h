@@ -27,10 +27,25 @@ hipError_t launch_mlp_features(const int32_t* A, int n, int d, const float* r, f
 // labels [n][2]: (1 if x_true_j != 0 and |x_true_j - x_hat_j| > thr else 0, x_true_j - x_hat_j).
 hipError_t launch_mlp_labels(const float* x_true, const float* x_hat, int n, double thr, float* labels,
                              hipStream_t s);
-// grad [P] = d(mean loss)/dw over the N samples, loss[0] = the mean loss (both
-// accumulated into zeroed buffers by this call).
+// One Adam step: w, m, v in place; c1 = 1 - beta1^t and c2 = 1 - beta2^t.
+struct AdamStep {
+    float* w;
+    float* m;
+    float* v;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+// Workgroups of a gradient launch; each sums the gradient over its share of the samples.
+constexpr int kGradMaxGroups = 512;
+// Floats of the scratch `part` that launch_mlp_grad needs for column weight d.
+size_t mlp_grad_scratch_floats(int d);
+// grad [P] = d(mean loss)/dw over the N samples, loss[0] = the mean loss (both written,
+// not accumulated).  part: scratch of mlp_grad_scratch_floats(d) floats, the
+// workgroups' shares, added in a fixed order (the result is deterministic).  With adam
+// the kernel that adds the shares also takes the Adam step on each parameter (that
+// kernel starts after every share has been computed from the old weights).
 hipError_t launch_mlp_grad(const float* feats, const float* labels, int N, int d, const float* w, float lam,
-                           float* grad, float* loss, hipStream_t s);
+                           float* grad, float* loss, float* part, hipStream_t s, const AdamStep* adam = nullptr);
 // One Adam step in place; c1 = 1 - beta1^t and c2 = 1 - beta2^t are the bias corrections.
 hipError_t launch_mlp_adam(float* w, const float* grad, float* m, float* v, int P, float lr, float b1, float b2,
                            float eps, float c1, float c2, hipStream_t s);

@@ -27,8 +27,9 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGradSamples = 64;     // samples per training workgroup
+constexpr int kGradTile = 16;        // samples per tile of the training kernel
 constexpr int kGradBlock = 256;
+constexpr int kGradW1Per = (kHidden * (kMaxD + 1) + kGradBlock - 1) / kGradBlock;   // W1 entries per thread
 constexpr float kInvSqrt2 = 0.70710678118654752f;
 constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
@@ -38,21 +39,23 @@ __device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(
 // significant bits) right after: Phi from Abramowitz & Stegun 7.1.26,
 //   erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2),  t = 1 / (1 + p x),
 // for x = |u| / sqrt(2) >= 0 (absolute error <= 1.5e-7), with the hardware's reciprocal
-// and base-2 exponential.
+// and base-2 exponential.  With tail = 1 - Phi(|u|) = (t/2)(a1 + a2 t + ...) exp(-x^2),
+// gelu(u) = u Phi(u) = max(u, 0) - |u| tail for either sign of u; 1/sqrt(2) is folded into
+// p and 1/2 into the a's, so that a GELU is 11 full-rate and 2 transcendental instructions.
 __device__ __forceinline__ float gelu_bf16(float u) {
-    constexpr float p = 0.3275911f;
-    constexpr float a1 = 0.254829592f, a2 = -0.284496736f, a3 = 1.421413741f, a4 = -1.453152027f,
-                    a5 = 1.061405429f;
+    constexpr float p = 0.3275911f * kInvSqrt2;
+    constexpr float a1 = 0.5f * 0.254829592f, a2 = 0.5f * -0.284496736f, a3 = 0.5f * 1.421413741f,
+                    a4 = 0.5f * -1.453152027f, a5 = 0.5f * 1.061405429f;
     constexpr float kHalfLog2e = 0.72134752044448170f;   // log2(e) / 2
-    const float x = fabsf(u) * kInvSqrt2;
-    const float t = __builtin_amdgcn_rcpf(fmaf(p, x, 1.0f));
+    const float a = fabsf(u);
+    const float t = __builtin_amdgcn_rcpf(fmaf(p, a, 1.0f));
     float q = fmaf(t, a5, a4);
     q = fmaf(t, q, a3);
     q = fmaf(t, q, a2);
     q = fmaf(t, q, a1);
-    const float e = __builtin_amdgcn_exp2f(-(u * u) * kHalfLog2e);   // exp(-x^2)
-    const float tail = (0.5f * t) * q * e;                            // 1 - Phi(|u|)
-    return u * (u >= 0.0f ? 1.0f - tail : tail);
+    const float e = __builtin_amdgcn_exp2f((u * u) * -kHalfLog2e);   // exp(-x^2)
+    const float tail = (t * q) * e;
+    return fmaf(-a, tail, fmaxf(u, 0.0f));
 }
 
 __device__ __forceinline__ float gelu_grad(float u) {
@@ -97,159 +100,248 @@ __global__ void k_mlp_labels(const float* __restrict__ x_true, const float* __re
 
 // ------------------------------------------------------------------ training
 
-// One workgroup: 64 samples.  LDS: the weights, the features, the labels and the
-// pre-activations and activations of both hidden layers.
+// One workgroup takes the tiles blockIdx.x, blockIdx.x + gridDim.x, ... of kGradTile
+// samples each and keeps the weights, the tile's features, labels, pre-activations and
+// activations in LDS.  Its share of the gradient of the mean loss is summed over its
+// tiles in registers and written to part[blockIdx.x][P], its share of the loss to
+// part[gridDim.x * P + blockIdx.x]; k_mlp_grad_sum adds the shares in a fixed order, so
+// the gradient does not depend on the order in which workgroups run.  Thread tid works
+// on sample tid / 16 and hidden units 4 (tid % 16) .. + 3 of a tile's activations.
 __global__ __launch_bounds__(kGradBlock) void k_mlp_grad(const float* __restrict__ feats,
                                                          const float* __restrict__ labels, int N, int F,
                                                          const float* __restrict__ w, float lam, float inv_n,
-                                                         float* __restrict__ grad, float* __restrict__ loss) {
-    extern __shared__ float lds[];
+                                                         float* __restrict__ part) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ float red[kGradBlock / 64];
     const int P = kHidden * F + kHidden + kHidden * kHidden + kHidden + 2 * kHidden + 2;
-    float* W = lds;
-    float* Fs = W + P;
-    float* Z1 = Fs + kGradSamples * F;
-    float* H1 = Z1 + kGradSamples * kHidden;
-    float* Z2 = H1 + kGradSamples * kHidden;
-    float* H2 = Z2 + kGradSamples * kHidden;
-    float* dO = H2 + kGradSamples * kHidden;
-    float* Ys = dO + 2 * kGradSamples;
-    const float* W1 = W;
-    const float* b1 = W1 + kHidden * F;
-    const float* W2 = b1 + kHidden;
-    const float* b2 = W2 + kHidden * kHidden;
-    const float* W3 = b2 + kHidden;
-    const float* b3 = W3 + 2 * kHidden;
-    const int tid = threadIdx.x;
-    const int s0 = blockIdx.x * kGradSamples;
-    const int ns = min(kGradSamples, N - s0);
-    for (int i = tid; i < P; i += kGradBlock) W[i] = w[i];
-    for (int i = tid; i < kGradSamples * F; i += kGradBlock) {
-        const int sm = i / F;
-        Fs[i] = sm < ns ? feats[static_cast<size_t>(s0) * F + i] : 0.0f;
-    }
-    for (int i = tid; i < 2 * kGradSamples; i += kGradBlock) {
-        const int sm = i >> 1;
-        Ys[i] = sm < ns ? labels[2 * static_cast<size_t>(s0) + i] : 0.0f;
-    }
-    __syncthreads();
-    constexpr int kAct = kGradSamples * kHidden;
-    // layer 1: element e = (sample, hidden)
-    for (int e = tid; e < kAct; e += kGradBlock) {
-        const int sm = e / kHidden, h = e % kHidden;
-        float a = 0.0f;
-        for (int k = 0; k < F; ++k) a = a + W1[h * F + k] * Fs[sm * F + k];
-        a = a + b1[h];
-        Z1[e] = a;
-        H1[e] = gelu(a);
-    }
-    __syncthreads();
-    for (int e = tid; e < kAct; e += kGradBlock) {
-        const int sm = e / kHidden, h = e % kHidden;
-        float a = 0.0f;
-        for (int k = 0; k < kHidden; ++k) a = a + W2[h * kHidden + k] * H1[sm * kHidden + k];
-        a = a + b2[h];
-        Z2[e] = a;
-        H2[e] = gelu(a);
-    }
-    __syncthreads();
-    // outputs, loss and the gradient at the outputs (one thread per sample)
-    float l = 0.0f;
-    if (tid < kGradSamples) {
-        const int sm = tid;
-        float o0 = 0.0f, o1 = 0.0f;
-        for (int k = 0; k < kHidden; ++k) {
-            o0 = o0 + W3[k] * H2[sm * kHidden + k];
-            o1 = o1 + W3[kHidden + k] * H2[sm * kHidden + k];
-        }
-        o0 = o0 + b3[0];
-        o1 = o1 + b3[1];
-        float g0 = 0.0f, g1 = 0.0f;
-        if (sm < ns) {
-            const float ya = Ys[2 * sm], yv = Ys[2 * sm + 1];
-            const float dv = o1 - yv;
-            l = fmaxf(o0, 0.0f) - ya * o0 + log1pf(expf(-fabsf(o0))) + lam * dv * dv;
-            const float sig = 1.0f / (1.0f + expf(-o0));
-            g0 = (sig - ya) * inv_n;
-            g1 = 2.0f * lam * dv * inv_n;
-        }
-        dO[2 * sm] = g0;
-        dO[2 * sm + 1] = g1;
-    }
-    for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
-    if ((tid & 63) == 0) red[tid >> 6] = l;
-    __syncthreads();
-    if (tid == 0) {
-        float t = 0.0f;
-        for (int wv = 0; wv < kGradBlock / 64; ++wv) t += red[wv];
-        atomicAdd(loss, t * inv_n);
-    }
-    // dZ2 = (dO W3) * gelu'(Z2), in place of Z2
-    for (int e = tid; e < kAct; e += kGradBlock) {
-        const int sm = e / kHidden, h = e % kHidden;
-        const float g = dO[2 * sm] * W3[h] + dO[2 * sm + 1] * W3[kHidden + h];
-        Z2[e] = g * gelu_grad(Z2[e]);
-    }
-    __syncthreads();
+    constexpr int kAct = kGradTile * kHidden;
+    float* W = lds;                          // the parameters, in the layout of mlp.h
+    float* W2T = W + ((P + 3) & ~3);         // W2 transposed, [k][h] (16-byte aligned)
+    float* Fs = W2T + kHidden * kHidden;     // [kGradTile][F]
+    float* Z1 = Fs + kGradTile * F;          // [kGradTile][kHidden]; later dZ1
+    float* H1 = Z1 + kAct;
+    float* Z2 = H1 + kAct;                   // later dZ2
+    float* H2 = Z2 + kAct;
+    float* dO = H2 + kAct;                   // [kGradTile][2]
+    float* Ys = dO + 2 * kGradTile;          // [kGradTile][2]
     const int oW1 = 0, ob1 = kHidden * F, oW2 = ob1 + kHidden, ob2 = oW2 + kHidden * kHidden,
               oW3 = ob2 + kHidden, ob3 = oW3 + 2 * kHidden;
-    // W3, b3
-    for (int i = tid; i < 2 * kHidden + 2; i += kGradBlock) {
-        float g = 0.0f;
-        if (i < 2 * kHidden) {
-            const int o = i / kHidden, k = i % kHidden;
-            for (int sm = 0; sm < kGradSamples; ++sm) g = g + dO[2 * sm + o] * H2[sm * kHidden + k];
-            atomicAdd(&grad[oW3 + i], g);
-        } else {
-            const int o = i - 2 * kHidden;
-            for (int sm = 0; sm < kGradSamples; ++sm) g = g + dO[2 * sm + o];
-            atomicAdd(&grad[ob3 + o], g);
-        }
-    }
-    // W2 [h][k] = sum_s dZ2[s][h] H1[s][k]; b2
-    for (int i = tid; i < kHidden * kHidden; i += kGradBlock) {
-        const int h = i / kHidden, k = i % kHidden;
-        float g = 0.0f;
-        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z2[sm * kHidden + h] * H1[sm * kHidden + k];
-        atomicAdd(&grad[oW2 + i], g);
-    }
-    for (int h = tid; h < kHidden; h += kGradBlock) {
-        float g = 0.0f;
-        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z2[sm * kHidden + h];
-        atomicAdd(&grad[ob2 + h], g);
-    }
-    // dZ1 = (dZ2 W2) * gelu'(Z1), in place of Z1
-    for (int e = tid; e < kAct; e += kGradBlock) {
-        const int sm = e / kHidden, k = e % kHidden;
-        float g = 0.0f;
-        for (int h = 0; h < kHidden; ++h) g = g + Z2[sm * kHidden + h] * W2[h * kHidden + k];
-        Z1[e] = g * gelu_grad(Z1[e]);
-    }
+    const float* W1 = W + oW1;
+    const float* b1 = W + ob1;
+    const float* W2 = W + oW2;
+    const float* b2 = W + ob2;
+    const float* W3 = W + oW3;
+    const float* b3 = W + ob3;
+    const int tid = threadIdx.x;
+    const int sa = tid >> 4, hb = tid & 15;  // sample and unit group of the activation work
+    for (int i = tid; i < P; i += kGradBlock) W[i] = w[i];
+    for (int i = tid; i < kHidden * kHidden; i += kGradBlock) W2T[i] = w[oW2 + (i & 63) * kHidden + (i >> 6)];
+    float gW2[16], gW1[kGradW1Per];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) gW2[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kGradW1Per; ++c) gW1[c] = 0.0f;
+    float gb1 = 0.0f, gb2 = 0.0f, gW3 = 0.0f, gb3 = 0.0f, lsum = 0.0f;
     __syncthreads();
-    // W1 [h][k] = sum_s dZ1[s][h] F[s][k]; b1
-    for (int i = tid; i < kHidden * F; i += kGradBlock) {
-        const int h = i / F, k = i % F;
-        float g = 0.0f;
-        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z1[sm * kHidden + h] * Fs[sm * F + k];
-        atomicAdd(&grad[oW1 + i], g);
+    for (int tile = blockIdx.x; tile * kGradTile < N; tile += gridDim.x) {
+        const int s0 = tile * kGradTile;
+        const int ns = min(kGradTile, N - s0);
+        for (int i = tid; i < kGradTile * F; i += kGradBlock)
+            Fs[i] = i / F < ns ? feats[static_cast<size_t>(s0) * F + i] : 0.0f;
+        if (tid < 2 * kGradTile) Ys[tid] = (tid >> 1) < ns ? labels[2 * static_cast<size_t>(s0) + tid] : 0.0f;
+        __syncthreads();
+        // layer 1
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int h = 4 * hb + i;
+            float a = 0.0f;
+            for (int k = 0; k < F; ++k) a = a + W1[h * F + k] * Fs[sa * F + k];
+            a = a + b1[h];
+            Z1[sa * kHidden + h] = a;
+            H1[sa * kHidden + h] = gelu(a);
+        }
+        __syncthreads();
+        // layer 2, from the transposed weights (a wave's 16 unit groups read 256
+        // consecutive bytes)
+        {
+            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+            for (int k = 0; k < kHidden; ++k) {
+                const float hv = H1[sa * kHidden + k];
+                const float4 wv = *reinterpret_cast<const float4*>(&W2T[k * kHidden + 4 * hb]);
+                a0 = a0 + wv.x * hv;
+                a1 = a1 + wv.y * hv;
+                a2 = a2 + wv.z * hv;
+                a3 = a3 + wv.w * hv;
+            }
+            const float av[4] = {a0, a1, a2, a3};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int h = 4 * hb + i;
+                const float z = av[i] + b2[h];
+                Z2[sa * kHidden + h] = z;
+                H2[sa * kHidden + h] = gelu(z);
+            }
+        }
+        __syncthreads();
+        // outputs, loss and the gradient at the outputs (one thread per sample)
+        if (tid < kGradTile) {
+            const int sm = tid;
+            float o0 = 0.0f, o1 = 0.0f;
+            for (int k = 0; k < kHidden; ++k) {
+                o0 = o0 + W3[k] * H2[sm * kHidden + k];
+                o1 = o1 + W3[kHidden + k] * H2[sm * kHidden + k];
+            }
+            o0 = o0 + b3[0];
+            o1 = o1 + b3[1];
+            float g0 = 0.0f, g1 = 0.0f;
+            if (sm < ns) {
+                const float ya = Ys[2 * sm], yv = Ys[2 * sm + 1];
+                const float dv = o1 - yv;
+                lsum = lsum + (fmaxf(o0, 0.0f) - ya * o0 + log1pf(expf(-fabsf(o0))) + lam * dv * dv);
+                const float sig = 1.0f / (1.0f + expf(-o0));
+                g0 = (sig - ya) * inv_n;
+                g1 = 2.0f * lam * dv * inv_n;
+            }
+            dO[2 * sm] = g0;
+            dO[2 * sm + 1] = g1;
+        }
+        __syncthreads();
+        // dZ2 = (dO W3) * gelu'(Z2), in place of Z2; W3 and b3 from dO and H2
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int h = 4 * hb + i, e = sa * kHidden + h;
+            const float g = dO[2 * sa] * W3[h] + dO[2 * sa + 1] * W3[kHidden + h];
+            Z2[e] = g * gelu_grad(Z2[e]);
+        }
+        if (tid < 2 * kHidden) {
+            const int o = tid >> 6, k = tid & 63;
+            for (int sm = 0; sm < kGradTile; ++sm) gW3 = gW3 + dO[2 * sm + o] * H2[sm * kHidden + k];
+        }
+        if (tid < 2)
+            for (int sm = 0; sm < kGradTile; ++sm) gb3 = gb3 + dO[2 * sm + tid];
+        __syncthreads();
+        // W2 [h][k] += sum_s dZ2[s][h] H1[s][k] (thread: h = tid / 4, 16 consecutive k); b2
+        {
+            const int h = tid >> 2, k0 = 16 * (tid & 3);
+            for (int sm = 0; sm < kGradTile; ++sm) {
+                const float dz = Z2[sm * kHidden + h];
+#pragma unroll
+                for (int c = 0; c < 16; c += 4) {
+                    const float4 hv = *reinterpret_cast<const float4*>(&H1[sm * kHidden + k0 + c]);
+                    gW2[c] = gW2[c] + dz * hv.x;
+                    gW2[c + 1] = gW2[c + 1] + dz * hv.y;
+                    gW2[c + 2] = gW2[c + 2] + dz * hv.z;
+                    gW2[c + 3] = gW2[c + 3] + dz * hv.w;
+                }
+            }
+        }
+        if (tid < kHidden)
+            for (int sm = 0; sm < kGradTile; ++sm) gb2 = gb2 + Z2[sm * kHidden + tid];
+        // dZ1 = (dZ2 W2) * gelu'(Z1), in place of Z1 (nothing else reads Z1 now)
+        {
+            float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, g3 = 0.0f;
+            for (int h = 0; h < kHidden; ++h) {
+                const float dz = Z2[sa * kHidden + h];
+                const float4 wv = *reinterpret_cast<const float4*>(&W2[h * kHidden + 4 * hb]);
+                g0 = g0 + dz * wv.x;
+                g1 = g1 + dz * wv.y;
+                g2 = g2 + dz * wv.z;
+                g3 = g3 + dz * wv.w;
+            }
+            const float gv[4] = {g0, g1, g2, g3};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = sa * kHidden + 4 * hb + i;
+                Z1[e] = gv[i] * gelu_grad(Z1[e]);
+            }
+        }
+        __syncthreads();
+        // W1 [h][k] += sum_s dZ1[s][h] F[s][k]; b1
+#pragma unroll
+        for (int c = 0; c < kGradW1Per; ++c) {
+            const int e = tid + c * kGradBlock;
+            if (e < kHidden * F) {
+                const int h = e / F, k = e % F;
+                for (int sm = 0; sm < kGradTile; ++sm) gW1[c] = gW1[c] + Z1[sm * kHidden + h] * Fs[sm * F + k];
+            }
+        }
+        if (tid < kHidden)
+            for (int sm = 0; sm < kGradTile; ++sm) gb1 = gb1 + Z1[sm * kHidden + tid];
+        __syncthreads();   // the next tile overwrites Fs, Ys and the activations
     }
-    for (int h = tid; h < kHidden; h += kGradBlock) {
-        float g = 0.0f;
-        for (int sm = 0; sm < kGradSamples; ++sm) g = g + Z1[sm * kHidden + h];
-        atomicAdd(&grad[ob1 + h], g);
+    float* __restrict__ out = part + static_cast<size_t>(blockIdx.x) * P;
+    {
+        const int h = tid >> 2, k0 = 16 * (tid & 3);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) out[oW2 + h * kHidden + k0 + c] = gW2[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kGradW1Per; ++c) {
+        const int e = tid + c * kGradBlock;
+        if (e < kHidden * F) out[oW1 + e] = gW1[c];
+    }
+    if (tid < kHidden) {
+        out[ob1 + tid] = gb1;
+        out[ob2 + tid] = gb2;
+    }
+    if (tid < 2 * kHidden) out[oW3 + tid] = gW3;
+    if (tid < 2) out[ob3 + tid] = gb3;
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off);
+    if ((tid & 63) == 0) red[tid >> 6] = lsum;
+    __syncthreads();
+    if (tid == 0) part[static_cast<size_t>(gridDim.x) * P + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One Adam step of parameter i with gradient gi (c1 = 1 - beta1^t, c2 = 1 - beta2^t).
+__device__ __forceinline__ void adam_update(const AdamStep& a, int i, float gi) {
+    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    a.w[i] = a.w[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+}
+
+// grad[p] = the sum of the G shares part[g][p]: thread slice sl adds shares sl, sl + 16,
+// ... (all loaded first; the missing ones add 0), then the 16 partial sums are added in
+// a fixed order.  loss[0] = inv_n times the sum of the G loss shares.  With ADAM the
+// step then updates parameter p.
+constexpr int kSumSlices = 16;
+constexpr int kSharesPerSlice = (kGradMaxGroups + kSumSlices - 1) / kSumSlices;
+template <bool ADAM>
+__global__ __launch_bounds__(64 * kSumSlices) void k_mlp_grad_sum(const float* __restrict__ part, int G, int P,
+                                                                  float inv_n, float* __restrict__ grad,
+                                                                  float* __restrict__ loss, AdamStep adam) {
+    __shared__ float red[kSumSlices][64];
+    const int c = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + c;
+    float v[kSharesPerSlice];
+#pragma unroll
+    for (int q = 0; q < kSharesPerSlice; ++q) {
+        const int g = sl + kSumSlices * q;
+        v[q] = (p < P && g < G) ? part[static_cast<size_t>(g) * P + p] : 0.0f;
+    }
+    float a = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kSharesPerSlice; ++q) a = a + v[q];
+    red[sl][c] = a;
+    __syncthreads();
+    if (sl == 0 && p < P) {
+        float t = 0.0f;
+        for (int q = 0; q < kSumSlices; ++q) t = t + red[q][c];
+        grad[p] = t;
+        if (ADAM) adam_update(adam, p, t);
+    }
+    if (blockIdx.x == 0 && sl == 1) {
+        float l = 0.0f;
+        for (int g = c; g < G; g += 64) l = l + part[static_cast<size_t>(G) * P + g];
+        for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
+        if (c == 0) loss[0] = l * inv_n;
     }
 }
 
-__global__ void k_mlp_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                           float* __restrict__ v, int P, float lr, float b1, float b2, float eps, float c1, float c2) {
+__global__ void k_mlp_adam(const float* __restrict__ g, int P, AdamStep a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    w[i] = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    if (i < P) adam_update(a, i, g[i]);
 }
 
 __global__ void k_zero_floats(float* __restrict__ p, long long count) {
@@ -618,11 +710,18 @@ hipError_t launch_mlp_labels(const float* x_true, const float* x_hat, int n, dou
 
 size_t mlp_grad_lds(int F) {
     const size_t P = static_cast<size_t>(mlp_params(F - 1));
-    return sizeof(float) * (P + kGradSamples * F + 4 * kGradSamples * kHidden + 4 * kGradSamples);
+    return sizeof(float) * (((P + 3) & ~static_cast<size_t>(3)) + kHidden * kHidden + kGradTile * F +
+                            4 * kGradTile * kHidden + 4 * kGradTile);
+}
+
+int mlp_grad_groups(int N) { return std::max(1, std::min(blocks_of(N, kGradTile), kGradMaxGroups)); }
+
+size_t mlp_grad_scratch_floats(int d) {
+    return static_cast<size_t>(kGradMaxGroups) * (static_cast<size_t>(mlp_params(d)) + 1);
 }
 
 hipError_t launch_mlp_grad(const float* feats, const float* labels, int N, int d, const float* w, float lam,
-                           float* grad, float* loss, hipStream_t s) {
+                           float* grad, float* loss, float* part, hipStream_t s, const AdamStep* adam) {
     const int F = d + 1;
     const size_t lds = mlp_grad_lds(F);
     static bool attr = false;
@@ -633,16 +732,21 @@ hipError_t launch_mlp_grad(const float* feats, const float* labels, int N, int d
         if (e != hipSuccess) return e;
         attr = true;
     }
-    k_zero_floats<<<blocks_of(mlp_params(d), 256), 256, 0, s>>>(grad, mlp_params(d));
-    k_zero_floats<<<1, 64, 0, s>>>(loss, 1);
-    k_mlp_grad<<<blocks_of(N, kGradSamples), kGradBlock, lds, s>>>(feats, labels, N, F, w, lam,
-                                                                    1.0f / static_cast<float>(N), grad, loss);
+    const int G = mlp_grad_groups(N), P = mlp_params(d);
+    k_mlp_grad<<<G, kGradBlock, lds, s>>>(feats, labels, N, F, w, lam, 1.0f / static_cast<float>(N), part);
+    if (adam)
+        k_mlp_grad_sum<true><<<blocks_of(P, 64), 64 * kSumSlices, 0, s>>>(part, G, P, 1.0f / static_cast<float>(N),
+                                                                         grad, loss, *adam);
+    else
+        k_mlp_grad_sum<false><<<blocks_of(P, 64), 64 * kSumSlices, 0, s>>>(part, G, P, 1.0f / static_cast<float>(N),
+                                                                          grad, loss, AdamStep{});
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_adam(float* w, const float* grad, float* m, float* v, int P, float lr, float b1, float b2,
                            float eps, float c1, float c2, hipStream_t s) {
-    k_mlp_adam<<<blocks_of(P, 256), 256, 0, s>>>(w, grad, m, v, P, lr, b1, b2, eps, c1, c2);
+    const AdamStep a{w, m, v, lr, b1, b2, eps, c1, c2};
+    k_mlp_adam<<<blocks_of(P, 256), 256, 0, s>>>(grad, P, a);
     return hipGetLastError();
 }
 

@@ -51,6 +51,9 @@ struct SweepProfile {
                                     // (large m only), the row kernel
     double total_ms[4] = {0.0, 0.0, 0.0, 0.0};   // sweep and row kernel: all launched, then executed
     long long launches = 0, executed = 0;
+    hipEvent_t learned_ev[2] = {nullptr, nullptr};   // around the learned decision of rl0_step
+    double learned_ms = 0.0;
+    long long learned_launches = 0;
 };
 SweepProfile g_prof;
 
@@ -992,13 +995,26 @@ int step_core(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, 
         lc.logit_t = logit_threshold(ip.t);
         lc.w = static_cast<const float*>(p->mlp);
         lc.value = w.learned;
+        const bool timed = g_prof.enabled;
+        if (timed) {
+            for (hipEvent_t& e : g_prof.learned_ev)
+                if (!e) HIP_TRY(hipEventCreate(&e));
+            HIP_TRY(hipEventRecord(g_prof.learned_ev[0], s));
+        }
         HIP_TRY(rl0::launch_learned_cols(lc, s));
+        if (timed) HIP_TRY(hipEventRecord(g_prof.learned_ev[1], s));
         lv = w.learned;
     }
     HIP_TRY(rl0::launch_iteration(dm, A, w, tables_of(dc), ip, dbg, s, nullptr, lv));
     HIP_TRY(rl0::launch_finish(dm, w, ip_end, x_hat, s));
     HIP_TRY(hipMemcpyAsync(b->st_host, w.st, offsetof(rl0::DevState, seg_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (learned && g_prof.enabled) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, g_prof.learned_ev[0], g_prof.learned_ev[1]));
+        g_prof.learned_ms += ms;
+        g_prof.learned_launches += 1;
+    }
     const rl0::DevState& ds = *b->st_host;
     if (int rc = err_code_of(ds.err)) return rc;
     const rl0::Slot& fin = ds.slot[(it + 1) & 1];
@@ -1150,24 +1166,30 @@ int decode_adaptive(Buffers* b, const DeviceConstants* dc0, const rl0::Problem& 
 struct MlpBuffers {
     float* grad = nullptr;
     float* losses = nullptr;
-    size_t cap_p = 0, cap_steps = 0;
+    float* part = nullptr;             // the gradient kernel's per-workgroup shares
+    size_t cap_p = 0, cap_steps = 0, cap_part = 0;
     std::vector<float> host_losses;
 };
 
 std::map<std::pair<int, hipStream_t>, MlpBuffers> g_mlp;
 
-int get_mlp_buffers(int device, hipStream_t s, size_t P, size_t steps, MlpBuffers** out) {
+// Gradient, per-step losses and the gradient kernel's scratch for column weight d.
+int get_mlp_buffers(int device, hipStream_t s, int d, size_t steps, MlpBuffers** out) {
     MlpBuffers& mb = g_mlp[{device, s}];
-    if (mb.cap_p < P || mb.cap_steps < steps) {
+    const size_t P = static_cast<size_t>(rl0::mlp_params(d)), part = rl0::mlp_grad_scratch_floats(d);
+    if (mb.cap_p < P || mb.cap_steps < steps || mb.cap_part < part) {
         HIP_TRY(hipStreamSynchronize(s));
+        const size_t np = std::max(P, mb.cap_p), ns = std::max<size_t>(std::max(steps, mb.cap_steps), 1),
+                     nq = std::max(part, mb.cap_part);
         if (mb.grad) HIP_TRY(hipFree(mb.grad));
         mb.grad = nullptr;
-        mb.cap_p = mb.cap_steps = 0;
-        const size_t np = std::max(P, mb.cap_p), ns = std::max<size_t>(std::max(steps, mb.cap_steps), 1);
-        if (hipMalloc(&mb.grad, sizeof(float) * (np + ns)) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(mlp)");
+        mb.cap_p = mb.cap_steps = mb.cap_part = 0;
+        if (hipMalloc(&mb.grad, sizeof(float) * (np + ns + nq)) != hipSuccess) return fail(RL0_ENOMEM, "hipMalloc(mlp)");
         mb.losses = mb.grad + np;
+        mb.part = mb.losses + ns;
         mb.cap_p = np;
         mb.cap_steps = ns;
+        mb.cap_part = nq;
     }
     *out = &mb;
     return RL0_OK;
@@ -1611,8 +1633,8 @@ int rl0_mlp_grad(const float* feats, const float* labels, int32_t N, int32_t d, 
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     MlpBuffers* mb = nullptr;
-    if (int rc = get_mlp_buffers(dev, s, rl0::mlp_params(d), 1, &mb)) return rc;
-    HIP_TRY(rl0::launch_mlp_grad(feats, labels, N, d, w, lam, grad, mb->losses, s));
+    if (int rc = get_mlp_buffers(dev, s, d, 1, &mb)) return rc;
+    HIP_TRY(rl0::launch_mlp_grad(feats, labels, N, d, w, lam, grad, mb->losses, mb->part, s));
     float l = 0.0f;
     HIP_TRY(hipMemcpyAsync(&l, mb->losses, sizeof(float), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1634,20 +1656,19 @@ int rl0_mlp_train(const float* feats, const float* labels, int64_t N, int32_t d,
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    const int P = rl0::mlp_params(d), F = d + 1;
+    const int F = d + 1;
     MlpBuffers* mb = nullptr;
-    if (int rc = get_mlp_buffers(dev, s, P, cfg->steps, &mb)) return rc;
+    if (int rc = get_mlp_buffers(dev, s, d, cfg->steps, &mb)) return rc;
     const int64_t nb = N / cfg->batch;
     for (int i = 0; i < cfg->steps; ++i) {
         const int64_t blk = (static_cast<int64_t>(cfg->t0) + i) % nb;
         const size_t off = static_cast<size_t>(blk) * cfg->batch;
-        HIP_TRY(rl0::launch_mlp_grad(feats + off * F, labels + off * 2, cfg->batch, d, w, cfg->lam, mb->grad,
-                                     mb->losses + i, s));
         const double t = static_cast<double>(cfg->t0) + i + 1;
         const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), t));
         const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), t));
-        HIP_TRY(rl0::launch_mlp_adam(w, mb->grad, adam_m, adam_v, P, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, c1,
-                                     c2, s));
+        const rl0::AdamStep adam{w, adam_m, adam_v, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, c1, c2};
+        HIP_TRY(rl0::launch_mlp_grad(feats + off * F, labels + off * 2, cfg->batch, d, w, cfg->lam, mb->grad,
+                                     mb->losses + i, mb->part, s, &adam));
     }
     if (cfg->steps > 0) {
         mb->host_losses.resize(cfg->steps);
@@ -1698,6 +1719,15 @@ int rl0_profile_enable(int32_t enable) {
     for (double& t : g_prof.total_ms) t = 0.0;
     g_prof.launches = 0;
     g_prof.executed = 0;
+    g_prof.learned_ms = 0.0;
+    g_prof.learned_launches = 0;
+    return RL0_OK;
+}
+
+int rl0_profile_read_learned(double* ms_total_h, int64_t* launches_h) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (ms_total_h) *ms_total_h = g_prof.learned_ms;
+    if (launches_h) *launches_h = g_prof.learned_launches;
     return RL0_OK;
 }
 
@@ -1755,6 +1785,10 @@ void rl0_release(void) {
     g_consts.clear();
     for (hipEvent_t e : g_prof.pool) (void)hipEventDestroy(e);
     g_prof.pool.clear();
+    for (hipEvent_t& e : g_prof.learned_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
 }
 
 }  // extern "C"

@@ -173,6 +173,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_profile_enable.argtypes = [I32]
         L.rl0_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+        L.rl0_profile_read_learned.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_decode_batched.argtypes = [ctypes.POINTER(Problem), I32, ctypes.POINTER(Stats), V]
         L.rl0_batch_schedule_get.argtypes = [ctypes.POINTER(BatchSchedule)]
         L.rl0_batch_timeline.argtypes = [I32, P, P, P, V]
@@ -196,7 +197,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_sketch_static", "rl0_validate",
-                     "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get",
+                     "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get", "rl0_profile_read_learned",
                      "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_batch_timeline", "rl0_mlp_init", "rl0_mlp_features",
                      "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam"):
             getattr(L, name).restype = ctypes.c_int
@@ -383,6 +384,15 @@ def profile_read_kernels() -> dict:
     names = ("sweep", "hk_rows")
     return {"all": {k: arr[i] for i, k in enumerate(names)}, "all_launches": cnt[0],
             "executed": {k: arr[2 + i] for i, k in enumerate(names)}, "executed_launches": cnt[1]}
+
+
+def profile_read_learned() -> tuple[float, int]:
+    """(total ms, launches) of the learned column decision timed in rl0_step since the last
+    profile_enable."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().rl0_profile_read_learned(ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, int(cnt.value)
 
 
 def validate_host(A_cols, m: int) -> None:
