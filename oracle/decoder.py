@@ -77,6 +77,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
+from . import general as _general
 from . import scores as _scores
 
 __all__ = [
@@ -126,28 +127,45 @@ class Constants:
     adaptive_k: int = 0       # rebuild the posteriors after each accepted iteration
     ell: int = 4
     k_post: float = 0.0       # the sparsity the current posteriors assume (k at the start)
+    signal: str = "gaussian"  # the laws mu and nu (module general; gaussian: eq:pz_approx)
+    noise: str = "gaussian"
 
 
 def make_constants(n, m, d, k, sigma, sigma_s=1.0, alpha=2.0, c=0.0, ell=4,
-                   max_iters=0, l1_test=0, variant=0, adaptive_k=0) -> Constants:
-    """Alg. 1 prologue: p_breve_z, p_breve_e for GM(n, m, k, d, N(0,ss^2), N(0,sn^2))."""
+                   max_iters=0, l1_test=0, variant=0, adaptive_k=0, signal="gaussian", noise="gaussian",
+                   tables=None) -> Constants:
+    """Alg. 1 prologue: p_breve_z, p_breve_e for GM(n, m, k, d, mu, nu), mu and nu of the
+    given families with standard deviations sigma_s and sigma: N(0, ss^2), N(0, sn^2) by
+    default (eq:pz_approx); otherwise the theorem's series (module general).  `tables` =
+    (Tz, Te) replaces the score tables by given ones."""
     # Alg. 1 takes the consensus level alpha from (1, d]
     if not (1.0 < alpha <= d):
         raise ValueError("alpha must be in (1, d]")
     if variant not in (0, 1):
         raise ValueError("variant must be 0 (continuous) or 1 (quantised)")
+    if signal not in _general.FAMILIES or noise not in _general.FAMILIES:
+        raise ValueError(f"signal and noise laws must be among {_general.FAMILIES}")
+    general = (signal, noise) != ("gaussian", "gaussian") or tables is not None
+    if adaptive_k and general:
+        raise ValueError("adaptive_k rebuilds the Gaussian posteriors of eq:pz_approx only")
     rho = k / m
     if c == 0.0:
         c = _scores.c_rule(m / n, rho, quantised=variant == 1)
     n_it = _scores.n_iters(c)
     if max_iters > 0:
         n_it = min(n_it, max_iters)
-    Tz = _scores.build_table("z", d, rho, sigma, sigma_s, ell)
-    Te = _scores.build_table("e", d, rho, sigma, sigma_s, ell)
+    if sigma == 0.0 or not general:
+        Tz = _scores.build_table("z", d, rho, sigma, sigma_s, ell)
+        Te = _scores.build_table("e", d, rho, sigma, sigma_s, ell)
+    elif tables is not None:
+        Tz, Te = tables
+    else:
+        Tz = _general.build_table("z", d, rho, (signal, sigma_s), (noise, sigma))
+        Te = _general.build_table("e", d, rho, (signal, sigma_s), (noise, sigma))
     return Constants(n=n, m=m, d=d, k=k, sigma=float(sigma), sigma_s=float(sigma_s),
                      alpha=np.float32(alpha), c=float(c), n_iters=n_it,
-                     tol=_scores.tolerance(m, sigma), Tz=Tz, Te=Te, l1_test=l1_test, variant=variant,
-                     adaptive_k=adaptive_k, ell=ell, k_post=float(k))
+                     tol=_general.noise_l1_mean(m, (noise, sigma)), Tz=Tz, Te=Te, l1_test=l1_test,
+                     variant=variant, adaptive_k=adaptive_k, ell=ell, k_post=float(k), signal=signal, noise=noise)
 
 
 def adapted_sparsity(C: Constants, x_hat: np.ndarray) -> float:
