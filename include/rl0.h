@@ -42,6 +42,13 @@ extern "C" {
 #define RL0_ERANGE (-6)     /* a value left the 64-bit fixed-point range (|v| >= 2^22) */
 
 #define RL0_TABLE_N 4096    /* intervals of each score table */
+/* floats of a set of score tables given by the caller (rl0_params.tables):
+ * T_z [RL0_TABLE_N + 1], T_e [RL0_TABLE_N + 1], inv_h_z, inv_h_e */
+#define RL0_TABLES_FLOATS (2 * (RL0_TABLE_N + 1) + 2)
+/* laws of the signal entries and of the noise (rl0_params.signal_law / noise_law), each
+ * symmetric about 0 and given by its standard deviation */
+#define RL0_LAW_GAUSSIAN 0  /* N(0, s^2) */
+#define RL0_LAW_LAPLACE 1   /* density exp(-|x|/b) / (2b), b = s / sqrt(2) */
 #define RL0_MAX_D 16        /* largest supported column weight d */
 
 /* Decoder parameters (Alg. 1 "KwData": alpha, mu, nu, c; variant flags of Table
@@ -74,7 +81,24 @@ typedef struct rl0_params {
                                sum_j rint(2^30 fl32(1 - Tz(|x_hat_j|))).  The host reads k_0
                                back after every iteration, so such a decode is launched
                                eagerly rather than replayed from a graph.  Ignored for
-                               sigma = 0.  rl0_step, learned and batched decodes: RL0_EINVAL */
+                               sigma = 0.  rl0_step, learned and batched decodes, other
+                               laws than Gaussian or given tables: RL0_EINVAL */
+    int32_t signal_law;     /* RL0_LAW_* of mu, standard deviation sigma_signal */
+    int32_t noise_law;      /* RL0_LAW_* of nu, standard deviation sigma.  Both Gaussian
+                               (the default): the tables of eq:pz_approx / eq:pe_approx.
+                               Otherwise the posteriors of Thm "Probabilities for general
+                               signal and noise distributions" (eq:pz_general,
+                               eq:pe_general), the whole series, tabulated like the
+                               Gaussian ones (range R = q sqrt(v0)/8, v0 = Var(nu) for z and
+                               2 Var(nu) for e, first q >= 8 with p_breve < 2^-27; p_breve =
+                               p / p(0); T[0] = 1); the stopping tolerance is m E|eta_i|
+                               (m sigma / sqrt(2) for Laplace noise) */
+    const float* tables;    /* NULL, or host pointer to RL0_TABLES_FLOATS floats: score
+                               tables to use instead of the library's (sigma > 0).  Each
+                               table must be finite, start at 1, stay in [0, 1] and be
+                               non-increasing; inv_h finite and > 0 (else RL0_EINVAL).
+                               Read during the call only (the library keeps a copy, keyed
+                               by a 64-bit hash of the floats) */
 } rl0_params;
 
 /* What a decode did.  l1 values are ||r_hat||_1; the fixed-point one is exact. */

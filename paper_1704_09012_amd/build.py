@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librl0.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["constants.cpp", "rl0.cpp", "kernels.hip", "batched.hip", "mlp.hip", "noalloc.hip"]
+SOURCES = ["constants.cpp", "general.cpp", "rl0.cpp", "kernels.hip", "batched.hip", "mlp.hip", "noalloc.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

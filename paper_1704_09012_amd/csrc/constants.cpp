@@ -14,6 +14,8 @@
 //   Sec. 4 "Stopping conditions"     tolerance m sigma sqrt(2/pi)
 #include "constants.h"
 
+#include "general.h"
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -162,13 +164,26 @@ bool compute_constants(const Problem& pr, HostConstants* hc) {
                        : c_rule(static_cast<double>(pr.m) / pr.n, static_cast<double>(pr.k) / pr.m, pr.variant == 1);
     hc->n_iters = iterations_for(hc->c);
     if (pr.max_iters > 0 && pr.max_iters < hc->n_iters) hc->n_iters = pr.max_iters;
-    hc->tol = pr.m * pr.sigma * std::sqrt(2.0 / M_PI);
+    const Law mu{pr.signal_law, pr.sigma_s}, nu{pr.noise_law, pr.sigma};
+    // Sec. 4: ||r||_1 <= E||eta||_1 = m E|eta_i| (m sigma sqrt(2/pi) for Gaussian noise)
+    hc->tol = pr.noise_law == kLawGaussian ? pr.m * pr.sigma * std::sqrt(2.0 / M_PI) : pr.m * pr.sigma / std::sqrt(2.0);
     const double rho = (pr.k_post > 0.0 ? pr.k_post : static_cast<double>(pr.k)) / pr.m;
     if (hc->exact) {
         std::memset(hc->table_z, 0, sizeof(hc->table_z));
         std::memset(hc->table_e, 0, sizeof(hc->table_e));
         hc->inv_h_z = hc->inv_h_e = 0.0f;
         hc->range_z = hc->range_e = 0.0;
+    } else if (pr.tables) {
+        std::memcpy(hc->table_z, pr.tables, sizeof(hc->table_z));
+        std::memcpy(hc->table_e, pr.tables + kTableN + 1, sizeof(hc->table_e));
+        hc->inv_h_z = pr.tables[2 * (kTableN + 1)];
+        hc->inv_h_e = pr.tables[2 * (kTableN + 1) + 1];
+        hc->range_z = kTableN / static_cast<double>(hc->inv_h_z);
+        hc->range_e = kTableN / static_cast<double>(hc->inv_h_e);
+    } else if (pr.signal_law != kLawGaussian || pr.noise_law != kLawGaussian) {
+        if (!build_general_table('z', pr.d, rho, mu, nu, hc->table_z, &hc->inv_h_z, &hc->range_z) ||
+            !build_general_table('e', pr.d, rho, mu, nu, hc->table_e, &hc->inv_h_e, &hc->range_e))
+            return false;
     } else {
         build_table('z', pr.d, rho, pr.sigma, pr.sigma_s, pr.ell, hc->table_z, &hc->inv_h_z,
                     &hc->range_z);

@@ -16,6 +16,9 @@ struct Problem {
     int max_iters = 0;
     int variant = 0;   // 0 continuous scores, 1 quantised
     double k_post = 0.0;   // the sparsity the posteriors assume (adaptive_k); 0 = k
+    int signal_law = 0, noise_law = 0;   // LawFamily of mu and nu (both Gaussian: eq:pz_approx)
+    const float* tables = nullptr;       // given score tables: T_z, T_e ([kTableN + 1] each), inv_h_z, inv_h_e
+    unsigned long long tables_hash = 0;  // of those floats (the constants cache's key)
 };
 
 struct HostConstants {
@@ -36,6 +39,7 @@ struct HostConstants {
 
 double c_rule(double delta, double rho = 0.0, bool quantised = false);
 int iterations_for(double c);
+// False if the posteriors of the given laws cannot be tabulated.
 bool compute_constants(const Problem& pr, HostConstants* hc);
 float table_score(const float* T, float inv_h, float a);
 

@@ -101,7 +101,8 @@ struct DeviceConstants {
     size_t bytes = 0;                 // size of the d_tables allocation
 };
 
-using ConstKey = std::tuple<int, int, int, int, int, uint32_t, uint32_t, double, int, int, int>;
+using ConstKey = std::tuple<int, int, int, int, int, uint32_t, uint32_t, double, int, int, int, int, int, bool,
+                            unsigned long long>;
 std::map<ConstKey, std::unique_ptr<DeviceConstants>> g_consts;
 
 uint32_t fbits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
@@ -110,7 +111,8 @@ uint32_t fbits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 // written with a blocking copy, so it is ready before any later launch.
 ConstKey key_of(const rl0::Problem& pr, int device) {
     return ConstKey{device, pr.n, pr.m, pr.d, pr.k, fbits(static_cast<float>(pr.sigma)),
-                    fbits(static_cast<float>(pr.sigma_s)), pr.c, pr.ell, pr.max_iters, pr.variant};
+                    fbits(static_cast<float>(pr.sigma_s)), pr.c, pr.ell, pr.max_iters, pr.variant,
+                    pr.signal_law, pr.noise_law, pr.tables != nullptr, pr.tables_hash};
 }
 
 // Device copy of computed constants: both tables and the per-iteration thresholds (tau,
@@ -160,7 +162,8 @@ int get_constants(const rl0::Problem& pr, int device, DeviceConstants** out) {
         return RL0_OK;
     }
     auto dc = std::make_unique<DeviceConstants>();
-    rl0::compute_constants(pr, &dc->hc);
+    if (!rl0::compute_constants(pr, &dc->hc))
+        return fail(RL0_EINVAL, "the posteriors of these signal and noise laws could not be tabulated");
     if (int rc = upload_constants(dc.get())) return rc;
     *out = dc.get();
     g_consts.emplace(key, std::move(dc));
@@ -188,11 +191,17 @@ int get_constants_many(const std::vector<rl0::Problem>& prs, int device, std::ve
     for (auto& f : fresh) f = std::make_unique<DeviceConstants>();
     const size_t nt = std::min<size_t>(fresh.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
     std::vector<std::thread> pool;
+    std::vector<char> ok(fresh.size(), 1);
     for (size_t t = 0; t < nt; ++t)
         pool.emplace_back([&, t] {
-            for (size_t f = t; f < fresh.size(); f += nt) rl0::compute_constants(prs[fresh_src[f]], &fresh[f]->hc);
+            for (size_t f = t; f < fresh.size(); f += nt)
+                ok[f] = rl0::compute_constants(prs[fresh_src[f]], &fresh[f]->hc) ? 1 : 0;
         });
     for (auto& th : pool) th.join();
+    for (size_t f = 0; f < fresh.size(); ++f)
+        if (!ok[f])
+            return fail(RL0_EINVAL, "instance " + std::to_string(fresh_src[f]) +
+                                        ": the posteriors of these signal and noise laws could not be tabulated");
     for (size_t f = 0; f < fresh.size(); ++f)
         if (int rc = upload_constants(fresh[f].get())) return rc;
     for (auto& kv : fresh_of) g_consts.emplace(kv.first, std::move(fresh[kv.second]));
@@ -330,6 +339,24 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     if (p->adaptive_k != 0 && p->adaptive_k != 1) return fail(RL0_EINVAL, "adaptive_k must be 0 or 1");
     if (p->adaptive_k == 1 && p->posterior == 1)
         return fail(RL0_EINVAL, "adaptive_k applies to the analytic posteriors only");
+    for (int32_t law : {p->signal_law, p->noise_law})
+        if (law != RL0_LAW_GAUSSIAN && law != RL0_LAW_LAPLACE)
+            return fail(RL0_EINVAL, "signal_law and noise_law must be RL0_LAW_GAUSSIAN or RL0_LAW_LAPLACE");
+    if (p->adaptive_k == 1 && (p->tables || p->signal_law != RL0_LAW_GAUSSIAN || p->noise_law != RL0_LAW_GAUSSIAN))
+        return fail(RL0_EINVAL, "adaptive_k rebuilds the Gaussian posteriors only (no other laws, no given tables)");
+    if (p->tables) {
+        const float* t = p->tables;
+        for (int k = 0; k < 2; ++k) {
+            const float* T = t + k * (RL0_TABLE_N + 1);
+            if (T[0] != 1.0f) return fail(RL0_EINVAL, "tables: each table must start at 1");
+            for (int i = 0; i <= RL0_TABLE_N; ++i) {
+                if (!(T[i] >= 0.0f && T[i] <= 1.0f)) return fail(RL0_EINVAL, "tables: entries must lie in [0, 1]");
+                if (i > 0 && T[i] > T[i - 1]) return fail(RL0_EINVAL, "tables: entries must be non-increasing");
+            }
+            const float ih = t[2 * (RL0_TABLE_N + 1) + k];
+            if (!(ih > 0.0f) || !std::isfinite(ih)) return fail(RL0_EINVAL, "tables: inv_h must be finite and > 0");
+        }
+    }
     return RL0_OK;
 }
 
@@ -352,6 +379,9 @@ void params_key(const rl0_params* p, rl0_params* out) {
     k.validate = p->validate;
     k.variant = p->variant;
     k.adaptive_k = p->adaptive_k;
+    k.signal_law = p->signal_law;
+    k.noise_law = p->noise_law;
+    // given tables enter through the constants (their device copy is part of the key)
 }
 
 rl0::Problem problem_of(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
@@ -363,6 +393,16 @@ rl0::Problem problem_of(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     pr.ell = p->series_terms;
     pr.max_iters = p->max_iters;
     pr.variant = p->variant;
+    pr.signal_law = p->signal_law;
+    pr.noise_law = p->noise_law;
+    if (p->tables) {
+        // FNV-1a over the floats' bytes
+        unsigned long long h = 1469598103934665603ull;
+        const unsigned char* bytes = reinterpret_cast<const unsigned char*>(p->tables);
+        for (size_t i = 0; i < sizeof(float) * RL0_TABLES_FLOATS; ++i) h = (h ^ bytes[i]) * 1099511628211ull;
+        pr.tables = p->tables;
+        pr.tables_hash = h;
+    }
     return pr;
 }
 
@@ -1146,7 +1186,7 @@ int decode_adaptive(Buffers* b, const DeviceConstants* dc0, const rl0::Problem& 
         if (!b->adapted) b->adapted = std::make_unique<DeviceConstants>();
         // every launch that read the previous constants has completed (the stream is
         // synchronised), so the one set is rewritten in place
-        rl0::compute_constants(pr, &b->adapted->hc);
+        if (!rl0::compute_constants(pr, &b->adapted->hc)) return fail(RL0_EINVAL, "adaptive_k: constants failed");
         if (int rc = upload_constants(b->adapted.get())) return rc;
         dc = b->adapted.get();
         if (dc->hc.tau_bits[it + 1] != tau_old)
@@ -1225,7 +1265,8 @@ int rl0_compute_constants(const rl0_params* p, int32_t n, int32_t m, int32_t d, 
     if (int rc = check_params(p, n, m, d)) return rc;
     if (!out) return fail(RL0_EINVAL, "out is NULL");
     rl0::HostConstants hc;
-    rl0::compute_constants(problem_of(p, n, m, d), &hc);
+    if (!rl0::compute_constants(problem_of(p, n, m, d), &hc))
+        return fail(RL0_EINVAL, "the posteriors of these signal and noise laws could not be tabulated");
     out->n_iters = hc.n_iters;
     out->exact = hc.exact ? 1 : 0;
     out->c = hc.c;

@@ -6,7 +6,8 @@ Figure 1) draws
   * supp(x) uniformly from the k-subsets of [n],
   * x_j iid mu on the support, eta_i iid nu,
 and measures y_hat = A x + eta.  Here mu = N(0, sigma_s^2) and nu = N(0, sigma_n^2)
-as in the paper's experiments (Sec. 4, "Stopping conditions").
+as in the paper's experiments (Sec. 4, "Stopping conditions"), or Laplace laws of the
+same standard deviations (scale b = s / sqrt(2)) for the general-distribution posteriors.
 
 This module only draws random numbers.  It holds none of the decoder's arithmetic and
 does not form the sketch A x: the oracle and the HIP library each form it themselves.
@@ -97,11 +98,14 @@ def draw_signal(rng: np.random.Generator, n: int, k: int, sigma_s: float = 1.0,
 
     ``kind="dyadic"`` draws instead nonzero integers in [-2^12, 2^12] times 2^-6 (exact in
     float32 and in any short float32 sum); such signals are dissociated with high
-    probability and serve the noiseless exact-recovery checks.
+    probability and serve the noiseless exact-recovery checks.  ``kind="laplace"`` draws
+    Laplace values of standard deviation sigma_s.
     """
     support = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
     if kind == "gaussian":
         values = rng.standard_normal(k, dtype=np.float32) * np.float32(sigma_s)
+    elif kind == "laplace":
+        values = rng.laplace(0.0, sigma_s / math.sqrt(2.0), size=k).astype(np.float32)
     elif kind == "dyadic":
         mag = rng.integers(1, 2 ** 12 + 1, size=k)
         sign = np.where(rng.integers(0, 2, size=k) == 1, 1, -1)
@@ -111,21 +115,27 @@ def draw_signal(rng: np.random.Generator, n: int, k: int, sigma_s: float = 1.0,
     return support, values.astype(np.float32)
 
 
-def draw_noise(rng: np.random.Generator, m: int, sigma: float) -> np.ndarray:
+def draw_noise(rng: np.random.Generator, m: int, sigma: float, kind: str = "gaussian") -> np.ndarray:
+    """eta iid N(0, sigma^2), or Laplace of standard deviation sigma (kind="laplace")."""
     if sigma == 0.0:
         return np.zeros(m, dtype=np.float32)
+    if kind == "laplace":
+        return rng.laplace(0.0, sigma / math.sqrt(2.0), size=m).astype(np.float32)
+    if kind != "gaussian":
+        raise ValueError(kind)
     return (rng.standard_normal(m, dtype=np.float32) * np.float32(sigma)).astype(np.float32)
 
 
 def draw_instance(n: int, m: int, k: int, d: int, sigma: float, seed: int,
-                  sigma_s: float = 1.0, kind: str = "gaussian") -> Instance:
-    """One seeded instance of GM(n, m, k, d, N(0, sigma_s^2), N(0, sigma^2))."""
+                  sigma_s: float = 1.0, kind: str = "gaussian", noise_kind: str = "gaussian") -> Instance:
+    """One seeded instance of GM(n, m, k, d, mu, nu): mu = N(0, sigma_s^2) (or the law of
+    `kind`), nu = N(0, sigma^2) (or Laplace of standard deviation sigma)."""
     if not (0 < k < m):
         raise ValueError("need 0 < k < m")
     rng = np.random.Generator(np.random.PCG64(seed))
     A_cols = draw_columns(rng, n, m, d)
     support, values = draw_signal(rng, n, k, sigma_s, kind)
-    eta = draw_noise(rng, m, sigma)
+    eta = draw_noise(rng, m, sigma, noise_kind)
     return Instance(n=n, m=m, k=k, d=d, sigma=float(sigma), sigma_s=float(sigma_s),
                     A_cols=A_cols, support=support, values=values, eta=eta)
 

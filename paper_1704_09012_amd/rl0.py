@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("RL0_LIBRARY") or os.path.join(_HERE, "librl0.so")
 
 RL0_TABLE_N = 4096
 RL0_MAX_D = 16
+RL0_TABLES_FLOATS = 2 * (RL0_TABLE_N + 1) + 2
+LAWS = {"gaussian": 0, "laplace": 1}          # RL0_LAW_GAUSSIAN, RL0_LAW_LAPLACE
 
 ERRORS = {
     -1: "RL0_EINVAL",
@@ -44,6 +46,9 @@ class Params(ctypes.Structure):
         ("validate", ctypes.c_int32),
         ("variant", ctypes.c_int32),
         ("adaptive_k", ctypes.c_int32),
+        ("signal_law", ctypes.c_int32),
+        ("noise_law", ctypes.c_int32),
+        ("tables", ctypes.c_void_p),
     ]
 
 
@@ -233,17 +238,38 @@ def _dev_ptr(t, dtype, shape=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def pack_tables(Tz, Te, inv_h_z, inv_h_e) -> np.ndarray:
+    """Score tables in the layout of rl0_params.tables (RL0_TABLES_FLOATS float32)."""
+    out = np.empty(RL0_TABLES_FLOATS, np.float32)
+    out[:RL0_TABLE_N + 1] = np.asarray(Tz, np.float32)
+    out[RL0_TABLE_N + 1:2 * (RL0_TABLE_N + 1)] = np.asarray(Te, np.float32)
+    out[-2:] = (np.float32(inv_h_z), np.float32(inv_h_e))
+    return out
+
+
+def _set_param(p: Params, key: str, val) -> None:
+    if not hasattr(p, key):
+        raise KeyError(key)
+    if key == "mlp" and hasattr(val, "data_ptr"):
+        # a parameter tensor: the learned decision
+        val = val.data_ptr()
+        p.posterior = 1
+    elif key in ("signal_law", "noise_law") and isinstance(val, str):
+        val = LAWS[val]
+    elif key == "tables" and val is not None and not isinstance(val, int):
+        arr = np.ascontiguousarray(val, dtype=np.float32)
+        if arr.shape != (RL0_TABLES_FLOATS,):
+            raise ValueError(f"tables must hold {RL0_TABLES_FLOATS} floats (pack_tables)")
+        p._tables_keep = arr            # the library reads it during each call
+        val = arr.ctypes.data
+    setattr(p, key, val)
+
+
 def params_default(n: int, m: int, d: int, k: int, sigma: float, **overrides) -> Params:
     p = Params()
     _check(lib().rl0_params_default(ctypes.byref(p), n, m, d, k, ctypes.c_float(sigma)))
     for key, val in overrides.items():
-        if not hasattr(p, key):
-            raise KeyError(key)
-        if key == "mlp" and hasattr(val, "data_ptr"):
-            # a parameter tensor: the learned decision
-            val = val.data_ptr()
-            p.posterior = 1
-        setattr(p, key, val)
+        _set_param(p, key, val)
     return p
 
 
@@ -322,12 +348,7 @@ def decode(A_cols, y, sigma: float | None = None, d: int | None = None, params: 
         params = params_default(n, m, dd, k, sigma, **overrides)
     else:
         for key, val in overrides.items():
-            if not hasattr(params, key):
-                raise KeyError(key)
-            if key == "mlp" and hasattr(val, "data_ptr"):
-                val = val.data_ptr()
-                params.posterior = 1
-            setattr(params, key, val)
+            _set_param(params, key, val)
     x = out if out is not None else torch.empty(n, dtype=torch.float32, device=y.device)
     st = Stats()
     _check(lib().rl0_decode(_dev_ptr(A_cols, torch.int32, (n, dd), "A_cols"), n, m, dd,

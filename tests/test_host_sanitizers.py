@@ -1,13 +1,15 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer.
 
-constants.cpp and rl0.cpp (the argument checks, the host constants: score tables,
-thresholds, c rule, the batched planner's checks, the bf16 packer, the host validator)
-are rebuilt with g++ -fsanitize=address,undefined and linked with the unchanged device
-objects of the normal build into a second copy of librl0.so.  The host-only tests of
-tests/test_capi_host.py then run against that copy (the binding loads the library named
-by RL0_LIBRARY) in a child process with the sanitizer runtime preloaded: any heap or
-stack overflow, use after free, signed overflow, misaligned or out-of-bounds access in
-those paths ends the child with an error.  No GPU is used."""
+constants.cpp, general.cpp and rl0.cpp (the argument checks, the host constants: score
+tables of the Gaussian and the general laws, thresholds, c rule, the batched planner's
+checks, the bf16 packer, the host validator) are rebuilt with g++
+-fsanitize=address,undefined and linked with the unchanged device objects of the normal
+build into a second copy of librl0.so.  The host-only tests of tests/test_capi_host.py,
+and those of tests/test_capi_general.py that do not wait on the oracle (general-law
+tables, given tables and their checks), then run against that copy (the binding loads the
+library named by RL0_LIBRARY) in a child process with the sanitizer runtime preloaded: any
+heap or stack overflow, use after free, signed overflow, misaligned or out-of-bounds
+access in those paths ends the child with an error.  No GPU is used."""
 import os
 import shutil
 import subprocess
@@ -18,7 +20,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1704_09012_amd", "csrc")
 OUT_DIR = os.path.join(ROOT, "_build", "host_sanitize")
-HOST_SOURCES = ("constants.cpp", "rl0.cpp")
+HOST_SOURCES = ("constants.cpp", "general.cpp", "rl0.cpp")
 DEVICE_OBJECTS = ("kernels.hip", "batched.hip", "mlp.hip", "noalloc.hip")
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
 
@@ -79,7 +81,8 @@ def test_host_paths_are_clean_under_asan_and_ubsan():
     r = subprocess.run([sys.executable, "-c", probe], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "sanitized library loaded" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
-                        os.path.join(ROOT, "tests", "test_capi_host.py")],
+                        "-k", "not match_the_oracle", os.path.join(ROOT, "tests", "test_capi_host.py"),
+                        os.path.join(ROOT, "tests", "test_capi_general.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=800)
     tail = r.stdout[-3000:] + r.stderr[-6000:]
     assert r.returncode == 0, tail
