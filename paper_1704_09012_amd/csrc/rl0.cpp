@@ -958,13 +958,13 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
             o.ms_total = call_ms;   // the whole batched launch
             o.fx_inexact_y = 0;
             o.fx_inexact_x = 0;
+            o.k_post = static_cast<double>(probs[i].params.k);
         }
         if (R.err && first_rc == RL0_OK) {
             first_rc = err_code_of(R.err);
             first_msg = "instance " + std::to_string(i) + ": " + g_last_error;
         }
     }
-    (void)probs;
     if (first_rc != RL0_OK) return fail(first_rc, first_msg);
     return RL0_OK;
 }
