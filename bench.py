@@ -75,11 +75,19 @@ def iteration_bytes(n: int, m: int, d: int, k: int, u: float) -> float:
 def _oracle_sample(args) -> tuple[int, float]:
     """One process of the CPU baseline: the oracle's first loop iterations of the seeded
     instance, as many as fit in budget_s seconds; returns (iterations, seconds)."""
-    n, m, k, d, sigma, seed, budget_s, variant, adaptive = args
+    n, m, k, d, sigma, seed, budget_s, variant, adaptive, laws = args
     from oracle import decoder as D
-    inst = I.draw_instance(n, m, k, d, sigma, seed)
+    from oracle import scores as S
+    inst = I.draw_instance(n, m, k, d, sigma, seed, kind=laws[0], noise_kind=laws[1])
     y_hat = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-    C = D.make_constants(n, m, d, k, sigma, variant=variant, adaptive_k=adaptive)
+    tables = None
+    if laws != ("gaussian", "gaussian"):
+        # the oracle's own tables of these laws, stored by tests/golden/make_tables.py
+        g = np.load(general_tables_path(n, m, k, d, laws))
+        tables = (S.Table(g["Tz"], np.float32(g["inv_h_z"]), float(g["R_z"])),
+                  S.Table(g["Te"], np.float32(g["inv_h_e"]), float(g["R_e"])))
+    C = D.make_constants(n, m, d, k, sigma, variant=variant, adaptive_k=adaptive, signal=laws[0], noise=laws[1],
+                         tables=tables)
     st = D.init_state(y_hat, n)
     t0 = time.perf_counter()
     done = 0
@@ -94,15 +102,19 @@ def _oracle_sample(args) -> tuple[int, float]:
     return done, time.perf_counter() - t0
 
 
+def general_tables_path(n, m, k, d, laws) -> str:
+    return os.path.join(ROOT, "tests", "golden", f"tables_n{n}_m{m}_k{k}_d{d}_snr{SNR}_{laws[0]}_{laws[1]}.npz")
+
+
 def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 8, variant: int = 0,
-                 adaptive: int = 0) -> dict:
+                 adaptive: int = 0, laws=("gaussian", "gaussian")) -> dict:
     """The oracle (test infrastructure) timed on the host: single-threaded numpy, first on
     one core, then `procs` processes at once on different seeds (the aggregate rate)."""
     import multiprocessing as mp
 
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    done1, dt1 = _oracle_sample((n, m, k, d, sigma, seeds[0], budget_s, variant, adaptive))
+    done1, dt1 = _oracle_sample((n, m, k, d, sigma, seeds[0], budget_s, variant, adaptive, laws))
     rate1 = d * n * done1 / dt1
     try:
         avail = len(os.sched_getaffinity(0))
@@ -112,7 +124,7 @@ def cpu_baseline(n, m, k, d, sigma, seeds, budget_s: float = 12.0, procs: int = 
     ctx = mp.get_context("spawn")
     with ctx.Pool(procs) as pool:
         res = pool.map(_oracle_sample,
-                       [(n, m, k, d, sigma, seeds[i % len(seeds)], budget_s, variant, adaptive)
+                       [(n, m, k, d, sigma, seeds[i % len(seeds)], budget_s, variant, adaptive, laws)
                         for i in range(procs)])
     agg = sum(d * n * it / t for it, t in res)
     its = [it for it, _ in res]
@@ -394,7 +406,7 @@ def bench_batched(args) -> int:
 
 
 def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int, workload: str,
-                 cpu: bool, variant: int = 0, adaptive: int = 0) -> int:
+                 cpu: bool, variant: int = 0, adaptive: int = 0, laws=("gaussian", "gaussian")) -> int:
     """Single decodes of `seeds` seeded instances of GM(N, M, K, DD) at SNR 40 dB, step i on
     seed i mod seeds (sketch + decode, graph replay), then the same steps again with HIP
     events on every loop kernel for the roofline."""
@@ -406,7 +418,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     seed_ids = [I.seed_for(config, 1, i) for i in range(seeds)]
     insts = []
     for sd in seed_ids:
-        inst = I.draw_instance(N, M, K, DD, sigma, sd)
+        inst = I.draw_instance(N, M, K, DD, sigma, sd, kind=laws[0], noise_kind=laws[1])
         insts.append({
             "inst": inst,
             "A": torch.from_numpy(inst.A_cols).to(dev),
@@ -414,7 +426,8 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
             "eta": torch.from_numpy(inst.eta).to(dev),
         })
         del inst
-    params = R.params_default(N, M, DD, K, sigma, variant=variant, adaptive_k=adaptive)
+    params = R.params_default(N, M, DD, K, sigma, variant=variant, adaptive_k=adaptive, signal_law=laws[0],
+                              noise_law=laws[1])
     y = torch.empty(M, dtype=torch.float32, device=dev)
     y_hat = torch.empty(M, dtype=torch.float32, device=dev)
     x_hat = torch.empty(N, dtype=torch.float32, device=dev)
@@ -482,6 +495,8 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         metric = metric.replace("Robust-l0", "Robust-l0-quantised", 1)
     if adaptive:
         metric = metric.replace("Robust-l0", "Robust-l0 (adaptive_k)", 1)
+    if laws != ("gaussian", "gaussian"):
+        metric = metric.replace("Robust-l0", f"Robust-l0 ({laws[0]} signal, {laws[1]} noise)", 1)
     out = {
         "metric": metric,
         "value": value,
@@ -502,6 +517,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         "data": "synthetic",
         "config": {"workload": workload, "n": N, "m": M, "d": DD, "k": K, "snr_db": SNR, "seeds": seeds,
                    "scores": "quantised" if variant == 1 else "continuous", "adaptive_k": adaptive,
+                   "laws": {"signal": laws[0], "noise": laws[1]},
                    "setup": ("one untimed decode per instance captures its graph before the warm-up; "
                              "y_hat and x_hat are fixed device buffers; the host constants of the "
                              "parameter set (score tables, thresholds) are computed once and cached")
@@ -529,7 +545,8 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     }
     if cpu:
         del insts
-        out["cpu_baseline"] = cpu_baseline(N, M, K, DD, sigma, seed_ids[:8], variant=variant, adaptive=adaptive)
+        out["cpu_baseline"] = cpu_baseline(N, M, K, DD, sigma, seed_ids[:8], variant=variant, adaptive=adaptive,
+                                           laws=laws)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -543,7 +560,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-n", type=int, default=2 ** 22, help="n of the phase-transition ladders")
     ap.add_argument("--workload", choices=["headline", "batched", "learned", "large", "quantised", "phase",
-                                           "adaptive"],
+                                           "adaptive", "laplace"],
                     default="headline",
                     help="batched: 512 uneven instances in one persistent launch, against "
                          "sequential single decodes of the same instances")
@@ -575,6 +592,12 @@ def main() -> int:
                             "Robust-l0-quantised decode of y_hat = A x + eta, n=2^20, m=104857, d=7, "
                             "k=10485 N(0,1) nonzeros, SNR 40 dB; step = sketch + decode",
                             cpu=not args.no_cpu_baseline, variant=1)
+    if args.workload == "laplace":
+        return bench_decode(args, N, M, K, DD, 2, args.seeds,
+                            "Robust-l0 decode of y_hat = A x + eta with Laplace signal (std 1) and Laplace noise, "
+                            "n=2^20, m=104857, d=7, k=10485, SNR 40 dB; posteriors of the general-distribution "
+                            "theorem tabulated by the library; step = sketch + decode",
+                            cpu=not args.no_cpu_baseline, laws=("laplace", "laplace"))
     if args.workload == "adaptive":
         return bench_decode(args, N, M, K, DD, 2, args.seeds,
                             "Robust-l0 decode with adaptive_k of y_hat = A x + eta, n=2^20, m=104857, d=7, "

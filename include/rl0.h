@@ -123,6 +123,20 @@ typedef struct rl0_stats {
                                the last k_0 */
 } rl0_stats;
 
+/* One executed loop iteration of the last decode (rl0_last_log), recorded on the device
+ * by the decision on it and by workgroup 0 of its two kernels. */
+typedef struct rl0_iter_log {
+    int64_t l1_trial_fx;    /* ||r||_1 of the iteration's trial iterate (units of 2^-30) */
+    int64_t l1_hat_fx;      /* ||r_hat||_1 after the decision on it (Alg. 1's acceptance test) */
+    int32_t accepted;       /* that decision */
+    int32_t updates;        /* column updates its sweep proposed */
+    float t;                /* its t */
+    int32_t it;             /* its loop index (learned decodes: the sub-iteration, 2j learned,
+                               2j + 1 the analytic retry at the same t) */
+    uint64_t sweep_start, sweep_end;  /* device wall clock (100 MHz) when workgroup 0 of the */
+    uint64_t rows_start, rows_end;    /* sweep and of the row kernel began and ended */
+} rl0_iter_log;
+
 /* Host copy of the decoder's constants, for inspection and tests. */
 typedef struct rl0_constants {
     int32_t n_iters;                 /* iterations the t-sweep allows */
@@ -347,6 +361,12 @@ int rl0_mlp_pack_bf16(const float* w_h, int32_t d, uint16_t* packed_h);
  * matrix cores as the decoder runs it (bf16 = 1, d <= 15). */
 int rl0_mlp_forward(const float* feats, int32_t N, int32_t d, const float* w, float* out, int32_t bf16,
                     void* stream);
+
+/* The per-iteration log of the last rl0_decode (or rl0_step) on this stream: the
+ * records of its executed iterations in order, at most cap of them, into out_h (host);
+ * *count_h <- the number of executed iterations (records beyond 4096 are not kept).
+ * Batched decodes keep no log.  Synchronises the stream. */
+int rl0_last_log(rl0_iter_log* out_h, int32_t cap, int32_t* count_h, void* stream);
 
 /* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of
  * replaying its captured graph), each loop kernel with a pair of HIP events that take

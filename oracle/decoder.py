@@ -415,13 +415,15 @@ def decode(A_cols, y_hat, C: Constants, keep_trace: bool = False) -> DecodeResul
     while st.it < C.n_iters and not converged(st, C):
         k_last = C.k_post
         out = step(A_cols, y_hat, st, C)
-        updates += int(out.sweep.updated.sum())
+        n_upd = int(out.sweep.updated.sum())
+        updates += n_upd
         xp = out.sweep.x_prime[out.sweep.updated]
         inexact_x += fx_inexact(xp[xp != 0])
         if C.adaptive_k and out.accepted and not C.Tz.exact:
             C = adapt(C, out.state.x_hat)
         if keep_trace:
-            trace.append((st.L_hat, out.L_trial, out.accepted))
+            # (||r_hat||_1 before, ||r||_1 of the trial iterate, accepted, column updates)
+            trace.append((st.L_hat, out.L_trial, out.accepted, n_upd))
         st = out.state
     return DecodeResult(x_hat=st.x_hat, r_hat=st.r_hat, L_hat=st.L_hat, iterations=st.it,
                         accepted=st.accepted, converged=converged(st, C),

@@ -40,6 +40,19 @@ struct Slot {
 
 // Nothing here is updated by contended atomics: every workgroup writes its own entry
 // (candidate segment length, proposed updates, partial ||r||_1) and readers add them up.
+// One executed loop iteration, recorded on the device (the layout of rl0_iter_log).
+constexpr int kLogCap = 4096;
+struct IterLog {
+    long long L_trial;     // ||r||_1 of the iteration's trial iterate, units of 2^-30
+    long long L_hat;       // ||r_hat||_1 after the decision on the iteration
+    int accepted;          // that decision
+    int updates;           // column updates the iteration's sweep proposed
+    float t;               // the iteration's t
+    int it;                // its loop index (the sub-iteration index in a learned decode)
+    unsigned long long sweep_start, sweep_end;   // wall clock (100 MHz) of workgroup 0 in the sweep
+    unsigned long long rows_start, rows_end;     //   and in the row kernel
+};
+
 struct DevState {
     Slot slot[2];
     unsigned long long kth_key[2];        // smallest key H_k keeps
@@ -61,6 +74,8 @@ struct DevState {
                                           // dense mode)
     unsigned hk_hist[2][kHistCopies][kHistBins];   // nonzero candidates by the top 11 bits of
                                                    // |x'_j|, one copy per XCD (added up by H_k)
+    IterLog log[kLogCap];                 // per executed iteration, by its ordinal (not cleared:
+                                          // a decode writes the records of the iterations it runs)
 };
 
 struct DecodeDims {

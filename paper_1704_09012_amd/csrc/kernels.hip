@@ -80,6 +80,17 @@ __device__ __forceinline__ Slot decide(const DevState* st, int it, int n_iters, 
     return decide_from(st->slot[(it & 1) ^ 1], st->err, it, n_iters, tol_fx, Lt);
 }
 
+// The per-iteration log's record of a decision d just taken on a pending iteration (its
+// trial norm Lt): the iteration is the d.iterations-th executed one.
+__device__ __forceinline__ void log_decision(DevState* st, const Slot& d, long long Lt) {
+    const int q = d.iterations - 1;
+    if (q < 0 || q >= kLogCap) return;
+    IterLog& lg = st->log[q];
+    lg.L_trial = Lt;
+    lg.L_hat = d.L_hat;
+    lg.accepted = d.accepted_last;
+}
+
 // trial_l1 computed by a whole workgroup (blockDim.x >= 64, a multiple of 64); the
 // result is returned to every thread.  The partial sums were written by other CUs, so
 // their loads are issued in parallel rather than one after another.
@@ -528,6 +539,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     DevState* st = a.w.st;
     const int words = (a.m + 31) >> 5;
     const bool bm_regs = words <= kBmPer * kSweepBlock;
+    const unsigned long long t_entry = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0ull;
 
     // ---- round 1
     for (int b = threadIdx.x; b < kHistBins; b += kSweepBlock) lhist[b] = 0u;
@@ -619,6 +631,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         else if (d.pending)
             d.t_step = a.ip.step;
         if (!d.done) d.last_par = me;
+        if (blockIdx.x == 0) {
+            if (prev.pending) log_decision(st, d, Lt);
+            if (d.pending && d.iterations < kLogCap) {
+                IterLog& lg = st->log[d.iterations];
+                lg.t = a.ip.t;
+                lg.it = it;
+                lg.sweep_start = t_entry;
+            }
+        }
         s_sh = d;
         seg_f = 0;
         seg_b = 0;
@@ -908,6 +929,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         const unsigned v = lhist[b];
         if (v) atomicAdd(&st->hk_hist[me][blockIdx.x % kHistCopies][b], v);
     }
+    if (blockIdx.x == 0 && tid == 0 && s.pending && s.iterations < kLogCap)
+        st->log[s.iterations].sweep_end = wall_clock64();
 }
 
 // ------------------------------------------------------------------ H_k and residual change
@@ -1113,6 +1136,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     const int row0 = blockIdx.x * per;
     const int row1 = min(a.m, row0 + per);
 
+    const unsigned long long t_entry = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0ull;
     // ---- round 1: slot, segment sizes and this workgroup's first rows
     const Slot s = st->slot[me];
     int myc = 0, myf = 0, myz = 0, myu = 0;
@@ -1158,7 +1182,13 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     }
     __syncthreads();
-    if (blockIdx.x == 0 && tid == 0 && upd_sh) atomicAdd(&st->updates_total, upd_sh);
+    if (blockIdx.x == 0 && tid == 0) {
+        if (upd_sh) atomicAdd(&st->updates_total, upd_sh);
+        if (s.pending && s.iterations < kLogCap) {
+            st->log[s.iterations].updates = upd_sh;
+            st->log[s.iterations].rows_start = t_entry;
+        }
+    }
     const bool all_kept = nz_sh <= a.k;
     const int* __restrict__ cj = a.w.cand_j[me];
     const float* __restrict__ cx = a.w.cand_x[me];
@@ -1386,6 +1416,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             st->flag_part[me][tr][blockIdx.x] = st_t;
             st->flag_part[me][c][blockIdx.x] = st_c;
         }
+        if (blockIdx.x == 0 && s.pending && s.iterations < kLogCap) st->log[s.iterations].rows_end = wall_clock64();
     }
 }
 
@@ -1462,7 +1493,12 @@ __global__ __launch_bounds__(kRowBlock) void k_rebuild_outer(const float* __rest
 __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n_iters, double tol_fx) {
     __shared__ long long red[4];
     const long long Lt = trial_l1_block(st, (it & 1) ^ 1, red);
-    if (threadIdx.x == 0) st->slot[it & 1] = decide(st, it, n_iters, tol_fx, Lt);
+    if (threadIdx.x == 0) {
+        const Slot p = st->slot[(it & 1) ^ 1];
+        const Slot d = decide_from(p, st->err, it, n_iters, tol_fx, Lt);
+        st->slot[it & 1] = d;
+        if (p.pending) log_decision(st, d, Lt);
+    }
 }
 
 // x_out = x_hat (or, with trial = 1, H_k(x') of the last executed iteration) from the
@@ -1475,8 +1511,12 @@ __global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __re
     if (decide_last) {
         const long long Lt = trial_l1_block(w.st, (it_end & 1) ^ 1, red);
         if (threadIdx.x == 0) {
-            fin_sh = decide(w.st, it_end, n_iters, tol_fx, Lt);
-            if (blockIdx.x == 0) w.st->slot[it_end & 1] = fin_sh;
+            const Slot p = w.st->slot[(it_end & 1) ^ 1];
+            fin_sh = decide_from(p, w.st->err, it_end, n_iters, tol_fx, Lt);
+            if (blockIdx.x == 0) {
+                w.st->slot[it_end & 1] = fin_sh;
+                if (p.pending) log_decision(w.st, fin_sh, Lt);
+            }
         }
     } else if (threadIdx.x == 0) {
         fin_sh = w.st->slot[it_end & 1];

@@ -241,6 +241,7 @@ struct Buffers {
     std::vector<GraphEntry> graphs;    // replayable decodes on this workspace
     unsigned long long uses = 0;
     std::unique_ptr<DeviceConstants> adapted;   // adaptive_k: the decode's current constants
+    int last_log_count = 0;            // executed iterations of the last decode (its log records)
 };
 
 bool graphs_enabled() {
@@ -1058,6 +1059,7 @@ int step_core(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, 
     const rl0::DevState& ds = *b->st_host;
     if (int rc = err_code_of(ds.err)) return rc;
     const rl0::Slot& fin = ds.slot[(it + 1) & 1];
+    b->last_log_count = fin.iterations;
     out->accepted = fin.accepted_last;
     out->L_hat = fin.L_hat;
     out->cur = fin.cur;
@@ -1137,6 +1139,7 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[0];   // sub-iteration 2N decides last
+    b->last_log_count = fin.iterations;
     if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f, b, p->k);
     return err_code_of(ds.err);
 }
@@ -1198,6 +1201,7 @@ int decode_adaptive(Buffers* b, const DeviceConstants* dc0, const rl0::Problem& 
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[it_end & 1];
+    b->last_log_count = fin.iterations;
     profile_collect(it_end, fin.iterations, dm.m > rl0::kPreRows);
     if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b, k_post);
     return err_code_of(ds.err);
@@ -1404,6 +1408,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[N & 1];
+    b->last_log_count = fin.iterations;
     profile_collect(N, fin.iterations, m > rl0::kPreRows);
     if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b, p->k);
     return err_code_of(ds.err);
@@ -1762,6 +1767,25 @@ int rl0_profile_enable(int32_t enable) {
     g_prof.executed = 0;
     g_prof.learned_ms = 0.0;
     g_prof.learned_launches = 0;
+    return RL0_OK;
+}
+
+static_assert(sizeof(rl0_iter_log) == sizeof(rl0::IterLog), "rl0_iter_log mirrors the device record");
+
+int rl0_last_log(rl0_iter_log* out_h, int32_t cap, int32_t* count_h, void* stream) {
+    if (cap < 0 || (cap > 0 && !out_h)) return fail(RL0_EINVAL, "out_h is NULL or cap < 0");
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto it = g_ws.find({dev, s});
+    const int count = (it == g_ws.end() || !it->second->block) ? 0 : it->second->last_log_count;
+    if (count_h) *count_h = count;
+    const int take = std::min({count, cap, rl0::kLogCap});
+    if (take > 0) {
+        HIP_TRY(hipMemcpyAsync(out_h, it->second->w.st->log, sizeof(rl0::IterLog) * take, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return RL0_OK;
 }
 

@@ -179,6 +179,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_profile_read_kernels.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         L.rl0_profile_read_learned.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+        L.rl0_last_log.argtypes = [P, I32, ctypes.POINTER(I32), V]
         L.rl0_decode_batched.argtypes = [ctypes.POINTER(Problem), I32, ctypes.POINTER(Stats), V]
         L.rl0_batch_schedule_get.argtypes = [ctypes.POINTER(BatchSchedule)]
         L.rl0_batch_timeline.argtypes = [I32, P, P, P, V]
@@ -203,6 +204,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_sketch_static", "rl0_validate",
                      "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get", "rl0_profile_read_learned",
+                     "rl0_last_log",
                      "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_batch_timeline", "rl0_mlp_init", "rl0_mlp_features",
                      "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam"):
             getattr(L, name).restype = ctypes.c_int
@@ -405,6 +407,20 @@ def profile_read_kernels() -> dict:
     names = ("sweep", "hk_rows")
     return {"all": {k: arr[i] for i, k in enumerate(names)}, "all_launches": cnt[0],
             "executed": {k: arr[2 + i] for i, k in enumerate(names)}, "executed_launches": cnt[1]}
+
+
+ITER_LOG = np.dtype([("l1_trial_fx", np.int64), ("l1_hat_fx", np.int64), ("accepted", np.int32),
+                     ("updates", np.int32), ("t", np.float32), ("it", np.int32), ("sweep_start", np.uint64),
+                     ("sweep_end", np.uint64), ("rows_start", np.uint64), ("rows_end", np.uint64)])
+
+
+def last_log(cap: int = 4096) -> np.ndarray:
+    """rl0_last_log: the per-iteration records of the last decode on the current stream (a
+    numpy structured array of dtype ITER_LOG)."""
+    out = np.zeros(cap, ITER_LOG)
+    count = ctypes.c_int32(0)
+    _check(lib().rl0_last_log(out.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(count), _stream()))
+    return out[:min(count.value, cap)]
 
 
 def profile_read_learned() -> tuple[float, int]:

@@ -16,6 +16,8 @@ workloads:
     0.01), seed 30100.  Its oracle decode takes about half an hour on one core;
   * the quantised variant (files decodeq_*) at n = 2^20, m = n/10, k = m/10, d = 7 at 20,
     40 and 60 dB, one seed each (c from eq:finetune_c_quant: 0.05, 20 iterations);
+  * Laplace signal and noise laws (decodel_*): n = 2^20, m = n/10, k = m/10, d = 7 at 40 dB,
+    decoded with the oracle's tables of those laws (make_tables.py writes them first);
   * Alg. 1's adaptive_k branch (files decodea_*): n = 2^20, m = n/10, k = m/10, d = 7 at
     20, 40 and 60 dB, the quantised variant at 40 dB (decodeaq_*), and n = 2^20, m = n/2,
     k = m/8, d = 8 at 40 dB (m above 393216); these also store the last k_0.
@@ -34,6 +36,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import decoder as D  # noqa: E402
+from oracle import scores as S  # noqa: E402
 from paper_1704_09012_amd import instances as I  # noqa: E402
 
 N = 2 ** 20
@@ -48,7 +51,9 @@ def case_name(snr: int, i: int) -> str:
     return f"decode_n1048576_d7_snr{snr}_i{i}.npz"
 
 
-# (file name, n, m, k of the signal, d, snr, seed, k of the decoder[, variant[, adaptive_k]])
+# (file name, n, m, k of the signal, d, snr, seed, k of the decoder[, variant[, adaptive_k[, laws]]]);
+# laws = (signal law, noise law), decoded with the oracle's tables of those laws stored by
+# make_tables.py
 CASES = [(case_name(snr, i), N, M, K, DD, snr, I.seed_for(2, si, i), K)
          for si, snr in enumerate(SNRS) for i in range(SEEDS_PER_SNR)]
 CASES += [(f"decodeq_n1048576_d7_snr{snr}_i0.npz", N, M, K, DD, snr, I.seed_for(6, si, 0), K, 1)
@@ -61,6 +66,8 @@ CASES += [(f"decodea_n1048576_d7_snr{snr}_i0.npz", N, M, K, DD, snr, I.seed_for(
 CASES.append(("decodeaq_n1048576_d7_snr40_i0.npz", N, M, K, DD, 40, I.seed_for(8, 1, 0), K, 1, 1))
 CASES.append(("decodea_n1048576_m524288_d8_snr40_i0.npz", N, N // 2, N // 16, 8, 40, I.seed_for(7, 1, 10), N // 16,
               0, 1))
+CASES.append(("decodel_n1048576_d7_snr40_laplace_laplace_i0.npz", N, M, K, DD, 40, I.seed_for(9, 1, 0), K, 0, 0,
+              ("laplace", "laplace")))
 CASES.append(("decode_n16777216_m2097152_d8_snr40_i0.npz", 2 ** 24, 2 ** 21, 2 ** 18, 8, 40, I.seed_for(3, 1, 0),
               2 ** 18))
 
@@ -69,17 +76,25 @@ def one(case):
     name, n, m, k, d, snr, seed, k_dec = case[:8]
     variant = case[8] if len(case) > 8 else 0
     adaptive = case[9] if len(case) > 9 else 0
+    laws = case[10] if len(case) > 10 else ("gaussian", "gaussian")
     sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
-    inst = I.draw_instance(n, m, k, d, sig, seed)
+    inst = I.draw_instance(n, m, k, d, sig, seed, kind=laws[0], noise_kind=laws[1])
     x = inst.x_dense()
     # only the support's columns contribute to A x
     y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-    C = D.make_constants(n, m, d, k_dec, sig, variant=variant, adaptive_k=adaptive)
+    tables = None
+    if laws != ("gaussian", "gaussian"):
+        g = np.load(os.path.join(HERE, f"tables_n{n}_m{m}_k{k_dec}_d{d}_snr{snr}_{laws[0]}_{laws[1]}.npz"))
+        tables = (S.Table(g["Tz"], np.float32(g["inv_h_z"]), float(g["R_z"])),
+                  S.Table(g["Te"], np.float32(g["inv_h_e"]), float(g["R_e"])))
+    C = D.make_constants(n, m, d, k_dec, sig, variant=variant, adaptive_k=adaptive, signal=laws[0], noise=laws[1],
+                         tables=tables)
     res = D.decode(inst.A_cols, y, C)
     supp = np.nonzero(res.x_hat)[0].astype(np.int32)
     path = os.path.join(HERE, name)
     np.savez_compressed(path, n=n, m=m, k=k, k_decode=k_dec, d=d, snr=snr, seed=seed, sigma=np.float32(sig),
                         variant=variant, adaptive_k=adaptive, k_post=np.float64(res.k_post),
+                        signal=laws[0], noise=laws[1],
                         fx_inexact_y=res.fx_inexact_y, fx_inexact_x=res.fx_inexact_x,
                         support=supp, values=res.x_hat[supp].astype(np.float32),
                         iterations=res.iterations, accepted=res.accepted, L_hat=np.int64(res.L_hat),

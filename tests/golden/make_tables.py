@@ -1,6 +1,6 @@
 """Write the oracle's score tables for non-Gaussian laws used by the GPU tests.
 
-    python tests/golden/make_tables.py [--jobs 6]
+    python tests/golden/make_tables.py [--jobs 6] [--only NAME_PREFIX]
 
 Only the CPU oracle (oracle/general.py) is called.  Each file (tables_*.npz) holds, for
 one problem shape and pair of laws (Thm "Probabilities for general signal and noise
@@ -32,6 +32,9 @@ CASES = [
     ("tables_n65536_m6553_k655_d7_snr30_laplace_laplace.npz", 65536, 6553, 655, 7, 30, "laplace", "laplace"),
     ("tables_n65536_m6553_k655_d7_snr40_gaussian_laplace.npz", 65536, 6553, 655, 7, 40, "gaussian", "laplace"),
     ("tables_n65536_m6553_k655_d7_snr40_laplace_gaussian.npz", 65536, 6553, 655, 7, 40, "laplace", "gaussian"),
+    # the headline shape with Laplace laws (bench.py --workload laplace, and its stored decode)
+    ("tables_n1048576_m104857_k10485_d7_snr40_laplace_laplace.npz", 2 ** 20, 104857, 10485, 7, 40, "laplace",
+     "laplace"),
 ]
 
 
@@ -54,9 +57,11 @@ def one(case):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)
+    ap.add_argument("--only", default="", help="write only the files whose name starts with this")
     a = ap.parse_args()
+    work = [c for c in CASES if c[0].startswith(a.only)]
     with ProcessPoolExecutor(a.jobs) as ex:
-        for path in ex.map(one, CASES):
+        for path in ex.map(one, work):
             print(os.path.basename(path), flush=True)
 
 

@@ -127,3 +127,33 @@ def test_library_tables_decode_like_the_oracle(name):
     assert np.count_nonzero(a) <= inst.k
     C = D.make_constants(inst.n, inst.m, inst.d, inst.k, sig, signal=sl, noise=nl, tables=tables)
     assert_same_decode(a, st1, D.decode(inst.A_cols, y, C))
+
+
+def _golden_l():
+    if not os.path.isdir(GOLDEN):
+        return []
+    return sorted(f for f in os.listdir(GOLDEN) if f.startswith("decodel_") and f.endswith(".npz"))
+
+
+@pytest.mark.parametrize("fname", _golden_l())
+def test_laplace_laws_full_size_against_stored_oracle(fname):
+    """n = 2^20, m = n/10, k = m/10, d = 7, Laplace signal and noise at 40 dB: the oracle's
+    decode with its tables of those laws (tests/golden/make_golden.py), against the
+    library's decode with the same given tables and with its own tables, bitwise."""
+    g = np.load(os.path.join(GOLDEN, fname))
+    n, m, k, d = int(g["n"]), int(g["m"]), int(g["k"]), int(g["d"])
+    sig = float(g["sigma"])
+    sl, nl = str(g["signal"]), str(g["noise"])
+    tab = np.load(os.path.join(GOLDEN, f"tables_n{n}_m{m}_k{k}_d{d}_snr{int(g['snr'])}_{sl}_{nl}.npz"))
+    packed = R.pack_tables(tab["Tz"], tab["Te"], tab["inv_h_z"], tab["inv_h_e"])
+    print(f"golden {fname}", flush=True)
+    inst = I.draw_instance(n, m, k, d, sig, int(g["seed"]), kind=sl, noise_kind=nl)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+    A, yt = dev(inst.A_cols), dev(y)
+    ref = np.zeros(n, np.float32)
+    ref[g["support"]] = g["values"]
+    for kw in (dict(tables=packed), {}):
+        xg, stg = R.decode(A, yt, sigma=sig, k=k, signal_law=sl, noise_law=nl, **kw)
+        assert np.array_equal(host(xg), ref)
+        assert stg["iterations"] == int(g["iterations"]) and stg["accepted"] == int(g["accepted"])
+        assert stg["l1_final_fx"] == int(g["L_hat"]) and stg["updates_total"] == int(g["updates_total"])

@@ -1,0 +1,86 @@
+"""The per-iteration log (rl0_last_log) against the oracle's trace of the same decode.
+
+For every executed iteration of Alg. 1's loop the device records ||r||_1 of the trial
+iterate, ||r_hat||_1 after the acceptance test, the decision, the column updates of the
+sweep and t; these are compared bitwise with oracle.decoder.decode(keep_trace=True).  The
+records' wall-clock stamps of workgroup 0 (sweep, then row kernel, iteration after
+iteration) must be ordered, and the updates must add up to the decode's updates_total."""
+import numpy as np
+import pytest
+
+from oracle import decoder as D
+from oracle import scores as S
+from paper_1704_09012_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_1704_09012_amd.rl0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_log(log, st, res, C):
+    assert len(log) == st["iterations"] == res.iterations
+    tr = res.trace
+    for i, (rec, (L_before, L_trial, acc, upd)) in enumerate(zip(log, tr)):
+        assert rec["l1_trial_fx"] == L_trial, i
+        assert bool(rec["accepted"]) == bool(acc), i
+        assert rec["l1_hat_fx"] == (L_trial if acc else L_before), i
+        assert rec["updates"] == upd, i
+        assert rec["t"] == S.t_of(i, C.c), i
+    assert int(log["updates"].sum()) == st["updates_total"]
+    if len(log):
+        assert log["l1_hat_fx"][-1] == st["l1_final_fx"]
+        stamps = np.stack([log["sweep_start"], log["sweep_end"], log["rows_start"], log["rows_end"]], 1)
+        flat = stamps.reshape(-1).astype(np.int64)
+        assert np.all(np.diff(flat) >= 0) and flat[-1] > flat[0]
+
+
+@pytest.mark.parametrize("n,m,k,d,snr,seed,variant", [
+    (1024, 256, 25, 7, 40, 1, 0), (1024, 256, 25, 7, 20, 2, 0), (1024, 256, 25, 7, 40, 3, 1),
+    (65536, 6553, 655, 7, 40, 4, 0), (50003, 2999, 400, 8, 30, 5, 0),
+    (200000, 400003, 40000, 6, 40, 8, 0),   # the large-m path (H_k's classification kernel)
+])
+def test_log_matches_the_oracle_trace(n, m, k, d, snr, seed, variant):
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, seed)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+    print(f"log n={n} m={m} variant={variant}", flush=True)
+    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, variant=variant)
+    log = R.last_log()
+    C = D.make_constants(n, m, d, k, sig, variant=variant)
+    res = D.decode(inst.A_cols, y, C, keep_trace=True)
+    check_log(log, st, res, C)
+
+
+def test_log_of_an_adaptive_decode():
+    n, m, d, k = 8192, 2048, 7, 200
+    sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, 9)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, adaptive_k=1)
+    C = D.make_constants(n, m, d, k, sig, adaptive_k=1)
+    check_log(R.last_log(), st, D.decode(inst.A_cols, y, C, keep_trace=True), C)
+
+
+def test_log_of_a_learned_decode_counts_its_sub_iterations():
+    n, m, d, k = 4096, 1024, 7, 80
+    sig = 2.0 ** -7
+    inst = I.draw_instance(n, m, k, d, sig, 71)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    w = R.mlp_init(d, 3)
+    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=w)
+    log = R.last_log()
+    assert len(log) == st["iterations"] and int(log["updates"].sum()) == st["updates_total"]
+    its = log["it"]
+    assert np.all(np.diff(its) > 0)                      # sub-iterations in order, skipped retries absent
+    C = D.make_constants(n, m, d, k, sig)
+    assert all(rec["t"] == S.t_of(int(rec["it"]) // 2, C.c) for rec in log)
+    # a learned sub-iteration 2j whose trial was accepted is followed by 2j + 2, never 2j + 1
+    for a, b, acc in zip(its[:-1], its[1:], log["accepted"][:-1]):
+        if a % 2 == 0 and acc:
+            assert b != a + 1
+    assert log["l1_hat_fx"][-1] == st["l1_final_fx"]
