@@ -93,6 +93,8 @@ typedef struct rl0_params {
                                2 Var(nu) for e, first q >= 8 with p_breve < 2^-27; p_breve =
                                p / p(0); T[0] = 1); the stopping tolerance is m E|eta_i|
                                (m sigma / sqrt(2) for Laplace noise) */
+    int32_t log;            /* 1 = record the per-iteration log of the decode (rl0_last_log;
+                               a few stores per iteration), 0 (default) = none */
     const float* tables;    /* NULL, or host pointer to RL0_TABLES_FLOATS floats: score
                                tables to use instead of the library's (sigma > 0).  Each
                                table must be finite, start at 1, stay in [0, 1] and be
@@ -362,10 +364,11 @@ int rl0_mlp_pack_bf16(const float* w_h, int32_t d, uint16_t* packed_h);
 int rl0_mlp_forward(const float* feats, int32_t N, int32_t d, const float* w, float* out, int32_t bf16,
                     void* stream);
 
-/* The per-iteration log of the last rl0_decode (or rl0_step) on this stream: the
- * records of its executed iterations in order, at most cap of them, into out_h (host);
- * *count_h <- the number of executed iterations (records beyond 4096 are not kept).
- * Batched decodes keep no log.  Synchronises the stream. */
+/* The per-iteration log of the last rl0_decode (or rl0_step) on this stream, when it ran
+ * with params.log = 1: the records of its executed iterations in order, at most cap of
+ * them, into out_h (host); *count_h <- the number of executed iterations (0 if that call
+ * did not log; records beyond 4096 are not kept).  Batched decodes keep no log.
+ * Synchronises the stream. */
 int rl0_last_log(rl0_iter_log* out_h, int32_t cap, int32_t* count_h, void* stream);
 
 /* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of

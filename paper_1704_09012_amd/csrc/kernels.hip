@@ -181,11 +181,14 @@ __global__ void k_sketch_finish(const long long* __restrict__ S, float* __restri
 
 // ------------------------------------------------------------------ prepare
 
-constexpr int kStateWords = static_cast<int>(sizeof(DevState) / sizeof(int));
+// the state a decode starts from: everything before the per-iteration log
+constexpr int kStateWords = static_cast<int>(offsetof(DevState, log) / sizeof(int));
+constexpr int kLogOnWord = static_cast<int>(offsetof(DevState, log_on) / sizeof(int));
 
-__global__ void k_prep_state(DevState* st) {
+__global__ void k_prep_state(DevState* st, int log_on) {
     int* p = reinterpret_cast<int*>(st);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kStateWords; i += gridDim.x * blockDim.x) p[i] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kStateWords; i += gridDim.x * blockDim.x)
+        p[i] = i == kLogOnWord ? log_on : 0;
 }
 
 // The starting support x0 as the candidate segments of the iteration before it0, in
@@ -556,10 +559,11 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         }
     }
     Slot prev{};
-    int err = 0;
+    int err = 0, log_on = 0;
     if (tid == 0) {
         prev = st->slot[pv];
         err = st->err;
+        log_on = st->log_on;
     }
     const int pc = st->seg_count[pv][seg];
     const int pf = st->seg_front[pv][seg];
@@ -631,7 +635,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         else if (d.pending)
             d.t_step = a.ip.step;
         if (!d.done) d.last_par = me;
-        if (blockIdx.x == 0) {
+        if (blockIdx.x == 0 && log_on) {
             if (prev.pending) log_decision(st, d, Lt);
             if (d.pending && d.iterations < kLogCap) {
                 IterLog& lg = st->log[d.iterations];
@@ -929,7 +933,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         const unsigned v = lhist[b];
         if (v) atomicAdd(&st->hk_hist[me][blockIdx.x % kHistCopies][b], v);
     }
-    if (blockIdx.x == 0 && tid == 0 && s.pending && s.iterations < kLogCap)
+    if (blockIdx.x == 0 && tid == 0 && log_on && s.pending && s.iterations < kLogCap)
         st->log[s.iterations].sweep_end = wall_clock64();
 }
 
@@ -1139,6 +1143,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     const unsigned long long t_entry = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0ull;
     // ---- round 1: slot, segment sizes and this workgroup's first rows
     const Slot s = st->slot[me];
+    const int log_on = (blockIdx.x == 0 && tid == 0) ? st->log_on : 0;
     int myc = 0, myf = 0, myz = 0, myu = 0;
     if (tid < nseg) {
         myc = st->seg_count[me][tid];
@@ -1184,7 +1189,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     __syncthreads();
     if (blockIdx.x == 0 && tid == 0) {
         if (upd_sh) atomicAdd(&st->updates_total, upd_sh);
-        if (s.pending && s.iterations < kLogCap) {
+        if (log_on && s.pending && s.iterations < kLogCap) {
             st->log[s.iterations].updates = upd_sh;
             st->log[s.iterations].rows_start = t_entry;
         }
@@ -1416,7 +1421,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             st->flag_part[me][tr][blockIdx.x] = st_t;
             st->flag_part[me][c][blockIdx.x] = st_c;
         }
-        if (blockIdx.x == 0 && s.pending && s.iterations < kLogCap) st->log[s.iterations].rows_end = wall_clock64();
+        if (log_on && s.pending && s.iterations < kLogCap) st->log[s.iterations].rows_end = wall_clock64();
     }
 }
 
@@ -1497,7 +1502,7 @@ __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n
         const Slot p = st->slot[(it & 1) ^ 1];
         const Slot d = decide_from(p, st->err, it, n_iters, tol_fx, Lt);
         st->slot[it & 1] = d;
-        if (p.pending) log_decision(st, d, Lt);
+        if (p.pending && st->log_on) log_decision(st, d, Lt);
     }
 }
 
@@ -1515,7 +1520,7 @@ __global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __re
             fin_sh = decide_from(p, w.st->err, it_end, n_iters, tol_fx, Lt);
             if (blockIdx.x == 0) {
                 w.st->slot[it_end & 1] = fin_sh;
-                if (p.pending) log_decision(w.st, fin_sh, Lt);
+                if (p.pending && w.st->log_on) log_decision(w.st, fin_sh, Lt);
             }
         }
     } else if (threadIdx.x == 0) {
@@ -1706,7 +1711,7 @@ hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, 
 }
 
 hipError_t launch_clear_state(DevState* st, hipStream_t s) {
-    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(st);
+    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(st, 0);
     return hipGetLastError();
 }
 
@@ -1729,7 +1734,7 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0, hipStream_t s,
                           float* x_zero) {
     const int slot = (ip0.it & 1) ^ 1;   // the slot iteration it0 reads as "previous"
-    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(w.st);
+    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(w.st, ip0.log);
     if (x_hat0) k_prep_support<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, dm.n, w, slot);
     k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], w.D, dm.m, w.st);
     // the packing pass validates the columns and clears x_zero; without packing they

@@ -340,6 +340,7 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     if (p->adaptive_k != 0 && p->adaptive_k != 1) return fail(RL0_EINVAL, "adaptive_k must be 0 or 1");
     if (p->adaptive_k == 1 && p->posterior == 1)
         return fail(RL0_EINVAL, "adaptive_k applies to the analytic posteriors only");
+    if (p->log != 0 && p->log != 1) return fail(RL0_EINVAL, "log must be 0 or 1");
     for (int32_t law : {p->signal_law, p->noise_law})
         if (law != RL0_LAW_GAUSSIAN && law != RL0_LAW_LAPLACE)
             return fail(RL0_EINVAL, "signal_law and noise_law must be RL0_LAW_GAUSSIAN or RL0_LAW_LAPLACE");
@@ -382,6 +383,7 @@ void params_key(const rl0_params* p, rl0_params* out) {
     k.adaptive_k = p->adaptive_k;
     k.signal_law = p->signal_law;
     k.noise_law = p->noise_law;
+    k.log = p->log;
     // given tables enter through the constants (their device copy is part of the key)
 }
 
@@ -512,6 +514,7 @@ rl0::IterParams iter_params(const DeviceConstants* dc, const rl0_params* p, int 
     ip.n_iters = N;
     ip.tol_fx = dc->hc.tol * 1073741824.0;
     ip.quant = dc->hc.quant ? 1 : 0;
+    ip.log = p->log;
     if (ip.quant && it < N) {
         ip.qe_bits = dc->hc.qe_bits[it];
         ip.qz_bits = dc->hc.qz_bits[it];
@@ -1059,7 +1062,7 @@ int step_core(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims& dm, 
     const rl0::DevState& ds = *b->st_host;
     if (int rc = err_code_of(ds.err)) return rc;
     const rl0::Slot& fin = ds.slot[(it + 1) & 1];
-    b->last_log_count = fin.iterations;
+    b->last_log_count = p->log ? fin.iterations : 0;
     out->accepted = fin.accepted_last;
     out->L_hat = fin.L_hat;
     out->cur = fin.cur;
@@ -1139,7 +1142,7 @@ int decode_learned(Buffers* b, const DeviceConstants* dc, const rl0::DecodeDims&
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[0];   // sub-iteration 2N decides last
-    b->last_log_count = fin.iterations;
+    b->last_log_count = p->log ? fin.iterations : 0;
     if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.t_step] : 1.0f, b, p->k);
     return err_code_of(ds.err);
 }
@@ -1201,7 +1204,7 @@ int decode_adaptive(Buffers* b, const DeviceConstants* dc0, const rl0::Problem& 
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[it_end & 1];
-    b->last_log_count = fin.iterations;
+    b->last_log_count = p->log ? fin.iterations : 0;
     profile_collect(it_end, fin.iterations, dm.m > rl0::kPreRows);
     if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b, k_post);
     return err_code_of(ds.err);
@@ -1408,7 +1411,7 @@ int rl0_decode(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, const flo
     HIP_TRY(hipStreamSynchronize(s));
     const rl0::DevState& ds = *b->st_host;
     const rl0::Slot& fin = ds.slot[N & 1];
-    b->last_log_count = fin.iterations;
+    b->last_log_count = p->log ? fin.iterations : 0;
     profile_collect(N, fin.iterations, m > rl0::kPreRows);
     if (st_h) fill_stats(st_h, ds, fin, dc, fin.iterations > 0 ? dc->hc.t[fin.iterations - 1] : 1.0f, b, p->k);
     return err_code_of(ds.err);

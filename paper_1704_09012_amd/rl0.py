@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("adaptive_k", ctypes.c_int32),
         ("signal_law", ctypes.c_int32),
         ("noise_law", ctypes.c_int32),
+        ("log", ctypes.c_int32),
         ("tables", ctypes.c_void_p),
     ]
 

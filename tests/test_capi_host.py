@@ -45,7 +45,7 @@ def test_params_default_follow_the_paper():
     ("k", 0), ("k", 256), ("alpha", 1.0), ("alpha", 7.5), ("c", 1.0), ("c", -0.1),
     ("sigma", -1.0), ("sigma", float("nan")), ("sigma_signal", 0.0), ("series_terms", 0),
     ("max_iters", -1), ("l1_test", 2), ("posterior", 3), ("variant", 2), ("variant", -1), ("adaptive_k", 2),
-    ("adaptive_k", -1),
+    ("adaptive_k", -1), ("log", 2), ("signal_law", 5),
 ])
 def test_bad_params_are_rejected_on_the_host(field, value):
     p = R.params_default(1024, 256, 7, 25, 0.01)

@@ -1,4 +1,5 @@
-"""The per-iteration log (rl0_last_log) against the oracle's trace of the same decode.
+"""The per-iteration log (rl0_last_log, params.log = 1) against the oracle's trace of the
+same decode.
 
 For every executed iteration of Alg. 1's loop the device records ||r||_1 of the trial
 iterate, ||r_hat||_1 after the acceptance test, the decision, the column updates of the
@@ -49,7 +50,7 @@ def test_log_matches_the_oracle_trace(n, m, k, d, snr, seed, variant):
     inst = I.draw_instance(n, m, k, d, sig, seed)
     y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
     print(f"log n={n} m={m} variant={variant}", flush=True)
-    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, variant=variant)
+    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, variant=variant, log=1)
     log = R.last_log()
     C = D.make_constants(n, m, d, k, sig, variant=variant)
     res = D.decode(inst.A_cols, y, C, keep_trace=True)
@@ -61,7 +62,7 @@ def test_log_of_an_adaptive_decode():
     sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
     inst = I.draw_instance(n, m, k, d, sig, 9)
     y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, adaptive_k=1)
+    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, adaptive_k=1, log=1)
     C = D.make_constants(n, m, d, k, sig, adaptive_k=1)
     check_log(R.last_log(), st, D.decode(inst.A_cols, y, C, keep_trace=True), C)
 
@@ -72,7 +73,7 @@ def test_log_of_a_learned_decode_counts_its_sub_iterations():
     inst = I.draw_instance(n, m, k, d, sig, 71)
     y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
     w = R.mlp_init(d, 3)
-    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=w)
+    _, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=w, log=1)
     log = R.last_log()
     assert len(log) == st["iterations"] and int(log["updates"].sum()) == st["updates_total"]
     its = log["it"]
@@ -84,3 +85,17 @@ def test_log_of_a_learned_decode_counts_its_sub_iterations():
         if a % 2 == 0 and acc:
             assert b != a + 1
     assert log["l1_hat_fx"][-1] == st["l1_final_fx"]
+
+
+def test_no_log_without_the_flag():
+    n, m, d, k = 1024, 256, 7, 25
+    sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, 1)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+    A, yt = dev(inst.A_cols), dev(y)
+    R.decode(A, yt, sigma=sig, k=k, log=1)
+    assert len(R.last_log()) > 0
+    x0, st0 = R.decode(A, yt, sigma=sig, k=k)
+    assert len(R.last_log()) == 0
+    x1, st1 = R.decode(A, yt, sigma=sig, k=k, log=1)   # the log changes nothing else
+    assert torch.equal(x0, x1) and R.stats_subset(st0) == R.stats_subset(st1)
