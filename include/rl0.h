@@ -126,7 +126,10 @@ typedef struct rl0_stats {
 } rl0_stats;
 
 /* One executed loop iteration of the last decode (rl0_last_log), recorded on the device
- * by the decision on it and by workgroup 0 of its two kernels. */
+ * by workgroup 0 of the iteration's row kernel and of the kernel that takes the decision
+ * on it (the sweep carries no logging code).  The row kernel starts once the sweep has
+ * ended, so the span between one record's rows_end and the next one's rows_start holds
+ * the next sweep and two kernel boundaries. */
 typedef struct rl0_iter_log {
     int64_t l1_trial_fx;    /* ||r||_1 of the iteration's trial iterate (units of 2^-30) */
     int64_t l1_hat_fx;      /* ||r_hat||_1 after the decision on it (Alg. 1's acceptance test) */
@@ -135,8 +138,8 @@ typedef struct rl0_iter_log {
     float t;                /* its t */
     int32_t it;             /* its loop index (learned decodes: the sub-iteration, 2j learned,
                                2j + 1 the analytic retry at the same t) */
-    uint64_t sweep_start, sweep_end;  /* device wall clock (100 MHz) when workgroup 0 of the */
-    uint64_t rows_start, rows_end;    /* sweep and of the row kernel began and ended */
+    uint64_t rows_start, rows_end;  /* device wall clock (100 MHz) when workgroup 0 of the
+                                       iteration's row kernel began and ended */
 } rl0_iter_log;
 
 /* Host copy of the decoder's constants, for inspection and tests. */

@@ -49,8 +49,7 @@ struct IterLog {
     int updates;           // column updates the iteration's sweep proposed
     float t;               // the iteration's t
     int it;                // its loop index (the sub-iteration index in a learned decode)
-    unsigned long long sweep_start, sweep_end;   // wall clock (100 MHz) of workgroup 0 in the sweep
-    unsigned long long rows_start, rows_end;     //   and in the row kernel
+    unsigned long long rows_start, rows_end;     // wall clock (100 MHz) of workgroup 0 in the row kernel
 };
 
 struct DevState {
@@ -60,7 +59,6 @@ struct DevState {
     int err;                              // ErrFlag bits
     int inexact_y;                        // entries of y whose fixed-point conversion rounds
     int inexact_x;                        // updated x'_j != 0 whose conversion rounds (all sweeps)
-    int log_on;                           // the decode records the per-iteration log
     int peek_cur, peek_done;              // the coming decision, evaluated ahead (learned decode,
     int peek_acc;                         //   adaptive_k): buffer, stop, accepted
     long long adapt_sum;                  // sum_j rint(2^30 fl32(1 - Tz(|x_hat_j|))) (adaptive_k)
@@ -109,7 +107,7 @@ struct IterParams {
     int quant = 0;        // quantised scores, with this iteration's thresholds:
     uint32_t qe_bits = 0; //   q_e(a) = 1 iff bits(|a|) <= qe_bits
     uint32_t qz_bits = 0; //   q_z(v) = 1 iff bits(|v|) <= qz_bits
-    int log = 0;          // (the prologue's) record the per-iteration log
+    int log = 0;          // record the iteration in the per-iteration log
 };
 
 // Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.  x_hat

@@ -183,12 +183,10 @@ __global__ void k_sketch_finish(const long long* __restrict__ S, float* __restri
 
 // the state a decode starts from: everything before the per-iteration log
 constexpr int kStateWords = static_cast<int>(offsetof(DevState, log) / sizeof(int));
-constexpr int kLogOnWord = static_cast<int>(offsetof(DevState, log_on) / sizeof(int));
 
-__global__ void k_prep_state(DevState* st, int log_on) {
+__global__ void k_prep_state(DevState* st) {
     int* p = reinterpret_cast<int*>(st);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kStateWords; i += gridDim.x * blockDim.x)
-        p[i] = i == kLogOnWord ? log_on : 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kStateWords; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // The starting support x0 as the candidate segments of the iteration before it0, in
@@ -542,7 +540,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     DevState* st = a.w.st;
     const int words = (a.m + 31) >> 5;
     const bool bm_regs = words <= kBmPer * kSweepBlock;
-    const unsigned long long t_entry = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0ull;
 
     // ---- round 1
     for (int b = threadIdx.x; b < kHistBins; b += kSweepBlock) lhist[b] = 0u;
@@ -559,11 +556,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         }
     }
     Slot prev{};
-    int err = 0, log_on = 0;
+    int err = 0;
     if (tid == 0) {
         prev = st->slot[pv];
         err = st->err;
-        log_on = st->log_on;
     }
     const int pc = st->seg_count[pv][seg];
     const int pf = st->seg_front[pv][seg];
@@ -635,15 +631,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         else if (d.pending)
             d.t_step = a.ip.step;
         if (!d.done) d.last_par = me;
-        if (blockIdx.x == 0 && log_on) {
-            if (prev.pending) log_decision(st, d, Lt);
-            if (d.pending && d.iterations < kLogCap) {
-                IterLog& lg = st->log[d.iterations];
-                lg.t = a.ip.t;
-                lg.it = it;
-                lg.sweep_start = t_entry;
-            }
-        }
         s_sh = d;
         seg_f = 0;
         seg_b = 0;
@@ -933,8 +920,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         const unsigned v = lhist[b];
         if (v) atomicAdd(&st->hk_hist[me][blockIdx.x % kHistCopies][b], v);
     }
-    if (blockIdx.x == 0 && tid == 0 && log_on && s.pending && s.iterations < kLogCap)
-        st->log[s.iterations].sweep_end = wall_clock64();
 }
 
 // ------------------------------------------------------------------ H_k and residual change
@@ -952,6 +937,8 @@ struct FinishArgs {
                        // fit in the sweep's LDS; the counts select its dense mode)
     int pre;        // k_hk_classify ran before: drops below the boundary bucket are in D and
                     // the bucket's entries are listed in w.bkey / w.bx
+    int log;        // record the iteration in the per-iteration log
+    float t;        // the iteration's t (for that log)
 };
 
 
@@ -1140,10 +1127,16 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     const int row0 = blockIdx.x * per;
     const int row1 = min(a.m, row0 + per);
 
-    const unsigned long long t_entry = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0ull;
+    // the per-iteration log (workgroup 0): this iteration's record, and the decision on the
+    // iteration before, which this iteration's sweep took (its trial norm is the sum of the
+    // partial sums that iteration's row kernel left in L_part)
+    const bool log_wg = a.log && blockIdx.x == 0;
+    const unsigned long long t_entry = (log_wg && tid == 0) ? wall_clock64() : 0ull;
+    long long lt_prev = 0;
+    if (log_wg && tid < 64)
+        for (int b = tid; b < kRowGrid; b += 64) lt_prev += st->L_part[me ^ 1][b];
     // ---- round 1: slot, segment sizes and this workgroup's first rows
     const Slot s = st->slot[me];
-    const int log_on = (blockIdx.x == 0 && tid == 0) ? st->log_on : 0;
     int myc = 0, myf = 0, myz = 0, myu = 0;
     if (tid < nseg) {
         myc = st->seg_count[me][tid];
@@ -1187,11 +1180,20 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     }
     __syncthreads();
+    if (log_wg && tid < 64)
+        for (int off = 32; off > 0; off >>= 1) lt_prev += __shfl_down(lt_prev, off);
     if (blockIdx.x == 0 && tid == 0) {
         if (upd_sh) atomicAdd(&st->updates_total, upd_sh);
-        if (log_on && s.pending && s.iterations < kLogCap) {
-            st->log[s.iterations].updates = upd_sh;
-            st->log[s.iterations].rows_start = t_entry;
+        if (log_wg) {
+            const Slot p = st->slot[me ^ 1];
+            if (p.pending) log_decision(st, s, lt_prev);
+            if (s.pending && s.iterations < kLogCap) {
+                IterLog& lg = st->log[s.iterations];
+                lg.updates = upd_sh;
+                lg.t = a.t;
+                lg.it = a.it;
+                lg.rows_start = t_entry;
+            }
         }
     }
     const bool all_kept = nz_sh <= a.k;
@@ -1421,7 +1423,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
             st->flag_part[me][tr][blockIdx.x] = st_t;
             st->flag_part[me][c][blockIdx.x] = st_c;
         }
-        if (log_on && s.pending && s.iterations < kLogCap) st->log[s.iterations].rows_end = wall_clock64();
+        if (log_wg && s.pending && s.iterations < kLogCap) st->log[s.iterations].rows_end = wall_clock64();
     }
 }
 
@@ -1495,14 +1497,14 @@ __global__ __launch_bounds__(kRowBlock) void k_rebuild_outer(const float* __rest
     }
 }
 
-__global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n_iters, double tol_fx) {
+__global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n_iters, double tol_fx, int log_on) {
     __shared__ long long red[4];
     const long long Lt = trial_l1_block(st, (it & 1) ^ 1, red);
     if (threadIdx.x == 0) {
         const Slot p = st->slot[(it & 1) ^ 1];
         const Slot d = decide_from(p, st->err, it, n_iters, tol_fx, Lt);
         st->slot[it & 1] = d;
-        if (p.pending && st->log_on) log_decision(st, d, Lt);
+        if (p.pending && log_on) log_decision(st, d, Lt);
     }
 }
 
@@ -1510,7 +1512,7 @@ __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n
 // candidate segments of the last executed iteration; x_out holds zeros beforehand.  With decide = 1 every workgroup first takes the
 // decision on the last iteration (it_end = n_iters) itself, and workgroup 0 records it.
 __global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end,
-                                                  int trial, int decide_last, int n_iters, double tol_fx) {
+                                                  int trial, int decide_last, int n_iters, double tol_fx, int log_on) {
     __shared__ long long red[4];
     __shared__ Slot fin_sh;
     if (decide_last) {
@@ -1520,7 +1522,7 @@ __global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __re
             fin_sh = decide_from(p, w.st->err, it_end, n_iters, tol_fx, Lt);
             if (blockIdx.x == 0) {
                 w.st->slot[it_end & 1] = fin_sh;
-                if (p.pending && w.st->log_on) log_decision(w.st, fin_sh, Lt);
+                if (p.pending && log_on) log_decision(w.st, fin_sh, Lt);
             }
         }
     } else if (threadIdx.x == 0) {
@@ -1711,7 +1713,7 @@ hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, 
 }
 
 hipError_t launch_clear_state(DevState* st, hipStream_t s) {
-    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(st, 0);
+    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(st);
     return hipGetLastError();
 }
 
@@ -1734,7 +1736,7 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
                           const float* x_hat0, const Workspace& w, const IterParams& ip0, hipStream_t s,
                           float* x_zero) {
     const int slot = (ip0.it & 1) ^ 1;   // the slot iteration it0 reads as "previous"
-    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(w.st, ip0.log);
+    k_prep_state<<<(kStateWords + 1023) / 1024, 256, 0, s>>>(w.st);
     if (x_hat0) k_prep_support<<<blocks(dm.n, 256), 256, 0, s>>>(x_hat0, dm.n, w, slot);
     k_prep_rows<<<blocks(dm.m, 256), 256, 0, s>>>(y, w.Sy, w.S[0], w.D, dm.m, w.st);
     // the packing pass validates the columns and clears x_zero; without packing they
@@ -1771,7 +1773,7 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
     const int pre = dm.m > kPreRows ? 1 : 0;
-    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, !a.bm_lds, pre};
+    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, !a.bm_lds, pre, ip.log, ip.t};
     if (pre) {
         e = launch_timed(k_hk_classify, kRowGrid, kRowBlock, s, ev ? ev + 2 : nullptr, fa);
         if (e != hipSuccess) return e;
@@ -1802,18 +1804,18 @@ hipError_t launch_rebuild_outer(const DecodeDims& dm, const Workspace& w, int bu
 hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterParams& ip_last,
                          float* x_out, hipStream_t s, bool x_zeroed) {
     if (!x_out) {
-        k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx);
+        k_decide_only<<<1, 256, 0, s>>>(w.st, ip_last.it, ip_last.n_iters, ip_last.tol_fx, ip_last.log);
         return hipGetLastError();
     }
     if (!x_zeroed) k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_out, dm.n);
-    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, 0, 1, ip_last.n_iters, ip_last.tol_fx);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, 0, 1, ip_last.n_iters, ip_last.tol_fx, ip_last.log);
     return hipGetLastError();
 }
 
 hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, float* x_trial,
                             hipStream_t s) {
     k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_trial, dm.n);
-    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, 1, 0, 0, 0.0);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, 1, 0, 0, 0.0, 0);
     return hipGetLastError();
 }
 

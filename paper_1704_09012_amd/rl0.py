@@ -411,8 +411,8 @@ def profile_read_kernels() -> dict:
 
 
 ITER_LOG = np.dtype([("l1_trial_fx", np.int64), ("l1_hat_fx", np.int64), ("accepted", np.int32),
-                     ("updates", np.int32), ("t", np.float32), ("it", np.int32), ("sweep_start", np.uint64),
-                     ("sweep_end", np.uint64), ("rows_start", np.uint64), ("rows_end", np.uint64)])
+                     ("updates", np.int32), ("t", np.float32), ("it", np.int32), ("rows_start", np.uint64),
+                     ("rows_end", np.uint64)])
 
 
 def last_log(cap: int = 4096) -> np.ndarray:
