@@ -1165,6 +1165,11 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         seg_cnt[tid] = myc;
         seg_frt[tid] = myf;
     }
+    if (log_wg && tid < 64) {
+        // recorded before the return below: the decision that stopped the loop is logged too
+        for (int off = 32; off > 0; off >>= 1) lt_prev += __shfl_down(lt_prev, off);
+        if (tid == 0 && st->slot[me ^ 1].pending) log_decision(st, s, lt_prev);
+    }
     __syncthreads();
     if (s.done) return;
     const int c = s.cur, tr = c ^ 1;
@@ -1180,13 +1185,9 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     }
     __syncthreads();
-    if (log_wg && tid < 64)
-        for (int off = 32; off > 0; off >>= 1) lt_prev += __shfl_down(lt_prev, off);
     if (blockIdx.x == 0 && tid == 0) {
         if (upd_sh) atomicAdd(&st->updates_total, upd_sh);
         if (log_wg) {
-            const Slot p = st->slot[me ^ 1];
-            if (p.pending) log_decision(st, s, lt_prev);
             if (s.pending && s.iterations < kLogCap) {
                 IterLog& lg = st->log[s.iterations];
                 lg.updates = upd_sh;
