@@ -40,6 +40,7 @@ extern "C" {
 #define RL0_EHIP (-4)       /* a HIP runtime call failed */
 #define RL0_ENOWEIGHTS (-5) /* learned posterior requested without weights */
 #define RL0_ERANGE (-6)     /* a value left the 64-bit fixed-point range (|v| >= 2^22) */
+#define RL0_EIO (-7)        /* a file could not be read or written, or is no valid checkpoint */
 
 #define RL0_TABLE_N 4096    /* intervals of each score table */
 /* floats of a set of score tables given by the caller (rl0_params.tables):
@@ -366,6 +367,49 @@ int rl0_mlp_pack_bf16(const float* w_h, int32_t d, uint16_t* packed_h);
  * matrix cores as the decoder runs it (bf16 = 1, d <= 15). */
 int rl0_mlp_forward(const float* feats, int32_t N, int32_t d, const float* w, float* out, int32_t bf16,
                     void* stream);
+
+/* Checkpoint of a training run of the learned column decision: the parameter vector w
+ * and Adam's moments adam_m, adam_v, with what resuming needs.  rl0_mlp_train called with
+ * the stored batch and hyper-parameters and t0 = step continues exactly (bit for bit) as
+ * the uninterrupted run would have: its batch order and bias corrections depend only on
+ * the step, and its gradient sum has a fixed order. */
+typedef struct rl0_mlp_ckpt {
+    int32_t d;          /* network input width d (features d + 1) */
+    int32_t dtype;      /* element type of the arrays: 0 = float32, the only one */
+    int64_t P;          /* entries of each array, rl0_mlp_num_params(d) */
+    uint64_t seed;      /* seed of the rl0_mlp_init that began the run (kept, not used) */
+    int64_t step;       /* Adam steps taken: the t0 of the next rl0_mlp_train */
+    rl0_train_cfg cfg;  /* lr, beta1, beta2, eps, lam and batch of those steps; on load
+                           steps = 0 and t0 = step (the file keeps neither) */
+} rl0_mlp_ckpt;
+
+/* File layout (little-endian, no padding; CRC-32 is that of IEEE 802.3 / zlib):
+ *   bytes  0..7   "RL0MLPCK"
+ *          8..11  format version, 1
+ *         12..15  dtype (0)          16..19  d            20..23  batch
+ *         24..31  P                  32..39  seed         40..47  step
+ *         48..67  lr, beta1, beta2, eps, lam (float32)
+ *         68..71  CRC-32 of the payload
+ *         72..75  CRC-32 of bytes 0..71
+ *         76..79  zero
+ *   payload from byte 80: w, adam_m, adam_v, float32 [P] each (12 P bytes).
+ *
+ * Save: info_h gives d, seed, step and cfg (its dtype and P are ignored and written as 0
+ * and rl0_mlp_num_params(d)); w, adam_m and adam_v are device arrays of that size, read
+ * on `stream` (synchronises).  The file is written to "<path>.tmp" and then renamed over
+ * path, so an interrupted save leaves any earlier checkpoint at path whole.  RL0_EINVAL
+ * for bad arguments, RL0_EIO if the file cannot be written. */
+int rl0_mlp_save(const char* path_h, const rl0_mlp_ckpt* info_h, const float* w, const float* adam_m,
+                 const float* adam_v, void* stream);
+
+/* Load: reads the whole file and checks it (magic, version, dtype, d in [1, 16],
+ * P = rl0_mlp_num_params(d), the file's size, both CRCs, finite hyper-parameters and
+ * step >= 0) before anything is written; RL0_EIO names the first check that failed, and
+ * then nothing is written.  On success *info_h is filled (may be NULL) and each of w,
+ * adam_m, adam_v that is not NULL (device arrays of P floats) receives its array on
+ * `stream` (synchronises); with all three NULL only the header is read back, to size
+ * the arrays. */
+int rl0_mlp_load(const char* path_h, rl0_mlp_ckpt* info_h, float* w, float* adam_m, float* adam_v, void* stream);
 
 /* The per-iteration log of the last rl0_decode (or rl0_step) on this stream, when it ran
  * with params.log = 1: the records of its executed iterations in order, at most cap of

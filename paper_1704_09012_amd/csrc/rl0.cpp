@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <cerrno>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
@@ -18,6 +20,8 @@
 #include <algorithm>
 #include <tuple>
 #include <vector>
+
+#include <unistd.h>
 
 #include "constants.h"
 #include "kernels.h"
@@ -1242,6 +1246,49 @@ int get_mlp_buffers(int device, hipStream_t s, int d, size_t steps, MlpBuffers**
     return RL0_OK;
 }
 
+// Training checkpoints (rl0_mlp_save, rl0_mlp_load).
+static_assert(__BYTE_ORDER__ == __ORDER_LITTLE_ENDIAN__, "the checkpoint layout is little-endian");
+
+constexpr char kCkptMagic[8] = {'R', 'L', '0', 'M', 'L', 'P', 'C', 'K'};
+constexpr uint32_t kCkptVersion = 1;
+constexpr size_t kCkptHeader = 80;
+
+// CRC-32 of IEEE 802.3 (reflected polynomial 0xEDB88320, initial and final complement),
+// the checksum zlib computes.
+uint32_t crc32_ieee(const unsigned char* p, size_t n) {
+    static const std::array<uint32_t, 256> table = [] {
+        std::array<uint32_t, 256> t{};
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int b = 0; b < 8; ++b) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            t[i] = c;
+        }
+        return t;
+    }();
+    uint32_t crc = 0xFFFFFFFFu;
+    for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xFFu] ^ (crc >> 8);
+    return ~crc;
+}
+
+template <class T>
+void put_le(unsigned char* b, size_t off, T v) { std::memcpy(b + off, &v, sizeof(T)); }
+
+template <class T>
+T get_le(const unsigned char* b, size_t off) {
+    T v;
+    std::memcpy(&v, b + off, sizeof(T));
+    return v;
+}
+
+bool ckpt_cfg_ok(const rl0_train_cfg& c) {
+    return std::isfinite(c.lr) && std::isfinite(c.beta1) && std::isfinite(c.beta2) && std::isfinite(c.eps) &&
+           std::isfinite(c.lam) && c.batch >= 1;
+}
+
+int ckpt_fail(const char* path, const std::string& why) {
+    return fail(RL0_EIO, std::string("checkpoint ") + path + ": " + why);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1759,6 +1806,107 @@ int rl0_mlp_forward(const float* feats, int32_t N, int32_t d, const float* w, fl
     if (!feats || !w || !out) return fail(RL0_EINVAL, "NULL pointer");
     std::lock_guard<std::mutex> lk(g_mu);
     HIP_TRY(rl0::launch_mlp_forward(feats, N, d, w, out, bf16 ? 1 : 0, static_cast<hipStream_t>(stream)));
+    return RL0_OK;
+}
+
+// ---------------------------------------------------------------- training checkpoints
+
+int rl0_mlp_save(const char* path_h, const rl0_mlp_ckpt* info_h, const float* w, const float* adam_m,
+                 const float* adam_v, void* stream) {
+    if (!path_h || !info_h || !w || !adam_m || !adam_v) return fail(RL0_EINVAL, "NULL pointer");
+    const int32_t d = info_h->d;
+    if (d < 1 || d > RL0_MAX_D) return fail(RL0_EINVAL, "d must be in [1, 16]");
+    if (info_h->step < 0) return fail(RL0_EINVAL, "step must be >= 0");
+    const rl0_train_cfg& c = info_h->cfg;
+    if (!ckpt_cfg_ok(c)) return fail(RL0_EINVAL, "cfg: finite hyper-parameters and batch >= 1 required");
+    const size_t P = static_cast<size_t>(rl0::mlp_params(d));
+    std::vector<unsigned char> buf(kCkptHeader + 12 * P, 0);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const float* arrays[3] = {w, adam_m, adam_v};
+    for (int a = 0; a < 3; ++a)
+        HIP_TRY(hipMemcpyAsync(buf.data() + kCkptHeader + a * 4 * P, arrays[a], 4 * P, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+
+    unsigned char* h = buf.data();
+    std::memcpy(h, kCkptMagic, 8);
+    put_le<uint32_t>(h, 8, kCkptVersion);
+    put_le<uint32_t>(h, 12, 0);
+    put_le<int32_t>(h, 16, d);
+    put_le<int32_t>(h, 20, c.batch);
+    put_le<int64_t>(h, 24, static_cast<int64_t>(P));
+    put_le<uint64_t>(h, 32, info_h->seed);
+    put_le<int64_t>(h, 40, info_h->step);
+    const float hp[5] = {c.lr, c.beta1, c.beta2, c.eps, c.lam};
+    for (int i = 0; i < 5; ++i) put_le<float>(h, 48 + 4 * i, hp[i]);
+    put_le<uint32_t>(h, 68, crc32_ieee(h + kCkptHeader, 12 * P));
+    put_le<uint32_t>(h, 72, crc32_ieee(h, 72));
+
+    const std::string tmp = std::string(path_h) + ".tmp";
+    std::FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return ckpt_fail(path_h, "cannot open " + tmp + " for writing: " + std::strerror(errno));
+    const size_t wrote = std::fwrite(buf.data(), 1, buf.size(), f);
+    const bool flushed = std::fflush(f) == 0 && fsync(fileno(f)) == 0;
+    const bool closed = std::fclose(f) == 0;
+    if (wrote != buf.size() || !flushed || !closed) {
+        std::remove(tmp.c_str());
+        return ckpt_fail(path_h, "writing " + tmp + " failed");
+    }
+    if (std::rename(tmp.c_str(), path_h) != 0) {
+        const std::string why = std::strerror(errno);
+        std::remove(tmp.c_str());
+        return ckpt_fail(path_h, "cannot rename " + tmp + ": " + why);
+    }
+    return RL0_OK;
+}
+
+int rl0_mlp_load(const char* path_h, rl0_mlp_ckpt* info_h, float* w, float* adam_m, float* adam_v, void* stream) {
+    if (!path_h) return fail(RL0_EINVAL, "path is NULL");
+    std::FILE* f = std::fopen(path_h, "rb");
+    if (!f) return ckpt_fail(path_h, std::string("cannot open: ") + std::strerror(errno));
+    std::unique_ptr<std::FILE, int (*)(std::FILE*)> guard(f, std::fclose);
+    unsigned char h[kCkptHeader];
+    if (std::fread(h, 1, kCkptHeader, f) != kCkptHeader) return ckpt_fail(path_h, "shorter than its 80-byte header");
+    if (std::memcmp(h, kCkptMagic, 8) != 0) return ckpt_fail(path_h, "not a checkpoint (magic)");
+    const uint32_t version = get_le<uint32_t>(h, 8);
+    if (version != kCkptVersion) return ckpt_fail(path_h, "format version " + std::to_string(version) + " is not 1");
+    if (get_le<uint32_t>(h, 72) != crc32_ieee(h, 72)) return ckpt_fail(path_h, "header checksum mismatch");
+    if (get_le<uint32_t>(h, 76) != 0) return ckpt_fail(path_h, "reserved header bytes are not zero");
+    if (get_le<uint32_t>(h, 12) != 0) return ckpt_fail(path_h, "dtype is not 0 (float32)");
+    rl0_mlp_ckpt info{};
+    info.d = get_le<int32_t>(h, 16);
+    info.dtype = 0;
+    info.P = get_le<int64_t>(h, 24);
+    info.seed = get_le<uint64_t>(h, 32);
+    info.step = get_le<int64_t>(h, 40);
+    info.cfg.batch = get_le<int32_t>(h, 20);
+    info.cfg.lr = get_le<float>(h, 48);
+    info.cfg.beta1 = get_le<float>(h, 52);
+    info.cfg.beta2 = get_le<float>(h, 56);
+    info.cfg.eps = get_le<float>(h, 60);
+    info.cfg.lam = get_le<float>(h, 64);
+    info.cfg.steps = 0;
+    if (info.d < 1 || info.d > RL0_MAX_D) return ckpt_fail(path_h, "d out of [1, 16]");
+    if (info.P != rl0::mlp_params(info.d)) return ckpt_fail(path_h, "P does not match d");
+    if (info.step < 0 || info.step > INT32_MAX) return ckpt_fail(path_h, "step out of [0, 2^31)");
+    if (!ckpt_cfg_ok(info.cfg)) return ckpt_fail(path_h, "bad hyper-parameters or batch");
+    info.cfg.t0 = static_cast<int32_t>(info.step);
+    const size_t P = static_cast<size_t>(info.P);
+    std::vector<unsigned char> payload(12 * P + 1);
+    const size_t got = std::fread(payload.data(), 1, payload.size(), f);
+    if (got < 12 * P) return ckpt_fail(path_h, "truncated payload");
+    if (got > 12 * P) return ckpt_fail(path_h, "bytes after the payload");
+    if (get_le<uint32_t>(h, 68) != crc32_ieee(payload.data(), 12 * P))
+        return ckpt_fail(path_h, "payload checksum mismatch");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    float* arrays[3] = {w, adam_m, adam_v};
+    bool any = false;
+    for (int a = 0; a < 3; ++a) {
+        if (!arrays[a]) continue;
+        HIP_TRY(hipMemcpyAsync(arrays[a], payload.data() + a * 4 * P, 4 * P, hipMemcpyHostToDevice, s));
+        any = true;
+    }
+    if (any) HIP_TRY(hipStreamSynchronize(s));
+    if (info_h) *info_h = info;
     return RL0_OK;
 }
 

@@ -28,6 +28,7 @@ ERRORS = {
     -4: "RL0_EHIP",
     -5: "RL0_ENOWEIGHTS",
     -6: "RL0_ERANGE",
+    -7: "RL0_EIO",
 }
 
 
@@ -151,6 +152,17 @@ class TrainCfg(ctypes.Structure):
     ]
 
 
+class MlpCkpt(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("P", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("step", ctypes.c_int64),
+        ("cfg", TrainCfg),
+    ]
+
+
 class Rl0Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -201,13 +213,16 @@ def lib() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_float), V]
         L.rl0_mlp_forward.argtypes = [P, I32, I32, P, P, I32, V]
         L.rl0_mlp_adam.argtypes = [P, P, P, P, I32, I32, ctypes.POINTER(TrainCfg), V]
+        L.rl0_mlp_save.argtypes = [ctypes.c_char_p, ctypes.POINTER(MlpCkpt), P, P, P, V]
+        L.rl0_mlp_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(MlpCkpt), P, P, P, V]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_sketch_static", "rl0_validate",
                      "rl0_decode", "rl0_step", "rl0_decode_batched", "rl0_batch_schedule_get", "rl0_profile_read_learned",
                      "rl0_last_log",
                      "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_batch_timeline", "rl0_mlp_init", "rl0_mlp_features",
-                     "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam"):
+                     "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam",
+                     "rl0_mlp_save", "rl0_mlp_load"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -606,6 +621,45 @@ def mlp_adam(w, grad, m, v, d: int, t: int, lr: float = 1e-3, beta1: float = 0.9
     _check(lib().rl0_mlp_adam(_dev_ptr(w, torch.float32, (P,), "w"), _dev_ptr(grad, torch.float32, (P,), "grad"),
                               _dev_ptr(m, torch.float32, (P,), "m"), _dev_ptr(v, torch.float32, (P,), "v"), d, t,
                               ctypes.byref(cfg), _stream()))
+
+
+def _ckpt_dict(c: MlpCkpt) -> dict:
+    cfg = {f: getattr(c.cfg, f) for f, _ in TrainCfg._fields_}
+    return {"d": c.d, "dtype": c.dtype, "P": c.P, "seed": c.seed, "step": c.step, "cfg": cfg}
+
+
+def mlp_save(path: str, w, m, v, d: int, step: int, seed: int = 0, lr: float = 1e-3, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-8, lam: float = 1.0, batch: int = 4096) -> None:
+    """rl0_mlp_save: the weights w and Adam's moments m, v (device tensors of
+    mlp_num_params(d) floats) after `step` Adam steps with these hyper-parameters."""
+    torch = _torch()
+    P = mlp_num_params(d)
+    info = MlpCkpt(d, 0, P, seed, step, TrainCfg(lr, beta1, beta2, eps, lam, batch, 0, 0))
+    _check(lib().rl0_mlp_save(os.fsencode(path), ctypes.byref(info), _dev_ptr(w, torch.float32, (P,), "w"),
+                              _dev_ptr(m, torch.float32, (P,), "m"), _dev_ptr(v, torch.float32, (P,), "v"),
+                              _stream()))
+
+
+def mlp_checkpoint_info(path: str) -> dict:
+    """The header of a checkpoint after rl0_mlp_load has checked the whole file (no GPU)."""
+    info = MlpCkpt()
+    _check(lib().rl0_mlp_load(os.fsencode(path), ctypes.byref(info), None, None, None, None))
+    return _ckpt_dict(info)
+
+
+def mlp_load(path: str, device="cuda", moments: bool = True):
+    """(header dict, w, m, v) of a checkpoint; m and v are None when moments is False."""
+    torch = _torch()
+    info = mlp_checkpoint_info(path)
+    P = info["P"]
+    w = torch.empty(P, dtype=torch.float32, device=device)
+    m = torch.empty_like(w) if moments else None
+    v = torch.empty_like(w) if moments else None
+    ptr = lambda t, name: _dev_ptr(t, torch.float32, (P,), name) if t is not None else None
+    again = MlpCkpt()
+    _check(lib().rl0_mlp_load(os.fsencode(path), ctypes.byref(again), ptr(w, "w"), ptr(m, "m"), ptr(v, "v"),
+                              _stream()))
+    return _ckpt_dict(again), w, m, v
 
 
 def mlp_forward(feats, w, bf16: bool = True):

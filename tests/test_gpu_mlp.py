@@ -5,7 +5,8 @@ Bars: features and labels bitwise; fp32 gradients within 1e-4 of the fp64 oracle
 inference within 1e-2 of the oracle's bf16 emulation (the accumulation order of the
 matrix cores is not specified); the learned iteration's decisions equal the oracle's
 wherever the logit is more than 1e-2 from the threshold; training lowers the loss; and
-a silent network reproduces the analytic decoder bit for bit.
+a silent network reproduces the analytic decoder bit for bit; training resumed from a
+checkpoint equals uninterrupted training bit for bit.
 """
 import math
 
@@ -302,6 +303,49 @@ def test_training_steps_match_the_oracle():
     assert settled.sum() >= 20
     assert np.max(np.abs(gw - wo)[settled]) <= 2e-2 * lr
     assert np.max(np.abs(gw - wo)) <= 2 * lr * 3
+
+
+def test_checkpoint_resume_is_exact(tmp_path):
+    """rl0_mlp_save after 7 Adam steps, rl0_mlp_load into new arrays and 5 more steps from
+    the stored step and hyper-parameters give, bit for bit, the weights and moments of 12
+    uninterrupted steps (the batch order and the bias corrections depend on the step only,
+    and the gradient sum has a fixed order).  The loaded arrays equal the saved ones, the
+    file's payload is their bytes and its CRC-32 is zlib's."""
+    import struct
+    import zlib
+
+    d, B = 7, 512
+    N = 5 * B + 100                       # five blocks and a remainder no step takes
+    rng = np.random.default_rng(81)
+    F = dev(rng.normal(0, 0.3, (N, d + 1)).astype(np.float32))
+    Y = dev(np.stack([(rng.random(N) < 0.3).astype(np.float32), rng.normal(0, 1, N).astype(np.float32)], 1))
+    hp = dict(lr=2e-3, beta1=0.9, beta2=0.99, eps=1e-7, lam=0.5, batch=B)
+
+    def fresh():
+        w = R.mlp_init(d, 4)
+        return w, torch.zeros_like(w), torch.zeros_like(w)
+
+    w1, m1, v1 = fresh()
+    R.mlp_train(F, Y, w1, m1, v1, steps=12, t0=0, **hp)
+    w2, m2, v2 = fresh()
+    R.mlp_train(F, Y, w2, m2, v2, steps=7, t0=0, **hp)
+    path = str(tmp_path / "mlp.ckpt")
+    R.mlp_save(path, w2, m2, v2, d, step=7, seed=4, **hp)
+    info, w3, m3, v3 = R.mlp_load(path)
+    assert torch.equal(w3, w2) and torch.equal(m3, m2) and torch.equal(v3, v2)
+    blob = open(path, "rb").read()
+    assert blob[80:] == host(w2).tobytes() + host(m2).tobytes() + host(v2).tobytes()
+    assert struct.unpack_from("<I", blob, 68)[0] == zlib.crc32(blob[80:])
+    cfg = info["cfg"]
+    assert info["step"] == 7 and cfg["t0"] == 7 and info["seed"] == 4 and info["d"] == d
+    R.mlp_train(F, Y, w3, m3, v3, steps=5, t0=cfg["t0"], lr=cfg["lr"], beta1=cfg["beta1"], beta2=cfg["beta2"],
+                eps=cfg["eps"], lam=cfg["lam"], batch=cfg["batch"])
+    assert torch.equal(w3, w1) and torch.equal(m3, m1) and torch.equal(v3, v1)
+    # a later save replaces the file whole; the weights alone can be read back
+    R.mlp_save(path, w3, m3, v3, d, step=12, seed=4, **hp)
+    info, w4, m4, v4 = R.mlp_load(path, moments=False)
+    assert info["step"] == 12 and m4 is None and v4 is None and torch.equal(w4, w1)
+    assert not (tmp_path / "mlp.ckpt.tmp").exists()
 
 
 def exact_net(d, sigma):

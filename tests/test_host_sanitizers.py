@@ -5,8 +5,9 @@ tables of the Gaussian and the general laws, thresholds, c rule, the batched pla
 checks, the bf16 packer, the host validator) are rebuilt with g++
 -fsanitize=address,undefined and linked with the unchanged device objects of the normal
 build into a second copy of librl0.so.  The host-only tests of tests/test_capi_host.py,
-and those of tests/test_capi_general.py that do not wait on the oracle (general-law
-tables, given tables and their checks), then run against that copy (the binding loads the
+those of tests/test_capi_general.py that do not wait on the oracle (general-law tables,
+given tables and their checks) and the checkpoint reader's checks of
+tests/test_capi_checkpoint.py then run against that copy (the binding loads the
 library named by RL0_LIBRARY) in a child process with the sanitizer runtime preloaded: any
 heap or stack overflow, use after free, signed overflow, misaligned or out-of-bounds
 access in those paths ends the child with an error.  No GPU is used."""
@@ -82,7 +83,8 @@ def test_host_paths_are_clean_under_asan_and_ubsan():
     assert r.returncode == 0 and "sanitized library loaded" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
                         "-k", "not match_the_oracle", os.path.join(ROOT, "tests", "test_capi_host.py"),
-                        os.path.join(ROOT, "tests", "test_capi_general.py")],
+                        os.path.join(ROOT, "tests", "test_capi_general.py"),
+                        os.path.join(ROOT, "tests", "test_capi_checkpoint.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=800)
     tail = r.stdout[-3000:] + r.stderr[-6000:]
     assert r.returncode == 0, tail
