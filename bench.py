@@ -528,7 +528,7 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": sweep_traffic() if (N, M, DD) == (2 ** 20, 104857, 7) else None,
-                     "kernel": f"k_sweep<{DD}, {'true' if large else 'false'}, {'true' if packed else 'false'}>",
+                     "kernel": f"k_sweep<{DD}, {'true' if large else 'false'}, {'true' if packed else 'false'}, false>",
                      "bytes_per_launch": B_it,
                      "bytes_model": "B_it = 4dn + 28m + 16dk + 12(k + u) per loop iteration, u = mean updates "
                                     f"per executed iteration ({u_mean:.1f}); one sweep launch per iteration",

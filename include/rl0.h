@@ -102,6 +102,12 @@ typedef struct rl0_params {
                                non-increasing; inv_h finite and > 0 (else RL0_EINVAL).
                                Read during the call only (the library keeps a copy, keyed
                                by a 64-bit hash of the floats) */
+    int32_t wg_order;       /* 0 (default): the workgroups of the loop kernels take their
+                               column and row tiles in launch order; 1: in the reverse
+                               order.  The results are the same bits either way (a check
+                               that nothing depends on the order in which the hardware
+                               runs workgroups).  rl0_decode and rl0_step; batched decodes
+                               vary their schedule through rl0_batch_schedule_set */
 } rl0_params;
 
 /* What a decode did.  l1 values are ||r_hat||_1; the fixed-point one is exact. */
@@ -417,6 +423,17 @@ int rl0_mlp_load(const char* path_h, rl0_mlp_ckpt* info_h, float* w, float* adam
  * did not log; records beyond 4096 are not kept).  Batched decodes keep no log.
  * Synchronises the stream. */
 int rl0_last_log(rl0_iter_log* out_h, int32_t cap, int32_t* count_h, void* stream);
+
+/* Device index checks.  The library also builds a checked copy of itself
+ * (librl0_checked.so): there every data-dependent index of the loop kernels (rows read
+ * from A_cols or its packed form, candidate-segment sizes and positions, the sweep's
+ * queue, H_k's boundary bucket, columns decoded from keys and written by the copy-out)
+ * is tested against its range before use; an index outside its range is replaced by 0,
+ * so that the kernel stays inside its buffers and finishes, and the source line of the
+ * first failed check is recorded.  *line_h <- that line since the last call (0: none;
+ * the record is then cleared), or -1 in the normal library, which has no checks.
+ * Synchronises the stream in the checked library. */
+int rl0_device_check(int32_t* line_h, void* stream);
 
 /* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of
  * replaying its captured graph), each loop kernel with a pair of HIP events that take

@@ -16,6 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librl0.so")
+# the same library with the loop kernels' index checks compiled in (rl0_device_check)
+CHECKED_OUT = os.path.join(HERE, "librl0_checked.so")
+CHECKED_SOURCE = "kernels.hip"
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["constants.cpp", "general.cpp", "rl0.cpp", "kernels.hip", "batched.hip", "mlp.hip", "noalloc.hip"]
@@ -37,29 +40,42 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, src + ".o")
+def _compile(src: str, checked: bool = False) -> str:
+    obj = os.path.join(BUILD_DIR, src + (".checked.o" if checked else ".o"))
     path = os.path.join(CSRC, src)
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [_hipcc(), *COMMON, *lang, "-c", path, "-o", obj]
+    defs = ["-DRL0_DEVICE_CHECKS=1"] if checked else []
+    cmd = [_hipcc(), *COMMON, *defs, *lang, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp"
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Builds librl0.so and librl0_checked.so (the latter differs only in the loop
+    kernels, compiled with their index checks)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs = [(src, False) for src in SOURCES] + [(CHECKED_SOURCE, True)]
+    # the two compiles of the largest source first, so that they overlap the others
+    jobs.sort(key=lambda j: j[0] != CHECKED_SOURCE)
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        done = dict(zip(jobs, ex.map(lambda j: _compile(*j), jobs)))
+    objs = [done[(src, False)] for src in SOURCES]
+    _link(objs, OUT)
+    _link([done[(CHECKED_SOURCE, True)] if src == CHECKED_SOURCE else done[(src, False)] for src in SOURCES],
+          CHECKED_OUT)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", CHECKED_OUT)
     return OUT
 
 

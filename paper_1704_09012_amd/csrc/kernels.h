@@ -108,6 +108,7 @@ struct IterParams {
     uint32_t qe_bits = 0; //   q_e(a) = 1 iff bits(|a|) <= qe_bits
     uint32_t qz_bits = 0; //   q_z(v) = 1 iff bits(|v|) <= qz_bits
     int log = 0;          // record the iteration in the per-iteration log
+    int wg_rev = 0;       // the loop kernels' workgroups take their tiles in reverse order
 };
 
 // Double-buffered decoder state; index b in {0, 1} is selected by Slot::cur.  x_hat
@@ -139,6 +140,10 @@ struct DebugOut {
     int* updated;        // [n] or nullptr (zeroed by the caller)
     float* omega;        // [n] or nullptr (zeroed by the caller)
 };
+
+// The source line of the first failed index check in the loop kernels since the last
+// call (0: none), which is then cleared; -1 when the library was built without the checks.
+hipError_t device_check_read(int* line, hipStream_t s);
 
 size_t workspace_bytes(int n, int m);
 void carve_workspace(void* base, int n, int m, Workspace* w);

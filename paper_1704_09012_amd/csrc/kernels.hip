@@ -39,6 +39,35 @@ constexpr int kBmLdsWords = 12288;                  // 48 KiB: bitmasks of m <= 
 constexpr int kBmPer = 4;                           // bitmask words per sweep thread held in registers
 constexpr int kRowBlock = 1024;
 
+// Checked builds (compiled with RL0_DEVICE_CHECKS=1 into a second copy of the library):
+// RL0_CHK(i, n) tests a data-dependent index (one read from memory or from an atomic
+// counter) against its range [0, n).  An index outside it records the source line of
+// the first failed check in g_check_line (read back by device_check_read) and becomes 0,
+// so that the access stays inside its buffer and the kernel runs to its end.  In normal
+// builds RL0_CHK(i, n) is i and RL0_CHECK_ROWS does nothing.
+#if RL0_DEVICE_CHECKS
+__device__ unsigned g_check_line;
+
+template <class I>
+__device__ __forceinline__ I check_index(I i, long long n, unsigned line) {
+    const long long v = static_cast<long long>(i);
+    if (v >= 0 && v < n) return i;
+    atomicCAS(&g_check_line, 0u, line);
+    return static_cast<I>(0);
+}
+#define RL0_CHK(i, n) check_index((i), static_cast<long long>(n), __LINE__)
+#define RL0_CHECK_ROWS(rows, m)                                                     \
+    do {                                                                            \
+        for (int q_ = 0; q_ < kSweepCols; ++q_)                                     \
+            for (int p_ = 0; p_ < D; ++p_) rows[q_][p_] = RL0_CHK(rows[q_][p_], m); \
+    } while (0)
+#else
+#define RL0_CHK(i, n) (i)
+#define RL0_CHECK_ROWS(rows, m) \
+    do {                        \
+    } while (0)
+#endif
+
 
 template <int BLOCK>
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
@@ -198,7 +227,7 @@ __global__ void k_prep_support(const float* __restrict__ x0, int n, Workspace w,
     if (v == 0.0f) return;
     const int seg = (j / kSweepChunk) % w.sweep_grid;
     const int o = atomicAdd(&w.st->seg_count[slot][seg], 1);
-    const size_t ix = static_cast<size_t>(seg) * w.seg_cap + (w.seg_cap - 1 - o);   // back of the segment
+    const size_t ix = static_cast<size_t>(seg) * w.seg_cap + (w.seg_cap - 1 - RL0_CHK(o, w.seg_cap));   // back of the segment
     w.cand_j[slot][ix] = j;
     w.cand_x[slot][ix] = v;
     w.cand_h[slot][ix] = v;
@@ -518,7 +547,16 @@ __device__ __forceinline__ void add_change(long long* Dl, const int (&rows)[D], 
 // PACKED: the indices come from the packed words (a.Apk), else from A_cols.  Both are
 // template parameters, so that no branch separates the index loads from the loads
 // before them (the compiler then waits for all of them at the first use of any).
-template <int D, bool DENSE, bool PACKED>
+// The workgroup's place in the grid: its launch index, or the mirror of it when rev is set
+// (every kernel of an iteration uses the same order; results do not depend on it).
+__device__ __forceinline__ int wg_index(int rev) {
+    return rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
+}
+
+// REV: the workgroups take their chunks and segments in reverse order (IterParams::wg_rev).
+// A template parameter: the sweep uses every scalar register, and one more live value
+// (the flag) made the compiler spill and wait for its load at the kernel's start.
+template <int D, bool DENSE, bool PACKED, bool REV>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     constexpr int kQueueRows = kQueueRowInts / D;
     __shared__ uint32_t bml[kBmLdsWords];
@@ -535,7 +573,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     __shared__ bool dense_sh;
     const int it = a.ip.it, me = it & 1, pv = me ^ 1;
     const int tid = threadIdx.x;
-    const int seg = blockIdx.x;
+    const unsigned wg = REV ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+    const int seg = wg;
     const size_t seg_base = static_cast<size_t>(seg) * a.w.seg_cap;
     DevState* st = a.w.st;
     const int words = (a.m + 31) >> 5;
@@ -561,8 +600,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         prev = st->slot[pv];
         err = st->err;
     }
-    const int pc = st->seg_count[pv][seg];
-    const int pf = st->seg_front[pv][seg];
+    const int pc = RL0_CHK(st->seg_count[pv][seg], a.w.seg_cap + 1);
+    const int pf = RL0_CHK(st->seg_front[pv][seg], pc + 1);
     const unsigned long long kthp = st->kth_key[pv];
     long long lp = tid < kRowGrid ? st->L_part[pv][tid] : 0;
     // flagged-row counts exist only where the bitmask does not fit in LDS
@@ -589,7 +628,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     // and the decision below wait only for the loads before them
     int rows[kSweepCols][D];
     uint4 pw[kSweepCols];
-    issue_rows<D, PACKED>(a.A, a.Apk, a.n, blockIdx.x * kSweepChunk, tid, pw, rows);
+    issue_rows<D, PACKED>(a.A, a.Apk, a.n, wg * kSweepChunk, tid, pw, rows);
     if (!a.tb.exact) {
         reinterpret_cast<float4*>(Tz)[tid] = tz4;
         reinterpret_cast<float4*>(Te)[tid] = te4;
@@ -640,9 +679,11 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     }
     __syncthreads();
     const Slot s = s_sh;
-    unpack_chunk<D, PACKED>(pw, rows, a.n, blockIdx.x * kSweepChunk, tid);   // the first chunk's indices
-    if (blockIdx.x == 0 && tid == 0) st->slot[me] = s;
+    unpack_chunk<D, PACKED>(pw, rows, a.n, wg * kSweepChunk, tid);   // the first chunk's indices
+    if (wg == 0 && tid == 0) st->slot[me] = s;
     if (s.done) return;
+    // (malformed columns stop the loop above, before any of their rows is used)
+    RL0_CHECK_ROWS(rows, a.m);
     const bool skip = !s.pending;   // a retry with nothing to retry
     const int c = s.cur;
     const int acc = s.accepted_last;
@@ -681,11 +722,12 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
         for (int wi = tid; wi < ((a.m + 255) >> 8); wi += kSweepBlock) bml[wi] = bsg[wi];
     }
 
-    for (int chunk = blockIdx.x; chunk < a.chunks; chunk += gridDim.x) {
+    for (int chunk = wg; chunk < a.chunks; chunk += gridDim.x) {
         const int cbase = chunk * kSweepChunk;
-        if (chunk != static_cast<int>(blockIdx.x)) {
+        if (chunk != static_cast<int>(wg)) {
             issue_rows<D, PACKED>(a.A, a.Apk, a.n, cbase, tid, pw, rows);
             unpack_chunk<D, PACKED>(pw, rows, a.n, cbase, tid);
+            RL0_CHECK_ROWS(rows, a.m);
         }
         reinterpret_cast<float4*>(supv)[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (tid == 0) qn = 0;
@@ -696,7 +738,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             int j = pj;
             float xp = pxp, xh = pxh;
             if (o != tid) {
-                const size_t ix = seg_base + o;
+                const size_t ix = seg_base + RL0_CHK(o, a.w.seg_cap);
                 j = a.w.cand_j[pv][ix];
                 xp = a.w.cand_x[pv][ix];
                 xh = a.w.cand_h[pv][ix];
@@ -708,7 +750,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             int j = qj;
             float xp = qxp, xh = qxh;
             if (o != tid) {
-                const size_t ix = seg_base + (a.w.seg_cap - 1 - o);
+                const size_t ix = seg_base + (a.w.seg_cap - 1 - RL0_CHK(o, a.w.seg_cap));
                 j = a.w.cand_j[pv][ix];
                 xp = a.w.cand_x[pv][ix];
                 xh = a.w.cand_h[pv][ix];
@@ -734,7 +776,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 if (upd) {
                     atomicAdd(&seg_upd, 1);
                     const float xp = svq[q] + lv;
-                    const int o = atomicAdd(&seg_f, 1);
+                    const int o = RL0_CHK(atomicAdd(&seg_f, 1), a.w.seg_cap);
                     out_j[o] = j;
                     out_x[o] = xp;
                     out_h[o] = svq[q];
@@ -745,7 +787,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     }
                     add_change<D>(a.w.D, rows[q], svq[q], xp, &st->err);
                 } else if (svq[q] != 0.0f) {
-                    const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                    const int o = RL0_CHK(a.w.seg_cap - 1 - atomicAdd(&seg_b, 1), a.w.seg_cap);
                     out_j[o] = j;
                     out_x[o] = svq[q];
                     out_h[o] = svq[q];
@@ -790,7 +832,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 if (upd) {
                     atomicAdd(&seg_upd, 1);
                     const float xp = xhq + om;
-                    const int o = atomicAdd(&seg_f, 1);
+                    const int o = RL0_CHK(atomicAdd(&seg_f, 1), a.w.seg_cap);
                     out_j[o] = j;
                     out_x[o] = xp;
                     out_h[o] = xhq;
@@ -801,7 +843,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                     }
                     add_change<D>(a.w.D, rq, xhq, xp, &st->err);
                 } else if (xhq != 0.0f) {
-                    const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                    const int o = RL0_CHK(a.w.seg_cap - 1 - atomicAdd(&seg_b, 1), a.w.seg_cap);
                     out_j[o] = j;
                     out_x[o] = xhq;
                     out_h[o] = xhq;
@@ -839,7 +881,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             }
             if (cm) {
                 const int qi = atomicAdd(&qn, 1);
-                queue[qi] = j;
+                queue[RL0_CHK(qi, kSweepChunk)] = j;
                 if (qi < kQueueRows) {
 #pragma unroll
                     for (int p = 0; p < D; ++p) qrows[qi * D + p] = rows[q][p];
@@ -847,7 +889,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
             } else if (svq[q] != 0.0f) {
                 // a support column with no candidate row keeps x'_j = x_hat_j: the back
                 // of the segment holds the entries with x' = x_hat, the front the others
-                const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                const int o = RL0_CHK(a.w.seg_cap - 1 - atomicAdd(&seg_b, 1), a.w.seg_cap);
                 out_j[o] = j;
                 out_x[o] = svq[q];
                 out_h[o] = svq[q];
@@ -867,14 +909,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
 #pragma unroll
                 for (int p = 0; p < D; ++p) rr[p] = qrows[e * D + p];
             } else {
-                const int32_t* __restrict__ col = a.A + static_cast<size_t>(jq) * D;
+                const int32_t* __restrict__ col = a.A + static_cast<size_t>(RL0_CHK(jq, a.n)) * D;
 #pragma unroll
-                for (int p = 0; p < D; ++p) rr[p] = col[p];
+                for (int p = 0; p < D; ++p) rr[p] = RL0_CHK(col[p], a.m);
             }
             float v[D];
 #pragma unroll
             for (int p = 0; p < D; ++p) v[p] = r[rr[p]];
-            const float xhq = supv[jq - cbase];
+            const float xhq = supv[RL0_CHK(jq - cbase, kSweepChunk)];
             unsigned int cm = 0u;
 #pragma unroll
             for (int p = 0; p < D; ++p)
@@ -888,7 +930,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 // an updated column goes to the front; its residual change is added at
                 // once, as if H_k keeps it (the select kernel takes back what it drops)
                 const float xp = xhq + om;
-                const int o = atomicAdd(&seg_f, 1);
+                const int o = RL0_CHK(atomicAdd(&seg_f, 1), a.w.seg_cap);
                 out_j[o] = jq;
                 out_x[o] = xp;
                 out_h[o] = xhq;
@@ -899,7 +941,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
                 }
                 add_change<D>(a.w.D, rr, xhq, xp, &st->err);
             } else if (xhq != 0.0f) {
-                const int o = a.w.seg_cap - 1 - atomicAdd(&seg_b, 1);
+                const int o = RL0_CHK(a.w.seg_cap - 1 - atomicAdd(&seg_b, 1), a.w.seg_cap);
                 out_j[o] = jq;
                 out_x[o] = xhq;
                 out_h[o] = xhq;
@@ -918,7 +960,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(SweepArgs a) {
     // H_k's first radix digit, counted for every workgroup at once
     for (int b = tid; b < kHistBins; b += kSweepBlock) {
         const unsigned v = lhist[b];
-        if (v) atomicAdd(&st->hk_hist[me][blockIdx.x % kHistCopies][b], v);
+        if (v) atomicAdd(&st->hk_hist[me][wg % kHistCopies][b], v);
     }
 }
 
@@ -939,6 +981,8 @@ struct FinishArgs {
                     // the bucket's entries are listed in w.bkey / w.bx
     int log;        // record the iteration in the per-iteration log
     float t;        // the iteration's t (for that log)
+    int wg_rev;     // workgroups take their row ranges in reverse order
+    int n;          // columns
 };
 
 
@@ -1031,9 +1075,9 @@ __global__ __launch_bounds__(kRowBlock) void k_hk_classify(FinishArgs a) {
     const Slot s = st->slot[me];
     int myc = 0, myz = 0;
     if (tid < nseg) {
-        myc = st->seg_count[me][tid];
+        myc = RL0_CHK(st->seg_count[me][tid], cap + 1);
         myz = st->seg_nz[me][tid];
-        seg_frt[tid] = st->seg_front[me][tid];
+        seg_frt[tid] = RL0_CHK(st->seg_front[me][tid], myc + 1);
     }
     if (tid == 0) nz_sh = 0;
     __syncthreads();
@@ -1060,7 +1104,7 @@ __global__ __launch_bounds__(kRowBlock) void k_hk_classify(FinishArgs a) {
     const int* __restrict__ cj = a.w.cand_j[me];
     const float* __restrict__ cx = a.w.cand_x[me];
     const int per = (count + gridDim.x - 1) / gridDim.x;
-    const int e0 = blockIdx.x * per, e1 = min(count, e0 + per);
+    const int e0 = wg_index(a.wg_rev) * per, e1 = min(count, e0 + per);
     for (int base = e0; base < e1; base += kRowBlock) {
         const int e = base + tid;
         float x = 0.0f;
@@ -1078,15 +1122,17 @@ __global__ __launch_bounds__(kRowBlock) void k_hk_classify(FinishArgs a) {
         const unsigned dg = x != 0.0f ? top_digit(x) : 0u;
         if (x != 0.0f && dg < d1) {
             const long long delta = to_fx(x, &st->err);
-            const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
+            const int32_t* __restrict__ col = a.A + static_cast<size_t>(RL0_CHK(j, a.n)) * a.d;
             for (int p = 0; p < a.d; ++p)
-                atomicAdd(reinterpret_cast<unsigned long long*>(&a.w.D[col[p]]), static_cast<unsigned long long>(delta));
+                atomicAdd(reinterpret_cast<unsigned long long*>(&a.w.D[RL0_CHK(col[p], a.m)]),
+                          static_cast<unsigned long long>(delta));
         }
         const bool put = gather && x != 0.0f && dg == d1;
         const int slot = wave_append(&st->bucket_n[me], put);
         if (put) {
-            a.w.bkey[me][slot] = hk_key(j, x);
-            a.w.bx[me][slot] = x;
+            const int b = RL0_CHK(slot, static_cast<long long>(nseg) * cap);
+            a.w.bkey[me][b] = hk_key(j, x);
+            a.w.bx[me][b] = x;
         }
     }
 }
@@ -1124,13 +1170,14 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     const int words = (a.m + 31) >> 5;
     // rows of this workgroup: [row0, row1), whole multiples of the block
     const int per = ((a.m + gridDim.x * kRowBlock - 1) / (gridDim.x * kRowBlock)) * kRowBlock;
-    const int row0 = blockIdx.x * per;
+    const int wg = wg_index(a.wg_rev);
+    const int row0 = wg * per;
     const int row1 = min(a.m, row0 + per);
 
     // the per-iteration log (workgroup 0): this iteration's record, and the decision on the
     // iteration before, which this iteration's sweep took (its trial norm is the sum of the
     // partial sums that iteration's row kernel left in L_part)
-    const bool log_wg = a.log && blockIdx.x == 0;
+    const bool log_wg = a.log && wg == 0;
     const unsigned long long t_entry = (log_wg && tid == 0) ? wall_clock64() : 0ull;
     long long lt_prev = 0;
     if (log_wg && tid < 64)
@@ -1139,10 +1186,10 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     const Slot s = st->slot[me];
     int myc = 0, myf = 0, myz = 0, myu = 0;
     if (tid < nseg) {
-        myc = st->seg_count[me][tid];
-        myf = st->seg_front[me][tid];
+        myc = RL0_CHK(st->seg_count[me][tid], cap + 1);
+        myf = RL0_CHK(st->seg_front[me][tid], myc + 1);
         myz = st->seg_nz[me][tid];
-        if (blockIdx.x == 0) myu = st->seg_updates[me][tid];
+        if (wg == 0) myu = st->seg_updates[me][tid];
     }
     long long s0 = 0, s1 = 0, dl = 0;
     {
@@ -1154,9 +1201,9 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     }
     // the next iteration's first-digit histograms are cleared here, a slice per workgroup
-    for (int i = blockIdx.x * kRowBlock + tid; i < kHistCopies * kHistBins; i += gridDim.x * kRowBlock)
+    for (int i = wg * kRowBlock + tid; i < kHistCopies * kHistBins; i += gridDim.x * kRowBlock)
         (&st->hk_hist[me ^ 1][0][0])[i] = 0u;
-    if (blockIdx.x == 0 && tid == 0) st->bucket_n[me ^ 1] = 0;
+    if (wg == 0 && tid == 0) st->bucket_n[me ^ 1] = 0;
     if (tid == 0) {
         nz_sh = 0;
         upd_sh = 0;
@@ -1185,7 +1232,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
     }
     __syncthreads();
-    if (blockIdx.x == 0 && tid == 0) {
+    if (wg == 0 && tid == 0) {
         if (upd_sh) atomicAdd(&st->updates_total, upd_sh);
         if (log_wg) {
             if (s.pending && s.iterations < kLogCap) {
@@ -1222,7 +1269,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     int cb = row0, ce = min(row1, row0 + kCorrRows);
     auto take_back = [&](int j, float x) {
         const long long delta = to_fx(x, &st->err);
-        const int32_t* __restrict__ col = a.A + static_cast<size_t>(j) * a.d;
+        const int32_t* __restrict__ col = a.A + static_cast<size_t>(RL0_CHK(j, a.n)) * a.d;
         for (int p = 0; p < a.d; ++p) {
             const int row = col[p];
             if (row >= cb && row < ce)
@@ -1245,7 +1292,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         const bool gather = !exact;
         if (a.pre) {
             // the columns below the bucket are already taken back; the bucket is listed
-            nbk = gather ? st->bucket_n[me] : 0;
+            nbk = gather ? RL0_CHK(st->bucket_n[me], static_cast<long long>(nseg) * cap + 1) : 0;
             if (nbk <= kBucketCap) {
                 for (int e = tid; e < nbk; e += kRowBlock) {
                     bkey[e] = a.w.bkey[me][e];
@@ -1327,7 +1374,7 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
         }
         __syncthreads();
     }
-    if (blockIdx.x == 0 && tid == 0) st->kth_key[me] = kth;
+    if (wg == 0 && tid == 0) st->kth_key[me] = kth;
 
     // ---- the rows, a correction window of kCorrRows rows at a time
     long long l = 0;
@@ -1414,15 +1461,15 @@ __global__ __launch_bounds__(kRowBlock) void k_finish_rows(FinishArgs a) {
     }
     const long long tot = block_sum_rows(l, sh);   // its barrier also publishes flw
     if (tid == 0) {
-        st->L_part[me][blockIdx.x] = tot;
+        st->L_part[me][wg] = tot;
         if (a.count_flags) {
             unsigned st_t = 0u, st_c = 0u;
             for (int w = 0; w < kRowBlock / 64; ++w) {
                 st_t += flw[w][0];
                 st_c += flw[w][1];
             }
-            st->flag_part[me][tr][blockIdx.x] = st_t;
-            st->flag_part[me][c][blockIdx.x] = st_c;
+            st->flag_part[me][tr][wg] = st_t;
+            st->flag_part[me][c][wg] = st_c;
         }
         if (log_wg && s.pending && s.iterations < kLogCap) st->log[s.iterations].rows_end = wall_clock64();
     }
@@ -1448,8 +1495,8 @@ __global__ __launch_bounds__(256) void k_adapt_sum(const Workspace w, ScoreTable
     __shared__ long long red[4];
     const int par = it & 1;
     const int seg = blockIdx.x;
-    const int cnt = w.st->seg_count[par][seg];
-    const int front = w.st->seg_front[par][seg];
+    const int cnt = RL0_CHK(w.st->seg_count[par][seg], w.seg_cap + 1);
+    const int front = RL0_CHK(w.st->seg_front[par][seg], cnt + 1);
     const unsigned long long kth = w.st->kth_key[par];
     long long acc = 0;
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
@@ -1512,7 +1559,7 @@ __global__ __launch_bounds__(256) void k_decide_only(DevState* st, int it, int n
 // x_out = x_hat (or, with trial = 1, H_k(x') of the last executed iteration) from the
 // candidate segments of the last executed iteration; x_out holds zeros beforehand.  With decide = 1 every workgroup first takes the
 // decision on the last iteration (it_end = n_iters) itself, and workgroup 0 records it.
-__global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __restrict__ x_out, int it_end,
+__global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __restrict__ x_out, int n, int it_end,
                                                   int trial, int decide_last, int n_iters, double tol_fx, int log_on) {
     __shared__ long long red[4];
     __shared__ Slot fin_sh;
@@ -1535,17 +1582,40 @@ __global__ __launch_bounds__(256) void k_copy_out(const Workspace w, float* __re
     const int acc = trial ? 1 : fin.accepted_last;
     const unsigned long long kth = w.st->kth_key[par];
     const int seg = blockIdx.x;
-    const int cnt = w.st->seg_count[par][seg];
-    const int front = w.st->seg_front[par][seg];
+    const int cnt = RL0_CHK(w.st->seg_count[par][seg], w.seg_cap + 1);
+    const int front = RL0_CHK(w.st->seg_front[par][seg], cnt + 1);
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
         const size_t ix = static_cast<size_t>(seg) * w.seg_cap + (e < front ? e : w.seg_cap - 1 - (e - front));
         const int j = w.cand_j[par][ix];
         const float v = current_value(acc, j, w.cand_x[par][ix], w.cand_h[par][ix], kth);
-        if (v != 0.0f) x_out[j] = v;
+        if (v != 0.0f) x_out[RL0_CHK(j, n)] = v;
     }
 }
 
 inline int blocks(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t device_check_read(int* line, hipStream_t s) {
+#if RL0_DEVICE_CHECKS
+    unsigned v = 0u;
+    hipError_t e = hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_check_line), sizeof(v), 0, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && v != 0u) {
+        const unsigned zero = 0u;
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_check_line), &zero, sizeof(zero), 0, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    *line = static_cast<int>(v);
+    return e;
+#else
+    (void)s;
+    *line = -1;
+    return hipSuccess;
+#endif
+}
+
+namespace {
 
 int sweep_grid(int n) {
     // one workgroup per CU, persistent over chunks of kSweepChunk columns
@@ -1577,17 +1647,23 @@ hipError_t launch_timed(K kernel, int grid, int block, hipStream_t s, const hipE
     return hipGetLastError();
 }
 
+template <int D, bool DENSE, bool PACKED>
+hipError_t launch_sweep_v(const SweepArgs& a, hipStream_t s, const hipEvent_t* ev) {
+    if (a.ip.wg_rev) return launch_timed(k_sweep<D, DENSE, PACKED, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+    return launch_timed(k_sweep<D, DENSE, PACKED, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+}
+
 template <int D>
 hipError_t launch_sweep_d(const SweepArgs& a, hipStream_t s, const hipEvent_t* ev) {
     // the flagged-row counts exist where the bitmask does not fit in LDS; packing fits
     // such an m only for d <= 6 (18 bits a row or more)
     if (a.Apk) {
-        if (a.bm_lds) return launch_timed(k_sweep<D, false, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
-        if constexpr (D <= 6) return launch_timed(k_sweep<D, true, true>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+        if (a.bm_lds) return launch_sweep_v<D, false, true>(a, s, ev);
+        if constexpr (D <= 6) return launch_sweep_v<D, true, true>(a, s, ev);
         return hipErrorInvalidValue;
     }
-    if (a.bm_lds) return launch_timed(k_sweep<D, false, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
-    return launch_timed(k_sweep<D, true, false>, a.w.sweep_grid, kSweepBlock, s, ev, a);
+    if (a.bm_lds) return launch_sweep_v<D, false, false>(a, s, ev);
+    return launch_sweep_v<D, true, false>(a, s, ev);
 }
 
 template <int D>
@@ -1774,7 +1850,8 @@ hipError_t launch_iteration(const DecodeDims& dm, const int32_t* A, const Worksp
     hipError_t e = launch_sweep(dm.d, a, s, ev ? ev : nullptr);
     if (e != hipSuccess) return e;
     const int pre = dm.m > kPreRows ? 1 : 0;
-    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, !a.bm_lds, pre, ip.log, ip.t};
+    const FinishArgs fa{A, dm.d, dm.k, dm.m, w, ip.it, ip.tau_next, a.bs_lds, !a.bm_lds, pre, ip.log, ip.t, ip.wg_rev,
+                        dm.n};
     if (pre) {
         e = launch_timed(k_hk_classify, kRowGrid, kRowBlock, s, ev ? ev + 2 : nullptr, fa);
         if (e != hipSuccess) return e;
@@ -1809,14 +1886,15 @@ hipError_t launch_finish(const DecodeDims& dm, const Workspace& w, const IterPar
         return hipGetLastError();
     }
     if (!x_zeroed) k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_out, dm.n);
-    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, ip_last.it, 0, 1, ip_last.n_iters, ip_last.tol_fx, ip_last.log);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_out, dm.n, ip_last.it, 0, 1, ip_last.n_iters, ip_last.tol_fx,
+                                            ip_last.log);
     return hipGetLastError();
 }
 
 hipError_t launch_trial_out(const DecodeDims& dm, const Workspace& w, int it_end, float* x_trial,
                             hipStream_t s) {
     k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_trial, dm.n);
-    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, it_end, 1, 0, 0, 0.0, 0);
+    k_copy_out<<<w.sweep_grid, 256, 0, s>>>(w, x_trial, dm.n, it_end, 1, 0, 0, 0.0, 0);
     return hipGetLastError();
 }
 

@@ -345,6 +345,7 @@ int check_params(const rl0_params* p, int32_t n, int32_t m, int32_t d) {
     if (p->adaptive_k == 1 && p->posterior == 1)
         return fail(RL0_EINVAL, "adaptive_k applies to the analytic posteriors only");
     if (p->log != 0 && p->log != 1) return fail(RL0_EINVAL, "log must be 0 or 1");
+    if (p->wg_order != 0 && p->wg_order != 1) return fail(RL0_EINVAL, "wg_order must be 0 or 1");
     for (int32_t law : {p->signal_law, p->noise_law})
         if (law != RL0_LAW_GAUSSIAN && law != RL0_LAW_LAPLACE)
             return fail(RL0_EINVAL, "signal_law and noise_law must be RL0_LAW_GAUSSIAN or RL0_LAW_LAPLACE");
@@ -388,6 +389,7 @@ void params_key(const rl0_params* p, rl0_params* out) {
     k.signal_law = p->signal_law;
     k.noise_law = p->noise_law;
     k.log = p->log;
+    k.wg_order = p->wg_order;
     // given tables enter through the constants (their device copy is part of the key)
 }
 
@@ -519,6 +521,7 @@ rl0::IterParams iter_params(const DeviceConstants* dc, const rl0_params* p, int 
     ip.tol_fx = dc->hc.tol * 1073741824.0;
     ip.quant = dc->hc.quant ? 1 : 0;
     ip.log = p->log;
+    ip.wg_rev = p->wg_order;
     if (ip.quant && it < N) {
         ip.qe_bits = dc->hc.qe_bits[it];
         ip.qz_bits = dc->hc.qz_bits[it];
@@ -1907,6 +1910,15 @@ int rl0_mlp_load(const char* path_h, rl0_mlp_ckpt* info_h, float* w, float* adam
     }
     if (any) HIP_TRY(hipStreamSynchronize(s));
     if (info_h) *info_h = info;
+    return RL0_OK;
+}
+
+int rl0_device_check(int32_t* line_h, void* stream) {
+    if (!line_h) return fail(RL0_EINVAL, "line_h is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    int line = 0;
+    HIP_TRY(rl0::device_check_read(&line, static_cast<hipStream_t>(stream)));
+    *line_h = line;
     return RL0_OK;
 }
 

@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
         ("noise_law", ctypes.c_int32),
         ("log", ctypes.c_int32),
         ("tables", ctypes.c_void_p),
+        ("wg_order", ctypes.c_int32),
     ]
 
 
@@ -215,6 +216,7 @@ def lib() -> ctypes.CDLL:
         L.rl0_mlp_adam.argtypes = [P, P, P, P, I32, I32, ctypes.POINTER(TrainCfg), V]
         L.rl0_mlp_save.argtypes = [ctypes.c_char_p, ctypes.POINTER(MlpCkpt), P, P, P, V]
         L.rl0_mlp_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(MlpCkpt), P, P, P, V]
+        L.rl0_device_check.argtypes = [ctypes.POINTER(I32), V]
         L.rl0_last_error.restype = ctypes.c_char_p
         L.rl0_release.argtypes = []
         for name in ("rl0_params_default", "rl0_compute_constants", "rl0_sketch", "rl0_sketch_static", "rl0_validate",
@@ -222,7 +224,7 @@ def lib() -> ctypes.CDLL:
                      "rl0_last_log",
                      "rl0_batch_schedule_set", "rl0_autotune_batched", "rl0_batch_timeline", "rl0_mlp_init", "rl0_mlp_features",
                      "rl0_mlp_labels", "rl0_mlp_grad", "rl0_mlp_train", "rl0_mlp_forward", "rl0_mlp_adam",
-                     "rl0_mlp_save", "rl0_mlp_load"):
+                     "rl0_mlp_save", "rl0_mlp_load", "rl0_device_check"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -399,6 +401,14 @@ def step(A_cols, y, params: Params, it: int, x_hat, r_hat, L_hat: int, debug: bo
     out = {"L_hat": int(L.value), "accepted": bool(acc.value)}
     out.update(dbg)
     return out
+
+
+def device_check() -> int:
+    """rl0_device_check: the kernels' source line of the first failed index check since the
+    last call (0: none), or -1 when the loaded library is the normal one."""
+    line = ctypes.c_int32(0)
+    _check(lib().rl0_device_check(ctypes.byref(line), None))   # the default stream
+    return line.value
 
 
 def profile_enable(enable: bool = True) -> None:

@@ -45,7 +45,7 @@ def test_params_default_follow_the_paper():
     ("k", 0), ("k", 256), ("alpha", 1.0), ("alpha", 7.5), ("c", 1.0), ("c", -0.1),
     ("sigma", -1.0), ("sigma", float("nan")), ("sigma_signal", 0.0), ("series_terms", 0),
     ("max_iters", -1), ("l1_test", 2), ("posterior", 3), ("variant", 2), ("variant", -1), ("adaptive_k", 2),
-    ("adaptive_k", -1), ("log", 2), ("signal_law", 5),
+    ("adaptive_k", -1), ("log", 2), ("signal_law", 5), ("wg_order", 2), ("wg_order", -1),
 ])
 def test_bad_params_are_rejected_on_the_host(field, value):
     p = R.params_default(1024, 256, 7, 25, 0.01)
@@ -302,3 +302,24 @@ def test_mlp_pack_bf16_matches_torch_bfloat16_conversion():
     got = R.mlp_pack_bf16(w, d)
     ref = torch.from_numpy(w).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     assert np.array_equal(got, ref)
+
+
+def test_device_checks_only_in_the_checked_library():
+    """The normal library has no device index checks (rl0_device_check reports -1 without
+    touching the GPU); the checked copy exports the same entry points."""
+    import ctypes
+    import os
+    import subprocess
+
+    line = ctypes.c_int32(7)
+    assert R.lib().rl0_device_check(ctypes.byref(line), None) == 0 and line.value == -1
+    checked = os.path.join(os.path.dirname(R.LIB_PATH), "librl0_checked.so")
+    if not os.path.exists(checked) or os.path.basename(R.LIB_PATH) != "librl0.so":
+        pytest.skip("librl0_checked.so is not built")
+
+    def exports(path):
+        out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
+        return {ln.split()[-1] for ln in out.splitlines() if " T rl0_" in ln}
+
+    names = exports(R.LIB_PATH)
+    assert "rl0_device_check" in names and exports(checked) == names
