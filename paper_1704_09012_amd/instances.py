@@ -157,11 +157,15 @@ def draw_batch_shapes(count: int, seed: int, d: int = 7, log2_n=(12, 18), delta=
 def draw_batch(count: int, seed: int, d: int = 7, **shape_kw) -> list[Instance]:
     """A batch of instances with the shapes of draw_batch_shapes, each drawn from its own
     seed (seed * 100000 + i) with sigma_n from its SNR."""
-    out = []
-    for i, (n, m, k, snr) in enumerate(draw_batch_shapes(count, seed, d, **shape_kw)):
-        sig = float(np.float32(sigma_for_snr(snr, n, m, k, d)))
-        out.append(draw_instance(n, m, k, d, sig, seed * 100000 + i))
-    return out
+    shapes = draw_batch_shapes(count, seed, d, **shape_kw)
+    return [batch_member(shapes, seed, i, d) for i in range(count)]
+
+
+def batch_member(shapes, seed: int, i: int, d: int = 7) -> Instance:
+    """Instance i of the batch draw_batch(len(shapes), seed, d) makes from these shapes."""
+    n, m, k, snr = shapes[i]
+    sig = float(np.float32(sigma_for_snr(snr, n, m, k, d)))
+    return draw_instance(n, m, k, d, sig, seed * 100000 + i)
 
 
 def draw_instance_device(n: int, m: int, k: int, d: int, sigma: float, seed: int, device="cuda",

@@ -20,7 +20,13 @@ workloads:
     decoded with the oracle's tables of those laws (make_tables.py writes them first);
   * Alg. 1's adaptive_k branch (files decodea_*): n = 2^20, m = n/10, k = m/10, d = 7 at
     20, 40 and 60 dB, the quantised variant at 40 dB (decodeaq_*), and n = 2^20, m = n/2,
-    k = m/8, d = 8 at 40 dB (m above 393216); these also store the last k_0.
+    k = m/8, d = 8 at 40 dB (m above 393216); these also store the last k_0;
+  * the batched workload (batch512_seed0.npz): the 512 uneven instances of
+    instances.draw_batch(512, 0, 7) (n log-uniform in [2^12, 2^18], m/n in [0.05, 0.5],
+    k/m in [0.05, 0.3], 20 to 60 dB), every one decoded by the oracle.  Per instance the
+    loop statistics and the SHA-256 of x_hat's support (int32, ascending) followed by its
+    values (float32), both little-endian: a bitwise comparison without storing 10^6
+    nonzeros.
 """
 from __future__ import annotations
 
@@ -103,12 +109,55 @@ def one(case):
     return path, res.iterations, res.accepted, err
 
 
+BATCH = (512, 0, 7)   # count, seed, d of the batched workload
+BATCH_FILE = "batch512_seed0.npz"
+
+
+def batch_one(i):
+    count, seed, d = BATCH
+    inst = I.batch_member(I.draw_batch_shapes(count, seed, d), seed, i, d)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, inst.m)
+    res = D.decode(inst.A_cols, y, D.make_constants(inst.n, inst.m, d, inst.k, inst.sigma))
+    supp = np.nonzero(res.x_hat)[0].astype(np.int32)
+    stats = (res.iterations, res.accepted, res.L_hat, int(res.converged), res.updates_total, res.fx_inexact_x)
+    return i, supp, res.x_hat[supp].astype(np.float32), stats
+
+
+def write_batch(jobs: int) -> None:
+    count = BATCH[0]
+    parts = [None] * count
+    # the largest instances first, so that none of them starts last
+    shapes = I.draw_batch_shapes(*BATCH)
+    order = sorted(range(count), key=lambda i: -shapes[i][0] * shapes[i][2] / shapes[i][1])
+    with ProcessPoolExecutor(jobs) as ex:
+        for i, supp, vals, stats in ex.map(batch_one, order):
+            parts[i] = (x_hat_digest(supp, vals), len(supp), stats)
+    st = np.array([p[2] for p in parts], np.int64)
+    np.savez_compressed(os.path.join(HERE, BATCH_FILE), count=count, seed=BATCH[1], d=BATCH[2],
+                        digest=np.array([p[0] for p in parts]), nnz=np.array([p[1] for p in parts], np.int64),
+                        iterations=st[:, 0], accepted=st[:, 1], L_hat=st[:, 2], converged=st[:, 3],
+                        updates_total=st[:, 4], fx_inexact_x=st[:, 5])
+    print(BATCH_FILE, "instances", count, "nonzeros", int(sum(p[1] for p in parts)), "converged",
+          int(st[:, 3].sum()), flush=True)
+
+
+def x_hat_digest(support, values) -> str:
+    """SHA-256 of the support (int32) then the values (float32), little-endian."""
+    import hashlib
+
+    h = hashlib.sha256(np.ascontiguousarray(support, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(values, dtype="<f4").tobytes())
+    return h.hexdigest()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)
     ap.add_argument("--only", default="", help="write only the files whose name starts with this")
     ap.add_argument("--missing", action="store_true", help="write only the files that do not exist yet")
     a = ap.parse_args()
+    if BATCH_FILE.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, BATCH_FILE))):
+        write_batch(a.jobs)
     work = [c for c in CASES if c[0].startswith(a.only)]
     if a.missing:
         work = [c for c in work if not os.path.exists(os.path.join(HERE, c[0]))]

@@ -1,7 +1,8 @@
 """Batched decoding (rl0_decode_batched) against the oracle and the single-decode path.
 
 Bar: every instance's x_hat and statistics are bitwise those of the oracle (small and
-mid sizes) or of rl0_decode, which is itself bitwise the oracle's (uneven batches of
+mid sizes, and all 512 instances of the batched workload against the oracle's stored
+decodes) or of rl0_decode, which is itself bitwise the oracle's (other uneven batches of
 the n in [2^12, 2^18] workload); schedules do not change results; a failing instance
 does not disturb the others.
 """
@@ -279,5 +280,51 @@ def test_batched_group_with_a_failing_instance():
         assert rc == -2 and st[len(probs) - 1].error_flags & 2
         for i, inst in enumerate(insts):
             same(host(probs[i]["out"]), st[i].as_dict(), oracle_of(inst))
+    finally:
+        R.batch_schedule_set(saved)
+
+
+def x_hat_digest(x) -> str:
+    """SHA-256 of the support of x (int32, ascending) then its values (float32),
+    little-endian: the digest tests/golden/make_golden.py stores for the oracle's x_hat."""
+    import hashlib
+
+    supp = np.nonzero(x)[0].astype("<i4")
+    h = hashlib.sha256(supp.tobytes())
+    h.update(np.ascontiguousarray(x[supp], dtype="<f4").tobytes())
+    return h.hexdigest()
+
+
+def test_batched_workload_against_stored_oracle():
+    """The batched workload itself: the 512 uneven instances of draw_batch(512, 0, 7)
+    (n log-uniform in [2^12, 2^18], the bench's batch) in one batched decode, under the
+    default schedule and under a schedule that splits the long instances over groups of
+    workgroups.  Every instance's x_hat (by digest) and loop statistics are bitwise the
+    oracle's, stored by tests/golden/make_golden.py."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch512_seed0.npz")
+    g = np.load(path)
+    insts = I.draw_batch(int(g["count"]), int(g["seed"]), int(g["d"]))
+    probs = problems_of(insts)
+    saved = R.batch_schedule_get()
+    try:
+        for name, sched in (("default", None), ("groups", group_schedule([1, 1, 1, 2, 4, 4, 4]))):
+            if sched is not None:
+                R.batch_schedule_set(sched)
+            print("batched workload, schedule", name, "sum n", sum(i.n for i in insts), flush=True)
+            stats = R.decode_batched(probs)
+            bad = []
+            for i, (pr, st) in enumerate(zip(probs, stats)):
+                ok = (x_hat_digest(host(pr["out"])) == str(g["digest"][i])
+                      and st["iterations"] == g["iterations"][i] and st["accepted"] == g["accepted"][i]
+                      and st["l1_final_fx"] == g["L_hat"][i] and st["converged"] == g["converged"][i]
+                      and st["updates_total"] == g["updates_total"][i] and st["fx_inexact_x"] == g["fx_inexact_x"][i]
+                      and st["error_flags"] == 0)
+                if not ok:
+                    bad.append(i)
+            assert not bad, f"instances differing from the oracle under {name}: {bad[:20]}"
+            for pr in probs:
+                pr["out"].zero_()
     finally:
         R.batch_schedule_set(saved)
