@@ -19,6 +19,8 @@ struct BatchProblem {
     const float* y;          // [m]
     float* x;                // [n] output; holds x_hat during the decode
     long long* S;            // [m] workspace: fixed-point residual of x_hat (of x' mid-iteration)
+    float* r;                // [m] workspace: fl32 of S, written with the outer-test bitmask at
+                             // the start of each iteration (the sweep's residual snapshot)
     float* xp;               // [n] workspace: x' (equals x_hat between iterations)
     int* stamp;              // [n] workspace: last iteration that put the column on the change list
     int* chg;                // [n] workspace: change list of the current iteration
@@ -70,6 +72,8 @@ struct BatchResult {
 struct BatchLaunch {
     int block;        // threads per workgroup: 256, 512 or 1024
     int per_cu;       // resident workgroups per compute unit the grid is sized for
+    int r_off = 0;    // float offset in dynamic LDS of the residual snapshot's region
+    int r_rows = 0;   // its rows: instances with m <= r_rows keep the snapshot in LDS
 };
 
 // Bytes rounded up to the 256-byte alignment every workspace array starts on.
@@ -79,8 +83,10 @@ size_t batched_lds_bytes(int max_m);
 // Workgroups of the batched kernel for column weight d and `block` threads that one
 // compute unit holds at once with `lds_bytes` of dynamic LDS (0 if the shape is invalid).
 int batched_max_resident(int d, int block, size_t lds_bytes);
-// Raise every batched kernel's dynamic LDS limit to what kBatchMaxRows needs (once per
-// device, before the first launch or capture).
+// Static LDS of the batched kernel for column weight d and `block` threads (0 if invalid).
+size_t batched_static_lds(int d, int block);
+// Raise every batched kernel's dynamic LDS limit to all that the compute unit's LDS leaves
+// beside its static LDS (once per device, before the first launch or capture).
 hipError_t batched_set_lds_limits();
 // Zero the queue counter, then the persistent decode of the `count` tickets in `order`
 // (instance * kTicketParts + part; a group's tickets are consecutive).  All instances

@@ -4,7 +4,8 @@
 // next instance from a queue (the host orders it largest first) and runs Alg. 1 for that
 // instance alone, so the only synchronisation is the workgroup barrier and the launch
 // drains when the queue is empty.  Per iteration a workgroup
-//   1. writes the outer-test bitmask |r_i| >= tau_it of its instance into LDS (ballot);
+//   1. writes the outer-test bitmask |r_i| >= tau_it of its instance into LDS (ballot),
+//      and r = fl32(S) beside S, which the sweep gathers (4 bytes a row instead of 8);
 //   2. sweeps its columns in tiles (the next tile's indices load while the current one is
 //      tested): a column whose rows hit the bitmask gathers its exact residuals and runs
 //      the consensus test; an update goes to x' and to the change list;
@@ -41,6 +42,7 @@ struct BatchShared {
     unsigned scan[BLOCK / 64];
     long long red[BLOCK / 64];
     int idx, nq, nchg, nupd, nzd, nkeys, err, digit;
+    int nflag[2];              // rows flagged by the outer test, by iteration parity
     unsigned above, bucket;
 };
 
@@ -189,16 +191,62 @@ __device__ __forceinline__ void load_tile(const int32_t* __restrict__ A, int n, 
 // join an LDS queue; the next tile's indices load while the queue is checked.  Once the
 // queue holds a column per thread (or the sweep ends) it is worked off one column per
 // thread, so the consensus test is balanced and its gathers are paid once per BLOCK
-// queued columns rather than once per tile.
+// queued columns rather than once per tile.  In the dense mode (a quarter of the rows
+// or more flagged, so that nearly every column has a candidate row) there is no queue:
+// each thread gathers the residuals of all its tile's rows at once, while the next tile's
+// indices load, and tests its own columns.  The two modes propose the same updates; only
+// the order of the change list differs, which nothing after the sweep depends on.
 template <int D, int BLOCK, int C>
 __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uint32_t* bm, int it,
-                         BatchShared<BLOCK>& sh, int j_begin, int j_end, int* nchg, int* chg) {
+                         BatchShared<BLOCK>& sh, int j_begin, int j_end, int* nchg, int* chg, bool dense,
+                         const float* rs) {
     const int tid = threadIdx.x;
     const int n = j_end;   // the columns [j_begin, j_end); j_begin is a multiple of 4
     constexpr int kTile = BLOCK * C;
     int cur[C][D];
     load_tile<D, C>(P.A, n, j_begin + tid * C, cur);
     int nupd = 0, nzd = 0;
+    if (dense) {
+        for (int base = j_begin; base < n; base += kTile) {
+            const int j0 = base + tid * C;
+            float v[C][D];
+            unsigned cm[C];
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                cm[q] = 0u;
+#pragma unroll
+                for (int p = 0; p < D; ++p) {
+                    const int r = cur[q][p];   // 0 past the end: a valid row, left unused
+                    v[q][p] = rs[r];
+                    cm[q] |= ((bm[r >> 5] >> (r & 31)) & 1u) << p;
+                }
+                if (j0 + q >= n) cm[q] = 0u;
+            }
+            if (base + kTile < n) load_tile<D, C>(P.A, n, base + kTile + tid * C, cur);
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const int j = j0 + q;
+                bool upd = false;
+                if (cm[q]) {
+                    float om = 0.0f;
+                    upd = column_update<D>(v[q], cm[q], tb, P.alpha, P.l1_test, &om);
+                    if (upd) {
+                        const float xh = P.x[j];
+                        const float xn = xh + om;
+                        P.xp[j] = xn;
+                        P.stamp[j] = it;
+                        ++nupd;
+                        nzd += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
+                    }
+                }
+                const int slot = wave_append(nchg, upd);
+                if (upd) chg[slot] = j;
+            }
+        }
+        if (nupd) atomicAdd(&sh.nupd, nupd);
+        if (nzd) atomicAdd(&sh.nzd, nzd);
+        return;
+    }
     for (int base = j_begin; base < n; base += kTile) {
         const int j0 = base + tid * C;
 #pragma unroll
@@ -232,7 +280,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                 for (int p = 0; p < D; ++p) rows[p] = col[p];
                 float v[D];
 #pragma unroll
-                for (int p = 0; p < D; ++p) v[p] = from_fx(P.S[rows[p]]);
+                for (int p = 0; p < D; ++p) v[p] = rs[rows[p]];
                 unsigned cm = 0u;
 #pragma unroll
                 for (int p = 0; p < D; ++p) cm |= ((bm[rows[p] >> 5] >> (rows[p] & 31)) & 1u) << p;
@@ -279,7 +327,7 @@ __device__ __forceinline__ long long apply_change(const BatchProblem& P, int j, 
 }
 
 template <int D, int BLOCK>
-__device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn, BatchShared<BLOCK>& sh) {
+__device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn, float* rs, BatchShared<BLOCK>& sh) {
     const unsigned long long t_start = wall_clock64();
     const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
@@ -337,6 +385,10 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             l += l1_term(from_fx(sfx));
         }
     }
+    if (tid == 0) {
+        sh.nflag[0] = 0;
+        sh.nflag[1] = 0;
+    }
     long long L_hat = wg_sum<BLOCK>(l, sh.red);
 
     int iters = 0, accepted = 0, updates = 0, supp = 0;
@@ -345,6 +397,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         if (sh.err != 0 || static_cast<double>(L_hat) <= P.tol_fx || it >= P.n_iters) break;
         // ---- 1. outer-test bitmask of this iteration's threshold
         const uint32_t tau = P.tau[it];
+        int flagged = 0;
         for (int base = 0; base < words * 32; base += BLOCK * kU) {
             long long sv[kU];
 #pragma unroll
@@ -355,22 +408,28 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int i = base + u * BLOCK + tid;
-                const bool pred = i < m && abs_bits(from_fx(sv[u])) >= tau;
+                const float rv = from_fx(sv[u]);
+                if (i < m) rs[i] = rv;   // (global: every member of a group writes the same values)
+                const bool pred = i < m && abs_bits(rv) >= tau;
                 const unsigned long long b = __ballot(pred);
                 if ((tid & 63) == 0) {
                     const int w = i >> 5;
                     if (w < words) bm[w] = static_cast<uint32_t>(b);
                     if (w + 1 < words) bm[w + 1] = static_cast<uint32_t>(b >> 32);
+                    flagged += __popcll(b);
                 }
             }
         }
+        if (flagged) atomicAdd(&sh.nflag[it & 1], flagged);
         if (tid == 0) {
             sh.nq = 0;
             sh.nchg = 0;
             sh.nupd = 0;
             sh.nzd = 0;
+            sh.nflag[(it & 1) ^ 1] = 0;   // the next iteration's count
         }
         __syncthreads();
+        const bool dense = 4ll * sh.nflag[it & 1] >= static_cast<long long>(m);
         // ---- 2. sweep (with this iteration's quantised-score thresholds)
         ScoreTables tbi = tb;
         if (P.quant) {
@@ -379,11 +438,11 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             tbi.qz_bits = P.qz[it];
         }
         if (P.cols == 1)
-            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg);
+            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg, dense, rs);
         else if (P.cols == 2)
-            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg);
+            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg, dense, rs);
         else
-            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg);
+            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg, dense, rs);
         __syncthreads();
         updates += sh.nupd;
         // ---- 3. H_k
@@ -539,7 +598,7 @@ __device__ __forceinline__ void member_slice(int count, int p, int G, int align,
 }
 
 template <int D, int BLOCK>
-__device__ __noinline__ void decode_instance_group(const BatchProblem P, int part, BatchResult* R, float* dyn,
+__device__ __noinline__ void decode_instance_group(const BatchProblem P, int part, BatchResult* R, float* dyn, float* rs,
                                       BatchShared<BLOCK>& sh) {
     const unsigned long long t_start = wall_clock64();
     const int tid = threadIdx.x;
@@ -593,6 +652,10 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         P.S[i] = sfx;
         l += l1_term(from_fx(sfx));
     }
+    if (tid == 0) {
+        sh.nflag[0] = 0;
+        sh.nflag[1] = 0;
+    }
     l = wg_sum<BLOCK>(l, sh.red);
     if (tid == 0) {
         if (l) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->L0), static_cast<unsigned long long>(l));
@@ -609,6 +672,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         if (err != 0 || static_cast<double>(L_hat) <= P.tol_fx || it >= P.n_iters) break;
         // ---- 1. the whole outer-test bitmask, in this member's LDS
         const uint32_t tau = P.tau[it];
+        int flagged = 0;
         for (int base = 0; base < words * 32; base += BLOCK * kU) {
             long long sv[kU];
 #pragma unroll
@@ -619,21 +683,27 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int i = base + u * BLOCK + tid;
-                const bool pred = i < m && abs_bits(from_fx(sv[u])) >= tau;
+                const float rv = from_fx(sv[u]);
+                if (i < m) rs[i] = rv;   // (global: every member of a group writes the same values)
+                const bool pred = i < m && abs_bits(rv) >= tau;
                 const unsigned long long b = __ballot(pred);
                 if ((tid & 63) == 0) {
                     const int w = i >> 5;
                     if (w < words) bm[w] = static_cast<uint32_t>(b);
                     if (w + 1 < words) bm[w + 1] = static_cast<uint32_t>(b >> 32);
+                    flagged += __popcll(b);
                 }
             }
         }
+        if (flagged) atomicAdd(&sh.nflag[it & 1], flagged);
         if (tid == 0) {
             sh.nq = 0;
             sh.nupd = 0;
             sh.nzd = 0;
+            sh.nflag[(it & 1) ^ 1] = 0;   // the next iteration's count
         }
         __syncthreads();
+        const bool dense = 4ll * sh.nflag[it & 1] >= static_cast<long long>(m);
         // the change list of this iteration: one of two, by parity, since a member may start
         // the next iteration while another still reads this one's list (after an accept)
         int* __restrict__ chg = par ? P.chg2 : P.chg;
@@ -645,11 +715,11 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
             tbi.qz_bits = P.qz[it];
         }
         if (P.cols == 1)
-            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg);
+            wg_sweep<D, BLOCK, 1>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg, dense, rs);
         else if (P.cols == 2)
-            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg);
+            wg_sweep<D, BLOCK, 2>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg, dense, rs);
         else
-            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg);
+            wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, c_lo, c_hi, &ctl->nchg[par], chg, dense, rs);
         __syncthreads();
         if (tid == 0) {
             if (sh.nupd) atomicAdd(&ctl->nupd[par], sh.nupd);
@@ -805,7 +875,8 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
 template <int D, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_decode_batched(const BatchProblem* __restrict__ probs,
                                                           const int* __restrict__ order, int count,
-                                                          BatchResult* __restrict__ res, int* __restrict__ counter) {
+                                                          BatchResult* __restrict__ res, int* __restrict__ counter,
+                                                          int r_off, int r_rows) {
     extern __shared__ float dyn[];
     __shared__ BatchShared<BLOCK> sh;
     for (;;) {
@@ -819,10 +890,12 @@ __global__ __launch_bounds__(BLOCK) void k_decode_batched(const BatchProblem* __
         const int ticket = __builtin_amdgcn_readfirstlane(order[q]);
         const int pi = ticket / kTicketParts, part = ticket % kTicketParts;
         const BatchProblem P = probs[pi];
+        // the residual snapshot in LDS when the instance's rows fit the region
+        float* rs = P.m <= r_rows ? dyn + r_off : P.r;
         if (P.group > 1)
-            decode_instance_group<D, BLOCK>(P, part, res + pi, dyn, sh);
+            decode_instance_group<D, BLOCK>(P, part, res + pi, dyn, rs, sh);
         else
-            decode_instance<D, BLOCK>(P, res + pi, dyn, sh);
+            decode_instance<D, BLOCK>(P, res + pi, dyn, rs, sh);
     }
 }
 
@@ -834,22 +907,32 @@ __global__ void k_zero_words(int* __restrict__ w, long long count) {
 }
 
 template <int D, int BLOCK>
-hipError_t launch_db(int grid, size_t lds, const BatchProblem* probs, const int* order, int count,
-                     BatchResult* res, int* counter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_db(const BatchLaunch& L, int grid, size_t lds, const BatchProblem* probs, const int* order,
+                     int count, BatchResult* res, int* counter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (e0) {
         hipExtLaunchKernelGGL(k_decode_batched<D, BLOCK>, dim3(grid), dim3(BLOCK), static_cast<uint32_t>(lds), s,
-                              e0, e1, 0, probs, order, count, res, counter);
+                              e0, e1, 0, probs, order, count, res, counter, L.r_off, L.r_rows);
     } else {
-        k_decode_batched<D, BLOCK><<<grid, BLOCK, lds, s>>>(probs, order, count, res, counter);
+        k_decode_batched<D, BLOCK><<<grid, BLOCK, lds, s>>>(probs, order, count, res, counter, L.r_off, L.r_rows);
     }
     return hipGetLastError();
 }
 
+constexpr size_t kCuLds = 160 * 1024;   // LDS of one gfx950 compute unit
+
+template <int D, int BLOCK>
+size_t static_lds_db() {
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_decode_batched<D, BLOCK>)) != hipSuccess) return 0;
+    return a.sharedSizeBytes;
+}
+
 template <int D, int BLOCK>
 hipError_t set_lds_limit() {
+    const size_t st = static_lds_db<D, BLOCK>();
+    if (st == 0 || st >= kCuLds) return hipErrorInvalidValue;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_decode_batched<D, BLOCK>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               static_cast<int>(batched_lds_bytes(kBatchMaxRows)));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kCuLds - st));
 }
 
 template <int D>
@@ -896,17 +979,38 @@ template <int D>
 hipError_t launch_d(const BatchLaunch& L, int grid, size_t lds, const BatchProblem* probs, const int* order,
                     int count, BatchResult* res, int* counter, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (L.block) {
-        case 256: return launch_db<D, 256>(grid, lds, probs, order, count, res, counter, s, e0, e1);
-        case 512: return launch_db<D, 512>(grid, lds, probs, order, count, res, counter, s, e0, e1);
-        case 1024: return launch_db<D, 1024>(grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 256: return launch_db<D, 256>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 512: return launch_db<D, 512>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
+        case 1024: return launch_db<D, 1024>(L, grid, lds, probs, order, count, res, counter, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int D>
+size_t static_lds_d(int block) {
+    switch (block) {
+        case 256: return static_lds_db<D, 256>();
+        case 512: return static_lds_db<D, 512>();
+        case 1024: return static_lds_db<D, 1024>();
+        default: return 0;
+    }
+}
+
+template <int... Ds>
+size_t static_lds_any(int d, int block, std::integer_sequence<int, Ds...>) {
+    size_t r = 0;
+    ((r = (d == Ds + 1 ? static_lds_d<Ds + 1>(block) : r)), ...);
+    return r;
 }
 
 }  // namespace
 
 hipError_t batched_set_lds_limits() {
     return set_lds_limits_all(std::make_integer_sequence<int, kMaxD>{});
+}
+
+size_t batched_static_lds(int d, int block) {
+    return static_lds_any(d, block, std::make_integer_sequence<int, kMaxD>{});
 }
 
 int batched_max_resident(int d, int block, size_t lds_bytes) {

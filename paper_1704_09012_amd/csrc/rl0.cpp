@@ -704,7 +704,8 @@ int plan_batch(const rl0_problem* probs, int count, hipStream_t s, BatchPlan* pl
     plan->d = probs[0].d;
     for (int i = 0; i < count; ++i) {
         plan->offs[i] = total;
-        total += rl0::al_host(8ull * probs[i].m) + 4 * rl0::al_host(4ull * probs[i].n) + rl0::al_host(8ull * probs[i].n);
+        total += rl0::al_host(8ull * probs[i].m) + rl0::al_host(4ull * probs[i].m) + 4 * rl0::al_host(4ull * probs[i].n) +
+                 rl0::al_host(8ull * probs[i].n);
         plan->max_m = std::max(plan->max_m, probs[i].m);
         plan->uniform_d = plan->uniform_d && probs[i].d == plan->d;
     }
@@ -813,6 +814,8 @@ int upload_batch(const rl0_problem* probs, const BatchPlan& P, const rl0_batch_s
         B.x = q.x_out;
         B.S = reinterpret_cast<long long*>(w);
         w += rl0::al_host(8ull * q.m);
+        B.r = reinterpret_cast<float*>(w);
+        w += rl0::al_host(4ull * q.m);
         B.xp = reinterpret_cast<float*>(w);
         w += rl0::al_host(4ull * q.n);
         B.stamp = reinterpret_cast<int*>(w);
@@ -857,13 +860,47 @@ size_t batch_lds(const BatchPlan& P) {
     return rl0::batched_lds_bytes(std::min(m, rl0::kBatchMaxRows));
 }
 
+// The launch of a plan under a schedule: the LDS its per_cu workgroups per compute unit
+// leave beside the tables and the bitmask holds the residual snapshot of instances with
+// at most r_rows rows (the others gather it from global memory).  *lds_total <- the
+// dynamic LDS per workgroup.
+rl0::BatchLaunch batch_launch(const BatchPlan& P, const rl0_batch_schedule& sc, size_t* lds_total) {
+    rl0::BatchLaunch L{sc.block, sc.per_cu};
+    const size_t base = batch_lds(P);
+    *lds_total = base;
+    // the static LDS of the kernel, the largest over d (one launch per d shares this
+    // dynamic size); queried once per block size (callers hold g_mu)
+    static size_t st_cache[3] = {0, 0, 0};
+    const int bi = sc.block == 256 ? 0 : sc.block == 512 ? 1 : sc.block == 1024 ? 2 : -1;
+    if (bi < 0) return L;
+    if (st_cache[bi] == 0) {
+        size_t st = 0;
+        for (int d = 1; d <= RL0_MAX_D; ++d) {
+            const size_t sd = rl0::batched_static_lds(d, sc.block);
+            if (sd == 0) return L;   // not queryable: no LDS snapshot
+            st = std::max(st, sd);
+        }
+        st_cache[bi] = st;
+    }
+    const size_t st = st_cache[bi];
+    const size_t share = (160u * 1024u) / static_cast<size_t>(std::max(1, sc.per_cu));
+    long long rows = 0;
+    if (share > st + base + 512) rows = static_cast<long long>((share - st - base - 512) / 4) & ~255ll;
+    rows = std::min<long long>(rows, ((static_cast<long long>(P.max_m) + 255) / 256) * 256);
+    if (rows < 1024) rows = 0;
+    L.r_off = static_cast<int>(base / 4);
+    L.r_rows = static_cast<int>(rows);
+    *lds_total = base + 4 * static_cast<size_t>(rows);
+    return L;
+}
+
 // Every launch of the plan (one per distinct d, in order), optionally timed; the groups'
 // shared blocks are cleared first by a fill kernel.
 int issue_batch(const BatchPlan& P, const rl0_batch_schedule& sc, const rl0_problem* probs, hipStream_t q,
                 bool timed) {
     const MetaView dv = meta_view(P.b->meta, P.count);
-    const rl0::BatchLaunch L{sc.block, sc.per_cu};
-    const size_t lds = batch_lds(P);
+    size_t lds = 0;
+    const rl0::BatchLaunch L = batch_launch(P, sc, &lds);
     const BatchTickets T = make_tickets(P, probs, sc);
     HIP_TRY(rl0::launch_zero_words(reinterpret_cast<int*>(dv.ctl),
                                    static_cast<long long>(P.count) * (sizeof(rl0::BatchCtl) / sizeof(int)), q));
@@ -885,7 +922,7 @@ int run_batch(const BatchPlan& P, const rl0_batch_schedule& sc, const rl0_proble
     key.d = P.d;
     key.block = sc.block;
     key.per_cu = sc.per_cu;
-    key.lds = batch_lds(P);
+    batch_launch(P, sc, &key.lds);
     key.meta = P.b->meta;
     {
         const BatchTickets T = make_tickets(P, probs, sc);
