@@ -516,13 +516,31 @@ def _problems(problems):
     return arr, keep
 
 
-def decode_batched(problems) -> list:
-    """rl0_decode_batched over a list of problem dicts; each dict's "out" (created if
-    absent) receives x_hat.  Returns the per-instance stats dicts."""
-    arr, _keep = _problems(problems)
-    st = (Stats * max(len(problems), 1))()
-    _check(lib().rl0_decode_batched(arr, len(problems), st, _stream()))
-    return [st[i].as_dict() for i in range(len(problems))]
+class PreparedBatch:
+    """A list of problem dicts marshalled once into the rl0_problem array, for repeated
+    batched decodes of the same tensors (their contents may change between calls)."""
+
+    def __init__(self, problems):
+        self.problems = problems
+        self.arr, self._keep = _problems(problems)
+        self.stats = (Stats * max(len(problems), 1))()
+
+    def __len__(self):
+        return len(self.problems)
+
+
+def decode_batched(problems, stats: bool = True):
+    """rl0_decode_batched over a list of problem dicts (or a PreparedBatch of them); each
+    dict's "out" (created if absent) receives x_hat.  Returns the per-instance stats
+    dicts, or None with stats=False (a PreparedBatch keeps them in .stats)."""
+    if isinstance(problems, PreparedBatch):
+        arr, st, count = problems.arr, problems.stats, len(problems)
+    else:
+        arr, _keep = _problems(problems)
+        count = len(problems)
+        st = (Stats * max(count, 1))()
+    _check(lib().rl0_decode_batched(arr, count, st, _stream()))
+    return [st[i].as_dict() for i in range(count)] if stats else None
 
 
 def batch_timeline(count: int):

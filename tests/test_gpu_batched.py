@@ -328,3 +328,28 @@ def test_batched_workload_against_stored_oracle():
                 pr["out"].zero_()
     finally:
         R.batch_schedule_set(saved)
+
+
+def test_prepared_batch_matches_the_list_call():
+    """A PreparedBatch (the problem array marshalled once) decodes as the list call does,
+    and again after the inputs' contents change."""
+    insts = mixed_batch()
+    probs = problems_of(insts)
+    st_list = R.decode_batched(probs)
+    x_list = [host(p["out"]).copy() for p in probs]
+    prep = R.PreparedBatch(probs)
+    for p in probs:
+        p["out"].zero_()
+    assert R.decode_batched(prep, stats=False) is None
+    for p, x in zip(probs, x_list):
+        assert np.array_equal(host(p["out"]), x)
+    st = [prep.stats[i].as_dict() for i in range(len(prep))]
+    assert [R.stats_subset(a) for a in st] == [R.stats_subset(b) for b in st_list]
+    # new measurements in the same buffers: the prepared array sees them
+    for inst, p in zip(insts, probs):
+        p["y"].copy_(dev(measured(inst)) * 0.5)
+    st2 = R.decode_batched(prep)
+    for inst, p, s2 in zip(insts, probs, st2):
+        C = D.make_constants(inst.n, inst.m, inst.d, inst.k, inst.sigma)
+        res = D.decode(inst.A_cols, measured(inst) * np.float32(0.5), C)
+        same(host(p["out"]), s2, res)
