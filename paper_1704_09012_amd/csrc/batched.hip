@@ -186,70 +186,6 @@ __device__ __forceinline__ void load_tile(const int32_t* __restrict__ A, int n, 
     }
 }
 
-// The column body of Alg. 1 (column_update) for a column most of whose rows pass the
-// outer test: the e-score of each of its D (D - 1) / 2 row pairs is taken once, since a
-// score depends on |v_p - v_l| alone and v_p - v_l = -(v_l - v_p) exactly in float32.
-// Each candidate row then adds its row's scores in the order column_update adds them
-// (l = 0 .. D - 1, 1 for l = p), and every candidate is evaluated in full: the bound
-// by which column_update skips some can only skip candidates that fail the test.  The
-// two functions return the same bits.
-template <int D>
-__device__ __forceinline__ bool column_update_pairs(const float (&v)[D], unsigned int cmask, const ScoreTables& tb,
-                                                    float alpha, int l1_test, float* omega_out) {
-    float n_z = 0.0f;
-    float S1 = 0.0f;
-#pragma unroll
-    for (int p = 0; p < D; ++p) {
-        const float z = tb.quant ? (abs_bits(v[p]) <= tb.qz_bits ? 1.0f : 0.0f)
-                                 : score(tb.Tz, tb.inv_h_z, tb.exact, fabsf(v[p]));
-        n_z = n_z + z;
-        S1 = S1 + fabsf(v[p]);
-    }
-    float w[D][D];
-#pragma unroll
-    for (int p = 0; p < D; ++p) {
-        w[p][p] = 1.0f;
-#pragma unroll
-        for (int l = p + 1; l < D; ++l) {
-            const float a = v[p] - v[l];
-            const float e = tb.quant ? (abs_bits(a) <= tb.qe_bits ? 1.0f : 0.0f)
-                                     : score(tb.Te, tb.inv_h_e, tb.exact, fabsf(a));
-            w[p][l] = e;
-            w[l][p] = e;
-        }
-    }
-    bool has = false;
-    float best_ne = 0.0f, best_om = 0.0f;
-#pragma unroll
-    for (int p = 0; p < D; ++p) {
-        if (!((cmask >> p) & 1u)) continue;
-        float n_e = 0.0f, s = 0.0f;
-#pragma unroll
-        for (int l = 0; l < D; ++l) {
-            n_e = n_e + w[p][l];
-            s = s + v[l] * w[p][l];
-        }
-        const float om = s / n_e;
-        bool l1_ok;
-        if (l1_test == 0) {
-            float Lp = 0.0f;
-#pragma unroll
-            for (int l = 0; l < D; ++l) Lp = Lp + fabsf(v[l] - om);
-            l1_ok = Lp <= S1;
-        } else {
-            l1_ok = fabsf(v[p] - om) <= fabsf(v[p]);
-        }
-        const bool pass = ((n_e - n_z) >= alpha) && l1_ok;
-        if (pass && (!has || n_e > best_ne)) {
-            has = true;
-            best_ne = n_e;
-            best_om = om;
-        }
-    }
-    *omega_out = best_om;
-    return has;
-}
-
 // Step 2 for one instance: the column sweep, C consecutive columns per thread per tile.
 // A tile's columns test their rows against the bitmask and those with a candidate row
 // join an LDS queue; the next tile's indices load while the queue is checked.  Once the
