@@ -66,6 +66,31 @@ def sweep_traffic():
     return 1024.0 * (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"])
 
 
+def instance_record(workload, inst, seed, snr, sigma, st, x_hat, x_true, rel, b_it) -> dict:
+    """One decoded instance as a record: the instance, its decode's statistics and device
+    time, throughput and algorithmic bytes, and its recovery (relative l2 error, the l1
+    success condition ||r_hat||_1 <= tol, and how much of the true support x_hat found)."""
+    true_s = x_true != 0
+    hat_s = x_hat != 0
+    found = int((true_s & hat_s).sum())
+    ms = float(st["ms_total"])
+    nnz_upd = inst.d * inst.n * st["iterations"]
+    return {"workload": workload, "seed": int(seed), "n": inst.n, "m": inst.m, "k": inst.k, "d": inst.d,
+            "snr_db": snr, "sigma": sigma, "iterations": st["iterations"], "accepted": st["accepted"],
+            "updates_total": st["updates_total"], "device_ms": ms,
+            "nnz_updates_per_s": nnz_upd / (ms * 1e-3) if ms > 0 else None,
+            "algorithmic_bytes": b_it * st["iterations"] + 4.0 * inst.d * inst.n,
+            "rel_l2_err": rel, "l1_success": bool(st["converged"]),
+            "support_found": found / max(int(true_s.sum()), 1), "support_size": int(hat_s.sum())}
+
+
+def write_records(path: str, records) -> None:
+    with open(path, "w") as f:
+        for r in records:
+            f.write(json.dumps(r) + "\n")
+    print(f"{len(records)} instance records written to {path}", file=sys.stderr, flush=True)
+
+
 def iteration_bytes(n: int, m: int, d: int, k: int, u: float) -> float:
     """Algorithmic bytes B_it of one loop iteration with u column updates (module
     docstring)."""
@@ -463,10 +488,16 @@ def bench_decode(args, N: int, M: int, K: int, DD: int, config: int, seeds: int,
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     # recovery error of every timed step's instance (outside the timed region)
+    records = []
     for i in range(min(args.steps, len(insts))):
-        one_step(i)
+        st_i = one_step(i)
         b = insts[i]
         rel.append(float(torch.linalg.norm(x_hat - b["x"]) / torch.linalg.norm(b["x"])))
+        if args.records:
+            records.append(instance_record(workload, b["inst"], seed_ids[i], SNR, sigma, st_i, x_hat, b["x"], rel[-1],
+                                           iteration_bytes(N, M, DD, K, st_i["updates_total"] / max(st_i["iterations"], 1))))
+    if args.records:
+        write_records(args.records, records)
 
     # Kernel durations: the same K steps again, with HIP events on the decode stream
     # around every sweep, select and row launch (a decode with events launches eagerly
@@ -569,6 +600,10 @@ def main() -> int:
                     help="batched: 512 uneven instances in one persistent launch, against "
                          "sequential single decodes of the same instances")
     ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--records", default="",
+                    help="single-decode workloads: write one JSON line per decoded instance (seed, sizes, SNR, "
+                         "iterations, device time, throughput, bytes, relative error, l1 success, support found) "
+                         "to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (3 times), the "
                          "reference kernel that scales HBM byte counters")
