@@ -26,7 +26,11 @@ workloads:
     k/m in [0.05, 0.3], 20 to 60 dB), every one decoded by the oracle.  Per instance the
     loop statistics and the SHA-256 of x_hat's support (int32, ascending) followed by its
     values (float32), both little-endian: a bitwise comparison without storing 10^6
-    nonzeros.
+    nonzeros;
+  * the headline workload's twenty seeds per SNR (c2digests_n1048576_d7_20seeds.npz):
+    n = 2^20, m = n/10, k = m/10, d = 7 at 20, 40 and 60 dB, seeds seed_for(2, snr index,
+    i) for i < 20 (the first five are also stored whole above); per instance the loop
+    statistics and the same SHA-256 of x_hat.
 """
 from __future__ import annotations
 
@@ -150,6 +154,36 @@ def x_hat_digest(support, values) -> str:
     return h.hexdigest()
 
 
+C2_FILE = "c2digests_n1048576_d7_20seeds.npz"
+C2_SEEDS = 20
+
+
+def c2_one(job):
+    si, i = job
+    snr = SNRS[si]
+    sig = float(np.float32(I.sigma_for_snr(snr, N, M, K, DD)))
+    inst = I.draw_instance(N, M, K, DD, sig, I.seed_for(2, si, i))
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, M)
+    res = D.decode(inst.A_cols, y, D.make_constants(N, M, DD, K, sig))
+    supp = np.nonzero(res.x_hat)[0].astype(np.int32)
+    stats = (res.iterations, res.accepted, res.L_hat, int(res.converged), res.updates_total, res.fx_inexact_x)
+    return si, i, x_hat_digest(supp, res.x_hat[supp].astype(np.float32)), stats
+
+
+def write_c2(jobs: int) -> None:
+    work = [(si, i) for si in range(len(SNRS)) for i in range(C2_SEEDS)]
+    digest = np.empty((len(SNRS), C2_SEEDS), dtype=object)
+    st = np.zeros((len(SNRS), C2_SEEDS, 6), np.int64)
+    with ProcessPoolExecutor(jobs) as ex:
+        for si, i, dg, stats in ex.map(c2_one, work):
+            digest[si, i] = dg
+            st[si, i] = stats
+    np.savez_compressed(os.path.join(HERE, C2_FILE), n=N, m=M, k=K, d=DD, snrs=np.array(SNRS), seeds=C2_SEEDS,
+                        digest=digest.astype("U64"), iterations=st[..., 0], accepted=st[..., 1], L_hat=st[..., 2],
+                        converged=st[..., 3], updates_total=st[..., 4], fx_inexact_x=st[..., 5])
+    print(C2_FILE, "instances", len(work), "converged", int(st[..., 3].sum()), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)
@@ -158,6 +192,8 @@ def main():
     a = ap.parse_args()
     if BATCH_FILE.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, BATCH_FILE))):
         write_batch(a.jobs)
+    if C2_FILE.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, C2_FILE))):
+        write_c2(a.jobs)
     work = [c for c in CASES if c[0].startswith(a.only)]
     if a.missing:
         work = [c for c in work if not os.path.exists(os.path.join(HERE, c[0]))]

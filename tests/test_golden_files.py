@@ -1,0 +1,38 @@
+"""The stored oracle results agree with one another (no GPU): the digests of the headline
+workload's twenty seeds per SNR (c2digests_*.npz) against the five whole decodes per SNR
+stored beside them, both written by tests/golden/make_golden.py from the oracle."""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+C2 = os.path.join(GOLDEN, "c2digests_n1048576_d7_20seeds.npz")
+
+
+def digest(support, values) -> str:
+    h = hashlib.sha256(np.ascontiguousarray(support, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(values, dtype="<f4").tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.skipif(not os.path.exists(C2), reason="digest file not stored")
+def test_twenty_seed_digests_match_the_whole_decodes():
+    c = np.load(C2)
+    assert c["digest"].shape == (3, 20) and list(c["snrs"]) == [20, 40, 60]
+    checked = 0
+    for si, snr in enumerate(c["snrs"]):
+        for i in range(20):
+            path = os.path.join(GOLDEN, f"decode_n1048576_d7_snr{int(snr)}_i{i}.npz")
+            if not os.path.exists(path):
+                continue
+            g = np.load(path)
+            assert digest(g["support"], g["values"]) == str(c["digest"][si, i]), (snr, i)
+            assert int(g["iterations"]) == c["iterations"][si, i] and int(g["accepted"]) == c["accepted"][si, i]
+            assert int(g["L_hat"]) == c["L_hat"][si, i] and int(g["updates_total"]) == c["updates_total"][si, i]
+            checked += 1
+    assert checked == 15
+    # the twenty decodes per SNR are distinct instances
+    for si in range(3):
+        assert len(set(str(x) for x in c["digest"][si])) == 20

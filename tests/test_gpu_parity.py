@@ -373,3 +373,40 @@ def test_decode_full_size_against_stored_oracle(fname):
     assert stg["l1_final_fx"] == int(g["L_hat"])
     if int(g["snr"]) >= 40 and k_dec == k:
         assert np.linalg.norm(xg - x) / np.linalg.norm(x) < 1e-2
+
+
+def _c2():
+    path = os.path.join(GOLDEN, "c2digests_n1048576_d7_20seeds.npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+@pytest.mark.parametrize("si", [0, 1, 2])
+def test_headline_workload_twenty_seeds_against_stored_oracle(si):
+    """n = 2^20, m = n/10, k = m/10, d = 7 at 20/40/60 dB, all twenty seeds per SNR the
+    workload names: x_hat (by the SHA-256 of its support and values) and the loop statistics
+    bitwise the oracle's (tests/golden/make_golden.py)."""
+    import hashlib
+
+    c = _c2()
+    if c is None:
+        pytest.skip("digest file not stored")
+    n, m, k, d = int(c["n"]), int(c["m"]), int(c["k"]), int(c["d"])
+    snr = int(c["snrs"][si])
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    bad = []
+    for i in range(int(c["seeds"])):
+        inst = I.draw_instance(n, m, k, d, sig, I.seed_for(2, si, i))
+        y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+        x_hat, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k)
+        xg = host(x_hat)
+        supp = np.nonzero(xg)[0].astype("<i4")
+        h = hashlib.sha256(supp.tobytes())
+        h.update(np.ascontiguousarray(xg[supp], dtype="<f4").tobytes())
+        ok = (h.hexdigest() == str(c["digest"][si, i]) and st["iterations"] == c["iterations"][si, i]
+              and st["accepted"] == c["accepted"][si, i] and st["l1_final_fx"] == c["L_hat"][si, i]
+              and st["converged"] == c["converged"][si, i] and st["updates_total"] == c["updates_total"][si, i]
+              and st["fx_inexact_x"] == c["fx_inexact_x"][si, i])
+        if not ok:
+            bad.append(i)
+    print(f"{snr} dB: {int(c['seeds'])} seeds, differing {bad}", flush=True)
+    assert not bad
