@@ -30,7 +30,10 @@ workloads:
   * the headline workload's twenty seeds per SNR (c2digests_n1048576_d7_20seeds.npz):
     n = 2^20, m = n/10, k = m/10, d = 7 at 20, 40 and 60 dB, seeds seed_for(2, snr index,
     i) for i < 20 (the first five are also stored whole above); per instance the loop
-    statistics and the same SHA-256 of x_hat.
+    statistics and the same SHA-256 of x_hat;
+  * the same for the quantised variant (c2qdigests_*: twenty seeds per SNR, seeds
+    seed_for(6, snr index, i)) and for Laplace signal and noise laws at 40 dB with the
+    oracle's tables of those laws (c2ldigests_*: ten seeds, seed_for(9, 1, i)).
 """
 from __future__ import annotations
 
@@ -155,33 +158,50 @@ def x_hat_digest(support, values) -> str:
 
 
 C2_FILE = "c2digests_n1048576_d7_20seeds.npz"
-C2_SEEDS = 20
+# digest sets of the headline shape: file -> (SNRs, seeds per SNR, variant, laws, seed_for's config)
+DIGEST_SETS = {
+    C2_FILE: (SNRS, 20, 0, ("gaussian", "gaussian"), 2),
+    "c2qdigests_n1048576_d7_20seeds.npz": (SNRS, 20, 1, ("gaussian", "gaussian"), 6),
+    "c2ldigests_n1048576_d7_snr40_10seeds.npz": ((40,), 10, 0, ("laplace", "laplace"), 9),
+}
 
 
-def c2_one(job):
-    si, i = job
-    snr = SNRS[si]
+def digest_one(job):
+    name, snr, i = job
+    _, _, variant, laws, cfg = DIGEST_SETS[name]
+    si = SNRS.index(snr)
     sig = float(np.float32(I.sigma_for_snr(snr, N, M, K, DD)))
-    inst = I.draw_instance(N, M, K, DD, sig, I.seed_for(2, si, i))
+    inst = I.draw_instance(N, M, K, DD, sig, I.seed_for(cfg, si, i), kind=laws[0], noise_kind=laws[1])
     y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, M)
-    res = D.decode(inst.A_cols, y, D.make_constants(N, M, DD, K, sig))
+    tables = None
+    if laws != ("gaussian", "gaussian"):
+        g = np.load(os.path.join(HERE, f"tables_n{N}_m{M}_k{K}_d{DD}_snr{snr}_{laws[0]}_{laws[1]}.npz"))
+        tables = (S.Table(g["Tz"], np.float32(g["inv_h_z"]), float(g["R_z"])),
+                  S.Table(g["Te"], np.float32(g["inv_h_e"]), float(g["R_e"])))
+    C = D.make_constants(N, M, DD, K, sig, variant=variant, signal=laws[0], noise=laws[1], tables=tables)
+    res = D.decode(inst.A_cols, y, C)
     supp = np.nonzero(res.x_hat)[0].astype(np.int32)
     stats = (res.iterations, res.accepted, res.L_hat, int(res.converged), res.updates_total, res.fx_inexact_x)
-    return si, i, x_hat_digest(supp, res.x_hat[supp].astype(np.float32)), stats
+    return name, snr, i, x_hat_digest(supp, res.x_hat[supp].astype(np.float32)), stats
 
 
-def write_c2(jobs: int) -> None:
-    work = [(si, i) for si in range(len(SNRS)) for i in range(C2_SEEDS)]
-    digest = np.empty((len(SNRS), C2_SEEDS), dtype=object)
-    st = np.zeros((len(SNRS), C2_SEEDS, 6), np.int64)
+def write_digest_sets(names, jobs: int) -> None:
+    work = [(nm, snr, i) for nm in names for snr in DIGEST_SETS[nm][0] for i in range(DIGEST_SETS[nm][1])]
+    out = {nm: ({}, {}) for nm in names}
     with ProcessPoolExecutor(jobs) as ex:
-        for si, i, dg, stats in ex.map(c2_one, work):
-            digest[si, i] = dg
-            st[si, i] = stats
-    np.savez_compressed(os.path.join(HERE, C2_FILE), n=N, m=M, k=K, d=DD, snrs=np.array(SNRS), seeds=C2_SEEDS,
-                        digest=digest.astype("U64"), iterations=st[..., 0], accepted=st[..., 1], L_hat=st[..., 2],
-                        converged=st[..., 3], updates_total=st[..., 4], fx_inexact_x=st[..., 5])
-    print(C2_FILE, "instances", len(work), "converged", int(st[..., 3].sum()), flush=True)
+        for nm, snr, i, dg, stats in ex.map(digest_one, work):
+            out[nm][0][(snr, i)] = dg
+            out[nm][1][(snr, i)] = stats
+    for nm in names:
+        snrs, seeds, variant, laws, cfg = DIGEST_SETS[nm]
+        digest = np.array([[out[nm][0][(snr, i)] for i in range(seeds)] for snr in snrs], dtype="U64")
+        st = np.array([[out[nm][1][(snr, i)] for i in range(seeds)] for snr in snrs], np.int64)
+        extra = {} if nm == C2_FILE else {"variant": variant, "signal": laws[0], "noise": laws[1], "config": cfg,
+                                          "snr_index": np.array([SNRS.index(x) for x in snrs])}
+        np.savez_compressed(os.path.join(HERE, nm), n=N, m=M, k=K, d=DD, snrs=np.array(snrs), seeds=seeds,
+                            digest=digest, iterations=st[..., 0], accepted=st[..., 1], L_hat=st[..., 2],
+                            converged=st[..., 3], updates_total=st[..., 4], fx_inexact_x=st[..., 5], **extra)
+        print(nm, "instances", digest.size, "converged", int(st[..., 3].sum()), flush=True)
 
 
 def main():
@@ -192,8 +212,10 @@ def main():
     a = ap.parse_args()
     if BATCH_FILE.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, BATCH_FILE))):
         write_batch(a.jobs)
-    if C2_FILE.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, C2_FILE))):
-        write_c2(a.jobs)
+    sets = [nm for nm in DIGEST_SETS if nm.startswith(a.only)
+            and not (a.missing and os.path.exists(os.path.join(HERE, nm)))]
+    if sets:
+        write_digest_sets(sets, a.jobs)
     work = [c for c in CASES if c[0].startswith(a.only)]
     if a.missing:
         work = [c for c in work if not os.path.exists(os.path.join(HERE, c[0]))]

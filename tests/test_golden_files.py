@@ -1,6 +1,7 @@
 """The stored oracle results agree with one another (no GPU): the digests of the headline
-workload's twenty seeds per SNR (c2digests_*.npz) against the five whole decodes per SNR
-stored beside them, both written by tests/golden/make_golden.py from the oracle."""
+workload's seeds (c2digests_*, and the quantised and Laplace-law sets c2qdigests_*,
+c2ldigests_*) against the whole decodes of the same instances stored beside them, all
+written by tests/golden/make_golden.py from the oracle."""
 import hashlib
 import os
 
@@ -36,3 +37,26 @@ def test_twenty_seed_digests_match_the_whole_decodes():
     # the twenty decodes per SNR are distinct instances
     for si in range(3):
         assert len(set(str(x) for x in c["digest"][si])) == 20
+
+
+@pytest.mark.parametrize("digests,whole", [
+    ("c2qdigests_n1048576_d7_20seeds.npz", "decodeq_n1048576_d7_snr{snr}_i0.npz"),
+    ("c2ldigests_n1048576_d7_snr40_10seeds.npz", "decodel_n1048576_d7_snr{snr}_laplace_laplace_i0.npz"),
+])
+def test_variant_digests_match_the_whole_decodes(digests, whole):
+    path = os.path.join(GOLDEN, digests)
+    if not os.path.exists(path):
+        pytest.skip("digest file not stored")
+    c = np.load(path)
+    checked = 0
+    for row, snr in enumerate(c["snrs"]):
+        w = os.path.join(GOLDEN, whole.format(snr=int(snr)))
+        if not os.path.exists(w):
+            continue
+        g = np.load(w)
+        assert int(g["seed"]) == 10000 * int(c["config"]) + 100 * int(c["snr_index"][row])   # seed i = 0
+        assert digest(g["support"], g["values"]) == str(c["digest"][row, 0])
+        assert int(g["iterations"]) == c["iterations"][row, 0] and int(g["L_hat"]) == c["L_hat"][row, 0]
+        checked += 1
+    assert checked == len(c["snrs"])
+    assert all(len(set(str(x) for x in c["digest"][r])) == int(c["seeds"]) for r in range(len(c["snrs"])))

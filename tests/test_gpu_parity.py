@@ -375,38 +375,49 @@ def test_decode_full_size_against_stored_oracle(fname):
         assert np.linalg.norm(xg - x) / np.linalg.norm(x) < 1e-2
 
 
-def _c2():
-    path = os.path.join(GOLDEN, "c2digests_n1048576_d7_20seeds.npz")
-    return np.load(path) if os.path.exists(path) else None
+def _digest_rows():
+    """(file, row) of every stored digest set of the headline shape."""
+    out = []
+    for f in ("c2digests_n1048576_d7_20seeds.npz", "c2qdigests_n1048576_d7_20seeds.npz",
+              "c2ldigests_n1048576_d7_snr40_10seeds.npz"):
+        path = os.path.join(GOLDEN, f)
+        if os.path.exists(path):
+            out += [(f, r) for r in range(len(np.load(path)["snrs"]))]
+    return out
 
 
-@pytest.mark.parametrize("si", [0, 1, 2])
-def test_headline_workload_twenty_seeds_against_stored_oracle(si):
-    """n = 2^20, m = n/10, k = m/10, d = 7 at 20/40/60 dB, all twenty seeds per SNR the
-    workload names: x_hat (by the SHA-256 of its support and values) and the loop statistics
-    bitwise the oracle's (tests/golden/make_golden.py)."""
+@pytest.mark.parametrize("fname,row", _digest_rows())
+def test_headline_workload_seeds_against_stored_oracle(fname, row):
+    """n = 2^20, m = n/10, k = m/10, d = 7: all twenty seeds per SNR (20/40/60 dB) the
+    workload names, continuous and quantised scores, and ten seeds with Laplace signal and
+    noise laws at 40 dB (the library's own tables of those laws): x_hat (by the SHA-256 of
+    its support and values) and the loop statistics bitwise the oracle's
+    (tests/golden/make_golden.py)."""
     import hashlib
 
-    c = _c2()
-    if c is None:
-        pytest.skip("digest file not stored")
+    c = np.load(os.path.join(GOLDEN, fname))
     n, m, k, d = int(c["n"]), int(c["m"]), int(c["k"]), int(c["d"])
-    snr = int(c["snrs"][si])
+    snr = int(c["snrs"][row])
+    variant = int(c["variant"]) if "variant" in c else 0
+    laws = (str(c["signal"]), str(c["noise"])) if "signal" in c else ("gaussian", "gaussian")
+    cfg = int(c["config"]) if "config" in c else 2
+    si = int(c["snr_index"][row]) if "snr_index" in c else row
     sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
     bad = []
     for i in range(int(c["seeds"])):
-        inst = I.draw_instance(n, m, k, d, sig, I.seed_for(2, si, i))
+        inst = I.draw_instance(n, m, k, d, sig, I.seed_for(cfg, si, i), kind=laws[0], noise_kind=laws[1])
         y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-        x_hat, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k)
+        x_hat, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, variant=variant, signal_law=laws[0],
+                             noise_law=laws[1])
         xg = host(x_hat)
         supp = np.nonzero(xg)[0].astype("<i4")
         h = hashlib.sha256(supp.tobytes())
         h.update(np.ascontiguousarray(xg[supp], dtype="<f4").tobytes())
-        ok = (h.hexdigest() == str(c["digest"][si, i]) and st["iterations"] == c["iterations"][si, i]
-              and st["accepted"] == c["accepted"][si, i] and st["l1_final_fx"] == c["L_hat"][si, i]
-              and st["converged"] == c["converged"][si, i] and st["updates_total"] == c["updates_total"][si, i]
-              and st["fx_inexact_x"] == c["fx_inexact_x"][si, i])
+        ok = (h.hexdigest() == str(c["digest"][row, i]) and st["iterations"] == c["iterations"][row, i]
+              and st["accepted"] == c["accepted"][row, i] and st["l1_final_fx"] == c["L_hat"][row, i]
+              and st["converged"] == c["converged"][row, i] and st["updates_total"] == c["updates_total"][row, i]
+              and st["fx_inexact_x"] == c["fx_inexact_x"][row, i])
         if not ok:
             bad.append(i)
-    print(f"{snr} dB: {int(c['seeds'])} seeds, differing {bad}", flush=True)
+    print(f"{fname} {snr} dB: {int(c['seeds'])} seeds, differing {bad}", flush=True)
     assert not bad
