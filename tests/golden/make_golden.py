@@ -32,8 +32,11 @@ workloads:
     i) for i < 20 (the first five are also stored whole above); per instance the loop
     statistics and the same SHA-256 of x_hat;
   * the same for the quantised variant (c2qdigests_*: twenty seeds per SNR, seeds
-    seed_for(6, snr index, i)) and for Laplace signal and noise laws at 40 dB with the
-    oracle's tables of those laws (c2ldigests_*: ten seeds, seed_for(9, 1, i)).
+    seed_for(6, snr index, i)), for Laplace signal and noise laws at 40 dB with the
+    oracle's tables of those laws (c2ldigests_*: ten seeds, seed_for(9, 1, i)), for the
+    adaptive_k branch (c2adigests_*: ten seeds per SNR, seed_for(7, snr index, i)) and for
+    the large-m shape n = 2^20, m = n/2, k = n/16, d = 8 at 40 dB (lmdigests_*: eight
+    seeds, seed_for(3, 1, 10 + i)).
 """
 from __future__ import annotations
 
@@ -158,27 +161,32 @@ def x_hat_digest(support, values) -> str:
 
 
 C2_FILE = "c2digests_n1048576_d7_20seeds.npz"
-# digest sets of the headline shape: file -> (SNRs, seeds per SNR, variant, laws, seed_for's config)
+GAUSS = ("gaussian", "gaussian")
+# digest sets: file -> (shape (n, m, k, d), SNRs, seeds per SNR, variant, adaptive_k, laws,
+# seed_for's config, first seed index)
 DIGEST_SETS = {
-    C2_FILE: (SNRS, 20, 0, ("gaussian", "gaussian"), 2),
-    "c2qdigests_n1048576_d7_20seeds.npz": (SNRS, 20, 1, ("gaussian", "gaussian"), 6),
-    "c2ldigests_n1048576_d7_snr40_10seeds.npz": ((40,), 10, 0, ("laplace", "laplace"), 9),
+    C2_FILE: ((N, M, K, DD), SNRS, 20, 0, 0, GAUSS, 2, 0),
+    "c2qdigests_n1048576_d7_20seeds.npz": ((N, M, K, DD), SNRS, 20, 1, 0, GAUSS, 6, 0),
+    "c2ldigests_n1048576_d7_snr40_10seeds.npz": ((N, M, K, DD), (40,), 10, 0, 0, ("laplace", "laplace"), 9, 0),
+    "c2adigests_n1048576_d7_10seeds.npz": ((N, M, K, DD), SNRS, 10, 0, 1, GAUSS, 7, 0),
+    "lmdigests_n1048576_m524288_d8_snr40_8seeds.npz": ((N, N // 2, N // 16, 8), (40,), 8, 0, 0, GAUSS, 3, 10),
 }
 
 
 def digest_one(job):
     name, snr, i = job
-    _, _, variant, laws, cfg = DIGEST_SETS[name]
+    (n, m, k, d), _, _, variant, adaptive, laws, cfg, i0 = DIGEST_SETS[name]
     si = SNRS.index(snr)
-    sig = float(np.float32(I.sigma_for_snr(snr, N, M, K, DD)))
-    inst = I.draw_instance(N, M, K, DD, sig, I.seed_for(cfg, si, i), kind=laws[0], noise_kind=laws[1])
-    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, M)
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, I.seed_for(cfg, si, i0 + i), kind=laws[0], noise_kind=laws[1])
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
     tables = None
-    if laws != ("gaussian", "gaussian"):
-        g = np.load(os.path.join(HERE, f"tables_n{N}_m{M}_k{K}_d{DD}_snr{snr}_{laws[0]}_{laws[1]}.npz"))
+    if laws != GAUSS:
+        g = np.load(os.path.join(HERE, f"tables_n{n}_m{m}_k{k}_d{d}_snr{snr}_{laws[0]}_{laws[1]}.npz"))
         tables = (S.Table(g["Tz"], np.float32(g["inv_h_z"]), float(g["R_z"])),
                   S.Table(g["Te"], np.float32(g["inv_h_e"]), float(g["R_e"])))
-    C = D.make_constants(N, M, DD, K, sig, variant=variant, signal=laws[0], noise=laws[1], tables=tables)
+    C = D.make_constants(n, m, d, k, sig, variant=variant, adaptive_k=adaptive, signal=laws[0], noise=laws[1],
+                         tables=tables)
     res = D.decode(inst.A_cols, y, C)
     supp = np.nonzero(res.x_hat)[0].astype(np.int32)
     stats = (res.iterations, res.accepted, res.L_hat, int(res.converged), res.updates_total, res.fx_inexact_x)
@@ -186,19 +194,22 @@ def digest_one(job):
 
 
 def write_digest_sets(names, jobs: int) -> None:
-    work = [(nm, snr, i) for nm in names for snr in DIGEST_SETS[nm][0] for i in range(DIGEST_SETS[nm][1])]
+    work = [(nm, snr, i) for nm in names for snr in DIGEST_SETS[nm][1] for i in range(DIGEST_SETS[nm][2])]
+    # the slowest instances first (the adaptive branch rebuilds its tables, the large-m shape)
+    work.sort(key=lambda w: -(DIGEST_SETS[w[0]][4] * 4 + (DIGEST_SETS[w[0]][0][1] > M)))
     out = {nm: ({}, {}) for nm in names}
     with ProcessPoolExecutor(jobs) as ex:
         for nm, snr, i, dg, stats in ex.map(digest_one, work):
             out[nm][0][(snr, i)] = dg
             out[nm][1][(snr, i)] = stats
     for nm in names:
-        snrs, seeds, variant, laws, cfg = DIGEST_SETS[nm]
+        (n, m, k, d), snrs, seeds, variant, adaptive, laws, cfg, i0 = DIGEST_SETS[nm]
         digest = np.array([[out[nm][0][(snr, i)] for i in range(seeds)] for snr in snrs], dtype="U64")
         st = np.array([[out[nm][1][(snr, i)] for i in range(seeds)] for snr in snrs], np.int64)
-        extra = {} if nm == C2_FILE else {"variant": variant, "signal": laws[0], "noise": laws[1], "config": cfg,
+        extra = {} if nm == C2_FILE else {"variant": variant, "adaptive_k": adaptive, "signal": laws[0],
+                                          "noise": laws[1], "config": cfg, "first_seed": i0,
                                           "snr_index": np.array([SNRS.index(x) for x in snrs])}
-        np.savez_compressed(os.path.join(HERE, nm), n=N, m=M, k=K, d=DD, snrs=np.array(snrs), seeds=seeds,
+        np.savez_compressed(os.path.join(HERE, nm), n=n, m=m, k=k, d=d, snrs=np.array(snrs), seeds=seeds,
                             digest=digest, iterations=st[..., 0], accepted=st[..., 1], L_hat=st[..., 2],
                             converged=st[..., 3], updates_total=st[..., 4], fx_inexact_x=st[..., 5], **extra)
         print(nm, "instances", digest.size, "converged", int(st[..., 3].sum()), flush=True)

@@ -1,7 +1,8 @@
 """The stored oracle results agree with one another (no GPU): the digests of the headline
-workload's seeds (c2digests_*, and the quantised and Laplace-law sets c2qdigests_*,
-c2ldigests_*) against the whole decodes of the same instances stored beside them, all
-written by tests/golden/make_golden.py from the oracle."""
+workload's seeds (c2digests_*; the quantised, Laplace-law and adaptive_k sets c2qdigests_*,
+c2ldigests_*, c2adigests_*; the large-m set lmdigests_*) against the whole decodes of the
+same instances stored beside them, all written by tests/golden/make_golden.py from the
+oracle."""
 import hashlib
 import os
 
@@ -42,6 +43,8 @@ def test_twenty_seed_digests_match_the_whole_decodes():
 @pytest.mark.parametrize("digests,whole", [
     ("c2qdigests_n1048576_d7_20seeds.npz", "decodeq_n1048576_d7_snr{snr}_i0.npz"),
     ("c2ldigests_n1048576_d7_snr40_10seeds.npz", "decodel_n1048576_d7_snr{snr}_laplace_laplace_i0.npz"),
+    ("c2adigests_n1048576_d7_10seeds.npz", "decodea_n1048576_d7_snr{snr}_i0.npz"),
+    ("lmdigests_n1048576_m524288_d8_snr40_8seeds.npz", "decode_n1048576_m524288_d8_snr{snr}_i0.npz"),
 ])
 def test_variant_digests_match_the_whole_decodes(digests, whole):
     path = os.path.join(GOLDEN, digests)
@@ -54,7 +57,8 @@ def test_variant_digests_match_the_whole_decodes(digests, whole):
         if not os.path.exists(w):
             continue
         g = np.load(w)
-        assert int(g["seed"]) == 10000 * int(c["config"]) + 100 * int(c["snr_index"][row])   # seed i = 0
+        first = int(c["first_seed"]) if "first_seed" in c else 0
+        assert int(g["seed"]) == 10000 * int(c["config"]) + 100 * int(c["snr_index"][row]) + first   # seed i = 0
         assert digest(g["support"], g["values"]) == str(c["digest"][row, 0])
         assert int(g["iterations"]) == c["iterations"][row, 0] and int(g["L_hat"]) == c["L_hat"][row, 0]
         checked += 1

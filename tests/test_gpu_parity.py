@@ -379,7 +379,8 @@ def _digest_rows():
     """(file, row) of every stored digest set of the headline shape."""
     out = []
     for f in ("c2digests_n1048576_d7_20seeds.npz", "c2qdigests_n1048576_d7_20seeds.npz",
-              "c2ldigests_n1048576_d7_snr40_10seeds.npz"):
+              "c2ldigests_n1048576_d7_snr40_10seeds.npz", "c2adigests_n1048576_d7_10seeds.npz",
+              "lmdigests_n1048576_m524288_d8_snr40_8seeds.npz"):
         path = os.path.join(GOLDEN, f)
         if os.path.exists(path):
             out += [(f, r) for r in range(len(np.load(path)["snrs"]))]
@@ -389,10 +390,11 @@ def _digest_rows():
 @pytest.mark.parametrize("fname,row", _digest_rows())
 def test_headline_workload_seeds_against_stored_oracle(fname, row):
     """n = 2^20, m = n/10, k = m/10, d = 7: all twenty seeds per SNR (20/40/60 dB) the
-    workload names, continuous and quantised scores, and ten seeds with Laplace signal and
-    noise laws at 40 dB (the library's own tables of those laws): x_hat (by the SHA-256 of
-    its support and values) and the loop statistics bitwise the oracle's
-    (tests/golden/make_golden.py)."""
+    workload names, continuous and quantised scores, ten seeds with Laplace signal and noise
+    laws at 40 dB (the library's own tables of those laws), ten seeds per SNR of the
+    adaptive_k branch; and eight seeds of the large-m shape (m = n/2, k = n/16, d = 8):
+    x_hat (by the SHA-256 of its support and values) and the loop statistics bitwise the
+    oracle's (tests/golden/make_golden.py)."""
     import hashlib
 
     c = np.load(os.path.join(GOLDEN, fname))
@@ -401,14 +403,16 @@ def test_headline_workload_seeds_against_stored_oracle(fname, row):
     variant = int(c["variant"]) if "variant" in c else 0
     laws = (str(c["signal"]), str(c["noise"])) if "signal" in c else ("gaussian", "gaussian")
     cfg = int(c["config"]) if "config" in c else 2
+    first = int(c["first_seed"]) if "first_seed" in c else 0
+    adaptive = int(c["adaptive_k"]) if "adaptive_k" in c else 0
     si = int(c["snr_index"][row]) if "snr_index" in c else row
     sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
     bad = []
     for i in range(int(c["seeds"])):
-        inst = I.draw_instance(n, m, k, d, sig, I.seed_for(cfg, si, i), kind=laws[0], noise_kind=laws[1])
+        inst = I.draw_instance(n, m, k, d, sig, I.seed_for(cfg, si, first + i), kind=laws[0], noise_kind=laws[1])
         y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
-        x_hat, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, variant=variant, signal_law=laws[0],
-                             noise_law=laws[1])
+        x_hat, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, variant=variant, adaptive_k=adaptive,
+                             signal_law=laws[0], noise_law=laws[1])
         xg = host(x_hat)
         supp = np.nonzero(xg)[0].astype("<i4")
         h = hashlib.sha256(supp.tobytes())
