@@ -425,3 +425,41 @@ def test_headline_workload_seeds_against_stored_oracle(fname, row):
             bad.append(i)
     print(f"{fname} {snr} dB: {int(c['seeds'])} seeds, differing {bad}", flush=True)
     assert not bad
+
+
+@pytest.mark.parametrize("n,m,k,d,snr,seed,j", [(65536, 6553, 655, 7, 40, 31, 5),
+                                                (1048576, 104857, 10485, 7, 40, 32, 12),
+                                                (1048576, 104857, 10485, 7, 20, 33, 20)])
+def test_resume_from_a_saved_iterate_matches_the_decode(n, m, k, d, snr, seed, j):
+    """The decoder's state is x_hat (rl0_step rebuilds the exact fixed-point residual and
+    ||r_hat||_1 from it): iterations 0 .. j-1 by rl0_step, x_hat saved to the host and
+    loaded into new device buffers, the remaining iterations by rl0_step until the loop's
+    stopping condition.  x_hat, ||r_hat||_1 and the iteration count equal one rl0_decode's."""
+    sig = float(np.float32(I.sigma_for_snr(snr, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, seed)
+    y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, m)
+    A, yt = dev(inst.A_cols), dev(y)
+    x_dec, st_dec = R.decode(A, yt, sigma=sig, k=k)
+    p = R.params_default(n, m, d, k, sig)
+    C = R.compute_constants(p, n, m, d)
+    tol = C.tol * 2.0 ** 30
+
+    def steps(x, r, L, it, stop):
+        while it < min(stop, C.n_iters):
+            if it > 0 and float(L) <= tol:
+                break
+            L = R.step(A, yt, p, it, x, r, L, debug=False)["L_hat"]
+            it += 1
+        return L, it
+
+    x = torch.zeros(n, dtype=torch.float32, device="cuda")
+    r = torch.empty(m, dtype=torch.float32, device="cuda")
+    L, it = steps(x, r, 0, 0, j)
+    saved = host(x).copy()                      # the checkpoint: x_hat and the iteration
+    del x, r
+    x2 = dev(saved)
+    r2 = torch.empty(m, dtype=torch.float32, device="cuda")
+    L, it = steps(x2, r2, L, it, C.n_iters)
+    print(f"resume n={n} snr={snr}: saved after {j}, {it} iterations in all", flush=True)
+    assert torch.equal(x2, x_dec)
+    assert L == st_dec["l1_final_fx"] and it == st_dec["iterations"]
