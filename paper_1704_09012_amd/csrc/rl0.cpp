@@ -641,9 +641,11 @@ int size_class(int n) {
 }
 
 rl0_batch_schedule default_schedule() {
+    // what the autotuner settles on for batches of uneven instances: one 1024-thread
+    // workgroup per CU, which leaves the most LDS for the residual snapshot
     rl0_batch_schedule s;
-    s.block = 256;
-    s.per_cu = 3;
+    s.block = 1024;
+    s.per_cu = 1;
     for (int c = 0; c < RL0_SIZE_CLASSES; ++c) {
         s.cols[c] = 4;
         s.group[c] = 4;   // the work estimate decides which instances are split (most are not)
