@@ -179,11 +179,35 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
 
 // Validates every column (rows strictly ascending in [0, m)) and scatters the nonzero
 // ones: a malformed column flags kErrIndex and adds nothing, so no write leaves S.
-__global__ void k_sketch_scatter(const int32_t* __restrict__ A, int n, int m, int d,
-                                 const float* __restrict__ x, long long* __restrict__ S, int* err) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// The columns [j0, j0 + cnt) of A ([n][d] row indices) into LDS, with one 16-byte load
+// per thread where the block's span is 16-byte aligned, all issued together.  (With d
+// not known at compile time, a thread's own loop over its column's d indices waits for
+// each load in turn.)  Every thread of the block must call.
+__device__ __forceinline__ void stage_columns(const int32_t* __restrict__ A, int d, int j0, int cnt, int* cols) {
+    const int total = cnt * d;
+    const int32_t* __restrict__ src = A + static_cast<size_t>(j0) * d;
+    if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0u) {
+        const int n4 = total >> 2;
+        for (int i = threadIdx.x; i < n4; i += blockDim.x)
+            reinterpret_cast<int4*>(cols)[i] = reinterpret_cast<const int4*>(src)[i];
+        for (int i = (n4 << 2) + threadIdx.x; i < total; i += blockDim.x) cols[i] = src[i];
+    } else {
+        for (int i = threadIdx.x; i < total; i += blockDim.x) cols[i] = src[i];
+    }
+    __syncthreads();
+}
+
+constexpr int kStageBlock = 256;   // threads (and columns) per block of the sketch
+
+__global__ __launch_bounds__(kStageBlock) void k_sketch_scatter(const int32_t* __restrict__ A, int n, int m, int d,
+                                                                const float* __restrict__ x,
+                                                                long long* __restrict__ S, int* err) {
+    __shared__ __align__(16) int cols_sh[kStageBlock * kMaxD];
+    const int j0 = blockIdx.x * kStageBlock;
+    const int j = j0 + threadIdx.x;
+    stage_columns(A, d, j0, min(kStageBlock, n - j0), cols_sh);
     if (j >= n) return;
-    const int32_t* col = A + static_cast<size_t>(j) * d;
+    const int* col = cols_sh + threadIdx.x * d;
     const float xj = x[j];
     int prev = -1;
     bool bad = false;
@@ -496,6 +520,8 @@ __device__ __forceinline__ void unpack_chunk(const uint4 (&w)[kSweepCols], int (
 template <int D>
 __global__ void k_pack_cols(const int32_t* __restrict__ A, int n, int m, uint4* __restrict__ Apk, int* err,
                             float* __restrict__ x_zero) {
+    // (the D loads of a thread's column are unrolled and issued together; staging the
+    // block's columns through LDS, as the sketch does, measured slower here)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     if (x_zero) x_zero[j] = 0.0f;
@@ -1784,7 +1810,7 @@ hipError_t launch_validate(const int32_t* A, int n, int m, int d, int* err, hipS
 hipError_t launch_sketch(const int32_t* A, int n, int m, int d, const float* x, float* y,
                          long long* S, int* err, hipStream_t s) {
     k_zero_ll<<<blocks(m, 256), 256, 0, s>>>(S, m);
-    if (n > 0) k_sketch_scatter<<<blocks(n, 256), 256, 0, s>>>(A, n, m, d, x, S, err);
+    if (n > 0) k_sketch_scatter<<<blocks(n, kStageBlock), kStageBlock, 0, s>>>(A, n, m, d, x, S, err);
     k_sketch_finish<<<blocks(m, 256), 256, 0, s>>>(S, y, m, err);
     return hipGetLastError();
 }
