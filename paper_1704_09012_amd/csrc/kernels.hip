@@ -143,10 +143,34 @@ __device__ __forceinline__ long long block_sum_rows(long long v, long long* sh) 
 
 // ------------------------------------------------------------------ small utilities
 
-__global__ void k_validate(const int32_t* __restrict__ A, int n, int m, int d, int* err) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// The columns [j0, j0 + cnt) of A ([n][d] row indices) into LDS, with one 16-byte load
+// per thread where the block's span is 16-byte aligned, all issued together.  (With d
+// not known at compile time, a thread's own loop over its column's d indices waits for
+// each load in turn.)  Every thread of the block must call.
+__device__ __forceinline__ void stage_columns(const int32_t* __restrict__ A, int d, int j0, int cnt, int* cols) {
+    const int total = cnt * d;
+    const int32_t* __restrict__ src = A + static_cast<size_t>(j0) * d;
+    if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0u) {
+        const int n4 = total >> 2;
+        for (int i = threadIdx.x; i < n4; i += blockDim.x)
+            reinterpret_cast<int4*>(cols)[i] = reinterpret_cast<const int4*>(src)[i];
+        for (int i = (n4 << 2) + threadIdx.x; i < total; i += blockDim.x) cols[i] = src[i];
+    } else {
+        for (int i = threadIdx.x; i < total; i += blockDim.x) cols[i] = src[i];
+    }
+    __syncthreads();
+}
+
+constexpr int kStageBlock = 256;   // threads (and columns) per block of the staged kernels
+
+__global__ __launch_bounds__(kStageBlock) void k_validate(const int32_t* __restrict__ A, int n, int m, int d,
+                                                          int* err) {
+    __shared__ __align__(16) int cols_sh[kStageBlock * kMaxD];
+    const int j0 = blockIdx.x * kStageBlock;
+    const int j = j0 + threadIdx.x;
+    stage_columns(A, d, j0, min(kStageBlock, n - j0), cols_sh);
     if (j >= n) return;
-    const int32_t* col = A + static_cast<size_t>(j) * d;
+    const int* col = cols_sh + threadIdx.x * d;
     int prev = -1;
     bool bad = false;
     for (int p = 0; p < d; ++p) {
@@ -179,25 +203,6 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
 
 // Validates every column (rows strictly ascending in [0, m)) and scatters the nonzero
 // ones: a malformed column flags kErrIndex and adds nothing, so no write leaves S.
-// The columns [j0, j0 + cnt) of A ([n][d] row indices) into LDS, with one 16-byte load
-// per thread where the block's span is 16-byte aligned, all issued together.  (With d
-// not known at compile time, a thread's own loop over its column's d indices waits for
-// each load in turn.)  Every thread of the block must call.
-__device__ __forceinline__ void stage_columns(const int32_t* __restrict__ A, int d, int j0, int cnt, int* cols) {
-    const int total = cnt * d;
-    const int32_t* __restrict__ src = A + static_cast<size_t>(j0) * d;
-    if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0u) {
-        const int n4 = total >> 2;
-        for (int i = threadIdx.x; i < n4; i += blockDim.x)
-            reinterpret_cast<int4*>(cols)[i] = reinterpret_cast<const int4*>(src)[i];
-        for (int i = (n4 << 2) + threadIdx.x; i < total; i += blockDim.x) cols[i] = src[i];
-    } else {
-        for (int i = threadIdx.x; i < total; i += blockDim.x) cols[i] = src[i];
-    }
-    __syncthreads();
-}
-
-constexpr int kStageBlock = 256;   // threads (and columns) per block of the sketch
 
 __global__ __launch_bounds__(kStageBlock) void k_sketch_scatter(const int32_t* __restrict__ A, int n, int m, int d,
                                                                 const float* __restrict__ x,
@@ -1803,7 +1808,7 @@ void carve_workspace(void* base, int n, int m, Workspace* w) {
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_validate(const int32_t* A, int n, int m, int d, int* err, hipStream_t s) {
-    if (n > 0) k_validate<<<blocks(n, 256), 256, 0, s>>>(A, n, m, d, err);
+    if (n > 0) k_validate<<<blocks(n, kStageBlock), kStageBlock, 0, s>>>(A, n, m, d, err);
     return hipGetLastError();
 }
 
@@ -1845,7 +1850,7 @@ hipError_t launch_prepare(const DecodeDims& dm, const int32_t* A, bool validate,
     // the packing pass validates the columns and clears x_zero; without packing they
     // run on their own
     if (!launch_pack(dm.d, A, dm.n, dm.m, w.Apk, validate ? &w.st->err : nullptr, x_zero, s)) {
-        if (validate) k_validate<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
+        if (validate) k_validate<<<blocks(dm.n, kStageBlock), kStageBlock, 0, s>>>(A, dm.n, dm.m, dm.d, &w.st->err);
         if (x_zero) k_zero_f32<<<blocks(dm.n, 256), 256, 0, s>>>(x_zero, dm.n);
     }
     if (x_hat0) k_prep_scatter<<<blocks(dm.n, 256), 256, 0, s>>>(A, dm.n, dm.d, x_hat0, w.S[0], w.st);
