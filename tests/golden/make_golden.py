@@ -26,7 +26,7 @@ workloads:
     k/m in [0.05, 0.3], 20 to 60 dB), every one decoded by the oracle.  Per instance the
     loop statistics and the SHA-256 of x_hat's support (int32, ascending) followed by its
     values (float32), both little-endian: a bitwise comparison without storing 10^6
-    nonzeros;
+    nonzeros; batch512q_seed0.npz holds the same batch decoded with the quantised scores;
   * the headline workload's twenty seeds per SNR (c2digests_n1048576_d7_20seeds.npz):
     n = 2^20, m = n/10, k = m/10, d = 7 at 20, 40 and 60 dB, seeds seed_for(2, snr index,
     i) for i < 20 (the first five are also stored whole above); per instance the loop
@@ -121,33 +121,37 @@ def one(case):
 
 BATCH = (512, 0, 7)   # count, seed, d of the batched workload
 BATCH_FILE = "batch512_seed0.npz"
+BATCH_FILES = {BATCH_FILE: 0, "batch512q_seed0.npz": 1}   # file -> variant (1: quantised scores)
 
 
-def batch_one(i):
+def batch_one(job):
+    i, variant = job
     count, seed, d = BATCH
     inst = I.batch_member(I.draw_batch_shapes(count, seed, d), seed, i, d)
     y = D.measure(inst.A_cols[inst.support], inst.values, inst.eta, inst.m)
-    res = D.decode(inst.A_cols, y, D.make_constants(inst.n, inst.m, d, inst.k, inst.sigma))
+    res = D.decode(inst.A_cols, y, D.make_constants(inst.n, inst.m, d, inst.k, inst.sigma, variant=variant))
     supp = np.nonzero(res.x_hat)[0].astype(np.int32)
     stats = (res.iterations, res.accepted, res.L_hat, int(res.converged), res.updates_total, res.fx_inexact_x)
     return i, supp, res.x_hat[supp].astype(np.float32), stats
 
 
-def write_batch(jobs: int) -> None:
+def write_batch(jobs: int, name: str = BATCH_FILE) -> None:
+    variant = BATCH_FILES[name]
     count = BATCH[0]
     parts = [None] * count
     # the largest instances first, so that none of them starts last
     shapes = I.draw_batch_shapes(*BATCH)
     order = sorted(range(count), key=lambda i: -shapes[i][0] * shapes[i][2] / shapes[i][1])
     with ProcessPoolExecutor(jobs) as ex:
-        for i, supp, vals, stats in ex.map(batch_one, order):
+        for i, supp, vals, stats in ex.map(batch_one, [(i, variant) for i in order]):
             parts[i] = (x_hat_digest(supp, vals), len(supp), stats)
     st = np.array([p[2] for p in parts], np.int64)
-    np.savez_compressed(os.path.join(HERE, BATCH_FILE), count=count, seed=BATCH[1], d=BATCH[2],
+    extra = {"variant": variant} if variant else {}
+    np.savez_compressed(os.path.join(HERE, name), count=count, seed=BATCH[1], d=BATCH[2], **extra,
                         digest=np.array([p[0] for p in parts]), nnz=np.array([p[1] for p in parts], np.int64),
                         iterations=st[:, 0], accepted=st[:, 1], L_hat=st[:, 2], converged=st[:, 3],
                         updates_total=st[:, 4], fx_inexact_x=st[:, 5])
-    print(BATCH_FILE, "instances", count, "nonzeros", int(sum(p[1] for p in parts)), "converged",
+    print(name, "instances", count, "nonzeros", int(sum(p[1] for p in parts)), "converged",
           int(st[:, 3].sum()), flush=True)
 
 
@@ -221,8 +225,9 @@ def main():
     ap.add_argument("--only", default="", help="write only the files whose name starts with this")
     ap.add_argument("--missing", action="store_true", help="write only the files that do not exist yet")
     a = ap.parse_args()
-    if BATCH_FILE.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, BATCH_FILE))):
-        write_batch(a.jobs)
+    for name in BATCH_FILES:
+        if name.startswith(a.only) and not (a.missing and os.path.exists(os.path.join(HERE, name))):
+            write_batch(a.jobs, name)
     sets = [nm for nm in DIGEST_SETS if nm.startswith(a.only)
             and not (a.missing and os.path.exists(os.path.join(HERE, nm)))]
     if sets:
