@@ -53,7 +53,9 @@ struct BatchCtl {
     long long L0;            // ||r||_1 of r = y, summed over the members
     long long dl[2];         // change of ||r||_1 by the iteration's residual change
     long long dsupp[2];      // change of |supp x'|
-    int pad[10];
+    int inexact_y;           // rounded conversions of y, summed over the members
+    int inexact_x;           // rounded conversions of updated x'_j, over the iterations
+    int pad[8];
 };
 static_assert(sizeof(BatchCtl) % 16 == 0, "BatchCtl keeps 16-byte alignment");
 
@@ -66,6 +68,8 @@ struct BatchResult {
     long long L_hat;
     int iterations, accepted, updates_total, err;
     unsigned long long t_start, t_end;   // wall clock (100 MHz) when the decode began and ended
+    int inexact_y;   // entries of y whose 2^-40 fixed-point conversion rounds
+    int inexact_x;   // updated x'_j != 0 whose conversion rounds, over the executed iterations
 };
 
 // The launch-wide part of a schedule.

@@ -42,6 +42,7 @@ struct BatchShared {
     unsigned scan[BLOCK / 64];
     long long red[BLOCK / 64];
     int idx, nq, nchg, nupd, nzd, nkeys, err, digit;
+    int ninx;                  // the sweep's updated x'_j != 0 whose conversion rounds
     int nflag[2];              // rows flagged by the outer test, by iteration parity
     unsigned above, bucket;
 };
@@ -205,7 +206,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
     constexpr int kTile = BLOCK * C;
     int cur[C][D];
     load_tile<D, C>(P.A, n, j_begin + tid * C, cur);
-    int nupd = 0, nzd = 0;
+    int nupd = 0, nzd = 0, ninx = 0;
     if (dense) {
         for (int base = j_begin; base < n; base += kTile) {
             const int j0 = base + tid * C;
@@ -237,6 +238,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                         P.stamp[j] = it;
                         ++nupd;
                         nzd += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
+                        ninx += (xn != 0.0f && fx_inexact(xn)) ? 1 : 0;
                     }
                 }
                 const int slot = wave_append(nchg, upd);
@@ -245,6 +247,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
         }
         if (nupd) atomicAdd(&sh.nupd, nupd);
         if (nzd) atomicAdd(&sh.nzd, nzd);
+        if (ninx) atomicAdd(&sh.ninx, ninx);
         return;
     }
     for (int base = j_begin; base < n; base += kTile) {
@@ -293,6 +296,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                     P.stamp[j] = it;
                     ++nupd;
                     nzd += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
+                    ninx += (xn != 0.0f && fx_inexact(xn)) ? 1 : 0;
                 }
             }
             const int slot = wave_append(nchg, upd);
@@ -303,6 +307,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
     }
     if (nupd) atomicAdd(&sh.nupd, nupd);
     if (nzd) atomicAdd(&sh.nzd, nzd);
+    if (ninx) atomicAdd(&sh.ninx, ninx);
 }
 
 // The fixed-point residual change of changing column j from xh to xn (d rows); with
@@ -364,7 +369,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         P.xp[j] = 0.0f;
         P.stamp[j] = -1;
     }
-    long long l = 0;
+    long long l = 0, ny = 0;
     for (int base = 0; base < m; base += BLOCK * kU) {
         float yv[kU];
 #pragma unroll
@@ -381,6 +386,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
                 atomicOr(&sh.err, kErrNonFinite);
             else
                 sfx = to_fx(yv[u], &sh.err);
+            ny += fx_inexact(yv[u]) ? 1 : 0;
             P.S[i] = sfx;
             l += l1_term(from_fx(sfx));
         }
@@ -390,8 +396,9 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         sh.nflag[1] = 0;
     }
     long long L_hat = wg_sum<BLOCK>(l, sh.red);
+    const int inexact_y = static_cast<int>(wg_sum<BLOCK>(ny, sh.red));
 
-    int iters = 0, accepted = 0, updates = 0, supp = 0;
+    int iters = 0, accepted = 0, updates = 0, supp = 0, inexact_x = 0;
     const int words = (m + 31) >> 5;
     for (int it = 0;; ++it) {
         if (sh.err != 0 || static_cast<double>(L_hat) <= P.tol_fx || it >= P.n_iters) break;
@@ -426,6 +433,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             sh.nchg = 0;
             sh.nupd = 0;
             sh.nzd = 0;
+            sh.ninx = 0;
             sh.nflag[(it & 1) ^ 1] = 0;   // the next iteration's count
         }
         __syncthreads();
@@ -445,6 +453,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             wg_sweep<D, BLOCK, 4>(P, tbi, bm, it, sh, 0, n, &sh.nchg, P.chg, dense, rs);
         __syncthreads();
         updates += sh.nupd;
+        inexact_x += sh.ninx;
         // ---- 3. H_k
         if (supp + sh.nzd > P.k) {
             int nk = 0;
@@ -520,6 +529,8 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         R->iterations = iters;
         R->accepted = accepted;
         R->updates_total = updates;
+        R->inexact_y = inexact_y;
+        R->inexact_x = inexact_x;
         R->err = sh.err;
         R->t_start = t_start;
         R->t_end = wall_clock64();
@@ -585,6 +596,8 @@ __device__ __forceinline__ void group_failed(BatchResult* R) {
         R->iterations = 0;
         R->accepted = 0;
         R->updates_total = 0;
+        R->inexact_y = 0;
+        R->inexact_x = 0;
         R->err = kErrTimeout;
     }
 }
@@ -641,7 +654,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         P.xp[j] = 0.0f;
         P.stamp[j] = -1;
     }
-    long long l = 0;
+    long long l = 0, ny = 0;
     for (int i = r_lo + tid; i < r_hi; i += BLOCK) {
         const float yv = P.y[i];
         long long sfx = 0;
@@ -649,6 +662,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
             atomicOr(&sh.err, kErrNonFinite);
         else
             sfx = to_fx(yv, &sh.err);
+        ny += fx_inexact(yv) ? 1 : 0;
         P.S[i] = sfx;
         l += l1_term(from_fx(sfx));
     }
@@ -657,8 +671,10 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         sh.nflag[1] = 0;
     }
     l = wg_sum<BLOCK>(l, sh.red);
+    ny = wg_sum<BLOCK>(ny, sh.red);
     if (tid == 0) {
         if (l) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->L0), static_cast<unsigned long long>(l));
+        if (ny) atomicAdd(&ctl->inexact_y, static_cast<int>(ny));
         if (sh.err) atomicOr(&ctl->err, sh.err);
     }
     if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
@@ -700,6 +716,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
             sh.nq = 0;
             sh.nupd = 0;
             sh.nzd = 0;
+            sh.ninx = 0;
             sh.nflag[(it & 1) ^ 1] = 0;   // the next iteration's count
         }
         __syncthreads();
@@ -724,6 +741,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         if (tid == 0) {
             if (sh.nupd) atomicAdd(&ctl->nupd[par], sh.nupd);
             if (sh.nzd) atomicAdd(&ctl->nzd[par], sh.nzd);
+            if (sh.ninx) atomicAdd(&ctl->inexact_x, sh.ninx);   // a running total: read at the end
         }
         if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
         // the next iteration's counters: every member has passed the previous iteration's
@@ -865,6 +883,8 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         R->iterations = iters;
         R->accepted = accepted;
         R->updates_total = updates;
+        R->inexact_y = __hip_atomic_load(&ctl->inexact_y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R->inexact_x = __hip_atomic_load(&ctl->inexact_x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         R->err = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         R->t_start = t_start;
         R->t_end = wall_clock64();

@@ -1006,8 +1006,8 @@ int collect_batch(const rl0_problem* probs, const BatchPlan& P, rl0_stats* st, h
             o.t_final = R.iterations > 0 ? dc->hc.t[R.iterations - 1] : 1.0f;
             o.error_flags = R.err;
             o.ms_total = call_ms;   // the whole batched launch
-            o.fx_inexact_y = 0;
-            o.fx_inexact_x = 0;
+            o.fx_inexact_y = R.inexact_y;
+            o.fx_inexact_x = R.inexact_x;
             o.k_post = static_cast<double>(probs[i].params.k);
         }
         if (R.err && first_rc == RL0_OK) {

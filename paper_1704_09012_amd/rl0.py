@@ -79,7 +79,6 @@ class Stats(ctypes.Structure):
 # stats fields that depend only on the inputs (ms_total is a timing), and of those the
 # ones a batched decode reports too (it does not count fixed-point roundings)
 DETERMINISTIC_STATS = tuple(f for f, _ in Stats._fields_ if f != "ms_total")
-LOOP_STATS = tuple(f for f in DETERMINISTIC_STATS if not f.startswith("fx_inexact"))
 
 
 def stats_subset(st: dict, fields=DETERMINISTIC_STATS) -> dict:
