@@ -149,27 +149,35 @@ def test_training_lowers_the_loss():
 
 
 def test_trained_network_gain_over_the_analytic_rule():
-    """Train on trajectories of the n = 1024 workload (2000 decodes, SNR in [20, 60] dB)
-    and decode unseen n = 2^17 instances at 20 and 40 dB with and without the network.
-    What it gains: it reaches the paper's stopping condition (||r||_1 <= m sigma
-    sqrt(2/pi)) on more instances, within the 1e-2 error bar at 40 dB."""
+    """Train on trajectories of the n = 1024 workload (2000 decodes, SNR in [20, 60] dB;
+    the training is deterministic) and decode 12 unseen n = 2^17 instances at each of 20,
+    40 and 60 dB with and without the network.
+
+    What it gains: at 20 and 40 dB it reaches the paper's stopping condition
+    (||r||_1 <= m sigma sqrt(2/pi)) on 24 of 24 instances against 5 of 24 for the analytic
+    rule; the test requires a lead of at least 12.  What it loses: at 60 dB the analytic
+    rule stops on 12 of 12 and the learned one on 2, and the learned relative error is a
+    little larger at every SNR (0.095 against 0.088 at worst at 20 dB, 0.0062 against
+    0.0055 at 40 dB, 5.7e-4 against 4.7e-4 at 60 dB); the test holds both to the error
+    bars 0.15, 1e-2 and 1e-3."""
     from paper_1704_09012_amd import learned as Lrn
     F, Y = Lrn.trajectories(2000, 1)
     w, loss = Lrn.train(F, Y, epochs=30)
     n = 2 ** 17
     m, k = n // 10, n // 100
-    conv = {"analytic": 0, "learned": 0}
-    for snr in (20, 40):
-        rows = Lrn.compare(w, n, m, k, snr, range(70000, 70004))
+    conv = {snr: {"analytic": 0, "learned": 0} for snr in (20, 40, 60)}
+    bar = {20: 0.15, 40: 1e-2, 60: 1e-3}
+    for snr in (20, 40, 60):
+        rows = Lrn.compare(w, n, m, k, snr, range(70000, 70012))
         for r in rows:
             print(snr, r["seed"], {t: (round(r[t]["rel_err"], 5), r[t]["iterations"], r[t]["converged"])
                                   for t in ("analytic", "learned")}, flush=True)
-            for t in conv:
-                conv[t] += r[t]["converged"]
-            if snr == 40:
-                assert r["learned"]["rel_err"] < 1e-2 and r["analytic"]["rel_err"] < 1e-2
-    print("converged (of 8):", conv, "train loss", loss, flush=True)
-    assert conv["learned"] > conv["analytic"]
+            for t in ("analytic", "learned"):
+                conv[snr][t] += r[t]["converged"]
+                assert r[t]["rel_err"] < bar[snr], (snr, r["seed"], t)
+    print("converged (of 12 per SNR):", conv, "train loss", loss, flush=True)
+    lead = sum(conv[s]["learned"] - conv[s]["analytic"] for s in (20, 40))
+    assert lead >= 12, conv
 
 
 def median_net(d, sigma, bias):
