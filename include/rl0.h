@@ -269,7 +269,8 @@ typedef struct rl0_batch_schedule {
 
 /* Decode count instances (probs_h: host array).  Every instance is checked as in
  * rl0_decode before anything runs (RL0_EINVAL names the first bad one in
- * rl0_last_error); m must be <= RL0_BATCH_MAX_M.  st_h (host, count entries, may be
+ * rl0_last_error); m must be <= RL0_BATCH_MAX_M, and posterior = 1 and adaptive_k = 1
+ * are refused (RL0_EINVAL).  st_h (host, count entries, may be
  * NULL) receives each instance's statistics; the stream is synchronised.  When a
  * decode fails on the device (malformed A_cols with validate = 1, non-finite y,
  * fixed-point range), that instance's x_out and stats.error_flags say so, the others

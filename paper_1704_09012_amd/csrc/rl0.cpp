@@ -690,6 +690,8 @@ int plan_batch(const rl0_problem* probs, int count, hipStream_t s, BatchPlan* pl
         auto bad = [&](int rc) { return fail(rc, "instance " + std::to_string(i) + ": " + g_last_error); };
         if (int rc = check_params(&q.params, q.n, q.m, q.d)) return bad(rc);
         if (q.params.adaptive_k) return bad(fail(RL0_EINVAL, "adaptive_k is not supported by batched decodes"));
+        if (q.params.posterior != 0)
+            return bad(fail(RL0_EINVAL, "the learned posterior (posterior = 1) is not supported by batched decodes"));
         if (!q.A_cols || !q.y || !q.x_out) return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": NULL pointer");
         if (reinterpret_cast<uintptr_t>(q.A_cols) % 16)
             return fail(RL0_EINVAL, "instance " + std::to_string(i) + ": A_cols must be 16-byte aligned");

@@ -207,6 +207,16 @@ def test_adaptive_k_is_refused_where_it_does_not_apply():
     assert b"instance 1" in L.rl0_last_error() and b"adaptive_k" in L.rl0_last_error()
 
 
+def test_batched_refuses_the_learned_posterior():
+    # the batched kernel has only the analytic decision: a learned request is an error,
+    # before any device work, rather than an analytic decode
+    L = R.lib()
+    arr = (R.Problem * 3)(_fake_problem(), _fake_problem(), _fake_problem())
+    arr[2].params.posterior, arr[2].params.mlp = 1, 4096
+    assert L.rl0_decode_batched(arr, 3, None, None) == -1
+    assert b"instance 2" in L.rl0_last_error() and b"posterior" in L.rl0_last_error()
+
+
 def test_batch_schedule_rejects_bad_fields():
     L = R.lib()
     for bad in ({"block": 128, "per_cu": 1, "cols": [4] * 12}, {"block": 256, "per_cu": 0, "cols": [4] * 12},
