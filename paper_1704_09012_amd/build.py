@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librl0.so")
 # the same library with the loop kernels' index checks compiled in (rl0_device_check)
 CHECKED_OUT = os.path.join(HERE, "librl0_checked.so")
-CHECKED_SOURCE = "kernels.hip"
+CHECKED_SOURCES = ("kernels.hip", "batched.hip")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["constants.cpp", "general.cpp", "rl0.cpp", "kernels.hip", "batched.hip", "mlp.hip", "noalloc.hip"]
@@ -63,17 +63,16 @@ def _link(objs, out: str) -> None:
 
 def build(verbose: bool = False) -> str:
     """Builds librl0.so and librl0_checked.so (the latter differs only in the loop
-    kernels, compiled with their index checks)."""
+    kernels and the batched kernel, compiled with their index checks)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    jobs = [(src, False) for src in SOURCES] + [(CHECKED_SOURCE, True)]
-    # the two compiles of the largest source first, so that they overlap the others
-    jobs.sort(key=lambda j: j[0] != CHECKED_SOURCE)
+    jobs = [(src, False) for src in SOURCES] + [(src, True) for src in CHECKED_SOURCES]
+    # the compiles of the largest sources first, so that they overlap the others
+    jobs.sort(key=lambda j: j[0] not in CHECKED_SOURCES)
     with ThreadPoolExecutor(max_workers=4) as ex:
         done = dict(zip(jobs, ex.map(lambda j: _compile(*j), jobs)))
     objs = [done[(src, False)] for src in SOURCES]
     _link(objs, OUT)
-    _link([done[(CHECKED_SOURCE, True)] if src == CHECKED_SOURCE else done[(src, False)] for src in SOURCES],
-          CHECKED_OUT)
+    _link([done[(src, src in CHECKED_SOURCES)] for src in SOURCES], CHECKED_OUT)
     if verbose:
         print("built", OUT, "and", CHECKED_OUT)
     return OUT

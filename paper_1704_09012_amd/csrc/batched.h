@@ -89,6 +89,9 @@ size_t batched_lds_bytes(int max_m);
 int batched_max_resident(int d, int block, size_t lds_bytes);
 // Static LDS of the batched kernel for column weight d and `block` threads (0 if invalid).
 size_t batched_static_lds(int d, int block);
+// The source line of the first failed index check in the batched kernel since the last
+// call (0: none; the record is then cleared), or -1 where the checks are not compiled in.
+hipError_t batched_check_read(int* line, hipStream_t s);
 // Raise every batched kernel's dynamic LDS limit to all that the compute unit's LDS leaves
 // beside its static LDS (once per device, before the first launch or capture).
 hipError_t batched_set_lds_limits();

@@ -32,6 +32,28 @@ namespace rl0 {
 
 namespace {
 
+// Checked builds (compiled with RL0_DEVICE_CHECKS=1 into the second copy of the library):
+// BCHK(i, n) tests a data-dependent index (a row read from A_cols, a slot taken from an
+// append counter, a column read back from a list or decoded from a key) against [0, n).
+// Outside it, the source line of the first failed check is recorded in
+// g_batched_check_line (read back by batched_check_read) and the index becomes 0, so that
+// the access stays inside its buffer and the decode runs to its end.  In normal builds
+// BCHK(i, n) is i.
+#if RL0_DEVICE_CHECKS
+__device__ unsigned g_batched_check_line;
+
+template <class I>
+__device__ __forceinline__ I bchk(I i, long long n, unsigned line) {
+    const long long v = static_cast<long long>(i);
+    if (v >= 0 && v < n) return i;
+    atomicCAS(&g_batched_check_line, 0u, line);
+    return static_cast<I>(0);
+}
+#define BCHK(i, n) bchk((i), static_cast<long long>(n), __LINE__)
+#else
+#define BCHK(i, n) (i)
+#endif
+
 constexpr int kBins = 2048;
 constexpr int kTabStride = kTableStrideFloats;   // floats from the start of Tz to Te in LDS
 
@@ -121,7 +143,7 @@ __device__ unsigned long long wg_select_kth(const BatchProblem& P, BatchShared<B
             const bool nz = v[u] != 0.0f;
             const unsigned long long key = nz ? hk_key(base + u * BLOCK + tid, v[u]) : 0ull;
             const int slot = wave_append(&sh.nkeys, nz);
-            if (nz) P.keys[slot] = key;
+            if (nz) P.keys[BCHK(slot, P.n)] = key;
             hist_add(sh.hist, static_cast<unsigned>(key >> 52), nz);
         }
     }
@@ -141,7 +163,7 @@ __device__ unsigned long long wg_select_kth(const BatchProblem& P, BatchShared<B
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     const int e = base + u * BLOCK + tid;
-                    kv[u] = e < nk ? P.keys[e] : 0ull;
+                    kv[u] = e < nk ? P.keys[BCHK(e, P.n)] : 0ull;
                 }
 #pragma unroll
                 for (int u = 0; u < kU; ++u)
@@ -217,7 +239,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                 cm[q] = 0u;
 #pragma unroll
                 for (int p = 0; p < D; ++p) {
-                    const int r = cur[q][p];   // 0 past the end: a valid row, left unused
+                    const int r = BCHK(cur[q][p], P.m);   // 0 past the end: a valid row, left unused
                     v[q][p] = rs[r];
                     cm[q] |= ((bm[r >> 5] >> (r & 31)) & 1u) << p;
                 }
@@ -242,7 +264,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                     }
                 }
                 const int slot = wave_append(nchg, upd);
-                if (upd) chg[slot] = j;
+                if (upd) chg[BCHK(slot, P.n)] = j;
             }
         }
         if (nupd) atomicAdd(&sh.nupd, nupd);
@@ -258,12 +280,12 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
             if (j0 + q < n) {
 #pragma unroll
                 for (int p = 0; p < D; ++p) {
-                    const int r = cur[q][p];
+                    const int r = BCHK(cur[q][p], P.m);
                     hit |= (bm[r >> 5] >> (r & 31)) & 1u;
                 }
             }
             const int slot = wave_append(&sh.nq, hit != 0u);
-            if (hit) sh.queue[slot] = j0 + q;
+            if (hit) sh.queue[BCHK(slot, BLOCK * 5)] = j0 + q;
         }
         const bool more = base + kTile < n;
         if (more) load_tile<D, C>(P.A, n, base + kTile + tid * C, cur);
@@ -276,11 +298,11 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
             bool upd = false;
             int j = 0;
             if (e < nq) {
-                j = sh.queue[e];
+                j = BCHK(sh.queue[BCHK(e, BLOCK * 5)], n);
                 const int32_t* __restrict__ col = P.A + static_cast<size_t>(j) * D;
                 int rows[D];
 #pragma unroll
-                for (int p = 0; p < D; ++p) rows[p] = col[p];
+                for (int p = 0; p < D; ++p) rows[p] = BCHK(col[p], P.m);
                 float v[D];
 #pragma unroll
                 for (int p = 0; p < D; ++p) v[p] = rs[rows[p]];
@@ -300,7 +322,7 @@ __device__ void wg_sweep(const BatchProblem& P, const ScoreTables& tb, const uin
                 }
             }
             const int slot = wave_append(nchg, upd);
-            if (upd) chg[slot] = j;
+            if (upd) chg[BCHK(slot, P.n)] = j;
         }
         if (tid == 0) sh.nq = 0;
         __syncthreads();
@@ -320,7 +342,7 @@ __device__ __forceinline__ long long apply_change(const BatchProblem& P, int j, 
     const int32_t* __restrict__ col = P.A + static_cast<size_t>(j) * D;
     int rows[D];
 #pragma unroll
-    for (int p = 0; p < D; ++p) rows[p] = col[p];
+    for (int p = 0; p < D; ++p) rows[p] = BCHK(col[p], P.m);
     long long dl = 0;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
@@ -464,16 +486,16 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
                 bool add = false;
                 int j = 0;
                 if (e < nk) {
-                    const unsigned long long key = P.keys[e];
+                    const unsigned long long key = P.keys[BCHK(e, P.n)];
                     if (key < kth) {
-                        j = static_cast<int>(0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull));
+                        j = BCHK(static_cast<int>(0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull)), P.n);
                         P.xp[j] = 0.0f;
                         add = P.stamp[j] != it;
                         if (add) P.stamp[j] = it;
                     }
                 }
                 const int slot = wave_append(&sh.nchg, add);
-                if (add) P.chg[slot] = j;
+                if (add) P.chg[BCHK(slot, P.n)] = j;
             }
             __syncthreads();
         }
@@ -486,7 +508,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int c = base + u * BLOCK + tid;
-                jj[u] = c < nchg ? P.chg[c] : -1;
+                jj[u] = c < nchg ? BCHK(P.chg[BCHK(c, P.n)], P.n) : -1;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -507,7 +529,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
         ++iters;
         if (acc) {
             for (int c = tid; c < nchg; c += BLOCK) {
-                const int j = P.chg[c];
+                const int j = BCHK(P.chg[BCHK(c, P.n)], P.n);
                 P.x[j] = P.xp[j];
             }
             L_hat = Lt;
@@ -515,7 +537,7 @@ __device__ void decode_instance(const BatchProblem P, BatchResult* R, float* dyn
             ++accepted;
         } else {
             for (int c = tid; c < nchg; c += BLOCK) {
-                const int j = P.chg[c];
+                const int j = BCHK(P.chg[BCHK(c, P.n)], P.n);
                 const float xh = P.x[j], xn = P.xp[j];
                 if (xh == xn) continue;
                 P.xp[j] = xh;
@@ -770,7 +792,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
                 for (int u = 0; u < kU; ++u) {
                     const bool nz = v[u] != 0.0f;
                     const int slot = wave_append(&ctl->nkeys[par], nz);
-                    if (nz) P.keys[slot] = hk_key(base + u * BLOCK + tid, v[u]);
+                    if (nz) P.keys[BCHK(slot, P.n)] = hk_key(base + u * BLOCK + tid, v[u]);
                 }
             }
             if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
@@ -788,7 +810,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
 #pragma unroll
                     for (int u = 0; u < kU; ++u) {
                         const int e = base + u * BLOCK + tid;
-                        kv[u] = e < nk ? P.keys[e] : 0ull;
+                        kv[u] = e < nk ? P.keys[BCHK(e, P.n)] : 0ull;
                     }
 #pragma unroll
                     for (int u = 0; u < kU; ++u)
@@ -813,16 +835,16 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
                 bool add = false;
                 int j = 0;
                 if (e < k_hi) {
-                    const unsigned long long key = P.keys[e];
+                    const unsigned long long key = P.keys[BCHK(e, P.n)];
                     if (key < kth) {
-                        j = static_cast<int>(0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull));
+                        j = BCHK(static_cast<int>(0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull)), P.n);
                         P.xp[j] = 0.0f;
                         add = P.stamp[j] != it;
                         if (add) P.stamp[j] = it;
                     }
                 }
                 const int slot = wave_append(&ctl->nchg[par], add);
-                if (add) chg[slot] = j;
+                if (add) chg[BCHK(slot, P.n)] = j;
             }
             if (!group_barrier<BLOCK>(ctl, G, ++nbar, sh)) return group_failed(R);
         }
@@ -832,7 +854,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
         member_slice(nchg, part, G, 1, &h_lo, &h_hi);
         long long dl = 0, dsupp = 0;
         for (int c = h_lo + tid; c < h_hi; c += BLOCK) {
-            const int j = chg[c];
+            const int j = BCHK(chg[BCHK(c, P.n)], P.n);
             const float xh = P.x[j], xn = P.xp[j];
             if (xh == xn) continue;
             dsupp += (xn != 0.0f ? 1 : 0) - (xh != 0.0f ? 1 : 0);
@@ -858,7 +880,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
             // and x' there before any barrier, so no barrier is needed here (S is final
             // since the barrier above; the owners' writes are published by the next one)
             for (int c = tid; c < nchg; c += BLOCK) {
-                const int j = chg[c];
+                const int j = BCHK(chg[BCHK(c, P.n)], P.n);
                 if (j >= c_lo && j < c_hi) P.x[j] = P.xp[j];
             }
             L_hat = Lt;
@@ -866,7 +888,7 @@ __device__ __noinline__ void decode_instance_group(const BatchProblem P, int par
             ++accepted;
         } else {
             for (int c = h_lo + tid; c < h_hi; c += BLOCK) {
-                const int j = chg[c];
+                const int j = BCHK(chg[BCHK(c, P.n)], P.n);
                 const float xh = P.x[j], xn = P.xp[j];
                 if (xh == xn) continue;
                 P.xp[j] = xh;
@@ -1024,6 +1046,26 @@ size_t static_lds_any(int d, int block, std::integer_sequence<int, Ds...>) {
 }
 
 }  // namespace
+
+hipError_t batched_check_read(int* line, hipStream_t s) {
+#if RL0_DEVICE_CHECKS
+    unsigned v = 0u;
+    hipError_t e =
+        hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_batched_check_line), sizeof(v), 0, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && v != 0u) {
+        const unsigned zero = 0u;
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_batched_check_line), &zero, sizeof(zero), 0, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    *line = static_cast<int>(v);
+    return e;
+#else
+    (void)s;
+    *line = -1;
+    return hipSuccess;
+#endif
+}
 
 hipError_t batched_set_lds_limits() {
     return set_lds_limits_all(std::make_integer_sequence<int, kMaxD>{});

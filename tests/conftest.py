@@ -26,4 +26,5 @@ def _device_index_checks(request):
     assert R.device_check() == 0, "a failed device index check before this test"
     yield
     line = R.device_check()
-    assert line == 0, f"device index check failed at kernels.hip line {line}"
+    where = f"batched.hip line {line - 100000}" if line >= 100000 else f"kernels.hip line {line}"
+    assert line == 0, f"device index check failed at {where}"
