@@ -430,13 +430,15 @@ int rl0_last_log(rl0_iter_log* out_h, int32_t cap, int32_t* count_h, void* strea
  * from A_cols or its packed form, candidate-segment sizes and positions, the sweep's
  * queue, H_k's boundary bucket, columns decoded from keys and written by the copy-out;
  * in the batched kernel rows read from A_cols, queue, change-list and key-list slots, and
- * columns read back from those lists or decoded from keys) is tested against its range
- * before use; an index outside its range is replaced by 0, so that the kernel stays
- * inside its buffers and finishes, and the source line of the first failed check is
- * recorded.  *line_h <- that line since the last call (0: none; the records are then
- * cleared; a line of the batched kernel's source is reported as 100000 + line, and a
- * single-decode line first when both failed), or -1 in the normal library, which has no
- * checks.  Synchronises the stream in the checked library. */
+ * columns read back from those lists or decoded from keys; in the learned decision's
+ * network kernel rows read from A_cols, queue slots and queued columns) is tested against
+ * its range before use; an index outside its range is replaced by 0, so that the kernel
+ * stays inside its buffers and finishes, and the source line of the first failed check
+ * is recorded.  *line_h <- that line since the last call (0: none; the records are then
+ * cleared; a line of the batched kernel's source is reported as 100000 + line, one of the
+ * network kernel's as 200000 + line, and a single-decode line first, then a batched one,
+ * when several failed), or -1 in the normal library, which has no checks.  Synchronises
+ * the stream in the checked library. */
 int rl0_device_check(int32_t* line_h, void* stream);
 
 /* Kernel timing.  While enabled, rl0_decode launches its kernels one by one (instead of

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librl0.so")
 # the same library with the loop kernels' index checks compiled in (rl0_device_check)
 CHECKED_OUT = os.path.join(HERE, "librl0_checked.so")
-CHECKED_SOURCES = ("kernels.hip", "batched.hip")
+CHECKED_SOURCES = ("kernels.hip", "batched.hip", "mlp.hip")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["constants.cpp", "general.cpp", "rl0.cpp", "kernels.hip", "batched.hip", "mlp.hip", "noalloc.hip"]
@@ -63,7 +63,7 @@ def _link(objs, out: str) -> None:
 
 def build(verbose: bool = False) -> str:
     """Builds librl0.so and librl0_checked.so (the latter differs only in the loop
-    kernels and the batched kernel, compiled with their index checks)."""
+    kernels, the batched kernel and the network kernel, compiled with their index checks)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = [(src, False) for src in SOURCES] + [(src, True) for src in CHECKED_SOURCES]
     # the compiles of the largest sources first, so that they overlap the others

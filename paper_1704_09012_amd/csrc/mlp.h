@@ -71,4 +71,9 @@ struct LearnedCols {
 };
 hipError_t launch_learned_cols(const LearnedCols& lc, hipStream_t s);
 
+// The source line of the first failed index check in the learned-decision kernel since
+// the last call (0: none; the record is then cleared), or -1 where the checks are not
+// compiled in.
+hipError_t mlp_check_read(int* line, hipStream_t s);
+
 }  // namespace rl0

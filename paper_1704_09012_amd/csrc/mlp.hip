@@ -24,6 +24,27 @@ namespace rl0 {
 
 namespace {
 
+// Checked builds (compiled with RL0_DEVICE_CHECKS=1 into the second copy of the library):
+// MCHK(i, n) tests a data-dependent index of the learned-decision kernel (a row read from
+// A_cols, a slot of a wave's queue, a queued column) against [0, n).  Outside it, the
+// source line of the first failed check is recorded in g_mlp_check_line (read back by
+// mlp_check_read) and the index becomes 0, so that the access stays inside its buffer and
+// the kernel runs to its end.  In normal builds MCHK(i, n) is i.
+#if RL0_DEVICE_CHECKS
+__device__ unsigned g_mlp_check_line;
+
+template <class I>
+__device__ __forceinline__ I mchk(I i, long long n, unsigned line) {
+    const long long v = static_cast<long long>(i);
+    if (v >= 0 && v < n) return i;
+    atomicCAS(&g_mlp_check_line, 0u, line);
+    return static_cast<I>(0);
+}
+#define MCHK(i, n) mchk((i), static_cast<long long>(n), __LINE__)
+#else
+#define MCHK(i, n) (i)
+#endif
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -607,7 +628,7 @@ __global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) 
         if (j < a.n) {
             int rows[D];
 #pragma unroll
-            for (int p = 0; p < D; ++p) rows[p] = a.A[static_cast<size_t>(j) * D + p];
+            for (int p = 0; p < D; ++p) rows[p] = MCHK(a.A[static_cast<size_t>(j) * D + p], a.m);
 #pragma unroll
             for (int p = 0; p < D; ++p) v[p] = r[rows[p]];
             need = true;
@@ -637,7 +658,7 @@ __global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) 
                     v[y - 1] = lo;
                     v[y] = hi;
                 }
-            const int slot = qn + __popcll(bal & ((1ull << lane) - 1ull));
+            const int slot = MCHK(qn + __popcll(bal & ((1ull << lane) - 1ull)), kQueueCap);
             bf16x8 f0, f1;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -654,12 +675,13 @@ __global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) 
             __builtin_amdgcn_wave_barrier();
             float lg, vl;
             mlp_tile(L, myf, lg, vl);
-            const int jj = myj[lane];
+            const int jj = MCHK(myj[lane], a.n);
             if (a.cache) a.cache[jj] = make_float2(lg, vl);
             a.value[jj] = lg >= a.logit_t ? vl : nan;
             // entries 64.. move to the front of the queue
             qn -= 64;
             if (lane < qn) {
+                (void)MCHK(64 + lane, kQueueCap);
                 const bf16x8* src = reinterpret_cast<const bf16x8*>(myf + (64 + lane) * kMlpMaxFeatures);
                 bf16x8* dst = reinterpret_cast<bf16x8*>(myf + lane * kMlpMaxFeatures);
                 const bf16x8 s0 = src[0], s1 = src[1];
@@ -677,7 +699,7 @@ __global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) 
         float lg, vl;
         mlp_tile(L, myf, lg, vl);
         if (lane < qn) {
-            const int jj = myj[lane];
+            const int jj = MCHK(myj[lane], a.n);
             if (a.cache) a.cache[jj] = make_float2(lg, vl);
             a.value[jj] = lg >= a.logit_t ? vl : nan;
         }
@@ -687,6 +709,25 @@ __global__ __launch_bounds__(kInferBlock, 4) void k_learned_cols(LearnedArgs a) 
 int blocks_of(long long count, int block) { return static_cast<int>((count + block - 1) / block); }
 
 }  // namespace
+
+hipError_t mlp_check_read(int* line, hipStream_t s) {
+#if RL0_DEVICE_CHECKS
+    unsigned v = 0u;
+    hipError_t e = hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_mlp_check_line), sizeof(v), 0, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && v != 0u) {
+        const unsigned zero = 0u;
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_mlp_check_line), &zero, sizeof(zero), 0, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    *line = static_cast<int>(v);
+    return e;
+#else
+    (void)s;
+    *line = -1;
+    return hipSuccess;
+#endif
+}
 
 hipError_t launch_mlp_features(const int32_t* A, int n, int d, const float* r, float sigma, float* feats,
                                hipStream_t s) {

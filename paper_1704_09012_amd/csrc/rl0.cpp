@@ -1954,16 +1954,20 @@ int rl0_mlp_load(const char* path_h, rl0_mlp_ckpt* info_h, float* w, float* adam
     return RL0_OK;
 }
 
-// rl0_device_check reports a line of the batched kernel's source as this base + line.
+// rl0_device_check reports a line of the batched kernel's source as this base + line,
+// and one of the learned-decision kernel's source as the second base + line.
 constexpr int kBatchedLineBase = 100000;
+constexpr int kLearnedLineBase = 200000;
 
 int rl0_device_check(int32_t* line_h, void* stream) {
     if (!line_h) return fail(RL0_EINVAL, "line_h is NULL");
     std::lock_guard<std::mutex> lk(g_mu);
-    int line = 0, bline = 0;
+    int line = 0, bline = 0, mline = 0;
     HIP_TRY(rl0::device_check_read(&line, static_cast<hipStream_t>(stream)));
     HIP_TRY(rl0::batched_check_read(&bline, static_cast<hipStream_t>(stream)));
-    *line_h = line != 0 ? line : (bline > 0 ? kBatchedLineBase + bline : 0);
+    HIP_TRY(rl0::mlp_check_read(&mline, static_cast<hipStream_t>(stream)));
+    *line_h = line != 0 ? line
+                        : (bline > 0 ? kBatchedLineBase + bline : (mline > 0 ? kLearnedLineBase + mline : 0));
     return RL0_OK;
 }
 

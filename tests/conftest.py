@@ -26,5 +26,6 @@ def _device_index_checks(request):
     assert R.device_check() == 0, "a failed device index check before this test"
     yield
     line = R.device_check()
-    where = f"batched.hip line {line - 100000}" if line >= 100000 else f"kernels.hip line {line}"
+    where = (f"mlp.hip line {line - 200000}" if line >= 200000 else
+             f"batched.hip line {line - 100000}" if line >= 100000 else f"kernels.hip line {line}")
     assert line == 0, f"device index check failed at {where}"
