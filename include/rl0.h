@@ -431,7 +431,7 @@ int rl0_last_log(rl0_iter_log* out_h, int32_t cap, int32_t* count_h, void* strea
  * queue, H_k's boundary bucket, columns decoded from keys and written by the copy-out;
  * in the batched kernel rows read from A_cols, queue, change-list and key-list slots, and
  * columns read back from those lists or decoded from keys; in the learned decision's
- * network kernel rows read from A_cols, queue slots and queued columns) is tested against
+ * network and feature kernels rows read from A_cols, queue slots and queued columns) is tested against
  * its range before use; an index outside its range is replaced by 0, so that the kernel
  * stays inside its buffers and finishes, and the source line of the first failed check
  * is recorded.  *line_h <- that line since the last call (0: none; the records are then

@@ -22,7 +22,7 @@ inline int mlp_params(int d) {
 }
 
 // feats [n][d+1]: sorted residual entries of each column's rows, then sigma.
-hipError_t launch_mlp_features(const int32_t* A, int n, int d, const float* r, float sigma, float* feats,
+hipError_t launch_mlp_features(const int32_t* A, int n, int m, int d, const float* r, float sigma, float* feats,
                                hipStream_t s);
 // labels [n][2]: (1 if x_true_j != 0 and |x_true_j - x_hat_j| > thr else 0, x_true_j - x_hat_j).
 hipError_t launch_mlp_labels(const float* x_true, const float* x_hat, int n, double thr, float* labels,

@@ -25,7 +25,7 @@ namespace rl0 {
 namespace {
 
 // Checked builds (compiled with RL0_DEVICE_CHECKS=1 into the second copy of the library):
-// MCHK(i, n) tests a data-dependent index of the learned-decision kernel (a row read from
+// MCHK(i, n) tests a data-dependent index of the learned-decision kernels (a row read from
 // A_cols, a slot of a wave's queue, a queued column) against [0, n).  Outside it, the
 // source line of the first failed check is recorded in g_mlp_check_line (read back by
 // mlp_check_read) and the index becomes 0, so that the access stays inside its buffer and
@@ -86,13 +86,13 @@ __device__ __forceinline__ float gelu_grad(float u) {
 // ------------------------------------------------------------------ features, labels
 
 template <int D>
-__global__ void k_mlp_features(const int32_t* __restrict__ A, int n, const float* __restrict__ r, float sigma,
+__global__ void k_mlp_features(const int32_t* __restrict__ A, int n, int m, const float* __restrict__ r, float sigma,
                                float* __restrict__ feats) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     float v[D];
 #pragma unroll
-    for (int p = 0; p < D; ++p) v[p] = r[A[static_cast<size_t>(j) * D + p]];
+    for (int p = 0; p < D; ++p) v[p] = r[MCHK(A[static_cast<size_t>(j) * D + p], m)];
     // insertion sort, ascending
 #pragma unroll
     for (int a = 1; a < D; ++a)
@@ -729,12 +729,12 @@ hipError_t mlp_check_read(int* line, hipStream_t s) {
 #endif
 }
 
-hipError_t launch_mlp_features(const int32_t* A, int n, int d, const float* r, float sigma, float* feats,
+hipError_t launch_mlp_features(const int32_t* A, int n, int m, int d, const float* r, float sigma, float* feats,
                                hipStream_t s) {
     const int g = blocks_of(n, 256);
     switch (d) {
 #define RL0_FEAT(D) \
-    case D: k_mlp_features<D><<<g, 256, 0, s>>>(A, n, r, sigma, feats); break;
+    case D: k_mlp_features<D><<<g, 256, 0, s>>>(A, n, m, r, sigma, feats); break;
         RL0_FEAT(1) RL0_FEAT(2) RL0_FEAT(3) RL0_FEAT(4) RL0_FEAT(5) RL0_FEAT(6) RL0_FEAT(7) RL0_FEAT(8)
         RL0_FEAT(9) RL0_FEAT(10) RL0_FEAT(11) RL0_FEAT(12) RL0_FEAT(13) RL0_FEAT(14) RL0_FEAT(15) RL0_FEAT(16)
 #undef RL0_FEAT

@@ -1750,7 +1750,7 @@ int rl0_mlp_features(const int32_t* A_cols, int32_t n, int32_t m, int32_t d, con
     if (int rc = check_dims(n, m, d)) return rc;
     if (!A_cols || !r || !feats) return fail(RL0_EINVAL, "NULL pointer");
     std::lock_guard<std::mutex> lk(g_mu);
-    HIP_TRY(rl0::launch_mlp_features(A_cols, n, d, r, sigma, feats, static_cast<hipStream_t>(stream)));
+    HIP_TRY(rl0::launch_mlp_features(A_cols, n, m, d, r, sigma, feats, static_cast<hipStream_t>(stream)));
     return RL0_OK;
 }
 
