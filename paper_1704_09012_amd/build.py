@@ -68,7 +68,7 @@ def build(verbose: bool = False) -> str:
     jobs = [(src, False) for src in SOURCES] + [(src, True) for src in CHECKED_SOURCES]
     # the compiles of the largest sources first, so that they overlap the others
     jobs.sort(key=lambda j: j[0] not in CHECKED_SOURCES)
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(8, len(os.sched_getaffinity(0))))) as ex:
         done = dict(zip(jobs, ex.map(lambda j: _compile(*j), jobs)))
     objs = [done[(src, False)] for src in SOURCES]
     _link(objs, OUT)
