@@ -127,7 +127,8 @@ typedef struct rl0_stats {
                                (|y_i| < 2^-17 and not a multiple of 2^-40); r_hat <- y is not
                                exact on those rows */
     int32_t fx_inexact_x;   /* updated entries x'_j != 0 whose conversion rounds, summed over
-                               the executed iterations (0 for learned decodes) */
+                               the executed iterations (in a learned decode over its learned
+                               and analytic sub-iterations) */
     double k_post;          /* the sparsity the posteriors assumed last: k, or with adaptive_k
                                the last k_0 */
 } rl0_stats;
