@@ -238,7 +238,7 @@ def learned_sweep(A_cols, r_hat, x_hat, t: float, sigma: float, w: np.ndarray):
 def learned_step(A_cols, y_hat, state, C, w: np.ndarray):
     """One iteration at t = t_of(state.it) with the learned decision; H_k, the residual
     and the acceptance test as in the analytic step.  Returns (new state, accepted,
-    updated mask, value, logit)."""
+    updated mask, value, logit, x_prime)."""
     t = _scores.t_of(state.it, C.c)
     x_prime, upd, value, logit = learned_sweep(A_cols, state.r_hat, state.x_hat, t, C.sigma, w)
     x_trial = _dec.hard_threshold(x_prime, C.k)
@@ -246,27 +246,37 @@ def learned_step(A_cols, y_hat, state, C, w: np.ndarray):
     L_trial = _dec.l1_fixed(r_trial)
     if L_trial < state.L_hat:
         new = _dec.State(x_hat=x_trial, r_hat=r_trial, L_hat=L_trial, it=state.it + 1, accepted=state.accepted + 1)
-        return new, True, upd, value, logit
+        return new, True, upd, value, logit, x_prime
     new = _dec.State(x_hat=state.x_hat, r_hat=state.r_hat, L_hat=state.L_hat, it=state.it + 1,
                      accepted=state.accepted)
-    return new, False, upd, value, logit
+    return new, False, upd, value, logit, x_prime
 
 
-def learned_decode(A_cols, y_hat, C, w: np.ndarray):
+def learned_decode(A_cols, y_hat, C, w: np.ndarray, count_inexact: bool = False):
     """At each t: a learned iteration, and if it is not accepted, the analytic one at the
-    same t.  Returns (x_hat, iterations executed, accepted, L_hat)."""
+    same t.  Returns (x_hat, iterations executed, accepted, L_hat); with count_inexact,
+    also the number of updated x'_j != 0 whose 2^-40 fixed-point conversion rounds,
+    summed over every executed sub-iteration (the decoder's fx_inexact_x)."""
     A_cols = np.asarray(A_cols)
     st = _dec.init_state(y_hat, A_cols.shape[0])
     iters = 0
+    inexact_x = 0
     for it in range(C.n_iters):
         if _dec.converged(st, C):
             break
         st.it = it
-        new, acc, *_ = learned_step(A_cols, y_hat, st, C, w)
+        new, acc, upd, _, _, x_prime = learned_step(A_cols, y_hat, st, C, w)
+        xp = x_prime[upd]
+        inexact_x += _dec.fx_inexact(xp[xp != 0])
         iters += 1
         if not acc:
             st.it = it
-            new = _dec.step(A_cols, y_hat, st, C).state
+            out = _dec.step(A_cols, y_hat, st, C)
+            new = out.state
+            xp = out.sweep.x_prime[out.sweep.updated]
+            inexact_x += _dec.fx_inexact(xp[xp != 0])
             iters += 1
         st = new
+    if count_inexact:
+        return st.x_hat, iters, st.accepted, st.L_hat, inexact_x
     return st.x_hat, iters, st.accepted, st.L_hat

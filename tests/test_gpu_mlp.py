@@ -122,18 +122,31 @@ def test_learned_step_decisions_match_the_oracle(d):
         assert np.max(np.abs(go[both] - value[both]), initial=0.0) <= 1e-2
 
 
-def test_silent_network_reproduces_the_analytic_decoder():
+@pytest.mark.parametrize("shift", [0, 20])
+def test_silent_network_reproduces_the_analytic_decoder(shift):
+    """A network whose logit stays below threshold: the learned decode is the analytic
+    one.  With the instance scaled by 2^-20 (y and sigma; exact in float) its x'_j fall
+    below 2^-17, so the count of rounded updates (fx_inexact_x, over the learned and the
+    analytic sub-iterations) is not 0 and is the oracle's, by both of its routes."""
     n, m, k, d = 4096, 800, 70, 7
     sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
     inst = I.draw_instance(n, m, k, d, sig, 41)
     y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
+    if shift:
+        scale = np.float32(2.0 ** -shift)
+        y = y * scale
+        sig *= float(scale)
     w = np.zeros(M.n_params(d), np.float32)
     w[-2] = -1e4
     wt = dev(w)
     xg, stg = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=wt)
-    ref = D.decode(inst.A_cols, y, D.make_constants(n, m, d, k, sig))
+    C = D.make_constants(n, m, d, k, sig)
+    ref = D.decode(inst.A_cols, y, C)
     assert np.array_equal(host(xg), ref.x_hat)
     assert stg["l1_final_fx"] == ref.L_hat and stg["accepted"] == ref.accepted
+    *_, inexact = M.learned_decode(inst.A_cols, y, C, w, count_inexact=True)
+    assert stg["fx_inexact_x"] == inexact == ref.fx_inexact_x
+    assert inexact > 0 or not shift
 
 
 def test_training_lowers_the_loss():
@@ -394,9 +407,10 @@ def test_device_learned_decode_matches_the_oracle(n, m, k, seed):
     y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m)
     w = exact_net(d, sig)
     C = D.make_constants(n, m, d, k, sig)
-    xo, io, ao, Lo = M.learned_decode(inst.A_cols, y, C, w)
+    xo, io, ao, Lo, inx = M.learned_decode(inst.A_cols, y, C, w, count_inexact=True)
     xg, st = R.decode(dev(inst.A_cols), dev(y), sigma=sig, k=k, mlp=dev(w))
     print(f"n={n}: oracle iterations {io}, accepted {ao}; gpu {st['iterations']}, {st['accepted']}", flush=True)
     assert ao > 0
     assert np.array_equal(host(xg), xo)
     assert st["iterations"] == io and st["accepted"] == ao and st["l1_final_fx"] == Lo
+    assert st["fx_inexact_x"] == inx

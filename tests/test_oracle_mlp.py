@@ -186,3 +186,23 @@ def test_learned_loop_with_a_silent_network_is_the_analytic_loop():
     x, iters, acc, L = M.learned_decode(inst.A_cols, y, C, w)
     ref = D.decode(inst.A_cols, y, C)
     assert np.array_equal(x, ref.x_hat) and L == ref.L_hat and acc == ref.accepted
+
+
+
+def test_learned_loop_counts_rounded_updates_as_the_analytic_loop():
+    """With the silent network the learned loop's count of updated x'_j != 0 whose 2^-40
+    fixed-point conversion rounds is the analytic decode's fx_inexact_x (only the retries
+    update).  The instance is scaled by 2^-20 (y and sigma; exact in float), so that
+    its x'_j fall below 2^-17 and the count is not 0."""
+    n, m, k, d = 512, 128, 10, 7
+    sig = float(np.float32(I.sigma_for_snr(40, n, m, k, d)))
+    inst = I.draw_instance(n, m, k, d, sig, 12)
+    scale = np.float32(2.0 ** -20)
+    y = D.measure(inst.A_cols, inst.x_dense(), inst.eta, m) * scale
+    C = D.make_constants(n, m, d, k, sig * float(scale))
+    w = np.zeros(M.n_params(d), np.float32)
+    w[-2] = -1e4
+    x, iters, acc, L, inexact = M.learned_decode(inst.A_cols, y, C, w, count_inexact=True)
+    ref = D.decode(inst.A_cols, y, C)
+    assert np.array_equal(x, ref.x_hat) and L == ref.L_hat
+    assert inexact == ref.fx_inexact_x > 0
